@@ -1,0 +1,751 @@
+/*
+ * Plain FP64 CPU oracle for enhanced MsRSB preconditioning
+ * (Bosma, Klevtsov, Moyner, Castelletto, arXiv:1912.06934).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * source with the HIP library and is deliberately slow and literal: plain
+ * loops, double precision, no blocking, no fusion, built with
+ * -ffp-contract=off so every product and sum is rounded as written.
+ * OpenMP is used only over independent rows (each row's arithmetic is done
+ * in a fixed order by one thread), so results do not depend on the number
+ * of threads.
+ *
+ * Every function names the passage of the paper it follows.  Sparse
+ * matrices are CSR (int32 row pointers and column indices, columns sorted
+ * ascending, FP64 values).
+ *
+ * Return codes: 0 ok, -1 bad argument, -6 singular coarse matrix,
+ * -7 Krylov breakdown (non-finite value or non-positive curvature in CG),
+ * -8 iteration limit reached.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EARG (-1)
+#define ORC_ESING (-6)
+#define ORC_EBREAK (-7)
+#define ORC_ENOCONV (-8)
+
+/* ------------------------------------------------------------------ */
+/* Filter and Jacobi operator: eq. (negoffdiag), eq. (Dhat_zero_rowsum),
+ * Alg. 1 (first three statements), SDC block diagonal (Sec. 4).
+ *
+ * G is A restricted to same-component couplings (comp = index % bs).  With
+ * filter != 0 its off-diagonal entries are min(A_ij, 0).  Dhat_ii is minus
+ * the sum of G's off-diagonal entries of row i, so L + Dhat + U has zero
+ * row sums.  The smoothing update P - omega Dhat^{-1} Ghat P equals J P with
+ *   J_ii = 1 - omega,   J_ij = -omega G_ij / Dhat_ii   (j != i).
+ * A row with Dhat_ii == 0 has nothing to smooth against and is frozen
+ * (J_i = e_i).  J is returned on A's pattern (cross-component and frozen
+ * entries are explicit zeros).  dhat may be NULL.
+ */
+int orc_filter_jacobi(int n, const int *rp, const int *ci, const double *a,
+                      int bs, int filter, double omega, double *jv,
+                      double *dhat)
+{
+    if (n < 0 || bs < 1) return ORC_EARG;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int i = 0; i < n; ++i) {
+        double d = 0.0;
+        int has_diag = 0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (j == i) { has_diag = 1; continue; }
+            if (j % bs != i % bs) continue;
+            double g = a[e];
+            if (filter && g > 0.0) g = 0.0;
+            d -= g;
+        }
+        if (!has_diag) bad = 1;
+        if (dhat) dhat[i] = d;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (d == 0.0) {
+                jv[e] = (j == i) ? 1.0 : 0.0;
+            } else if (j == i) {
+                jv[e] = 1.0 - omega;
+            } else if (j % bs != i % bs) {
+                jv[e] = 0.0;
+            } else {
+                double g = a[e];
+                if (filter && g > 0.0) g = 0.0;
+                jv[e] = -omega * g / d;
+            }
+        }
+    }
+    return bad ? ORC_EARG : ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Initial basis (Sec. 2.1): column j is the characteristic function of
+ * coarse block j, so P_ij = 1 if j == part(i), else 0, on P's pattern.
+ * Fails if part(i) is not in row i's pattern. */
+int orc_init_basis(int n, const int *prp, const int *pci, const int *part,
+                   double *pv)
+{
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        int found = 0;
+        for (int e = prp[i]; e < prp[i + 1]; ++e) {
+            pv[e] = (pci[e] == part[i]) ? 1.0 : 0.0;
+            if (pci[e] == part[i]) found = 1;
+        }
+        if (!found) bad = 1;
+    }
+    return bad ? ORC_EARG : ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* One restricted smoothing iteration (eq. (smoother) with the support
+ * restriction and the renormalisation of Alg. 1).
+ *
+ * For each row i and each j in row i's (frozen) pattern:
+ *   T_ij = sum over the J-neighbours k of i, in ascending k, of J_ik P_kj.
+ * Products P_kj whose column j is not in row i's pattern are dropped: that
+ * keeps every basis function inside its support.  Then
+ *   delta_ij = T_ij - P_ij          (the restricted update)
+ *   s_i      = sum_j T_ij           (ascending j)
+ *   Pnew_ij  = T_ij / s_i           (rescale the updated values, so every
+ *                                    row of P sums to one).
+ * If eit != NULL, *eit = max |delta_ij| over rows with interior[i] != 0.
+ */
+int orc_smooth_step(int n, const int *rp, const int *ci, const double *jv,
+                    const int *prp, const int *pci, const double *pin,
+                    double *pout, const uint8_t *interior, double *eit)
+{
+    double emax = 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : emax) reduction(| : bad)
+    for (int i = 0; i < n; ++i) {
+        int p0 = prp[i], np = prp[i + 1] - prp[i];
+        double t[64];
+        if (np > 64 || np < 1) { bad = 1; continue; }
+        for (int s = 0; s < np; ++s) t[s] = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int k = ci[e];
+            double w = jv[e];
+            for (int q = prp[k]; q < prp[k + 1]; ++q) {
+                int c = pci[q];
+                for (int s = 0; s < np; ++s) {
+                    if (pci[p0 + s] == c) {
+                        double prod = w * pin[q];
+                        t[s] = t[s] + prod;
+                        break;
+                    }
+                }
+            }
+        }
+        double rs = 0.0;
+        for (int s = 0; s < np; ++s) rs = rs + t[s];
+        for (int s = 0; s < np; ++s) {
+            double d = t[s] - pin[p0 + s];
+            if (interior && interior[i]) {
+                double ad = fabs(d);
+                if (ad > emax || ad != ad) emax = (ad != ad) ? INFINITY : ad;
+            }
+            pout[p0 + s] = t[s] / rs;
+        }
+    }
+    if (eit) *eit = emax;
+    return bad ? ORC_EARG : ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 1 loop: iterate the restricted smoothing from the P given in pv
+ * (warm start, Alg. 2) for k = 0, 1, ...; after iteration k, when
+ * k mod nit == 0, e_it is computed and the loop stops if e_it <= tol.
+ * At most kmax iterations.  A negative tol never stops early.
+ * *iters = iterations done; eit_hist[k] = e_it after iteration k, or -1
+ * when it was not computed (eit_hist may be NULL). */
+int orc_basis(int n, const int *rp, const int *ci, const double *jv,
+              const int *prp, const int *pci, double *pv,
+              const uint8_t *interior, int kmax, double tol, int nit,
+              int *iters, double *eit_last, double *eit_hist)
+{
+    if (nit < 1 || kmax < 0) return ORC_EARG;
+    int64_t nnzp = prp[n];
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(nnzp > 0 ? nnzp : 1));
+    if (!tmp) return ORC_EARG;
+    double *src = pv, *dst = tmp;
+    int k = 0, rc = ORC_OK;
+    double e = INFINITY;
+    for (k = 0; k < kmax; ++k) {
+        int check = (k % nit) == 0;
+        double ek = -1.0;
+        rc = orc_smooth_step(n, rp, ci, jv, prp, pci, src, dst, interior,
+                             check ? &ek : NULL);
+        if (rc) break;
+        if (eit_hist) eit_hist[k] = check ? ek : -1.0;
+        double *sw = src; src = dst; dst = sw;
+        if (check) {
+            e = ek;
+            if (e <= tol) { ++k; break; }
+        }
+    }
+    if (src != pv) memcpy(pv, src, sizeof(double) * (size_t)nnzp);
+    free(tmp);
+    if (iters) *iters = k;
+    if (eit_last) *eit_last = e;
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Galerkin coarse operator, eq. (lin_system_coarse) with R = P^T (Alg. 2):
+ *   Ac[j,l] = sum_i P_ij * ( sum_k A_ik P_kl )
+ * with the full, unfiltered A.  i runs ascending, and the inner sum over k
+ * ascending.  Ac is dense, row-major, nc x nc.  Coarse rows are
+ * independent, so they are computed in parallel from the transpose of P's
+ * pattern. */
+int orc_rap(int n, const int *rp, const int *ci, const double *a, int nc,
+            const int *prp, const int *pci, const double *pv, double *ac)
+{
+    int64_t nnzp = prp[n];
+    /* transpose of P: for each coarse j, the fine rows i (ascending) */
+    int *cnt = (int *)calloc((size_t)nc + 1, sizeof(int));
+    int *ti = (int *)malloc(sizeof(int) * (size_t)(nnzp > 0 ? nnzp : 1));
+    int64_t *te = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnzp > 0 ? nnzp : 1));
+    if (!cnt || !ti || !te) { free(cnt); free(ti); free(te); return ORC_EARG; }
+    for (int64_t e = 0; e < nnzp; ++e) {
+        if (pci[e] < 0 || pci[e] >= nc) { free(cnt); free(ti); free(te); return ORC_EARG; }
+        cnt[pci[e] + 1]++;
+    }
+    for (int j = 0; j < nc; ++j) cnt[j + 1] += cnt[j];
+    int *pos = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    memcpy(pos, cnt, sizeof(int) * (size_t)nc);
+    for (int i = 0; i < n; ++i)
+        for (int e = prp[i]; e < prp[i + 1]; ++e) {
+            int j = pci[e];
+            ti[pos[j]] = i;
+            te[pos[j]] = e;
+            pos[j]++;
+        }
+    free(pos);
+    memset(ac, 0, sizeof(double) * (size_t)nc * (size_t)nc);
+#pragma omp parallel
+    {
+        double *ap = (double *)calloc((size_t)nc, sizeof(double));
+        int *touched = (int *)malloc(sizeof(int) * (size_t)nc);
+        char *mark = (char *)calloc((size_t)nc, 1);
+#pragma omp for schedule(dynamic, 4)
+        for (int j = 0; j < nc; ++j) {
+            double *row = ac + (size_t)j * nc;
+            for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
+                int i = ti[t];
+                double pij = pv[te[t]];
+                /* row i of A P, accumulated over k ascending */
+                int nt = 0;
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    int k = ci[e];
+                    for (int q = prp[k]; q < prp[k + 1]; ++q) {
+                        int l = pci[q];
+                        double prod = a[e] * pv[q];
+                        if (!mark[l]) { mark[l] = 1; touched[nt++] = l; ap[l] = 0.0; }
+                        ap[l] = ap[l] + prod;
+                    }
+                }
+                for (int u = 0; u < nt; ++u) {
+                    int l = touched[u];
+                    double prod = pij * ap[l];
+                    row[l] = row[l] + prod;
+                    mark[l] = 0;
+                }
+            }
+        }
+        free(ap); free(touched); free(mark);
+    }
+    free(cnt); free(ti); free(te);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Coarse solver M_c^{-1} = A_c^{-1} (Alg. 2): dense LU with partial
+ * pivoting, in place, row-major.  At step k the pivot is the first row
+ * r >= k with the largest |a_rk|; an exact zero pivot means A_c is
+ * singular.  piv[k] = the row swapped with row k. */
+int orc_lu(int nc, double *a, int *piv)
+{
+    for (int k = 0; k < nc; ++k) {
+        int p = k;
+        double best = fabs(a[(size_t)k * nc + k]);
+        for (int r = k + 1; r < nc; ++r) {
+            double v = fabs(a[(size_t)r * nc + k]);
+            if (v > best) { best = v; p = r; }
+        }
+        piv[k] = p;
+        if (best == 0.0 || best != best) return ORC_ESING;
+        if (p != k)
+            for (int c = 0; c < nc; ++c) {
+                double t = a[(size_t)k * nc + c];
+                a[(size_t)k * nc + c] = a[(size_t)p * nc + c];
+                a[(size_t)p * nc + c] = t;
+            }
+        double d = a[(size_t)k * nc + k];
+#pragma omp parallel for schedule(static)
+        for (int r = k + 1; r < nc; ++r) {
+            double l = a[(size_t)r * nc + k] / d;
+            a[(size_t)r * nc + k] = l;
+            for (int c = k + 1; c < nc; ++c) {
+                double prod = l * a[(size_t)k * nc + c];
+                a[(size_t)r * nc + c] = a[(size_t)r * nc + c] - prod;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Solve (LU) x = Pm b in place (trans == 0), or the transposed system
+ * A^T x = b (trans != 0), from orc_lu's factors. */
+void orc_lu_solve(int nc, const double *lu, const int *piv, double *b, int trans)
+{
+    if (!trans) {
+        for (int k = 0; k < nc; ++k)
+            if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+        for (int r = 0; r < nc; ++r) {
+            double s = b[r];
+            for (int c = 0; c < r; ++c) s = s - lu[(size_t)r * nc + c] * b[c];
+            b[r] = s;
+        }
+        for (int r = nc - 1; r >= 0; --r) {
+            double s = b[r];
+            for (int c = r + 1; c < nc; ++c) s = s - lu[(size_t)r * nc + c] * b[c];
+            b[r] = s / lu[(size_t)r * nc + r];
+        }
+    } else {
+        /* A = Pm^T L U  =>  A^T = U^T L^T Pm:  solve U^T y = b, L^T w = y, x = Pm^T w */
+        for (int r = 0; r < nc; ++r) {
+            double s = b[r];
+            for (int c = 0; c < r; ++c) s = s - lu[(size_t)c * nc + r] * b[c];
+            b[r] = s / lu[(size_t)r * nc + r];
+        }
+        for (int r = nc - 1; r >= 0; --r) {
+            double s = b[r];
+            for (int c = r + 1; c < nc; ++c) s = s - lu[(size_t)c * nc + r] * b[c];
+            b[r] = s;
+        }
+        for (int k = nc - 1; k >= 0; --k)
+            if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* ILU(0): incomplete LU on A's own pattern, natural order (the IKJ
+ * elimination restricted to existing entries).  lu holds L (unit
+ * diagonal, not stored) strictly below the diagonal and U on and above
+ * it, on A's pattern, so (L U)_ij = A_ij wherever A has an entry. */
+int orc_ilu0(int n, const int *rp, const int *ci, const double *a, double *lu)
+{
+    int64_t nnz = rp[n];
+    memcpy(lu, a, sizeof(double) * (size_t)nnz);
+    int *diag = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *where = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) { diag[i] = -1; where[i] = -1; }
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] == i) diag[i] = e;
+    int rc = ORC_OK;
+    for (int i = 0; i < n && rc == ORC_OK; ++i) {
+        if (diag[i] < 0) { rc = ORC_EARG; break; }
+        for (int e = rp[i]; e < rp[i + 1]; ++e) where[ci[e]] = e;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int k = ci[e];
+            if (k >= i) break;
+            double pivot = lu[diag[k]];
+            if (pivot == 0.0) { rc = ORC_ESING; break; }
+            double lik = lu[e] / pivot;
+            lu[e] = lik;
+            for (int f = diag[k] + 1; f < rp[k + 1]; ++f) {
+                int w = where[ci[f]];
+                if (w >= 0) {
+                    double prod = lik * lu[f];
+                    lu[w] = lu[w] - prod;
+                }
+            }
+        }
+        for (int e = rp[i]; e < rp[i + 1]; ++e) where[ci[e]] = -1;
+    }
+    free(diag);
+    free(where);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Two-stage preconditioner (Alg. 3 and Alg. 4). */
+typedef struct {
+    int n;
+    const int *rp, *ci;
+    const double *a;          /* fine operator (A, or A^T for the adjoint) */
+    int nc;
+    const int *prp, *pci;
+    const double *pv;         /* prolongation P; R = P^T */
+    const double *lu;         /* LU of A_c (nc x nc) */
+    const int *piv;
+    int lu_trans;             /* solve with A_c^T instead of A_c */
+    int use_ms;               /* 0: smoother only (no coarse stage) */
+    int pre_kind, pre_sweeps; /* 0 none, 1 Jacobi, 2 l1-Jacobi, 3 ILU(0) */
+    int post_kind, post_sweeps;
+    const double *ilu;        /* ILU(0) factors on A's pattern when used */
+} orc_prec;
+
+static void spmv(int n, const int *rp, const int *ci, const double *a,
+                 const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) s = s + a[e] * x[ci[e]];
+        y[i] = s;
+    }
+}
+
+/* z += M^{-1} (v - A z) for one sweep of the given smoother */
+static void smooth_sweep(const orc_prec *m, int kind, const double *v,
+                         double *z, double *tmp)
+{
+    int n = m->n;
+    const int *rp = m->rp, *ci = m->ci;
+    const double *a = m->a;
+    spmv(n, rp, ci, a, z, tmp);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) tmp[i] = v[i] - tmp[i];
+    if (kind == 1 || kind == 2) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            double d = 0.0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                if (kind == 1) { if (ci[e] == i) d = a[e]; }
+                else d = d + fabs(a[e]);
+            }
+            z[i] = z[i] + tmp[i] / d;
+        }
+    } else if (kind == 3) {
+        /* forward: L y = res (unit lower), backward: U w = y */
+        for (int i = 0; i < n; ++i) {
+            double s = tmp[i];
+            for (int e = rp[i]; e < rp[i + 1] && ci[e] < i; ++e) s = s - m->ilu[e] * tmp[ci[e]];
+            tmp[i] = s;
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = tmp[i], d = 0.0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                if (ci[e] == i) d = m->ilu[e];
+                else if (ci[e] > i) s = s - m->ilu[e] * tmp[ci[e]];
+            }
+            tmp[i] = s / d;
+        }
+        for (int i = 0; i < n; ++i) z[i] = z[i] + tmp[i];
+    }
+}
+
+/* z = B v, Alg. 4: z = 0; pre-smoothing; z += P A_c^{-1} P^T (v - A z);
+ * post-smoothing.  work needs 2n + nc doubles. */
+static void prec_apply(const orc_prec *m, const double *v, double *z, double *work)
+{
+    int n = m->n;
+    double *tmp = work, *res = work + n, *vc = work + 2 * (size_t)n;
+    for (int i = 0; i < n; ++i) z[i] = 0.0;
+    for (int s = 0; s < m->pre_sweeps; ++s) smooth_sweep(m, m->pre_kind, v, z, tmp);
+    if (m->use_ms) {
+        spmv(n, m->rp, m->ci, m->a, z, res);
+        for (int i = 0; i < n; ++i) res[i] = v[i] - res[i];
+        for (int j = 0; j < m->nc; ++j) vc[j] = 0.0;
+        for (int i = 0; i < n; ++i)                       /* v_c = R r, R = P^T */
+            for (int e = m->prp[i]; e < m->prp[i + 1]; ++e)
+                vc[m->pci[e]] = vc[m->pci[e]] + m->pv[e] * res[i];
+        orc_lu_solve(m->nc, m->lu, m->piv, vc, m->lu_trans); /* w_c = M_c^{-1} v_c */
+        for (int i = 0; i < n; ++i) {                      /* z += P w_c */
+            double s = 0.0;
+            for (int e = m->prp[i]; e < m->prp[i + 1]; ++e) s = s + m->pv[e] * vc[m->pci[e]];
+            z[i] = z[i] + s;
+        }
+    }
+    for (int s = 0; s < m->post_sweeps; ++s) smooth_sweep(m, m->post_kind, v, z, tmp);
+}
+
+int orc_apply(const orc_prec *m, const double *v, double *z)
+{
+    double *work = (double *)malloc(sizeof(double) * (2 * (size_t)m->n + (size_t)m->nc + 1));
+    if (!work) return ORC_EARG;
+    prec_apply(m, v, z, work);
+    free(work);
+    return ORC_OK;
+}
+
+static double dot(int n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = s + x[i] * y[i];
+    return s;
+}
+
+static int is_finite(double x) { return x == x && x - x == 0.0; }
+
+/* Preconditioned CG with the flexible (Polak-Ribiere) beta
+ *   beta = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k,
+ * which stays valid for a non-symmetric or inexact preconditioner.
+ * x holds x0 on entry.  The loop stops when the recursive residual drops
+ * below rtol ||f||; the true residual ||f - A x|| is then recomputed and
+ * the iteration restarts from x if it is still above.  Iterations count
+ * products A p.  hist (may be NULL) receives ||r_k||/||f|| for
+ * k = 0..iters. */
+int orc_pcg(const orc_prec *m, const double *f, double *x, double rtol,
+            int maxit, int *iters, double *true_rel, double *hist, int hist_cap)
+{
+    int n = m->n;
+    size_t N = (size_t)n;
+    double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N),
+           *zold = malloc(sizeof(double) * N), *p = malloc(sizeof(double) * N),
+           *q = malloc(sizeof(double) * N),
+           *work = malloc(sizeof(double) * (2 * N + (size_t)m->nc + 1));
+    int rc = ORC_ENOCONV, it = 0;
+    double fn = sqrt(dot(n, f, f));
+    if (fn == 0.0) fn = 1.0;
+    double rr = 0.0;
+    int restart = 1;
+    double rz = 0.0;
+    while (it <= maxit) {
+        if (restart) {
+            spmv(n, m->rp, m->ci, m->a, x, q);
+            for (int i = 0; i < n; ++i) r[i] = f[i] - q[i];
+            rr = sqrt(dot(n, r, r));
+            if (hist && it < hist_cap) hist[it] = rr / fn;
+            if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
+            if (rr <= rtol * fn) { rc = ORC_OK; break; }
+            if (it == maxit) break;
+            prec_apply(m, r, z, work);
+            for (int i = 0; i < n; ++i) p[i] = z[i];
+            rz = dot(n, r, z);
+            restart = 0;
+        }
+        spmv(n, m->rp, m->ci, m->a, p, q);
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0) || !is_finite(pq) || !is_finite(rz)) { rc = ORC_EBREAK; break; }
+        double alpha = rz / pq;
+        for (int i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+        ++it;
+        rr = sqrt(dot(n, r, r));
+        if (hist && it < hist_cap) hist[it] = rr / fn;
+        if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
+        if (rr <= rtol * fn) { restart = 1; continue; }
+        if (it >= maxit) break;
+        for (int i = 0; i < n; ++i) zold[i] = z[i];
+        prec_apply(m, r, z, work);
+        double num = 0.0;
+        for (int i = 0; i < n; ++i) num = num + r[i] * (z[i] - zold[i]);
+        double rznew = dot(n, r, z);
+        double beta = num / rz;
+        rz = rznew;
+        for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+    spmv(n, m->rp, m->ci, m->a, x, q);
+    for (int i = 0; i < n; ++i) r[i] = f[i] - q[i];
+    if (true_rel) *true_rel = sqrt(dot(n, r, r)) / fn;
+    if (iters) *iters = it;
+    free(r); free(z); free(zold); free(p); free(q); free(work);
+    return rc;
+}
+
+/* Right-preconditioned restarted GMRES(m): Arnoldi with modified
+ * Gram-Schmidt on A B, Givens rotations for the least-squares problem,
+ * x = x0 + B (V y) at the end of each cycle.  Stops on the recursive
+ * residual, then checks the true residual as in orc_pcg.  Iterations count
+ * Arnoldi steps. */
+int orc_gmres(const orc_prec *m, const double *f, double *x, int restart,
+              double rtol, int maxit, int *iters, double *true_rel,
+              double *hist, int hist_cap)
+{
+    int n = m->n, mm = restart;
+    size_t N = (size_t)n;
+    if (mm < 1) return ORC_EARG;
+    double *V = malloc(sizeof(double) * N * (size_t)(mm + 1));
+    double *H = calloc((size_t)(mm + 1) * (size_t)mm, sizeof(double));
+    double *cs = malloc(sizeof(double) * (size_t)mm), *sn = malloc(sizeof(double) * (size_t)mm);
+    double *g = malloc(sizeof(double) * (size_t)(mm + 1)), *y = malloc(sizeof(double) * (size_t)mm);
+    double *w = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *work = malloc(sizeof(double) * (2 * N + (size_t)m->nc + 1));
+    double fn = sqrt(dot(n, f, f));
+    if (fn == 0.0) fn = 1.0;
+    int it = 0, rc = ORC_ENOCONV;
+    for (;;) {
+        spmv(n, m->rp, m->ci, m->a, x, w);
+        for (int i = 0; i < n; ++i) w[i] = f[i] - w[i];
+        double beta = sqrt(dot(n, w, w));
+        if (hist && it < hist_cap) hist[it] = beta / fn;
+        if (!is_finite(beta)) { rc = ORC_EBREAK; break; }
+        if (beta <= rtol * fn) { rc = ORC_OK; break; }
+        if (it >= maxit) break;
+        for (int i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int k = 0; k <= mm; ++k) g[k] = 0.0;
+        g[0] = beta;
+        int j = 0;
+        int converged = 0;
+        for (j = 0; j < mm && it < maxit; ++j) {
+            double *vj = V + (size_t)j * N, *vn = V + (size_t)(j + 1) * N;
+            prec_apply(m, vj, z, work);
+            spmv(n, m->rp, m->ci, m->a, z, w);
+            for (int i = 0; i <= j; ++i) {
+                double *vi = V + (size_t)i * N;
+                double h = dot(n, w, vi);
+                H[(size_t)i * mm + j] = h;
+                for (int t = 0; t < n; ++t) w[t] = w[t] - h * vi[t];
+            }
+            double hn = sqrt(dot(n, w, w));
+            H[(size_t)(j + 1) * mm + j] = hn;
+            if (hn != 0.0)
+                for (int t = 0; t < n; ++t) vn[t] = w[t] / hn;
+            for (int i = 0; i < j; ++i) {
+                double h0 = H[(size_t)i * mm + j], h1 = H[(size_t)(i + 1) * mm + j];
+                H[(size_t)i * mm + j] = cs[i] * h0 + sn[i] * h1;
+                H[(size_t)(i + 1) * mm + j] = -sn[i] * h0 + cs[i] * h1;
+            }
+            double h0 = H[(size_t)j * mm + j], h1 = H[(size_t)(j + 1) * mm + j];
+            double den = sqrt(h0 * h0 + h1 * h1);
+            if (den == 0.0 || !is_finite(den)) { rc = ORC_EBREAK; converged = -1; break; }
+            cs[j] = h0 / den;
+            sn[j] = h1 / den;
+            H[(size_t)j * mm + j] = den;
+            H[(size_t)(j + 1) * mm + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            double res = fabs(g[j + 1]);
+            if (hist && it < hist_cap) hist[it] = res / fn;
+            if (res <= rtol * fn || hn == 0.0) { converged = 1; ++j; break; }
+        }
+        /* back substitution for y, then x += B (V y) */
+        for (int r = j - 1; r >= 0; --r) {
+            double s = g[r];
+            for (int c = r + 1; c < j; ++c) s = s - H[(size_t)r * mm + c] * y[c];
+            y[r] = s / H[(size_t)r * mm + r];
+        }
+        for (int t = 0; t < n; ++t) {
+            double s = 0.0;
+            for (int r = 0; r < j; ++r) s = s + V[(size_t)r * N + t] * y[r];
+            w[t] = s;
+        }
+        prec_apply(m, w, z, work);
+        for (int t = 0; t < n; ++t) x[t] = x[t] + z[t];
+        if (converged < 0) break;
+    }
+    spmv(n, m->rp, m->ci, m->a, x, w);
+    for (int i = 0; i < n; ++i) w[i] = f[i] - w[i];
+    if (true_rel) *true_rel = sqrt(dot(n, w, w)) / fn;
+    if (iters) *iters = it;
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(z); free(work);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Two-point flux approximation on a Cartesian grid (App. B.1 with the
+ * flux split eq. (num_flux_split)).  Cells are numbered x + nx (y + ny z);
+ * dim = 2 uses nz = 1 and unit depth.  k = exp(logk).  For the face between
+ * neighbouring cells K, L in axis d, with area a_d and spacing h_d, each
+ * half-cell contributes t = 2 k a_d / h_d and the face transmissibility is
+ * the series (harmonic) combination T = t_K t_L / (t_K + t_L).  A domain
+ * face with Dirichlet value g (bc[2d] for the low side, bc[2d+1] for the
+ * high side; NaN = no flow) adds T_b = 2 k_K a_d / h_d to A_KK and T_b g
+ * to f_K.  Columns are sorted; the diagonal is always present.
+ * rp must hold n+1 ints and ci/val up to 7n entries. */
+int orc_tpfa(int dim, int nx, int ny, int nz, double hx, double hy, double hz,
+             const double *logk, const double *bc, int *rp, int *ci,
+             double *val, double *rhs)
+{
+    if (dim == 2) nz = 1;
+    if (dim != 2 && dim != 3) return ORC_EARG;
+    int n = nx * ny * nz;
+    int nd[3] = {nx, ny, nz};
+    double h[3] = {hx, hy, dim == 3 ? hz : 1.0};
+    double area[3] = {h[1] * h[2], h[0] * h[2], h[0] * h[1]};
+    if (dim == 2) { area[0] = h[1]; area[1] = h[0]; }
+    int64_t e = 0;
+    rp[0] = 0;
+    for (int c = 0; c < n; ++c) {
+        int xyz[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+        int stride[3] = {1, nx, nx * ny};
+        double kk = exp(logk[c]);
+        double diag = 0.0, f = 0.0;
+        /* neighbours in ascending index: z-, y-, x-, self, x+, y+, z+ */
+        int order[7][2] = {{2, -1}, {1, -1}, {0, -1}, {-1, 0}, {0, 1}, {1, 1}, {2, 1}};
+        int64_t diag_pos = -1;
+        for (int t = 0; t < 7; ++t) {
+            int d = order[t][0], s = order[t][1];
+            if (d < 0) { diag_pos = e; ci[e] = c; val[e] = 0.0; ++e; continue; }
+            if (d >= dim) continue;
+            int nb = xyz[d] + s;
+            if (nb < 0 || nb >= nd[d]) {
+                double g = bc[2 * d + (s > 0 ? 1 : 0)];
+                if (g == g) {
+                    double tb = 2.0 * kk * area[d] / h[d];
+                    diag = diag + tb;
+                    f = f + tb * g;
+                }
+                continue;
+            }
+            int L = c + s * stride[d];
+            double kl = exp(logk[L]);
+            double tK = 2.0 * kk * area[d] / h[d], tL = 2.0 * kl * area[d] / h[d];
+            double T = tK * tL / (tK + tL);
+            diag = diag + T;
+            ci[e] = L;
+            val[e] = -T;
+            ++e;
+        }
+        val[diag_pos] = diag;
+        rhs[c] = f;
+        rp[c + 1] = (int)e;
+    }
+    return ORC_OK;
+}
+
+/* Gradient of an objective J(p) with respect to log k through the TPFA
+ * system A(k) p = f(k), given the adjoint lambda solving A^T lambda = dJ/dp:
+ *   dJ/dlog k_K = -lambda^T (dA/dlog k_K p - df/dlog k_K).
+ * With T = t_K t_L / (t_K + t_L) and t = 2 k a/h one has
+ * dT/dlog k_K = T t_L/(t_K + t_L) = T k_L/(k_K + k_L), and a Dirichlet face
+ * has dT_b/dlog k_K = T_b, so
+ *   g_K = -[ sum over faces (K,L) of T k_L/(k_K+k_L) (p_K - p_L)(lam_K - lam_L)
+ *            + sum over Dirichlet faces of K of T_b (p_K - g_b) lam_K ].
+ * This derivation is not in the paper (which has no adjoint); it follows
+ * from the TPFA transmissibilities above. */
+int orc_tpfa_grad(int dim, int nx, int ny, int nz, double hx, double hy, double hz,
+                  const double *logk, const double *bc, const double *p,
+                  const double *lam, double *grad)
+{
+    if (dim == 2) nz = 1;
+    int n = nx * ny * nz;
+    int nd[3] = {nx, ny, nz};
+    double h[3] = {hx, hy, dim == 3 ? hz : 1.0};
+    double area[3] = {h[1] * h[2], h[0] * h[2], h[0] * h[1]};
+    if (dim == 2) { area[0] = h[1]; area[1] = h[0]; }
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < n; ++c) {
+        int xyz[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+        int stride[3] = {1, nx, nx * ny};
+        double kk = exp(logk[c]);
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int nb = xyz[d] + sg;
+                if (nb < 0 || nb >= nd[d]) {
+                    double g = bc[2 * d + (sg > 0 ? 1 : 0)];
+                    if (g == g) {
+                        double tb = 2.0 * kk * area[d] / h[d];
+                        s = s + tb * (p[c] - g) * lam[c];
+                    }
+                    continue;
+                }
+                int L = c + sg * stride[d];
+                double kl = exp(logk[L]);
+                double tK = 2.0 * kk * area[d] / h[d], tL = 2.0 * kl * area[d] / h[d];
+                double T = tK * tL / (tK + tL);
+                double dT = T * kl / (kk + kl);
+                s = s + dT * (p[c] - p[L]) * (lam[c] - lam[L]);
+            }
+        grad[c] = -s;
+    }
+    return ORC_OK;
+}
