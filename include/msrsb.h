@@ -1,0 +1,262 @@
+/*
+ * msrsb.h - C ABI of the MI355X (gfx950) enhanced MsRSB preconditioner.
+ *
+ * Method: Bosma, Klevtsov, Moyner, Castelletto, "Enhanced multiscale
+ * restriction-smoothed basis (MsRSB) preconditioning with applications to
+ * porous media flow and geomechanics", arXiv:1912.06934.
+ *
+ * The calls follow the paper's statement of the problem:
+ *   A u = f                                   (eq. linsys_general)
+ *   SetupMsRSBpreconditioner(A)               (Alg. 2)
+ *     P = EnhancedMsRSB(A, P)                 (Alg. 1)  -> msrsb_setup_basis
+ *     R = P^T, A_c = R A P, M_c^{-1}          (Alg. 2)  -> msrsb_build_coarse
+ *   ApplyMsRSBTwoLevelPreconditioner(A, v)    (Alg. 3, Alg. 4)
+ *                                                       -> msrsb_apply_preconditioner
+ *   Krylov acceleration (PCG, GMRES)          (Sec. 3.2, Sec. 4.1)
+ *                                                       -> msrsb_solve
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns msrsb_status; the message of the last failure is
+ *   msrsb_last_error().  Nothing aborts and no C++ exception crosses the ABI.
+ * - `where` says where caller buffers live: MSRSB_HOST (pageable or pinned
+ *   host memory) or MSRSB_DEVICE (device memory on the context's GPU).
+ * - Inputs are copied into context-owned device memory before the call
+ *   returns; the caller may free or reuse its buffers afterwards.  Outputs
+ *   go into caller buffers.  The context owns P, J, A_c, its inverse, the
+ *   smoother data and all workspaces; msrsb_destroy frees them.
+ * - All device work is ordered on the context's stream (set at creation or
+ *   with msrsb_set_stream).  Calls that return host-visible results
+ *   synchronise that stream; the others return once the work is queued.
+ * - Sparse matrices are CSR with int32 row pointers and column indices,
+ *   columns strictly ascending within a row, the diagonal present, FP64
+ *   values.  Vectors are FP64.
+ * - Order of calls: set_matrix (or assemble_tpfa) -> set_coarse ->
+ *   setup_basis -> build_coarse -> apply / solve.  A call out of order
+ *   returns MSRSB_E_STATE.  update_values keeps P and the coarse solver as a
+ *   (stale) preconditioner until setup is run again.
+ * - One context per host thread; there is no global mutable state.
+ */
+#ifndef MSRSB_H
+#define MSRSB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msrsb_ctx msrsb_ctx;
+
+typedef enum {
+    MSRSB_OK = 0,
+    MSRSB_E_ARG = -1,              /* invalid argument or input data */
+    MSRSB_E_STATE = -2,            /* call out of order */
+    MSRSB_E_HIP = -3,              /* HIP runtime error */
+    MSRSB_E_NOMEM = -4,            /* device allocation failed */
+    MSRSB_E_BASIS_DIVERGED = -5,   /* e_it non-finite, or P left [0,1] */
+    MSRSB_E_COARSE_SINGULAR = -6,  /* zero pivot in the coarse factorisation */
+    MSRSB_E_BREAKDOWN = -7,        /* non-finite scalar, or p^T A p <= 0 in CG */
+    MSRSB_E_NOT_CONVERGED = -8     /* iteration limit reached */
+} msrsb_status;
+
+enum { MSRSB_HOST = 0, MSRSB_DEVICE = 1 };
+
+/* Smoothers of the two-stage preconditioner (Alg. 4). */
+enum {
+    MSRSB_SMOOTH_NONE = 0,
+    MSRSB_SMOOTH_JACOBI = 1,     /* M = diag(A) */
+    MSRSB_SMOOTH_L1JACOBI = 2,   /* M_ii = sum_j |A_ij| */
+    MSRSB_SMOOTH_ILU0 = 3        /* ILU(0) on A's pattern, natural order */
+};
+
+/* Krylov accelerators. */
+enum { MSRSB_KRYLOV_PCG = 0, MSRSB_KRYLOV_GMRES = 1 };
+
+/* Phases reported by msrsb_get_timings (milliseconds, last run of each). */
+enum {
+    MSRSB_PHASE_FILTER = 0,      /* filter + Jacobi operator */
+    MSRSB_PHASE_INIT = 1,        /* initial basis */
+    MSRSB_PHASE_SMOOTH = 2,      /* all restricted smoothing iterations */
+    MSRSB_PHASE_RAP = 3,         /* R = P^T values and A_c = R A P */
+    MSRSB_PHASE_FACTOR = 4,      /* coarse factorisation (inverse of A_c) */
+    MSRSB_PHASE_SOLVE = 5,       /* last msrsb_solve */
+    MSRSB_PHASE_SOLVE_T = 6,     /* last msrsb_solve_transpose */
+    MSRSB_PHASE_GRAD = 7,        /* last msrsb_tpfa_adjoint_grad */
+    MSRSB_PHASE_ASSEMBLE = 8,    /* last msrsb_assemble_tpfa */
+    MSRSB_PHASE_SMOOTHER_SETUP = 9, /* smoother data (diagonals, ILU(0)) */
+    MSRSB_N_PHASES = 10
+};
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (NULL = the null stream).  The stream must stay valid while the context
+ * uses it. */
+msrsb_status msrsb_create(msrsb_ctx **out, int device, void *hip_stream);
+/* Free the context and all its device memory (synchronises its stream). */
+void msrsb_destroy(msrsb_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none).  Never NULL. */
+const char *msrsb_last_error(const msrsb_ctx *ctx);
+/* Re-target the context to another stream of the same device. */
+msrsb_status msrsb_set_stream(msrsb_ctx *ctx, void *hip_stream);
+
+/* Fine operator A of eq. (linsys_general): n x n CSR.  block_size is 1 for
+ * scalar problems, or the number of displacement components (2 or 3) for
+ * vector problems with interleaved numbering dof = block_size*node + l; the
+ * basis is then built from the separate-displacement-component
+ * approximation (Sec. 4, eq. blk_stiff_SDC): couplings between different
+ * components are ignored by the filter.  Replaces any previous matrix and
+ * resets the state to "matrix set".
+ * Errors: E_ARG for n < 1, nnz != rowptr[n], unsorted or out-of-range
+ * columns, a missing diagonal or block_size not dividing n. */
+msrsb_status msrsb_set_matrix(msrsb_ctx *ctx, int32_t n, int64_t nnz,
+                              const int32_t *rowptr, const int32_t *col,
+                              const double *val, int32_t block_size, int where);
+
+/* New values on the same pattern (nnz values).  P, A_c and the smoother
+ * keep their old values until the next setup_basis / build_coarse. */
+msrsb_status msrsb_update_values(msrsb_ctx *ctx, const double *val, int where);
+
+/* Copy the current A out: rowptr (n+1), col (nnz) and val (nnz) buffers,
+ * any of which may be NULL. */
+msrsb_status msrsb_get_matrix(msrsb_ctx *ctx, int32_t *rowptr, int32_t *col,
+                              double *val, int where);
+
+/* Two-point flux approximation (App. B.1, flux split eq. num_flux_split)
+ * on a Cartesian grid of dims[0] x dims[1] (x dims[2] if dim == 3) cells of
+ * size h[0] x h[1] (x h[2]), numbered x + nx*(y + ny*z), unit depth in 2D.
+ * k = exp(log_k) per cell (n values).  bc[2d] / bc[2d+1] are Dirichlet
+ * pressures on the low / high domain face of axis d; NaN means no flow.
+ * Face transmissibility T = t_K t_L / (t_K + t_L), t = 2 k area / h; a
+ * Dirichlet face adds T_b = 2 k_K area / h to A_KK and T_b g to f_K.
+ * The result becomes the context's matrix exactly as msrsb_set_matrix would
+ * (same pattern on a repeated call with the same grid: then it acts as
+ * msrsb_update_values and keeps P for a warm start).  rhs_out (n values,
+ * may be NULL) receives f. */
+msrsb_status msrsb_assemble_tpfa(msrsb_ctx *ctx, int32_t dim, const int32_t dims[3],
+                                 const double h[3], const double *log_k,
+                                 const double bc[6], double *rhs_out, int where);
+
+/* Coarse partition and support regions (Sec. 2.1).  part[n] in [0, nc) is
+ * the coarse block of each fine row (the initial basis is its
+ * characteristic function).  The support pattern is CSR over fine rows:
+ * sup_col[sup_rowptr[i] .. sup_rowptr[i+1]) lists, ascending, the coarse
+ * basis functions whose support contains row i; it is P's frozen sparsity
+ * pattern and must contain part[i].  interior[i] != 0 marks rows that count
+ * in the convergence measure e_it (rows not on a support edge, Alg. 1).
+ * At most 32 entries per row.
+ * Errors: E_ARG for nc < 1 or nc > 4096, empty rows, unsorted or
+ * out-of-range columns, part[i] not in row i's pattern. */
+msrsb_status msrsb_set_coarse(msrsb_ctx *ctx, int32_t nc, const int32_t *part,
+                              const int32_t *sup_rowptr, const int32_t *sup_col,
+                              const uint8_t *interior, int where);
+
+typedef struct {
+    double omega;        /* relaxation factor, the paper uses 2/3 (Sec. 2.1) */
+    int32_t max_iter;    /* iteration cap */
+    double tol;          /* stop when e_it <= tol; negative = run max_iter */
+    int32_t check_every; /* n_it: e_it is computed when k mod n_it == 0 */
+    int32_t filter;      /* 1 = enhanced (filtered, eq. negoffdiag), 0 = naive */
+    int32_t fp32_basis;  /* 1 = J, P and the smoothing arithmetic in FP32
+                            (row sums and the division stay FP64) */
+    int32_t warm_start;  /* 1 = keep the current P as the start (Alg. 2) */
+} msrsb_basis_opts;
+
+typedef struct {
+    int32_t iters;        /* iterations done */
+    double e_it;          /* last computed e_it */
+    double max_rowsum_err;/* max_i |sum_j P_ij - 1| (FP64 sums) */
+    double p_min, p_max;  /* range of P's entries */
+} msrsb_basis_info;
+
+/* Alg. 1: filter (eq. negoffdiag) and zero-row-sum diagonal
+ * (eq. Dhat_zero_rowsum), then restricted Jacobi smoothing (eq. smoother)
+ * of the basis on its frozen support with renormalisation of every row of
+ * P to one.  Without warm_start P starts from the characteristic functions
+ * of the coarse blocks.  Synchronises; info may be NULL.
+ * Errors: E_STATE before set_coarse; E_BASIS_DIVERGED when e_it is not
+ * finite (typically the naive method on a non-M-matrix). */
+msrsb_status msrsb_setup_basis(msrsb_ctx *ctx, const msrsb_basis_opts *opts,
+                               msrsb_basis_info *info);
+
+/* Overwrite P's values (nnz_P values on the support pattern, FP64), e.g. to
+ * resume from a saved basis.  Marks the basis as set up. */
+msrsb_status msrsb_set_prolongation(msrsb_ctx *ctx, const double *val, int where);
+/* Copy P out (FP64 values; any pointer may be NULL). */
+msrsb_status msrsb_get_prolongation(msrsb_ctx *ctx, int32_t *rowptr, int32_t *col,
+                                    double *val, int where);
+
+typedef struct {
+    int32_t restriction; /* 0 = Galerkin R = P^T (Sec. 2); nothing else yet */
+} msrsb_coarse_opts;
+
+/* Alg. 2: R = P^T, A_c = R A P with the unfiltered A (eq.
+ * lin_system_coarse), and the coarse solver M_c^{-1} = A_c^{-1} computed
+ * exactly in FP64 (Gauss-Jordan with partial pivoting).  Synchronises.
+ * Errors: E_STATE before setup_basis; E_COARSE_SINGULAR on a zero pivot. */
+msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);
+/* Copy A_c out as a dense row-major nc x nc FP64 matrix. */
+msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *ctx, double *dense, int where);
+
+typedef struct {
+    int32_t krylov;          /* MSRSB_KRYLOV_PCG or MSRSB_KRYLOV_GMRES */
+    int32_t restart;         /* GMRES restart length */
+    double rtol;             /* stop at ||f - A u|| <= rtol ||f|| */
+    int32_t max_iter;
+    int32_t pre_smoother, pre_sweeps;
+    int32_t post_smoother, post_sweeps;
+    int32_t fp32_smoother;   /* 1 = smoother matrix values and arithmetic in FP32 */
+    int32_t use_multiscale;  /* 0 = smoother-only preconditioner */
+} msrsb_solve_opts;
+
+typedef struct {
+    int32_t iters;           /* Krylov iterations (products A p / Arnoldi steps) */
+    double true_rel_res;     /* ||f - A u|| / ||f||, recomputed at exit */
+    double *history;         /* optional host buffer: relative residual per
+                                iteration (recursive estimate) */
+    int32_t history_cap;     /* its capacity */
+} msrsb_solve_info;
+
+/* z = B v with B the two-stage preconditioner of Alg. 4: z = 0; pre-sweeps
+ * z += M_pre^{-1}(v - A z); z += P A_c^{-1} P^T (v - A z) (Alg. 3);
+ * post-sweeps.  n values each.  Errors: E_STATE before build_coarse (unless
+ * use_multiscale == 0). */
+msrsb_status msrsb_apply_preconditioner(msrsb_ctx *ctx, const msrsb_solve_opts *opts,
+                                        const double *v, double *z, int where);
+
+/* Solve A u = f (n values) with the preconditioned Krylov method; u holds
+ * the initial guess on entry and the solution on exit.  PCG uses the
+ * flexible Polak-Ribiere beta.  Convergence is tested on the recursive
+ * residual and confirmed on the true residual.  Synchronises; info may be
+ * NULL.  Errors: E_BREAKDOWN, E_NOT_CONVERGED (u still holds the last
+ * iterate and info the achieved residual). */
+msrsb_status msrsb_solve(msrsb_ctx *ctx, const double *f, double *u,
+                         const msrsb_solve_opts *opts, msrsb_solve_info *info,
+                         int where);
+
+/* Solve A^T lambda = g with the transposed preconditioner
+ * B^T (pre and post smoothers exchanged, P A_c^{-T} P^T), e.g. the adjoint
+ * system of a gradient computation. */
+msrsb_status msrsb_solve_transpose(msrsb_ctx *ctx, const double *g, double *lambda,
+                                   const msrsb_solve_opts *opts, msrsb_solve_info *info,
+                                   int where);
+
+/* Gradient of an objective with respect to log k through the TPFA system
+ * of the last msrsb_assemble_tpfa, given the pressure p and the adjoint
+ * lambda (A^T lambda = dJ/dp):
+ *   grad_K = -[ sum_{faces (K,L)} T k_L/(k_K+k_L) (p_K-p_L)(lam_K-lam_L)
+ *               + sum_{Dirichlet faces of K} T_b (p_K - g_b) lam_K ].
+ * (Derived from the TPFA transmissibilities; the paper has no adjoint.)
+ * All vectors n values.  Errors: E_STATE if A was not assembled by
+ * msrsb_assemble_tpfa. */
+msrsb_status msrsb_tpfa_adjoint_grad(msrsb_ctx *ctx, const double *log_k, const double *p,
+                                     const double *lambda, double *grad, int where);
+
+/* Milliseconds of the last run of each phase (MSRSB_PHASE_*), measured
+ * with HIP events on the context's stream.  Synchronises. */
+msrsb_status msrsb_get_timings(msrsb_ctx *ctx, double *ms_by_phase, int32_t n_phases);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSRSB_H */

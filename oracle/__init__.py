@@ -57,6 +57,7 @@ class Prec(C.Structure):
 
 
 def _declare(L):
+    L.orc_threads.argtypes = []
     L.orc_filter_jacobi.argtypes = [_I, _P, _P, _P, _I, _I, _D, _P, _P]
     L.orc_init_basis.argtypes = [_I, _P, _P, _P, _P]
     L.orc_smooth_step.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -99,6 +100,11 @@ def _check(rc, what):
 # ----------------------------------------------------------------------------
 # step-level wrappers
 # ----------------------------------------------------------------------------
+
+def threads():
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(lib().orc_threads())
+
 
 def filter_jacobi(rp, ci, a, bs=1, filt=True, omega=2.0 / 3.0):
     """J = I - omega Dhat^{-1} Ghat on A's pattern, and Dhat."""

@@ -24,11 +24,25 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define ORC_OK 0
 #define ORC_EARG (-1)
 #define ORC_ESING (-6)
 #define ORC_EBREAK (-7)
 #define ORC_ENOCONV (-8)
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Filter and Jacobi operator: eq. (negoffdiag), eq. (Dhat_zero_rowsum),

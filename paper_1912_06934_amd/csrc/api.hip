@@ -1,0 +1,877 @@
+// C ABI of the enhanced MsRSB library: argument checking, the state machine,
+// symbolic set-up on the host (patterns, transposes, level sets) and the
+// sequencing of device kernels.  Numerical work runs in the kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "solve.h"
+
+using namespace msrsb;
+
+namespace {
+
+msrsb_status fail(msrsb_ctx *c, msrsb_status code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) hipSetDevice(d);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+bool dalloc(T *&p, size_t count)
+{
+    dfree(p);
+    return hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(T)) ==
+           hipSuccess;
+}
+
+template <typename T>
+bool dalloc_keep(T *&p, size_t count)
+{
+    if (p) return true;
+    return hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(T)) ==
+           hipSuccess;
+}
+
+hipMemcpyKind kind_in(int where)
+{
+    return where == MSRSB_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_out(int where)
+{
+    return where == MSRSB_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+bool valid_where(int where) { return where == MSRSB_HOST || where == MSRSB_DEVICE; }
+
+// copy a caller buffer to a host vector (for checks and symbolic work)
+template <typename T>
+bool to_host(msrsb_ctx *c, std::vector<T> &out, const T *src, size_t count, int where)
+{
+    out.resize(count);
+    if (count == 0) return true;
+    if (where == MSRSB_HOST) {
+        std::memcpy(out.data(), src, count * sizeof(T));
+        return true;
+    }
+    if (hipMemcpyAsync(out.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, c->stream) !=
+        hipSuccess)
+        return false;
+    return hipStreamSynchronize(c->stream) == hipSuccess;
+}
+
+void phase_begin(msrsb_ctx *c, int ph)
+{
+    if (!c->ev_start[ph]) {
+        hipEventCreate(&c->ev_start[ph]);
+        hipEventCreate(&c->ev_stop[ph]);
+    }
+    hipEventRecord(c->ev_start[ph], c->stream);
+}
+
+void phase_end(msrsb_ctx *c, int ph)
+{
+    hipEventRecord(c->ev_stop[ph], c->stream);
+    c->ev_used[ph] = true;
+}
+
+void free_matrix(msrsb_ctx *c)
+{
+    dfree(c->rp);
+    dfree(c->ci);
+    dfree(c->diag_pos);
+    dfree(c->a);
+    dfree(c->a32);
+    dfree(c->at_rp);
+    dfree(c->at_ci);
+    dfree(c->at_src);
+    dfree(c->at);
+    dfree(c->at32);
+    if (c->j_own_pattern) {
+        dfree(c->jrp);
+        dfree(c->jci);
+    }
+    c->jrp = c->jci = nullptr;
+    c->j_own_pattern = false;
+    dfree(c->jv);
+    dfree(c->jv32);
+    dfree(c->ilu);
+    dfree(c->ilu_lev_ptr);
+    dfree(c->ilu_lev_rows);
+    dfree(c->ilu_lev_ptr_u);
+    dfree(c->ilu_lev_rows_u);
+    dfree(c->dinv_jac);
+    dfree(c->dinv_l1);
+    dfree(c->dinv_jac32);
+    dfree(c->dinv_l1_32);
+    dfree(c->dinv_jac_t);
+    dfree(c->dinv_l1_t);
+    dfree(c->dinv_jac32_t);
+    dfree(c->dinv_l1_32_t);
+    for (auto &p : c->w) dfree(p);
+    dfree(c->gm_v);
+    dfree(c->gm_h);
+    c->gm_cap = 0;
+    dfree(c->partials);
+    dfree(c->tlogk);
+    c->at_pattern = false;
+    c->smoother_valid = c->smoother32_valid = false;
+    c->smoother_t_valid = c->smoother32_t_valid = false;
+    c->ilu_valid = false;
+    c->tpfa = false;
+}
+
+void free_coarse(msrsb_ctx *c)
+{
+    dfree(c->part);
+    dfree(c->prp);
+    dfree(c->pci);
+    dfree(c->interior);
+    for (int t = 0; t < 2; ++t) {
+        dfree(c->p64[t]);
+        dfree(c->p32[t]);
+    }
+    dfree(c->rrp);
+    dfree(c->rci);
+    dfree(c->rsrc);
+    dfree(c->r64);
+    dfree(c->r32);
+    dfree(c->ac);
+    dfree(c->acinv);
+    dfree(c->gj_b);
+    dfree(c->piv);
+    dfree(c->colsrc);
+    dfree(c->vc);
+    dfree(c->wc);
+    dfree(c->partials);
+    c->has_coarse = c->has_basis = c->has_coarse_op = false;
+}
+
+// Validate a CSR pattern: monotone row pointers, sorted in-range columns,
+// diagonal present.  Fills diag positions.
+bool check_csr(const std::vector<int> &rp, const std::vector<int> &ci, int n,
+               std::vector<int> &dpos, std::string &why)
+{
+    if (rp[0] != 0) {
+        why = "rowptr[0] must be 0";
+        return false;
+    }
+    dpos.assign(n, -1);
+    for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) {
+            why = "rowptr not monotone at row " + std::to_string(i);
+            return false;
+        }
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            if (j < 0 || j >= n) {
+                why = "column out of range in row " + std::to_string(i);
+                return false;
+            }
+            if (e > rp[i] && ci[e - 1] >= j) {
+                why = "columns not strictly ascending in row " + std::to_string(i);
+                return false;
+            }
+            if (j == i) dpos[i] = e;
+        }
+        if (dpos[i] < 0) {
+            why = "missing diagonal in row " + std::to_string(i);
+            return false;
+        }
+    }
+    return true;
+}
+
+msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> &&hrp,
+                             std::vector<int> &&hci, const std::vector<int> &dpos, int bs)
+{
+    free_matrix(c);
+    c->n = n;
+    c->nnz = nnz;
+    c->bs = bs;
+    c->h_rp = std::move(hrp);
+    c->h_ci = std::move(hci);
+    if (!dalloc(c->rp, n + 1) || !dalloc(c->ci, nnz) || !dalloc(c->diag_pos, n) ||
+        !dalloc(c->a, nnz))
+        return fail(c, MSRSB_E_NOMEM, "device allocation of A failed");
+    hipMemcpyAsync(c->rp, c->h_rp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->ci, c->h_ci.data(), nnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->diag_pos, dpos.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    // J's pattern: A's own for scalar problems, same-component entries otherwise
+    if (bs == 1) {
+        c->jrp = c->rp;
+        c->jci = c->ci;
+        c->jnnz = nnz;
+        c->j_own_pattern = false;
+    } else {
+        std::vector<int> jrp(n + 1, 0), jci;
+        jci.reserve(nnz / bs + n);
+        for (int i = 0; i < n; ++i) {
+            for (int e = c->h_rp[i]; e < c->h_rp[i + 1]; ++e)
+                if (c->h_ci[e] % bs == i % bs) jci.push_back(c->h_ci[e]);
+            jrp[i + 1] = static_cast<int>(jci.size());
+        }
+        c->jnnz = static_cast<int64_t>(jci.size());
+        if (!dalloc(c->jrp, n + 1) || !dalloc(c->jci, c->jnnz))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of J failed");
+        c->j_own_pattern = true;
+        hipMemcpyAsync(c->jrp, jrp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+        hipMemcpyAsync(c->jci, jci.data(), c->jnnz * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "copying the pattern failed");
+    c->has_matrix = true;
+    return MSRSB_OK;
+}
+
+// explicit transpose pattern of A with a source map for the values
+msrsb_status ensure_transpose(msrsb_ctx *c)
+{
+    if (c->at_pattern) {
+        launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
+        return MSRSB_OK;
+    }
+    const int n = c->n;
+    std::vector<int> trp(n + 1, 0), tci(c->nnz), src(c->nnz);
+    for (int64_t e = 0; e < c->nnz; ++e) trp[c->h_ci[e] + 1]++;
+    for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    std::vector<int> pos(trp.begin(), trp.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int e = c->h_rp[i]; e < c->h_rp[i + 1]; ++e) {
+            const int j = c->h_ci[e];
+            tci[pos[j]] = i;
+            src[pos[j]] = e;
+            pos[j]++;
+        }
+    if (!dalloc(c->at_rp, n + 1) || !dalloc(c->at_ci, c->nnz) || !dalloc(c->at_src, c->nnz) ||
+        !dalloc(c->at, c->nnz))
+        return fail(c, MSRSB_E_NOMEM, "device allocation of A^T failed");
+    hipMemcpyAsync(c->at_rp, trp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->at_ci, tci.data(), c->nnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->at_src, src.data(), c->nnz * sizeof(int), hipMemcpyHostToDevice,
+                   c->stream);
+    launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "building A^T failed");
+    c->at_pattern = true;
+    return MSRSB_OK;
+}
+
+bool solve_opts_ok(msrsb_ctx *c, const msrsb_solve_opts *o)
+{
+    if (!o) return fail(c, MSRSB_E_ARG, "solve options are NULL"), false;
+    auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_ILU0; };
+    if (!sm_ok(o->pre_smoother) || !sm_ok(o->post_smoother) || o->pre_sweeps < 0 ||
+        o->post_sweeps < 0 || o->pre_sweeps > 64 || o->post_sweeps > 64)
+        return fail(c, MSRSB_E_ARG, "invalid smoother options"), false;
+    if (o->krylov != MSRSB_KRYLOV_PCG && o->krylov != MSRSB_KRYLOV_GMRES)
+        return fail(c, MSRSB_E_ARG, "invalid Krylov method"), false;
+    if (!(o->rtol > 0.0) || o->max_iter < 0)
+        return fail(c, MSRSB_E_ARG, "rtol must be > 0 and max_iter >= 0"), false;
+    if (o->krylov == MSRSB_KRYLOV_GMRES && (o->restart < 1 || o->restart > 64))
+        return fail(c, MSRSB_E_ARG, "GMRES restart must be in [1, 64]"), false;
+    if (o->use_multiscale && !c->has_coarse_op)
+        return fail(c, MSRSB_E_STATE, "build_coarse must run before a multiscale apply"), false;
+    return true;
+}
+
+msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solve_opts *o,
+                      msrsb_solve_info *info, int where, bool trans)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
+    if (!f || !u || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid vector arguments");
+    if (!solve_opts_ok(c, o)) return o ? (o->use_multiscale && !c->has_coarse_op ? MSRSB_E_STATE : MSRSB_E_ARG) : MSRSB_E_ARG;
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    if (trans && (st = ensure_transpose(c))) return st;
+    if ((st = ensure_smoother(c, o, trans))) return fail(c, st, c->err.empty() ? "smoother set-up failed" : c->err);
+    const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
+    double *df = c->w[5], *dx = c->w[6];
+    hipMemcpyAsync(df, f, bytes, kind_in(where), c->stream);
+    hipMemcpyAsync(dx, u, bytes, kind_in(where), c->stream);
+    const int ph = trans ? MSRSB_PHASE_SOLVE_T : MSRSB_PHASE_SOLVE;
+    phase_begin(c, ph);
+    st = o->krylov == MSRSB_KRYLOV_PCG ? pcg(c, df, dx, o, info, trans)
+                                       : gmres(c, df, dx, o, info, trans);
+    phase_end(c, ph);
+    hipMemcpyAsync(u, dx, bytes, kind_out(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "solve failed on the device");
+    if (st == MSRSB_E_BREAKDOWN) return fail(c, st, "Krylov breakdown (non-finite value or p^T A p <= 0)");
+    if (st == MSRSB_E_NOT_CONVERGED) return fail(c, st, "iteration limit reached");
+    if (st) return fail(c, st, "solve failed");
+    return MSRSB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msrsb_status msrsb_create(msrsb_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return MSRSB_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return MSRSB_E_ARG;
+    msrsb_ctx *c = new (std::nothrow) msrsb_ctx();
+    if (!c) return MSRSB_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard g(device);
+    if (!dalloc(c->dev_flag, 4) || !dalloc(c->eit_bits, 1) || !dalloc(c->scal, S_COUNT)) {
+        delete c;
+        return MSRSB_E_NOMEM;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return MSRSB_E_NOMEM;
+    }
+    *out = c;
+    return MSRSB_OK;
+}
+
+void msrsb_destroy(msrsb_ctx *c)
+{
+    if (!c) return;
+    DeviceGuard g(c->device);
+    hipStreamSynchronize(c->stream);
+    free_coarse(c);
+    free_matrix(c);
+    dfree(c->dev_flag);
+    dfree(c->eit_bits);
+    dfree(c->scal);
+    if (c->h_pinned) hipHostFree(c->h_pinned);
+    for (int p = 0; p < MSRSB_N_PHASES; ++p)
+        if (c->ev_start[p]) {
+            hipEventDestroy(c->ev_start[p]);
+            hipEventDestroy(c->ev_stop[p]);
+        }
+    delete c;
+}
+
+const char *msrsb_last_error(const msrsb_ctx *c) { return c ? c->err.c_str() : ""; }
+
+msrsb_status msrsb_set_stream(msrsb_ctx *c, void *hip_stream)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    hipStreamSynchronize(c->stream);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_set_matrix(msrsb_ctx *c, int32_t n, int64_t nnz, const int32_t *rowptr,
+                              const int32_t *col, const double *val, int32_t block_size,
+                              int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (n < 1 || nnz < n || !rowptr || !col || !val || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid matrix arguments");
+    if (block_size < 1 || block_size > 3 || n % block_size)
+        return fail(c, MSRSB_E_ARG, "block_size must be 1..3 and divide n");
+    if (nnz > INT32_MAX) return fail(c, MSRSB_E_ARG, "nnz exceeds int32 indexing");
+    std::vector<int> hrp, hci, dpos;
+    if (!to_host(c, hrp, rowptr, static_cast<size_t>(n) + 1, where) ||
+        !to_host(c, hci, col, static_cast<size_t>(nnz), where))
+        return fail(c, MSRSB_E_HIP, "reading the pattern failed");
+    if (hrp[n] != nnz) return fail(c, MSRSB_E_ARG, "rowptr[n] != nnz");
+    std::string why;
+    if (!check_csr(hrp, hci, n, dpos, why)) return fail(c, MSRSB_E_ARG, why);
+    free_coarse(c);
+    msrsb_status st = install_pattern(c, n, nnz, std::move(hrp), std::move(hci), dpos, block_size);
+    if (st) return st;
+    hipMemcpyAsync(c->a, val, nnz * sizeof(double), kind_in(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "copying the values failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_update_values(msrsb_ctx *c, const double *val, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
+    if (!val || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid values");
+    hipMemcpyAsync(c->a, val, c->nnz * sizeof(double), kind_in(where), c->stream);
+    c->smoother_valid = c->smoother32_valid = false;
+    c->smoother_t_valid = c->smoother32_t_valid = false;
+    c->ilu_valid = false;
+    if (c->at_pattern) launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "copying the values failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_get_matrix(msrsb_ctx *c, int32_t *rowptr, int32_t *col, double *val, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
+    if (!valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid where");
+    if (rowptr)
+        hipMemcpyAsync(rowptr, c->rp, (c->n + 1) * sizeof(int), kind_out(where), c->stream);
+    if (col) hipMemcpyAsync(col, c->ci, c->nnz * sizeof(int), kind_out(where), c->stream);
+    if (val) hipMemcpyAsync(val, c->a, c->nnz * sizeof(double), kind_out(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "copy failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_assemble_tpfa(msrsb_ctx *c, int32_t dim, const int32_t dims[3],
+                                 const double h[3], const double *log_k, const double bc[6],
+                                 double *rhs_out, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if ((dim != 2 && dim != 3) || !dims || !h || !log_k || !bc || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid TPFA arguments");
+    const int nx = dims[0], ny = dims[1], nz = dim == 3 ? dims[2] : 1;
+    if (nx < 1 || ny < 1 || nz < 1 || static_cast<int64_t>(nx) * ny * nz > (1 << 28))
+        return fail(c, MSRSB_E_ARG, "invalid grid size");
+    for (int d = 0; d < dim; ++d)
+        if (!(h[d] > 0.0)) return fail(c, MSRSB_E_ARG, "cell sizes must be positive");
+    const int n = nx * ny * nz;
+    const bool same = c->tpfa && c->has_matrix && c->tdim == dim && c->tdims[0] == nx &&
+                      c->tdims[1] == ny && c->tdims[2] == nz;
+    if (!same) {
+        // symbolic pattern: neighbours in ascending index order
+        std::vector<int> hrp(n + 1, 0), hci, dpos(n);
+        hci.reserve(static_cast<size_t>(n) * (2 * dim + 1));
+        const int stride[3] = {1, nx, nx * ny};
+        const int nd[3] = {nx, ny, nz};
+        for (int cidx = 0; cidx < n; ++cidx) {
+            const int xyz[3] = {cidx % nx, (cidx / nx) % ny, cidx / (nx * ny)};
+            for (int d = dim - 1; d >= 0; --d)
+                if (xyz[d] > 0) hci.push_back(cidx - stride[d]);
+            dpos[cidx] = static_cast<int>(hci.size());
+            hci.push_back(cidx);
+            for (int d = 0; d < dim; ++d)
+                if (xyz[d] + 1 < nd[d]) hci.push_back(cidx + stride[d]);
+            hrp[cidx + 1] = static_cast<int>(hci.size());
+        }
+        const int64_t nnz = static_cast<int64_t>(hci.size());
+        free_coarse(c);
+        msrsb_status st = install_pattern(c, n, nnz, std::move(hrp), std::move(hci), dpos, 1);
+        if (st) return st;
+        c->tpfa = true;
+        c->tdim = dim;
+        c->tdims[0] = nx;
+        c->tdims[1] = ny;
+        c->tdims[2] = nz;
+    }
+    for (int d = 0; d < 3; ++d) c->th[d] = d < dim ? h[d] : 1.0;
+    for (int t = 0; t < 6; ++t) c->tbc[t] = bc[t];
+    if (!dalloc_keep(c->tlogk, n)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+    double *drhs = nullptr;
+    if (rhs_out) {
+        if (!dalloc_keep(c->w[11], n)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+        drhs = c->w[11];
+    }
+    hipMemcpyAsync(c->tlogk, log_k, n * sizeof(double), kind_in(where), c->stream);
+    phase_begin(c, MSRSB_PHASE_ASSEMBLE);
+    launch_tpfa_values(c->stream, dim, c->tdims, c->th, c->tbc, c->tlogk, c->rp, c->a, drhs);
+    phase_end(c, MSRSB_PHASE_ASSEMBLE);
+    c->smoother_valid = c->smoother32_valid = false;
+    c->smoother_t_valid = c->smoother32_t_valid = false;
+    c->ilu_valid = false;
+    if (c->at_pattern) launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
+    if (rhs_out) hipMemcpyAsync(rhs_out, drhs, n * sizeof(double), kind_out(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "TPFA assembly failed on the device");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
+                              const int32_t *sup_rowptr, const int32_t *sup_col,
+                              const uint8_t *interior, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "set_matrix must come first");
+    if (nc < 1 || nc > kMaxCoarse)
+        return fail(c, MSRSB_E_ARG, "nc must be in [1, " + std::to_string(kMaxCoarse) + "]");
+    if (!part || !sup_rowptr || !sup_col || !interior || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid coarse arguments");
+    const int n = c->n;
+    std::vector<int> hpart, hprp, hpci;
+    std::vector<uint8_t> hint;
+    if (!to_host(c, hpart, part, n, where) || !to_host(c, hprp, sup_rowptr, n + 1, where))
+        return fail(c, MSRSB_E_HIP, "reading the partition failed");
+    if (hprp[0] != 0 || hprp[n] < n) return fail(c, MSRSB_E_ARG, "invalid support rowptr");
+    const int64_t pnnz = hprp[n];
+    if (!to_host(c, hpci, sup_col, pnnz, where) || !to_host(c, hint, interior, n, where))
+        return fail(c, MSRSB_E_HIP, "reading the supports failed");
+    int maxw = 0;
+    for (int i = 0; i < n; ++i) {
+        const int w = hprp[i + 1] - hprp[i];
+        if (w < 1 || w > kMaxPatternWidth)
+            return fail(c, MSRSB_E_ARG, "support row " + std::to_string(i) +
+                                            " must have 1.." + std::to_string(kMaxPatternWidth) +
+                                            " entries");
+        maxw = std::max(maxw, w);
+        bool found = false;
+        for (int e = hprp[i]; e < hprp[i + 1]; ++e) {
+            if (hpci[e] < 0 || hpci[e] >= nc)
+                return fail(c, MSRSB_E_ARG, "support column out of range in row " +
+                                                std::to_string(i));
+            if (e > hprp[i] && hpci[e - 1] >= hpci[e])
+                return fail(c, MSRSB_E_ARG, "support columns not ascending in row " +
+                                                std::to_string(i));
+            if (hpci[e] == hpart[i]) found = true;
+        }
+        if (!found)
+            return fail(c, MSRSB_E_ARG, "part[" + std::to_string(i) + "] not in its support row");
+    }
+    free_coarse(c);
+    c->nc = nc;
+    c->pnnz = pnnz;
+    c->pmaxw = maxw;
+    c->h_prp = hprp;
+    c->h_pci = hpci;
+    // R = P^T pattern (coarse rows, fine rows ascending) and the source map
+    std::vector<int> rrp(nc + 1, 0), rci(pnnz), rsrc(pnnz);
+    for (int64_t e = 0; e < pnnz; ++e) rrp[hpci[e] + 1]++;
+    for (int j = 0; j < nc; ++j) rrp[j + 1] += rrp[j];
+    {
+        std::vector<int> pos(rrp.begin(), rrp.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int e = hprp[i]; e < hprp[i + 1]; ++e) {
+                const int j = hpci[e];
+                rci[pos[j]] = i;
+                rsrc[pos[j]] = e;
+                pos[j]++;
+            }
+    }
+    const size_t nn = static_cast<size_t>(nc) * nc;
+    if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
+        !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, pnnz) ||
+        !dalloc(c->rsrc, pnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
+        !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
+        !dalloc(c->colsrc, nc))
+        return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+    hipMemcpyAsync(c->part, hpart.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->prp, hprp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->pci, hpci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->interior, hint.data(), n, hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->rrp, rrp.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->rci, rci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->rsrc, rsrc.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "copying the coarse data failed");
+    c->rmaxnb = c->bs == 1 ? 32 : kMaxCoarseNeighbours;
+    c->has_coarse = true;
+    c->has_basis = c->has_coarse_op = false;
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_basis_info *info)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
+    if (!o || !(o->omega > 0.0) || o->max_iter < 0 || o->check_every < 1)
+        return fail(c, MSRSB_E_ARG, "invalid basis options");
+    hipStream_t s = c->stream;
+    const bool fp32 = o->fp32_basis != 0;
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    // buffers of the requested precision
+    if (fp32) {
+        if (!dalloc_keep(c->jv32, c->jnnz) || !dalloc_keep(c->p32[0], c->pnnz) ||
+            !dalloc_keep(c->p32[1], c->pnnz) || !dalloc_keep(c->r32, c->pnnz))
+            return fail(c, MSRSB_E_NOMEM, "allocation of the FP32 basis failed");
+    } else {
+        if (!dalloc_keep(c->jv, c->jnnz) || !dalloc_keep(c->p64[0], c->pnnz) ||
+            !dalloc_keep(c->p64[1], c->pnnz) || !dalloc_keep(c->r64, c->pnnz))
+            return fail(c, MSRSB_E_NOMEM, "allocation of the FP64 basis failed");
+    }
+    phase_begin(c, MSRSB_PHASE_FILTER);
+    launch_filter_jacobi(s, c->n, c->bs, o->filter, o->omega, c->rp, c->ci, c->a, c->jrp,
+                         fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
+    phase_end(c, MSRSB_PHASE_FILTER);
+    phase_begin(c, MSRSB_PHASE_INIT);
+    const bool warm = o->warm_start && c->has_basis;
+    if (!warm) {
+        c->pcur = 0;
+        launch_init_basis(s, c->n, c->prp, c->pci, c->part, fp32 ? nullptr : c->p64[0],
+                          fp32 ? c->p32[0] : nullptr);
+    } else if (fp32 != c->p_is32) {
+        if (fp32)
+            launch_p_convert_down(s, c->pnnz, c->p64[c->pcur], c->p32[c->pcur]);
+        else {
+            if (!dalloc_keep(c->p64[c->pcur], c->pnnz))
+                return fail(c, MSRSB_E_NOMEM, "allocation failed");
+            launch_p_convert(s, c->pnnz, c->p32[c->pcur], c->p64[c->pcur]);
+        }
+    }
+    c->p_is32 = fp32;
+    phase_end(c, MSRSB_PHASE_INIT);
+    phase_begin(c, MSRSB_PHASE_SMOOTH);
+    int it = 0;
+    double e_last = -1.0;
+    for (it = 0; it < o->max_iter; ++it) {
+        const bool check = (it % o->check_every) == 0;
+        if (check) fill_u64_zero(s, c->eit_bits);
+        const int src = c->pcur, dst = 1 - c->pcur;
+        launch_smooth(s, c->n, c->pmaxw, fp32, c->jrp, c->jci, c->jv, c->jv32, c->prp, c->pci,
+                      c->p64[src], c->p64[dst], c->p32[src], c->p32[dst], c->interior,
+                      check ? c->eit_bits : nullptr);
+        c->pcur = dst;
+        if (check && o->tol >= 0.0) {
+            hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
+            if (hipStreamSynchronize(s) != hipSuccess)
+                return fail(c, MSRSB_E_HIP, "smoothing failed on the device");
+            e_last = c->h_pinned[0];
+            if (!std::isfinite(e_last)) {
+                ++it;
+                break;
+            }
+            if (e_last <= o->tol) {
+                ++it;
+                break;
+            }
+        }
+    }
+    phase_end(c, MSRSB_PHASE_SMOOTH);
+    // last computed e_it, and P's statistics
+    hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
+    launch_basis_stats(s, c->n, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur], c->partials,
+                       c->scal + S_TMP0);
+    hipMemcpyAsync(c->h_pinned + 1, c->scal + S_TMP0, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                   s);
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "smoothing failed on the device");
+    if (o->max_iter > 0) e_last = c->h_pinned[0];
+    c->has_basis = true;
+    c->has_coarse_op = false;
+    if (info) {
+        info->iters = it;
+        info->e_it = e_last;
+        info->max_rowsum_err = c->h_pinned[1];
+        info->p_min = c->h_pinned[2];
+        info->p_max = c->h_pinned[3];
+    }
+    if (!std::isfinite(e_last) || !std::isfinite(c->h_pinned[1]))
+        return fail(c, MSRSB_E_BASIS_DIVERGED, "basis smoothing diverged (e_it not finite)");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_set_prolongation(msrsb_ctx *c, const double *val, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
+    if (!val || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid values");
+    if (!dalloc_keep(c->p64[0], c->pnnz) || !dalloc_keep(c->p64[1], c->pnnz) ||
+        !dalloc_keep(c->r64, c->pnnz))
+        return fail(c, MSRSB_E_NOMEM, "allocation failed");
+    c->pcur = 0;
+    c->p_is32 = false;
+    hipMemcpyAsync(c->p64[0], val, c->pnnz * sizeof(double), kind_in(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");
+    c->has_basis = true;
+    c->has_coarse_op = false;
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_get_prolongation(msrsb_ctx *c, int32_t *rowptr, int32_t *col, double *val,
+                                    int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
+    if (!valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid where");
+    const hipMemcpyKind hk = where == MSRSB_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    if (rowptr) hipMemcpy(rowptr, c->h_prp.data(), (c->n + 1) * sizeof(int), hk);
+    if (col) hipMemcpy(col, c->h_pci.data(), c->pnnz * sizeof(int), hk);
+    if (val) {
+        if (!c->has_basis) return fail(c, MSRSB_E_STATE, "no basis yet");
+        const double *src = c->p64[c->pcur];
+        if (c->p_is32) {
+            if (!dalloc_keep(c->p64[1 - c->pcur], c->pnnz))
+                return fail(c, MSRSB_E_NOMEM, "allocation failed");
+            launch_p_convert(c->stream, c->pnnz, c->p32[c->pcur], c->p64[1 - c->pcur]);
+            src = c->p64[1 - c->pcur];
+        }
+        hipMemcpyAsync(val, src, c->pnnz * sizeof(double), kind_out(where), c->stream);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->has_basis) return fail(c, MSRSB_E_STATE, "setup_basis must come first");
+    if (o && o->restriction != 0)
+        return fail(c, MSRSB_E_ARG, "only the Galerkin restriction R = P^T is available");
+    hipStream_t s = c->stream;
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    const bool fp32 = c->p_is32;
+    if (fp32 ? !dalloc_keep(c->r32, c->pnnz) : !dalloc_keep(c->r64, c->pnnz))
+        return fail(c, MSRSB_E_NOMEM, "allocation failed");
+    const int nc = c->nc;
+    const int64_t nn = static_cast<int64_t>(nc) * nc;
+    phase_begin(c, MSRSB_PHASE_RAP);
+    launch_gather_r(s, c->pnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
+    for (;;) {
+        hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+        launch_fill(s, nn, c->ac, 0.0);
+        launch_rap(s, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci, c->a,
+                   c->prp, c->pci, c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag);
+        int hflag = 0;
+        hipMemcpyAsync(&hflag, c->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess)
+            return fail(c, MSRSB_E_HIP, "coarse operator failed on the device");
+        if (!hflag) break;
+        if (c->rmaxnb >= kMaxCoarseNeighbours)
+            return fail(c, MSRSB_E_ARG, "a coarse row has more than " +
+                                            std::to_string(kMaxCoarseNeighbours) +
+                                            " coarse neighbours");
+        c->rmaxnb = std::min(kMaxCoarseNeighbours, 2 * c->rmaxnb);
+    }
+    phase_end(c, MSRSB_PHASE_RAP);
+    phase_begin(c, MSRSB_PHASE_FACTOR);
+    double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
+    hipMemcpyAsync(work, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    int hflag = 0;
+    st = coarse_inverse(s, nc, work, c->acinv, c->gj_b, c->piv, c->colsrc, c->dev_flag, &hflag);
+    phase_end(c, MSRSB_PHASE_FACTOR);
+    if (st == MSRSB_E_COARSE_SINGULAR)
+        return fail(c, st, "zero pivot: the coarse operator is singular");
+    if (st) return fail(c, st, "coarse factorisation failed");
+    c->has_coarse_op = true;
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *c, double *dense, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (!c->has_coarse_op) return fail(c, MSRSB_E_STATE, "build_coarse must come first");
+    if (!dense || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid buffer");
+    hipMemcpyAsync(dense, c->ac, static_cast<size_t>(c->nc) * c->nc * sizeof(double),
+                   kind_out(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_apply_preconditioner(msrsb_ctx *c, const msrsb_solve_opts *o,
+                                        const double *v, double *z, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
+    if (!v || !z || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid vectors");
+    if (!solve_opts_ok(c, o)) return o && o->use_multiscale && !c->has_coarse_op ? MSRSB_E_STATE : MSRSB_E_ARG;
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    if ((st = ensure_smoother(c, o, false))) return st;
+    const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
+    hipMemcpyAsync(c->w[5], v, bytes, kind_in(where), c->stream);
+    apply_two_stage(c, o, c->w[5], c->w[6], false);
+    hipMemcpyAsync(z, c->w[6], bytes, kind_out(where), c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "apply failed");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solve_opts *o,
+                         msrsb_solve_info *info, int where)
+{
+    if (c) c->err.clear();
+    return do_solve(c, f, u, o, info, where, false);
+}
+
+msrsb_status msrsb_solve_transpose(msrsb_ctx *c, const double *g, double *lambda,
+                                   const msrsb_solve_opts *o, msrsb_solve_info *info, int where)
+{
+    if (c) c->err.clear();
+    return do_solve(c, g, lambda, o, info, where, true);
+}
+
+msrsb_status msrsb_tpfa_adjoint_grad(msrsb_ctx *c, const double *log_k, const double *p,
+                                     const double *lambda, double *grad, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->tpfa) return fail(c, MSRSB_E_STATE, "A was not assembled by msrsb_assemble_tpfa");
+    if (!log_k || !p || !lambda || !grad || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid vectors");
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
+    const double *dk = log_k, *dp = p, *dl = lambda;
+    double *dg = grad;
+    if (where == MSRSB_HOST) {
+        hipMemcpyAsync(c->w[7], log_k, bytes, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(c->w[8], p, bytes, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(c->w[9], lambda, bytes, hipMemcpyHostToDevice, c->stream);
+        dk = c->w[7];
+        dp = c->w[8];
+        dl = c->w[9];
+        dg = c->w[10];
+    }
+    phase_begin(c, MSRSB_PHASE_GRAD);
+    launch_tpfa_grad(c->stream, c->tdim, c->tdims, c->th, c->tbc, dk, dp, dl, dg);
+    phase_end(c, MSRSB_PHASE_GRAD);
+    if (where == MSRSB_HOST)
+        hipMemcpyAsync(grad, dg, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "gradient failed on the device");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_get_timings(msrsb_ctx *c, double *ms, int32_t n_phases)
+{
+    if (!c || !ms || n_phases < 0) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "sync failed");
+    for (int p = 0; p < n_phases; ++p) {
+        ms[p] = 0.0;
+        if (p < MSRSB_N_PHASES && c->ev_used[p]) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, c->ev_start[p], c->ev_stop[p]) == hipSuccess) ms[p] = t;
+        }
+    }
+    return MSRSB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,18 @@
+// Preconditioner and Krylov drivers shared by the C ABI.
+#pragma once
+
+#include "internal.h"
+
+namespace msrsb {
+
+msrsb_status ensure_workspace(msrsb_ctx *c);
+msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans);
+void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
+                     bool trans);
+msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                 msrsb_solve_info *info, bool trans);
+msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                   msrsb_solve_info *info, bool trans);
+void fill_u64_zero(hipStream_t s, unsigned long long *p);
+
+}  // namespace msrsb

@@ -1,0 +1,427 @@
+// Two-stage preconditioner (Alg. 3, Alg. 4) and the Krylov drivers (PCG with
+// the flexible Polak-Ribiere beta, right-preconditioned restarted GMRES).
+// All vector arithmetic runs in device kernels; the host only queues work and
+// reads the residual norm to decide when to stop.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "solve.h"
+
+namespace msrsb {
+namespace {
+
+inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
+
+__global__ void k_fill_u64(unsigned long long *p) { p[0] = 0ull; }
+
+// --- GMRES small dense algebra (single thread; m <= 64) ---
+// Apply the previous Givens rotations to the new Hessenberg column h (j+2
+// entries: h[0..j] from the Gram-Schmidt, h[j+1] = ||w||^2 in nrm2), form the
+// new rotation, update g and write |g[j+1]| to res.
+__global__ void k_gmres_givens(int j, int m, double *__restrict__ H, const double *__restrict__ h,
+                               const double *__restrict__ nrm2, double *__restrict__ cs,
+                               double *__restrict__ sn, double *__restrict__ g,
+                               double *__restrict__ res)
+{
+    if (threadIdx.x != 0) return;
+    double col[65];
+    for (int i = 0; i <= j; ++i) col[i] = h[i];
+    col[j + 1] = sqrt(nrm2[0]);
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = sqrt(a * a + b * b);
+    double c = 1.0, s = 0.0;
+    if (den > 0.0) {
+        c = a / den;
+        s = b / den;
+    }
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) H[static_cast<int64_t>(i) * m + j] = col[i];
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    res[0] = fabs(g[j + 1]);
+    res[1] = den;
+}
+
+// y = H(0:k,0:k)^{-1} g(0:k) (upper triangular back substitution)
+__global__ void k_gmres_solve(int k, int m, const double *__restrict__ H,
+                              const double *__restrict__ g, double *__restrict__ y)
+{
+    if (threadIdx.x != 0) return;
+    for (int r = k - 1; r >= 0; --r) {
+        double s = g[r];
+        for (int c = r + 1; c < k; ++c) s -= H[static_cast<int64_t>(r) * m + c] * y[c];
+        y[r] = s / H[static_cast<int64_t>(r) * m + r];
+    }
+}
+
+__global__ void k_gmres_init_g(int m, double *__restrict__ g, const double *__restrict__ nrm2)
+{
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = sqrt(nrm2[0]);
+}
+
+__global__ void k_vec_add(int k, double *__restrict__ a, const double *__restrict__ b)
+{
+    const int t = threadIdx.x;
+    if (t < k) a[t] += b[t];
+}
+
+struct Op {
+    const int *rp, *ci;
+    const double *a;
+    const float *a32;
+    const double *dj, *dl1;
+    const float *dj32, *dl132;
+};
+
+Op fine_op(msrsb_ctx *c, bool trans)
+{
+    Op o;
+    if (!trans) {
+        o.rp = c->rp;
+        o.ci = c->ci;
+        o.a = c->a;
+        o.a32 = c->a32;
+        o.dj = c->dinv_jac;
+        o.dl1 = c->dinv_l1;
+        o.dj32 = c->dinv_jac32;
+        o.dl132 = c->dinv_l1_32;
+    } else {
+        o.rp = c->at_rp;
+        o.ci = c->at_ci;
+        o.a = c->at;
+        o.a32 = c->at32;
+        o.dj = c->dinv_jac_t;
+        o.dl1 = c->dinv_l1_t;
+        o.dj32 = c->dinv_jac32_t;
+        o.dl132 = c->dinv_l1_32_t;
+    }
+    return o;
+}
+
+template <typename T>
+msrsb_status dev_alloc(T **p, size_t count)
+{
+    if (*p) return MSRSB_OK;
+    if (hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T)) !=
+        hipSuccess)
+        return MSRSB_E_NOMEM;
+    return MSRSB_OK;
+}
+
+// one smoothing sweep z += M^{-1} (v - A z); zero: z is known to be zero
+// (then it is not read).  The result may land in *spare, in which case the
+// two pointers are exchanged.
+void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, double **z,
+           double **spare, bool zero, double *tmp)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    if (kind == MSRSB_SMOOTH_JACOBI || kind == MSRSB_SMOOTH_L1JACOBI) {
+        const bool l1 = kind == MSRSB_SMOOTH_L1JACOBI;
+        launch_sweep(s, n, o.rp, o.ci, o.a, o.a32, l1 ? o.dl1 : o.dj, l1 ? o.dl132 : o.dj32, fp32,
+                     v, *z, *spare, zero);
+        std::swap(*z, *spare);
+    } else if (kind == MSRSB_SMOOTH_ILU0) {
+        if (zero) {
+            launch_copy(s, n, v, tmp);
+            launch_fill(s, n, *z, 0.0);
+        } else {
+            launch_residual(s, n, o.rp, o.ci, o.a, v, *z, tmp);
+        }
+        launch_ilu0_apply(c, tmp, *z, nullptr);
+    }
+}
+
+}  // namespace
+
+msrsb_status ensure_workspace(msrsb_ctx *c)
+{
+    const size_t n = static_cast<size_t>(c->n);
+    for (auto &p : c->w)
+        if (dev_alloc(&p, n)) return MSRSB_E_NOMEM;
+    const size_t np = std::max<size_t>({n / kBlock + 2, 2 * static_cast<size_t>(kReduceBlocks),
+                                        64 * static_cast<size_t>(std::max(c->nc, 1)) + 64,
+                                        static_cast<size_t>(64 * 66)});
+    if (dev_alloc(&c->partials, np) || dev_alloc(&c->scal, S_COUNT) ||
+        dev_alloc(&c->vc, std::max(c->nc, 1)) || dev_alloc(&c->wc, std::max(c->nc, 1)) ||
+        dev_alloc(&c->eit_bits, 1) || dev_alloc(&c->dev_flag, 4))
+        return MSRSB_E_NOMEM;
+    if (!c->h_pinned && hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(double),
+                                      hipHostMallocDefault) != hipSuccess)
+        return MSRSB_E_NOMEM;
+    return MSRSB_OK;
+}
+
+msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans)
+{
+    const bool need_ilu =
+        o->pre_smoother == MSRSB_SMOOTH_ILU0 || o->post_smoother == MSRSB_SMOOTH_ILU0;
+    if (need_ilu && trans) {
+        c->err = "ILU(0) is not available for the transposed solve";
+        return MSRSB_E_ARG;
+    }
+    const bool fp32 = o->fp32_smoother != 0;
+    const size_t n = static_cast<size_t>(c->n);
+    hipStream_t s = c->stream;
+    if (!trans) {
+        if (!c->smoother_valid || (fp32 && !c->smoother32_valid)) {
+            if (dev_alloc(&c->dinv_jac, n) || dev_alloc(&c->dinv_l1, n)) return MSRSB_E_NOMEM;
+            if (fp32 && (dev_alloc(&c->dinv_jac32, n) || dev_alloc(&c->dinv_l1_32, n) ||
+                         dev_alloc(&c->a32, static_cast<size_t>(c->nnz))))
+                return MSRSB_E_NOMEM;
+            hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+            launch_diag_inverses(s, c->n, c->rp, c->ci, c->a, c->dinv_jac, c->dinv_l1,
+                                 fp32 ? c->dinv_jac32 : nullptr, fp32 ? c->dinv_l1_32 : nullptr,
+                                 fp32 ? c->a32 : nullptr, c->nnz, c->dev_flag);
+            c->smoother_valid = true;
+            c->smoother32_valid = fp32;
+        }
+    } else {
+        if (!c->smoother_t_valid || (fp32 && !c->smoother32_t_valid)) {
+            if (dev_alloc(&c->dinv_jac_t, n) || dev_alloc(&c->dinv_l1_t, n)) return MSRSB_E_NOMEM;
+            if (fp32 && (dev_alloc(&c->dinv_jac32_t, n) || dev_alloc(&c->dinv_l1_32_t, n) ||
+                         dev_alloc(&c->at32, static_cast<size_t>(c->nnz))))
+                return MSRSB_E_NOMEM;
+            hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+            launch_diag_inverses(s, c->n, c->at_rp, c->at_ci, c->at, c->dinv_jac_t, c->dinv_l1_t,
+                                 fp32 ? c->dinv_jac32_t : nullptr,
+                                 fp32 ? c->dinv_l1_32_t : nullptr, fp32 ? c->at32 : nullptr,
+                                 c->nnz, c->dev_flag);
+            c->smoother_t_valid = true;
+            c->smoother32_t_valid = fp32;
+        }
+    }
+    if (need_ilu && !c->ilu_valid) {
+        const msrsb_status st = ilu0_setup(c);
+        if (st != MSRSB_OK) {
+            c->err = st == MSRSB_E_COARSE_SINGULAR ? "zero pivot in ILU(0)" : "ILU(0) setup failed";
+            return st == MSRSB_E_COARSE_SINGULAR ? MSRSB_E_BREAKDOWN : st;
+        }
+    }
+    return MSRSB_OK;
+}
+
+// z = B v (Alg. 4): z = 0; pre-smoothing; z += P M_c^{-1} R (v - A z);
+// post-smoothing.  With trans the preconditioner of A^T is applied: A^T,
+// smoothers of A^T, pre and post exchanged, and A_c^{-T}.
+void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
+                     bool trans)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const Op op = fine_op(c, trans);
+    const bool fp32 = o->fp32_smoother != 0;
+    int pre_k = o->pre_smoother, pre_n = o->pre_sweeps;
+    int post_k = o->post_smoother, post_n = o->post_sweeps;
+    if (trans) {
+        std::swap(pre_k, post_k);
+        std::swap(pre_n, post_n);
+    }
+    if (pre_k == MSRSB_SMOOTH_NONE) pre_n = 0;
+    if (post_k == MSRSB_SMOOTH_NONE) post_n = 0;
+    double *z = c->w[8], *spare = c->w[9], *tmp = c->w[10];
+    bool zero = true;
+    for (int t = 0; t < pre_n; ++t) {
+        sweep(c, op, pre_k, fp32, v, &z, &spare, zero, tmp);
+        zero = false;
+    }
+    if (o->use_multiscale) {
+        const double *res = v;
+        if (!zero) {
+            launch_residual(s, n, op.rp, op.ci, op.a, v, z, tmp);
+            res = tmp;
+        }
+        launch_restrict(s, c->nc, c->rrp, c->rci, c->p_is32, c->r64, c->r32, res, c->vc);
+        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
+        if (zero) launch_fill(s, n, z, 0.0);
+        launch_prolong_add(s, n, c->prp, c->pci, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
+                           c->wc, z);
+        zero = false;
+    }
+    for (int t = 0; t < post_n; ++t) {
+        sweep(c, op, post_k, fp32, v, &z, &spare, zero, tmp);
+        zero = false;
+    }
+    if (zero)
+        launch_fill(s, n, zout, 0.0);
+    else
+        launch_copy(s, n, z, zout);
+}
+
+static msrsb_status read_scalars(msrsb_ctx *c, int first, int count)
+{
+    hipMemcpyAsync(c->h_pinned, c->scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
+                   c->stream);
+    return hipStreamSynchronize(c->stream) == hipSuccess ? MSRSB_OK : MSRSB_E_HIP;
+}
+
+// Preconditioned CG with flexible beta.  f, x device pointers (x = x0 on entry).
+msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                 msrsb_solve_info *info, bool trans)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const Op op = fine_op(c, trans);
+    double *r = c->w[0], *z = c->w[1], *zold = c->w[2], *p = c->w[3], *q = c->w[4];
+    double *sc = c->scal;
+    hipMemsetAsync(sc, 0, S_COUNT * sizeof(double), s);
+    launch_dot(s, n, f, f, c->partials, sc + S_FF);
+    if (read_scalars(c, S_FF, 1)) return MSRSB_E_HIP;
+    double fn = std::sqrt(c->h_pinned[0]);
+    if (fn == 0.0) fn = 1.0;
+    const double thr2 = (o->rtol * fn) * (o->rtol * fn);
+    int it = 0;
+    msrsb_status rc = MSRSB_E_NOT_CONVERGED;
+    bool restart = true;
+    hipEvent_t ev;
+    hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    double *hist = info ? info->history : nullptr;
+    const int hcap = info ? info->history_cap : 0;
+    while (it <= o->max_iter) {
+        if (restart) {
+            launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+            launch_dot(s, n, r, r, c->partials, sc + S_RR);
+            if (read_scalars(c, S_RR, 1)) { rc = MSRSB_E_HIP; break; }
+            const double rr = c->h_pinned[0];
+            if (hist && it < hcap) hist[it] = std::sqrt(rr) / fn;
+            if (!std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }
+            if (rr <= thr2) { rc = MSRSB_OK; break; }
+            if (it == o->max_iter) break;
+            apply_two_stage(c, o, r, z, trans);
+            launch_copy(s, n, z, p);
+            launch_dot(s, n, r, z, c->partials, sc + S_RZ_OLD);
+            restart = false;
+        }
+        launch_spmv_dot(s, n, op.rp, op.ci, op.a, p, q, c->partials, sc + S_PQ);
+        launch_cg_alpha(s, sc);
+        launch_cg_update(s, n, x, r, p, q, sc, c->partials, sc + S_RR);
+        ++it;
+        hipMemcpyAsync(c->h_pinned, sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(c->h_pinned + 1, sc + S_BREAK, sizeof(double), hipMemcpyDeviceToHost, s);
+        hipEventRecord(ev, s);
+        // queue the next preconditioner application while the host waits
+        std::swap(z, zold);
+        apply_two_stage(c, o, r, z, trans);
+        launch_dot2(s, n, r, z, zold, c->partials, sc + S_RZ, sc + S_RZDIFF);
+        launch_cg_beta(s, sc);
+        launch_p_update(s, n, p, z, sc);
+        if (hipEventSynchronize(ev) != hipSuccess) { rc = MSRSB_E_HIP; break; }
+        const double rr = c->h_pinned[0], brk = c->h_pinned[1];
+        if (hist && it < hcap) hist[it] = std::sqrt(rr) / fn;
+        if (brk != 0.0 || !std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }
+        if (rr <= thr2) { restart = true; continue; }
+        if (it >= o->max_iter) break;
+    }
+    hipEventDestroy(ev);
+    // true residual at exit
+    launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+    launch_dot(s, n, r, r, c->partials, sc + S_TMP0);
+    if (read_scalars(c, S_TMP0, 1)) return MSRSB_E_HIP;
+    if (info) {
+        info->iters = it;
+        info->true_rel_res = std::sqrt(c->h_pinned[0]) / fn;
+    }
+    return rc;
+}
+
+// Right-preconditioned GMRES(m) with classical Gram-Schmidt applied twice.
+msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                   msrsb_solve_info *info, bool trans)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const int m = std::max(1, std::min(o->restart, 64));
+    const Op op = fine_op(c, trans);
+    if (c->gm_cap < m) {
+        if (c->gm_v) hipFree(c->gm_v);
+        if (c->gm_h) hipFree(c->gm_h);
+        c->gm_v = c->gm_h = nullptr;
+        if (dev_alloc(&c->gm_v, static_cast<size_t>(m + 1) * n) ||
+            dev_alloc(&c->gm_h, static_cast<size_t>(m + 1) * m + 8 * (m + 2)))
+            return MSRSB_E_NOMEM;
+        c->gm_cap = m;
+    }
+    double *V = c->gm_v;
+    double *H = c->gm_h;                        // (m+1) x m
+    double *cs = H + (m + 1) * m, *sn = cs + (m + 2), *g = sn + (m + 2), *y = g + (m + 2);
+    double *hc = y + (m + 2), *h2 = hc + (m + 2), *gsc = h2 + (m + 2);  // gsc: 2 scalars
+    double *w = c->w[0], *zt = c->w[1], *r = c->w[2];
+    double *sc = c->scal;
+    launch_dot(s, n, f, f, c->partials, sc + S_FF);
+    if (read_scalars(c, S_FF, 1)) return MSRSB_E_HIP;
+    double fn = std::sqrt(c->h_pinned[0]);
+    if (fn == 0.0) fn = 1.0;
+    int it = 0;
+    msrsb_status rc = MSRSB_E_NOT_CONVERGED;
+    double *hist = info ? info->history : nullptr;
+    const int hcap = info ? info->history_cap : 0;
+    for (;;) {
+        launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+        launch_dot(s, n, r, r, c->partials, sc + S_RR);
+        if (read_scalars(c, S_RR, 1)) return MSRSB_E_HIP;
+        const double beta = std::sqrt(c->h_pinned[0]);
+        if (hist && it < hcap) hist[it] = beta / fn;
+        if (!std::isfinite(beta)) { rc = MSRSB_E_BREAKDOWN; break; }
+        if (beta <= o->rtol * fn) { rc = MSRSB_OK; break; }
+        if (it >= o->max_iter) break;
+        launch_norm_scale(s, n, r, V, c->partials, sc + S_RR);
+        k_gmres_init_g<<<1, 64, 0, s>>>(m, g, sc + S_RR);
+        int j = 0;
+        bool done = false, brk = false;
+        for (j = 0; j < m && it < o->max_iter; ++j) {
+            const double *vj = V + static_cast<int64_t>(j) * n;
+            double *vn = V + static_cast<int64_t>(j + 1) * n;
+            apply_two_stage(c, o, vj, zt, trans);
+            launch_spmv(s, n, op.rp, op.ci, op.a, zt, w);
+            // CGS2: h = V^T w; w -= V h; h2 = V^T w; w -= V h2; h += h2
+            launch_multi_dot(s, n, j + 1, V, n, w, c->partials, hc);
+            launch_multi_axpy(s, n, j + 1, V, n, hc, w, -1.0);
+            launch_multi_dot(s, n, j + 1, V, n, w, c->partials, h2);
+            launch_multi_axpy(s, n, j + 1, V, n, h2, w, -1.0);
+            k_vec_add<<<1, 64, 0, s>>>(j + 1, hc, h2);
+            launch_norm_scale(s, n, w, vn, c->partials, sc + S_TMP1);
+            k_gmres_givens<<<1, 64, 0, s>>>(j, m, H, hc, sc + S_TMP1, cs, sn, g, gsc);
+            hipMemcpyAsync(c->h_pinned, gsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
+            ++it;
+            const double res = c->h_pinned[0], den = c->h_pinned[1];
+            if (hist && it < hcap) hist[it] = res / fn;
+            if (!std::isfinite(res) || !(den > 0.0)) { brk = true; break; }
+            if (res <= o->rtol * fn) { done = true; ++j; break; }
+        }
+        if (j > 0) {
+            k_gmres_solve<<<1, 64, 0, s>>>(j, m, H, g, y);
+            launch_fill(s, n, w, 0.0);
+            launch_multi_axpy(s, n, j, V, n, y, w, 1.0);
+            apply_two_stage(c, o, w, zt, trans);
+            launch_axpy(s, n, 1.0, zt, x);
+        }
+        if (brk) { rc = MSRSB_E_BREAKDOWN; break; }
+        (void)done;
+    }
+    launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+    launch_dot(s, n, r, r, c->partials, sc + S_TMP0);
+    if (read_scalars(c, S_TMP0, 1)) return MSRSB_E_HIP;
+    const double tr = std::sqrt(c->h_pinned[0]) / fn;
+    if (info) {
+        info->iters = it;
+        info->true_rel_res = tr;
+    }
+    if (rc == MSRSB_OK && !(tr <= o->rtol)) rc = MSRSB_E_NOT_CONVERGED;
+    return rc;
+}
+
+void fill_u64_zero(hipStream_t s, unsigned long long *p) { k_fill_u64<<<1, 1, 0, s>>>(p); }
+
+}  // namespace msrsb

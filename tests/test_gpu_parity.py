@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same
+seeded inputs, through the C ABI.
+
+Tolerances: P and A_c to 1e-12 (relative to their largest entry) in FP64;
+solutions to 1e-8 relative with both sides solved to 1e-12; the adjoint
+gradient to 1e-8 of its largest entry.  The FP64 kernels use fused
+multiply-adds and a different summation order, so agreement is to rounding,
+not bitwise; the smoothing iteration is non-expansive (J is non-negative
+and row-stochastic once filtered), so the difference after K iterations
+stays near K * (stencil size) * 2^-53.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from _cases import tpfa_inputs, oracle_setup, gpu_setup_tpfa, gpu_setup_matrix, rel_max
+
+pytestmark = pytest.mark.gpu
+
+# (workload recipe, dims, block): several tiles plus a ragged tail
+CASES = [("c1", None, None),                 # 32^2, 16 coarse blocks (full size)
+         ("c1", (37, 29), 8),                # partial coarse blocks on both axes
+         ("c5", (24, 20, 18), 8),            # 3D, ragged last blocks
+         ("c4", (32, 32, 32), 8)]            # layered channels
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    return torch
+
+
+def _id(c):
+    return f"{c[0]}-{'x'.join(map(str, c[1])) if c[1] else 'full'}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_tpfa_assembly_matches_oracle(torch_cuda, case):
+    cfg = tpfa_inputs(*case)
+    s, rhs, _ = gpu_setup_tpfa(cfg, kmax=1)
+    rp, ci, a = s.get_matrix()
+    assert np.array_equal(rp, cfg["rp"]) and np.array_equal(ci, cfg["ci"])
+    np.testing.assert_allclose(a, cfg["a"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(rhs.cpu().numpy(), cfg["f"], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_basis_and_coarse_operator_match_oracle(torch_cuda, case):
+    cfg = tpfa_inputs(*case)
+    orc = oracle_setup(cfg)
+    s, _, info = gpu_setup_tpfa(cfg)
+    _, _, pv = s.get_prolongation()
+    assert info["iters"] == 100 and orc.basis_iters == 100
+    assert rel_max(pv, orc.pv) <= 1e-12
+    assert info["max_rowsum_err"] <= 8 * np.finfo(float).eps
+    assert 0.0 <= info["p_min"] and info["p_max"] <= 1.0
+    assert abs(info["e_it"] - orc.eit) <= 1e-12 * max(orc.eit, 1e-300) + 1e-15
+    ac = s.get_coarse_matrix()
+    assert rel_max(ac, orc.ac) <= 1e-12
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+@pytest.mark.parametrize("smoother", [((0, 0), (1, 1)), ((2, 2), (2, 2)), ((1, 1), (0, 0))],
+                         ids=["jac-post", "l1x2", "jac-pre"])
+def test_preconditioner_apply_matches_oracle(torch_cuda, case, smoother):
+    cfg = tpfa_inputs(*case)
+    orc = oracle_setup(cfg)
+    s, _, _ = gpu_setup_tpfa(cfg)
+    v = np.random.default_rng(7).standard_normal(cfg["rp"].size - 1)
+    pre, post = smoother
+    z_ref = orc.apply(v, pre=pre, post=post)
+    z = np.zeros_like(v)
+    s.apply(v, z, pre=pre, post=post)
+    assert rel_max(z, z_ref) <= 1e-11
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_solution_matches_oracle(torch_cuda, case):
+    cfg = tpfa_inputs(*case)
+    orc = oracle_setup(cfg)
+    s, rhs, _ = gpu_setup_tpfa(cfg)
+    pre, post = cfg["pre"], cfg["post"]
+    ref = orc.solve(cfg["f"], rtol=1e-12, pre=pre, post=post)
+    assert ref["status"] == 0
+    u = np.zeros(cfg["rp"].size - 1)
+    info = s.solve(cfg["f"], u, rtol=1e-12, pre=pre, post=post)
+    assert info["true_rel_res"] <= 1e-12
+    assert rel_max(u, ref["x"]) <= 1e-8
+    # at the benchmark tolerance the iteration counts agree closely
+    r8 = orc.solve(cfg["f"], rtol=1e-8, pre=pre, post=post)
+    u8 = np.zeros_like(u)
+    i8 = s.solve(cfg["f"], u8, rtol=1e-8, pre=pre, post=post)
+    assert abs(i8["iters"] - r8["iters"]) <= 1
+    assert i8["true_rel_res"] <= 1e-8
+
+
+def test_device_buffers_and_stream(torch_cuda):
+    torch = torch_cuda
+    cfg = tpfa_inputs("c1")
+    orc = oracle_setup(cfg)
+    s, rhs, _ = gpu_setup_tpfa(cfg)
+    u = torch.zeros_like(rhs)
+    info = s.solve(rhs, u, rtol=1e-12, pre=(0, 0), post=(1, 1))
+    ref = orc.solve(cfg["f"], rtol=1e-12, pre=(0, 0), post=(1, 1))
+    torch.cuda.synchronize()
+    assert rel_max(u.cpu().numpy(), ref["x"]) <= 1e-8
+    assert info["iters"] > 0
+
+
+def test_deterministic(torch_cuda):
+    cfg = tpfa_inputs("c4", (32, 32, 32), 8)
+    out = []
+    for _ in range(2):
+        s, rhs, _ = gpu_setup_tpfa(cfg)
+        _, _, pv = s.get_prolongation()
+        ac = s.get_coarse_matrix()
+        u = np.zeros(cfg["rp"].size - 1)
+        s.solve(cfg["f"], u, rtol=1e-8, pre=(2, 2), post=(2, 2))
+        out.append((pv, ac, u))
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+
+
+def test_fp32_basis_form(torch_cuda):
+    cfg = tpfa_inputs("c4", (32, 32, 32), 8)
+    orc = oracle_setup(cfg)
+    s, rhs, info = gpu_setup_tpfa(cfg, fp32_basis=True)
+    _, _, pv = s.get_prolongation()
+    err = np.max(np.abs(pv - orc.pv))
+    # FP32 values with FP64 row sums: P error is FP32 rounding accumulated
+    assert err <= 1e-5, err
+    assert info["max_rowsum_err"] <= 8 * 2.0 ** -24
+    u = np.zeros(cfg["rp"].size - 1)
+    r = s.solve(cfg["f"], u, rtol=1e-8, pre=(2, 2), post=(2, 2), fp32_smoother=True)
+    assert r["true_rel_res"] <= 1e-8
+    ref = orc.solve(cfg["f"], rtol=1e-12, pre=(2, 2), post=(2, 2))
+    assert rel_max(u, ref["x"]) <= 1e-6
+
+
+def test_transpose_solve_nonsymmetric(torch_cuda):
+    cfg = tpfa_inputs("c1", (24, 24), 6)
+    A = sp.csr_matrix((cfg["a"], cfg["ci"], cfg["rp"])).tolil()
+    rng = np.random.default_rng(0)
+    for i in range(575):
+        if (i + 1) % 24:
+            A[i, i + 1] += 0.06 * A[i, i] * rng.uniform()
+    A = A.tocsr()
+    A.sort_indices()
+    cfg.update(rp=A.indptr.astype(np.int32), ci=A.indices.astype(np.int32), a=A.data)
+    orc = oracle_setup(cfg)
+    s, _ = gpu_setup_matrix(cfg)
+    g = rng.standard_normal(576)
+    ref = orc.solve(g, krylov="gmres", rtol=1e-12, pre=(1, 1), post=(1, 1), transpose=True)
+    lam = np.zeros(576)
+    info = s.solve_transpose(g, lam, krylov="gmres", rtol=1e-12, pre=(1, 1), post=(1, 1))
+    assert info["true_rel_res"] <= 1e-12
+    assert rel_max(lam, ref["x"]) <= 1e-8
+    x = np.zeros(576)
+    s.solve(g, x, krylov="gmres", rtol=1e-12, post=(1, 1))
+    np.testing.assert_allclose(A @ x, g, atol=1e-10 * np.abs(g).max())
+
+
+def test_adjoint_gradient_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_06934_amd import MsrsbTPFASolve, TPFAProblem
+    cfg = tpfa_inputs("c5", (24, 20, 16), 8)
+    obs, d = cfg["obs"] % (cfg["rp"].size - 1), cfg["data"]
+    sup = cfg["supports"]
+    prob = TPFAProblem(dims=cfg["dims"], h=cfg["h"], bc=tuple(cfg["bc"]),
+                       coarse=dict(nc=sup["nc"], part=sup["part"], prp=sup["prp"],
+                                   pci=sup["pci"], interior=sup["interior"]),
+                       rtol=1e-12, fp32_basis=True)
+    lk = torch.tensor(cfg["logk"], device="cuda", requires_grad=True)
+    p = MsrsbTPFASolve.apply(lk, prob)
+    ob = torch.as_tensor(obs, device="cuda")
+    J = ((p[ob] - torch.as_tensor(d, device="cuda")) ** 2).sum()
+    J.backward()
+    g = lk.grad.cpu().numpy()
+    # oracle: forward and adjoint solves at 1e-12, then the gradient formula
+    orc = oracle_setup(cfg)
+    pr = orc.solve(cfg["f"], rtol=1e-12, pre=(2, 2), post=(2, 2))["x"]
+    gp = np.zeros_like(pr)
+    np.add.at(gp, obs, 2 * (pr[obs] - d))
+    lam = orc.solve(gp, rtol=1e-12, pre=(2, 2), post=(2, 2), transpose=True)["x"]
+    g_ref = oracle.tpfa_grad(cfg["dims"], cfg["h"], cfg["logk"], cfg["bc"], pr, lam)
+    assert np.max(np.abs(g - g_ref)) <= 1e-8 * np.max(np.abs(g_ref))
