@@ -136,8 +136,13 @@ def test_fp32_basis_form(torch_cuda):
     u = np.zeros(cfg["rp"].size - 1)
     r = s.solve(cfg["f"], u, rtol=1e-8, pre=(2, 2), post=(2, 2), fp32_smoother=True)
     assert r["true_rel_res"] <= 1e-8
+    # the FP64 outer iteration restores full accuracy: solved to 1e-12 the
+    # FP32-basis form reaches the same solution as the FP64 oracle
+    u = np.zeros(cfg["rp"].size - 1)
+    r = s.solve(cfg["f"], u, rtol=1e-12, pre=(2, 2), post=(2, 2), fp32_smoother=True)
+    assert r["true_rel_res"] <= 1e-12
     ref = orc.solve(cfg["f"], rtol=1e-12, pre=(2, 2), post=(2, 2))
-    assert rel_max(u, ref["x"]) <= 1e-6
+    assert rel_max(u, ref["x"]) <= 1e-8
 
 
 def test_transpose_solve_nonsymmetric(torch_cuda):
