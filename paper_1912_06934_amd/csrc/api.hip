@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 
 #include "internal.h"
 #include "solve.h"
@@ -136,6 +137,19 @@ void free_matrix(msrsb_ctx *c)
     c->gm_cap = 0;
     dfree(c->partials);
     dfree(c->tlogk);
+    dfree(c->a_slot);
+    dfree(c->a_dia);
+    dfree(c->a_dia32);
+    dfree(c->at_slot);
+    dfree(c->at_dia);
+    dfree(c->at_dia32);
+    dfree(c->jcol_ell);
+    c->a_off = DiaOffsets();
+    c->at_off = DiaOffsets();
+    c->j_off = DiaOffsets();
+    c->j_dia = false;
+    c->jw = 0;
+    c->a_symmetric = false;
     c->at_pattern = false;
     c->smoother_valid = c->smoother32_valid = false;
     c->smoother_t_valid = c->smoother32_t_valid = false;
@@ -161,11 +175,21 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->ac);
     dfree(c->acinv);
     dfree(c->gj_b);
+    dfree(c->spd_buf);
     dfree(c->piv);
     dfree(c->colsrc);
     dfree(c->vc);
     dfree(c->wc);
     dfree(c->partials);
+    dfree(c->pcol_ell);
+    dfree(c->p_csr_tmp);
+    dfree(c->band);
+    if (c->jmap_idx) hipFree(c->jmap_idx);
+    c->jmap_idx = nullptr;
+    dfree(c->jmap_tab);
+    c->jmap_kind = 0;
+    c->jmap_ntab = 0;
+    c->pw = 0;
     c->has_coarse = c->has_basis = c->has_coarse_op = false;
 }
 
@@ -204,6 +228,47 @@ bool check_csr(const std::vector<int> &rp, const std::vector<int> &ci, int n,
     return true;
 }
 
+// The distinct column offsets j - i of a CSR pattern, ascending, if there are
+// at most kMaxDiag of them (the operator is stored as diagonals then).
+bool dia_offsets(const std::vector<int> &rp, const std::vector<int> &ci, int n,
+                 std::vector<int> &offs)
+{
+    offs.clear();
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int d = ci[e] - i;
+            if (std::find(offs.begin(), offs.end(), d) == offs.end()) {
+                offs.push_back(d);
+                if (static_cast<int>(offs.size()) > kMaxDiag) return false;
+            }
+        }
+    std::sort(offs.begin(), offs.end());
+    return !offs.empty();
+}
+
+// After A's values change: its DIA copy, the symmetry flag, A^T's values and
+// the smoother data (rebuilt lazily).
+msrsb_status refresh_values(msrsb_ctx *c)
+{
+    hipStream_t s = c->stream;
+    if (c->a_off.n > 0) launch_csr_to_dia(s, c->n, c->a_off.n, c->rp, c->a_slot, c->a, c->a_dia, nullptr);
+    hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+    launch_check_symmetric(s, c->n, c->rp, c->ci, c->a, c->dev_flag);
+    int flag = 1;
+    hipMemcpyAsync(&flag, c->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (c->at_pattern) {
+        launch_gather_values(s, c->nnz, c->at_src, c->a, c->at);
+        if (c->at_off.n > 0)
+            launch_csr_to_dia(s, c->n, c->at_off.n, c->at_rp, c->at_slot, c->at, c->at_dia, nullptr);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(c, MSRSB_E_HIP, "value update failed");
+    c->a_symmetric = flag == 0;
+    c->smoother_valid = c->smoother32_valid = false;
+    c->smoother_t_valid = c->smoother32_t_valid = false;
+    c->ilu_valid = false;
+    return MSRSB_OK;
+}
+
 msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> &&hrp,
                              std::vector<int> &&hci, const std::vector<int> &dpos, int bs)
 {
@@ -219,14 +284,32 @@ msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> 
     hipMemcpyAsync(c->rp, c->h_rp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->ci, c->h_ci.data(), nnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->diag_pos, dpos.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    // DIA form of A when its rows use at most kMaxDiag distinct offsets
+    {
+        std::vector<int> offs;
+        if (dia_offsets(c->h_rp, c->h_ci, n, offs)) {
+            c->a_off.n = static_cast<int>(offs.size());
+            for (size_t t = 0; t < offs.size(); ++t) c->a_off.off[t] = offs[t];
+            std::vector<int8_t> slot(nnz);
+            for (int i = 0; i < n; ++i)
+                for (int e = c->h_rp[i]; e < c->h_rp[i + 1]; ++e)
+                    slot[e] = static_cast<int8_t>(
+                        std::lower_bound(offs.begin(), offs.end(), c->h_ci[e] - i) - offs.begin());
+            if (!dalloc(c->a_slot, nnz) || !dalloc(c->a_dia, static_cast<size_t>(n) * offs.size()))
+                return fail(c, MSRSB_E_NOMEM, "device allocation of A (DIA) failed");
+            hipMemcpy(c->a_slot, slot.data(), nnz, hipMemcpyHostToDevice);
+        }
+    }
     // J's pattern: A's own for scalar problems, same-component entries otherwise
+    std::vector<int> jrp, jci;
+    const std::vector<int> *pjrp = &c->h_rp, *pjci = &c->h_ci;
     if (bs == 1) {
         c->jrp = c->rp;
         c->jci = c->ci;
         c->jnnz = nnz;
         c->j_own_pattern = false;
     } else {
-        std::vector<int> jrp(n + 1, 0), jci;
+        jrp.assign(n + 1, 0);
         jci.reserve(nnz / bs + n);
         for (int i = 0; i < n; ++i) {
             for (int e = c->h_rp[i]; e < c->h_rp[i + 1]; ++e)
@@ -237,10 +320,33 @@ msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> 
         if (!dalloc(c->jrp, n + 1) || !dalloc(c->jci, c->jnnz))
             return fail(c, MSRSB_E_NOMEM, "device allocation of J failed");
         c->j_own_pattern = true;
-        hipMemcpyAsync(c->jrp, jrp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice,
-                       c->stream);
-        hipMemcpyAsync(c->jci, jci.data(), c->jnnz * sizeof(int), hipMemcpyHostToDevice,
-                       c->stream);
+        hipMemcpy(c->jrp, jrp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice);
+        hipMemcpy(c->jci, jci.data(), c->jnnz * sizeof(int), hipMemcpyHostToDevice);
+        pjrp = &jrp;
+        pjci = &jci;
+    }
+    // J's values are stored [jw][n]: DIA order when its offsets are few, else
+    // ELL with explicit columns
+    {
+        std::vector<int> offs;
+        if (dia_offsets(*pjrp, *pjci, n, offs)) {
+            c->j_dia = true;
+            c->jw = static_cast<int>(offs.size());
+            c->j_off.n = c->jw;
+            for (int t = 0; t < c->jw; ++t) c->j_off.off[t] = offs[t];
+        } else {
+            int w = 0;
+            for (int i = 0; i < n; ++i) w = std::max(w, (*pjrp)[i + 1] - (*pjrp)[i]);
+            c->j_dia = false;
+            c->jw = w;
+            std::vector<int> jcol(static_cast<size_t>(w) * n, -1);
+            for (int i = 0; i < n; ++i)
+                for (int e = (*pjrp)[i]; e < (*pjrp)[i + 1]; ++e)
+                    jcol[static_cast<size_t>(e - (*pjrp)[i]) * n + i] = (*pjci)[e];
+            if (!dalloc(c->jcol_ell, jcol.size()))
+                return fail(c, MSRSB_E_NOMEM, "device allocation of J failed");
+            hipMemcpy(c->jcol_ell, jcol.data(), jcol.size() * sizeof(int), hipMemcpyHostToDevice);
+        }
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "copying the pattern failed");
@@ -251,10 +357,7 @@ msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> 
 // explicit transpose pattern of A with a source map for the values
 msrsb_status ensure_transpose(msrsb_ctx *c)
 {
-    if (c->at_pattern) {
-        launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
-        return MSRSB_OK;
-    }
+    if (c->at_pattern) return MSRSB_OK;  // values are kept current by refresh_values
     const int n = c->n;
     std::vector<int> trp(n + 1, 0), tci(c->nnz), src(c->nnz);
     for (int64_t e = 0; e < c->nnz; ++e) trp[c->h_ci[e] + 1]++;
@@ -275,28 +378,43 @@ msrsb_status ensure_transpose(msrsb_ctx *c)
     hipMemcpyAsync(c->at_src, src.data(), c->nnz * sizeof(int), hipMemcpyHostToDevice,
                    c->stream);
     launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
+    std::vector<int> offs;
+    if (dia_offsets(trp, tci, n, offs)) {
+        c->at_off.n = static_cast<int>(offs.size());
+        for (size_t t = 0; t < offs.size(); ++t) c->at_off.off[t] = offs[t];
+        std::vector<int8_t> slot(c->nnz);
+        for (int i = 0; i < n; ++i)
+            for (int e = trp[i]; e < trp[i + 1]; ++e)
+                slot[e] = static_cast<int8_t>(
+                    std::lower_bound(offs.begin(), offs.end(), tci[e] - i) - offs.begin());
+        if (!dalloc(c->at_slot, c->nnz) || !dalloc(c->at_dia, static_cast<size_t>(n) * offs.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of A^T (DIA) failed");
+        hipMemcpyAsync(c->at_slot, slot.data(), c->nnz, hipMemcpyHostToDevice, c->stream);
+        launch_csr_to_dia(c->stream, n, c->at_off.n, c->at_rp, c->at_slot, c->at, c->at_dia,
+                          nullptr);
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "building A^T failed");
     c->at_pattern = true;
     return MSRSB_OK;
 }
 
-bool solve_opts_ok(msrsb_ctx *c, const msrsb_solve_opts *o)
+msrsb_status solve_opts_check(msrsb_ctx *c, const msrsb_solve_opts *o)
 {
-    if (!o) return fail(c, MSRSB_E_ARG, "solve options are NULL"), false;
+    if (!o) return fail(c, MSRSB_E_ARG, "solve options are NULL");
     auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_ILU0; };
     if (!sm_ok(o->pre_smoother) || !sm_ok(o->post_smoother) || o->pre_sweeps < 0 ||
         o->post_sweeps < 0 || o->pre_sweeps > 64 || o->post_sweeps > 64)
-        return fail(c, MSRSB_E_ARG, "invalid smoother options"), false;
+        return fail(c, MSRSB_E_ARG, "invalid smoother options");
     if (o->krylov != MSRSB_KRYLOV_PCG && o->krylov != MSRSB_KRYLOV_GMRES)
-        return fail(c, MSRSB_E_ARG, "invalid Krylov method"), false;
+        return fail(c, MSRSB_E_ARG, "invalid Krylov method");
     if (!(o->rtol > 0.0) || o->max_iter < 0)
-        return fail(c, MSRSB_E_ARG, "rtol must be > 0 and max_iter >= 0"), false;
+        return fail(c, MSRSB_E_ARG, "rtol must be > 0 and max_iter >= 0");
     if (o->krylov == MSRSB_KRYLOV_GMRES && (o->restart < 1 || o->restart > 64))
-        return fail(c, MSRSB_E_ARG, "GMRES restart must be in [1, 64]"), false;
+        return fail(c, MSRSB_E_ARG, "GMRES restart must be in [1, 64]");
     if (o->use_multiscale && !c->has_coarse_op)
-        return fail(c, MSRSB_E_STATE, "build_coarse must run before a multiscale apply"), false;
-    return true;
+        return fail(c, MSRSB_E_STATE, "build_coarse must run before a multiscale apply");
+    return MSRSB_OK;
 }
 
 msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solve_opts *o,
@@ -306,21 +424,28 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
     DeviceGuard g(c->device);
     if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
     if (!f || !u || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid vector arguments");
-    if (!solve_opts_ok(c, o)) return o ? (o->use_multiscale && !c->has_coarse_op ? MSRSB_E_STATE : MSRSB_E_ARG) : MSRSB_E_ARG;
-    msrsb_status st = ensure_workspace(c);
+    msrsb_status st = solve_opts_check(c, o);
+    if (st) return st;
+    st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
     if (trans && (st = ensure_transpose(c))) return st;
     if ((st = ensure_smoother(c, o, trans))) return fail(c, st, c->err.empty() ? "smoother set-up failed" : c->err);
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
-    double *df = c->w[5], *dx = c->w[6];
-    hipMemcpyAsync(df, f, bytes, kind_in(where), c->stream);
-    hipMemcpyAsync(dx, u, bytes, kind_in(where), c->stream);
+    // device buffers are used in place; host buffers are staged
+    const double *df = f;
+    double *dx = u;
+    if (where == MSRSB_HOST) {
+        hipMemcpyAsync(c->w[5], f, bytes, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(c->w[6], u, bytes, hipMemcpyHostToDevice, c->stream);
+        df = c->w[5];
+        dx = c->w[6];
+    }
     const int ph = trans ? MSRSB_PHASE_SOLVE_T : MSRSB_PHASE_SOLVE;
     phase_begin(c, ph);
     st = o->krylov == MSRSB_KRYLOV_PCG ? pcg(c, df, dx, o, info, trans)
                                        : gmres(c, df, dx, o, info, trans);
     phase_end(c, ph);
-    hipMemcpyAsync(u, dx, bytes, kind_out(where), c->stream);
+    if (where == MSRSB_HOST) hipMemcpyAsync(u, dx, bytes, hipMemcpyDeviceToHost, c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "solve failed on the device");
     if (st == MSRSB_E_BREAKDOWN) return fail(c, st, "Krylov breakdown (non-finite value or p^T A p <= 0)");
@@ -350,7 +475,7 @@ msrsb_status msrsb_create(msrsb_ctx **out, int device, void *hip_stream)
         return MSRSB_E_NOMEM;
     }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess) {
         delete c;
         return MSRSB_E_NOMEM;
     }
@@ -411,9 +536,7 @@ msrsb_status msrsb_set_matrix(msrsb_ctx *c, int32_t n, int64_t nnz, const int32_
     msrsb_status st = install_pattern(c, n, nnz, std::move(hrp), std::move(hci), dpos, block_size);
     if (st) return st;
     hipMemcpyAsync(c->a, val, nnz * sizeof(double), kind_in(where), c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, MSRSB_E_HIP, "copying the values failed");
-    return MSRSB_OK;
+    return refresh_values(c);
 }
 
 msrsb_status msrsb_update_values(msrsb_ctx *c, const double *val, int where)
@@ -423,13 +546,7 @@ msrsb_status msrsb_update_values(msrsb_ctx *c, const double *val, int where)
     if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
     if (!val || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid values");
     hipMemcpyAsync(c->a, val, c->nnz * sizeof(double), kind_in(where), c->stream);
-    c->smoother_valid = c->smoother32_valid = false;
-    c->smoother_t_valid = c->smoother32_t_valid = false;
-    c->ilu_valid = false;
-    if (c->at_pattern) launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
-    if (hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, MSRSB_E_HIP, "copying the values failed");
-    return MSRSB_OK;
+    return refresh_values(c);
 }
 
 msrsb_status msrsb_get_matrix(msrsb_ctx *c, int32_t *rowptr, int32_t *col, double *val, int where)
@@ -502,14 +619,8 @@ msrsb_status msrsb_assemble_tpfa(msrsb_ctx *c, int32_t dim, const int32_t dims[3
     phase_begin(c, MSRSB_PHASE_ASSEMBLE);
     launch_tpfa_values(c->stream, dim, c->tdims, c->th, c->tbc, c->tlogk, c->rp, c->a, drhs);
     phase_end(c, MSRSB_PHASE_ASSEMBLE);
-    c->smoother_valid = c->smoother32_valid = false;
-    c->smoother_t_valid = c->smoother32_t_valid = false;
-    c->ilu_valid = false;
-    if (c->at_pattern) launch_gather_values(c->stream, c->nnz, c->at_src, c->a, c->at);
     if (rhs_out) hipMemcpyAsync(rhs_out, drhs, n * sizeof(double), kind_out(where), c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, MSRSB_E_HIP, "TPFA assembly failed on the device");
-    return MSRSB_OK;
+    return refresh_values(c);
 }
 
 msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
@@ -558,20 +669,29 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     c->nc = nc;
     c->pnnz = pnnz;
     c->pmaxw = maxw;
+    c->pw = maxw <= 4 ? 4 : (maxw <= kMapWidth ? kMapWidth : maxw);
+    const int pw = c->pw;
     c->h_prp = hprp;
     c->h_pci = hpci;
-    // R = P^T pattern (coarse rows, fine rows ascending) and the source map
+    if (static_cast<int64_t>(pw) * n >= INT32_MAX)
+        return fail(c, MSRSB_E_ARG, "support pattern too large for int32 ELL indexing");
+    // P's ELL columns, and R = P^T (coarse rows, fine rows ascending) with the
+    // ELL index of every entry
+    std::vector<int> pcol(static_cast<size_t>(pw) * n, -1);
+    for (int i = 0; i < n; ++i)
+        for (int e = hprp[i]; e < hprp[i + 1]; ++e)
+            pcol[static_cast<size_t>(i) * pw + (e - hprp[i])] = hpci[e];
     std::vector<int> rrp(nc + 1, 0), rci(pnnz), rsrc(pnnz);
     for (int64_t e = 0; e < pnnz; ++e) rrp[hpci[e] + 1]++;
-    for (int j = 0; j < nc; ++j) rrp[j + 1] += rrp[j];
+    for (int jj = 0; jj < nc; ++jj) rrp[jj + 1] += rrp[jj];
     {
         std::vector<int> pos(rrp.begin(), rrp.end() - 1);
         for (int i = 0; i < n; ++i)
             for (int e = hprp[i]; e < hprp[i + 1]; ++e) {
-                const int j = hpci[e];
-                rci[pos[j]] = i;
-                rsrc[pos[j]] = e;
-                pos[j]++;
+                const int jj = hpci[e];
+                rci[pos[jj]] = i;
+                rsrc[pos[jj]] = i * pw + (e - hprp[i]);
+                pos[jj]++;
             }
     }
     const size_t nn = static_cast<size_t>(nc) * nc;
@@ -579,7 +699,8 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, pnnz) ||
         !dalloc(c->rsrc, pnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
         !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
-        !dalloc(c->colsrc, nc))
+        !dalloc(c->colsrc, nc) || !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2) ||
+        !dalloc(c->spd_buf, 64 * 64 + 128 * static_cast<size_t>(nc)))
         return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
     hipMemcpyAsync(c->part, hpart.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->prp, hprp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
@@ -588,8 +709,66 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     hipMemcpyAsync(c->rrp, rrp.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->rci, rci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->rsrc, rsrc.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->pcol_ell, pcol.data(), pcol.size() * sizeof(int), hipMemcpyHostToDevice,
+                   c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "copying the coarse data failed");
+    // slot maps of the smoothing product, stored as indices into a table of
+    // the distinct maps (one byte per J entry when there are at most 256)
+    if (maxw <= kMapWidth) {
+        const size_t m = static_cast<size_t>(c->jw) * n;
+        uint32_t *dmaps = nullptr;
+        if (!dalloc(dmaps, m)) return fail(c, MSRSB_E_NOMEM, "allocation of the slot maps failed");
+        launch_build_maps(c->stream, n, pw, c->jw, c->j_off, c->j_dia ? nullptr : c->jcol_ell,
+                          c->jrp, c->jci, c->pcol_ell, dmaps);
+        std::vector<uint32_t> hm(m);
+        hipMemcpyAsync(hm.data(), dmaps, m * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            dfree(dmaps);
+            return fail(c, MSRSB_E_HIP, "building the slot maps failed");
+        }
+        std::unordered_map<uint32_t, uint32_t> dict;
+        std::vector<uint32_t> table;
+        std::vector<uint16_t> idx(m);
+        bool small = true;
+        for (size_t t = 0; t < m && small; ++t) {
+            auto it = dict.find(hm[t]);
+            if (it == dict.end()) {
+                if (table.size() >= 65536) {
+                    small = false;
+                    break;
+                }
+                it = dict.emplace(hm[t], static_cast<uint32_t>(table.size())).first;
+                table.push_back(hm[t]);
+            }
+            idx[t] = static_cast<uint16_t>(it->second);
+        }
+        if (!small) {
+            c->jmap_kind = 3;
+            c->jmap_idx = dmaps;
+        } else {
+            dfree(dmaps);
+            if (!dalloc(c->jmap_tab, table.size()))
+                return fail(c, MSRSB_E_NOMEM, "allocation of the slot maps failed");
+            hipMemcpy(c->jmap_tab, table.data(), table.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+            c->jmap_ntab = static_cast<int>(table.size());
+            if (table.size() <= 256) {
+                std::vector<uint8_t> i8(idx.begin(), idx.end());
+                uint8_t *d = nullptr;
+                if (!dalloc(d, m)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+                hipMemcpy(d, i8.data(), m, hipMemcpyHostToDevice);
+                c->jmap_idx = d;
+                c->jmap_kind = 1;
+            } else {
+                uint16_t *d = nullptr;
+                if (!dalloc(d, m)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+                hipMemcpy(d, idx.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice);
+                c->jmap_idx = d;
+                c->jmap_kind = 2;
+            }
+        }
+    }
     c->rmaxnb = c->bs == 1 ? 32 : kMaxCoarseNeighbours;
     c->has_coarse = true;
     c->has_basis = c->has_coarse_op = false;
@@ -608,58 +787,65 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     const bool fp32 = o->fp32_basis != 0;
     msrsb_status st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
-    // buffers of the requested precision
+    const size_t jm = static_cast<size_t>(c->jw) * c->n, pm = static_cast<size_t>(c->pw) * c->n;
     if (fp32) {
-        if (!dalloc_keep(c->jv32, c->jnnz) || !dalloc_keep(c->p32[0], c->pnnz) ||
-            !dalloc_keep(c->p32[1], c->pnnz) || !dalloc_keep(c->r32, c->pnnz))
+        if (!dalloc_keep(c->jv32, jm) || !dalloc_keep(c->p32[0], pm) ||
+            !dalloc_keep(c->p32[1], pm) || !dalloc_keep(c->r32, c->pnnz))
             return fail(c, MSRSB_E_NOMEM, "allocation of the FP32 basis failed");
     } else {
-        if (!dalloc_keep(c->jv, c->jnnz) || !dalloc_keep(c->p64[0], c->pnnz) ||
-            !dalloc_keep(c->p64[1], c->pnnz) || !dalloc_keep(c->r64, c->pnnz))
+        if (!dalloc_keep(c->jv, jm) || !dalloc_keep(c->p64[0], pm) ||
+            !dalloc_keep(c->p64[1], pm) || !dalloc_keep(c->r64, c->pnnz))
             return fail(c, MSRSB_E_NOMEM, "allocation of the FP64 basis failed");
     }
     phase_begin(c, MSRSB_PHASE_FILTER);
-    launch_filter_jacobi(s, c->n, c->bs, o->filter, o->omega, c->rp, c->ci, c->a, c->jrp,
-                         fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
+    launch_filter_jacobi(s, c->n, c->bs, o->filter, o->omega, c->rp, c->ci, c->a, c->jw, c->j_off,
+                         c->j_dia, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
     phase_end(c, MSRSB_PHASE_FILTER);
     phase_begin(c, MSRSB_PHASE_INIT);
     const bool warm = o->warm_start && c->has_basis;
     if (!warm) {
         c->pcur = 0;
-        launch_init_basis(s, c->n, c->prp, c->pci, c->part, fp32 ? nullptr : c->p64[0],
+        launch_init_basis(s, c->n, c->pw, c->pcol_ell, c->part, fp32 ? nullptr : c->p64[0],
                           fp32 ? c->p32[0] : nullptr);
     } else if (fp32 != c->p_is32) {
-        if (fp32)
-            launch_p_convert_down(s, c->pnnz, c->p64[c->pcur], c->p32[c->pcur]);
-        else {
-            if (!dalloc_keep(c->p64[c->pcur], c->pnnz))
-                return fail(c, MSRSB_E_NOMEM, "allocation failed");
-            launch_p_convert(s, c->pnnz, c->p32[c->pcur], c->p64[c->pcur]);
+        if (fp32) {
+            launch_p_convert_down(s, pm, c->p64[c->pcur], c->p32[c->pcur]);
+        } else {
+            if (!dalloc_keep(c->p64[c->pcur], pm)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+            launch_p_convert(s, pm, c->p32[c->pcur], c->p64[c->pcur]);
         }
     }
     c->p_is32 = fp32;
     phase_end(c, MSRSB_PHASE_INIT);
+    SmoothArgs sa;
+    sa.n = c->n;
+    sa.pw = c->pw;
+    sa.jw = c->jw;
+    sa.joff = c->j_off;
+    sa.jcol = c->j_dia ? nullptr : c->jcol_ell;
+    sa.pcol = c->pcol_ell;
+    sa.jmap_kind = c->jmap_kind;
+    sa.jmap_idx = c->jmap_idx;
+    sa.jmap_tab = c->jmap_tab;
+    sa.jmap_ntab = c->jmap_ntab;
+    sa.interior = c->interior;
     phase_begin(c, MSRSB_PHASE_SMOOTH);
     int it = 0;
     double e_last = -1.0;
     for (it = 0; it < o->max_iter; ++it) {
         const bool check = (it % o->check_every) == 0;
         if (check) fill_u64_zero(s, c->eit_bits);
+        sa.eit = check ? c->eit_bits : nullptr;
         const int src = c->pcur, dst = 1 - c->pcur;
-        launch_smooth(s, c->n, c->pmaxw, fp32, c->jrp, c->jci, c->jv, c->jv32, c->prp, c->pci,
-                      c->p64[src], c->p64[dst], c->p32[src], c->p32[dst], c->interior,
-                      check ? c->eit_bits : nullptr);
+        launch_smooth(s, sa, fp32, c->jv, c->jv32, c->p64[src], c->p64[dst], c->p32[src],
+                      c->p32[dst]);
         c->pcur = dst;
         if (check && o->tol >= 0.0) {
             hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
             if (hipStreamSynchronize(s) != hipSuccess)
                 return fail(c, MSRSB_E_HIP, "smoothing failed on the device");
             e_last = c->h_pinned[0];
-            if (!std::isfinite(e_last)) {
-                ++it;
-                break;
-            }
-            if (e_last <= o->tol) {
+            if (!std::isfinite(e_last) || e_last <= o->tol) {
                 ++it;
                 break;
             }
@@ -668,8 +854,8 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     phase_end(c, MSRSB_PHASE_SMOOTH);
     // last computed e_it, and P's statistics
     hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
-    launch_basis_stats(s, c->n, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur], c->partials,
-                       c->scal + S_TMP0);
+    launch_basis_stats(s, c->n, c->pw, c->pcol_ell, fp32, c->p64[c->pcur], c->p32[c->pcur],
+                       c->partials, c->scal + S_TMP0);
     hipMemcpyAsync(c->h_pinned + 1, c->scal + S_TMP0, 3 * sizeof(double), hipMemcpyDeviceToHost,
                    s);
     if (hipStreamSynchronize(s) != hipSuccess)
@@ -695,12 +881,14 @@ msrsb_status msrsb_set_prolongation(msrsb_ctx *c, const double *val, int where)
     DeviceGuard g(c->device);
     if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
     if (!val || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid values");
-    if (!dalloc_keep(c->p64[0], c->pnnz) || !dalloc_keep(c->p64[1], c->pnnz) ||
-        !dalloc_keep(c->r64, c->pnnz))
+    const size_t pm = static_cast<size_t>(c->pw) * c->n;
+    if (!dalloc_keep(c->p64[0], pm) || !dalloc_keep(c->p64[1], pm) ||
+        !dalloc_keep(c->r64, c->pnnz) || !dalloc_keep(c->p_csr_tmp, c->pnnz))
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     c->pcur = 0;
     c->p_is32 = false;
-    hipMemcpyAsync(c->p64[0], val, c->pnnz * sizeof(double), kind_in(where), c->stream);
+    hipMemcpyAsync(c->p_csr_tmp, val, c->pnnz * sizeof(double), kind_in(where), c->stream);
+    launch_csr_to_ell(c->stream, c->n, c->pw, c->prp, c->p_csr_tmp, c->p64[0]);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");
     c->has_basis = true;
     c->has_coarse_op = false;
@@ -719,14 +907,10 @@ msrsb_status msrsb_get_prolongation(msrsb_ctx *c, int32_t *rowptr, int32_t *col,
     if (col) hipMemcpy(col, c->h_pci.data(), c->pnnz * sizeof(int), hk);
     if (val) {
         if (!c->has_basis) return fail(c, MSRSB_E_STATE, "no basis yet");
-        const double *src = c->p64[c->pcur];
-        if (c->p_is32) {
-            if (!dalloc_keep(c->p64[1 - c->pcur], c->pnnz))
-                return fail(c, MSRSB_E_NOMEM, "allocation failed");
-            launch_p_convert(c->stream, c->pnnz, c->p32[c->pcur], c->p64[1 - c->pcur]);
-            src = c->p64[1 - c->pcur];
-        }
-        hipMemcpyAsync(val, src, c->pnnz * sizeof(double), kind_out(where), c->stream);
+        if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+        launch_ell_to_csr(c->stream, c->n, c->pw, c->prp, c->p_is32, c->p64[c->pcur],
+                          c->p32[c->pcur], c->p_csr_tmp);
+        hipMemcpyAsync(val, c->p_csr_tmp, c->pnnz * sizeof(double), kind_out(where), c->stream);
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");
     return MSRSB_OK;
@@ -748,15 +932,21 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     const int nc = c->nc;
     const int64_t nn = static_cast<int64_t>(nc) * nc;
+    if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
     phase_begin(c, MSRSB_PHASE_RAP);
     launch_gather_r(s, c->pnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
+    launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
+                      c->p_csr_tmp);
     for (;;) {
         hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+        hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
         launch_fill(s, nn, c->ac, 0.0);
-        launch_rap(s, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci, c->a,
-                   c->prp, c->pci, c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag);
+        launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
+                   c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->ac, c->dev_flag,
+                   c->band);
         int hflag = 0;
         hipMemcpyAsync(&hflag, c->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(c->h_band, c->band, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (hipStreamSynchronize(s) != hipSuccess)
             return fail(c, MSRSB_E_HIP, "coarse operator failed on the device");
         if (!hflag) break;
@@ -768,10 +958,21 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     }
     phase_end(c, MSRSB_PHASE_RAP);
     phase_begin(c, MSRSB_PHASE_FACTOR);
-    double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
-    hipMemcpyAsync(work, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
     int hflag = 0;
-    st = coarse_inverse(s, nc, work, c->acinv, c->gj_b, c->piv, c->colsrc, c->dev_flag, &hflag);
+    st = MSRSB_E_COARSE_SINGULAR;
+    if (c->a_symmetric) {
+        // symmetric positive definite A_c: band-limited Gauss-Jordan without
+        // pivoting; a non-positive pivot falls back to partial pivoting
+        hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+        st = coarse_inverse_spd(s, nc, c->acinv, c->h_band[0], c->h_band[1], c->spd_buf,
+                                c->spd_buf + 64 * 64, c->dev_flag, &hflag);
+    }
+    if (st == MSRSB_E_COARSE_SINGULAR) {
+        double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
+        hipMemcpyAsync(work, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+        st = coarse_inverse(s, nc, work, c->acinv, c->gj_b, c->piv, c->colsrc, c->dev_flag,
+                            &hflag);
+    }
     phase_end(c, MSRSB_PHASE_FACTOR);
     if (st == MSRSB_E_COARSE_SINGULAR)
         return fail(c, st, "zero pivot: the coarse operator is singular");
@@ -800,13 +1001,14 @@ msrsb_status msrsb_apply_preconditioner(msrsb_ctx *c, const msrsb_solve_opts *o,
     c->err.clear();
     if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "no matrix set");
     if (!v || !z || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid vectors");
-    if (!solve_opts_ok(c, o)) return o && o->use_multiscale && !c->has_coarse_op ? MSRSB_E_STATE : MSRSB_E_ARG;
-    msrsb_status st = ensure_workspace(c);
+    msrsb_status st = solve_opts_check(c, o);
+    if (st) return st;
+    st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
     if ((st = ensure_smoother(c, o, false))) return st;
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
     hipMemcpyAsync(c->w[5], v, bytes, kind_in(where), c->stream);
-    apply_two_stage(c, o, c->w[5], c->w[6], false);
+    apply_two_stage(c, o, c->w[5], c->w[6], false, nullptr);
     hipMemcpyAsync(z, c->w[6], bytes, kind_out(where), c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "apply failed");
     return MSRSB_OK;

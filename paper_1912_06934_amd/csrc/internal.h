@@ -16,6 +16,14 @@ constexpr int kMaxPatternWidth = 32;  // max support entries per fine row
 constexpr int kMaxCoarse = 4096;      // dense coarse inverse limit
 constexpr int kReduceBlocks = 1024;   // partial-sum slots of two-stage reductions
 constexpr int kMaxCoarseNeighbours = 96;  // LDS slots per coarse row in R A P
+constexpr int kMaxDiag = 32;          // most diagonals of a DIA operator
+constexpr int kMapWidth = 8;          // P rows up to this width use slot maps
+
+// Offsets of a diagonal (DIA) operator, passed to kernels by value.
+struct DiaOffsets {
+    int n = 0;
+    int off[kMaxDiag] = {};
+};
 
 // Device scalars of the Krylov drivers (one FP64 array on the device).
 enum Scalar {
@@ -59,6 +67,7 @@ struct msrsb_ctx {
     float *a32 = nullptr;
     std::vector<int> h_rp, h_ci;
     bool smoother_valid = false;
+    bool a_symmetric = false;           // A_ij == A_ji exactly (checked on the device)
 
     // transpose of A (for msrsb_solve_transpose), values gathered from A
     int *at_rp = nullptr, *at_ci = nullptr, *at_src = nullptr, *at_diag = nullptr;
@@ -66,12 +75,37 @@ struct msrsb_ctx {
     bool at_pattern = false;
     bool a_symmetric_pattern_checked = false;
 
-    // Jacobi operator J (filtered), CSR; aliases rp/ci when bs == 1
+    // DIA form of A (when its rows use few distinct column offsets)
+    msrsb::DiaOffsets a_off;
+    int8_t *a_slot = nullptr;           // DIA slot of every CSR entry
+    double *a_dia = nullptr;            // [a_off.n][n]
+    float *a_dia32 = nullptr;
+    bool a_dia32_valid = false;
+    msrsb::DiaOffsets at_off;           // DIA form of A^T (built with the transpose)
+    int8_t *at_slot = nullptr;
+    double *at_dia = nullptr;
+    float *at_dia32 = nullptr;
+    bool at_dia32_valid = false;
+
+    // Jacobi operator J (filtered): CSR pattern (aliases rp/ci when bs == 1)
+    // and ELL values [jw][n], in DIA order (k = i + j_off.off[o]) or with
+    // explicit ELL columns jcol_ell
     int *jrp = nullptr, *jci = nullptr;
     int64_t jnnz = 0;
     bool j_own_pattern = false;
-    double *jv = nullptr;
+    int jw = 0;
+    msrsb::DiaOffsets j_off;
+    bool j_dia = false;
+    int *jcol_ell = nullptr;            // [jw][n], -1 = empty (only when !j_dia)
+    double *jv = nullptr;               // [jw][n]
     float *jv32 = nullptr;
+    // slot maps of the smoothing product: for J entry (o, i) and output slot
+    // s of row i, the slot of row k's pattern that holds the same coarse
+    // column (4 bits each, 0xF = none), stored as indices into a table
+    int jmap_kind = 0;                  // 0 none, 1 uint8 index, 2 uint16 index, 3 full
+    void *jmap_idx = nullptr;
+    uint32_t *jmap_tab = nullptr;
+    int jmap_ntab = 0;
 
     // coarse partition and P (frozen pattern)
     int nc = 0;
@@ -80,19 +114,28 @@ struct msrsb_ctx {
     int64_t pnnz = 0;
     int pmaxw = 0;
     std::vector<int> h_prp, h_pci;
+    // P values live in row-major ELL layout (slot s of row i at i*pw + s, pw =
+    // 4 or 8 when the pattern allows, else its width), the slots of a row in
+    // ascending coarse column order, padding = 0 / col -1
+    int pw = 0;
+    int *pcol_ell = nullptr;
     double *p64[2] = {nullptr, nullptr};
     float *p32[2] = {nullptr, nullptr};
     int pcur = 0;          // which buffer holds the current P
     bool p_is32 = false;   // current P lives in p32[pcur]
+    double *p_csr_tmp = nullptr;  // CSR copy for msrsb_get_prolongation
 
     // R = P^T (CSR over coarse rows) with the source index into P
     int *rrp = nullptr, *rci = nullptr, *rsrc = nullptr;
     double *r64 = nullptr;
     float *r32 = nullptr;
     int rmaxnb = 0;  // max coarse neighbours of a coarse row (RAP)
+    int *band = nullptr;  // lower and upper bandwidth of A_c (device)
+    int h_band[2] = {0, 0};
 
     // coarse operator and its inverse
     double *ac = nullptr, *acinv = nullptr, *gj_b = nullptr;
+    double *spd_buf = nullptr;  // diagonal-block inverse and super-panel rows (SPD path)
     int *piv = nullptr, *colsrc = nullptr, *dev_flag = nullptr;
 
     // smoothers (diagonal inverses of A, and of A^T for the transposed solve)
@@ -132,27 +175,47 @@ struct msrsb_ctx {
 namespace msrsb {
 
 // ---- basis kernels (k_basis.hip) ----
-void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega,
-                          const int *rp, const int *ci, const double *a,
-                          const int *jrp, double *jv64, float *jv32);
-void launch_init_basis(hipStream_t s, int n, const int *prp, const int *pci, const int *part,
+struct SmoothArgs {
+    int n = 0, pw = 0, jw = 0;
+    DiaOffsets joff;
+    const int *jcol = nullptr;          // explicit J columns, or null for DIA order
+    const int *pcol = nullptr;          // P's ELL columns
+    int jmap_kind = 0;
+    const void *jmap_idx = nullptr;
+    const uint32_t *jmap_tab = nullptr;
+    int jmap_ntab = 0;
+    const uint8_t *interior = nullptr;
+    unsigned long long *eit = nullptr;  // null: e_it not computed this iteration
+};
+void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
+                          const int *ci, const double *a, int jw, const DiaOffsets &joff,
+                          bool use_dia, double *jv64, float *jv32);
+void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32);
-void launch_smooth(hipStream_t s, int n, int maxw, bool fp32, const int *jrp, const int *jci,
-                   const double *jv64, const float *jv32, const int *prp, const int *pci,
-                   const double *pin64, double *pout64, const float *pin32, float *pout32,
-                   const uint8_t *interior, unsigned long long *eit_bits);
-void launch_basis_stats(hipStream_t s, int n, const int *prp, bool fp32, const double *p64,
-                        const float *p32, double *partials, double *out3);
+void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,
+                   const float *jv32, const double *pin64, double *pout64, const float *pin32,
+                   float *pout32);
+void launch_basis_stats(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
+                        const double *p64, const float *p32, double *partials, double *out3);
 void launch_p_convert(hipStream_t s, int64_t m, const float *src, double *dst);
 void launch_p_convert_down(hipStream_t s, int64_t m, const double *src, float *dst);
+void launch_ell_to_csr(hipStream_t s, int n, int pw, const int *prp, bool fp32,
+                       const double *pe64, const float *pe32, double *pcsr);
+void launch_csr_to_ell(hipStream_t s, int n, int pw, const int *prp, const double *pcsr,
+                       double *pe64);
+void launch_build_maps(hipStream_t s, int n, int pw, int jw, const DiaOffsets &joff,
+                       const int *jcol, const int *jrp, const int *jci, const int *pcol,
+                       uint32_t *maps);
 
 // ---- coarse kernels (k_coarse.hip) ----
 void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const double *p64,
                      const float *p32, double *r64, float *r32);
-void launch_rap(hipStream_t s, int nc, int maxnb, const int *rrp, const int *rci, bool fp32,
-                const double *r64, const float *r32, const int *rp, const int *ci,
-                const double *a, const int *prp, const int *pci, const double *p64,
-                const float *p32, double *ac, int *flag);
+void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
+                bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
+                const double *a, const DiaOffsets &d, const double *ad, const int *prp,
+                const int *pci, const double *pcsr, double *ac, int *flag, int *band);
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu, double *G,
+                                double *B, int *flag, int *host_flag);
 void launch_fill(hipStream_t s, int64_t m, double *x, double v);
 msrsb_status coarse_inverse(hipStream_t s, int nc, double *ac_work, double *inv_out,
                             double *bbuf, int *piv, int *colsrc, int *flag, int *host_flag);
@@ -169,25 +232,42 @@ void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const doub
                   const double *v, const double *zin, double *zout, bool zero_start);
 void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool fp32,
                      const double *r64, const float *r32, const double *x, double *xc);
-void launch_prolong_add(hipStream_t s, int n, const int *prp, const int *pci, bool fp32,
-                        const double *p64, const float *p32, const double *wc, double *z);
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
                 double *out);
-void launch_dot2(hipStream_t s, int n, const double *r, const double *z, const double *zold,
-                 double *partials, double *out_rz, double *out_rzdiff);
-void launch_spmv_dot(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
-                     const double *p, double *q, double *partials, double *out_pq);
-void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                      const double *q, const double *scal, double *partials, double *out_rr);
-void launch_cg_alpha(hipStream_t s, double *scal);
-void launch_cg_beta(hipStream_t s, double *scal);
-void launch_p_update(hipStream_t s, int n, double *p, const double *z, const double *scal);
 void launch_copy(hipStream_t s, int n, const double *x, double *y);
 void launch_axpy(hipStream_t s, int n, double alpha_host, const double *x, double *y);
 void launch_diag_inverses(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
                           double *dj, double *dl1, float *dj32, float *dl1_32, float *a32,
                           int64_t nnz, int *flag);
 void launch_gather_values(hipStream_t s, int64_t m, const int *src, const double *a, double *out);
+
+// ---- DIA / fused PCG kernels (k_krylov.hip) ----
+void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,
+                     double *y);
+void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
+                         const double *f, const double *x, double *r);
+void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
+                      const float *a32, const double *dinv64, const float *dinv32,
+                      const double *v, const double *zin, double *zout, bool zero2);
+void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
+                           const double *a64, const float *a32, const double *dinv64,
+                           const float *dinv32, const double *r, const double *zin, double *zout,
+                           const double *zold, double *part, double *scal);
+void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, const double *zold,
+                      double *part, double *scal);
+void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *ad,
+                       const int *rp, const int *ci, const double *a, const double *z,
+                       const double *pold, double *pnew, double *q, double *part, double *scal);
+void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
+                       const double *q, double *part, double *scal, double *host_out);
+void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
+                        const double *p64, const float *p32, const double *wc, double *z,
+                        bool zero);
+void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,
+                       const double *a, double *ad64, float *ad32);
+
+void launch_check_symmetric(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
+                            int *flag);
 
 // ---- GMRES helpers (k_krylov.hip) ----
 void launch_multi_dot(hipStream_t s, int n, int k, const double *V, int64_t ldv,

@@ -1,10 +1,20 @@
 // Basis construction kernels: filter + Jacobi operator, initial basis and the
 // restricted smoothing iteration of enhanced MsRSB (Sec. 2.1, Sec. 3.1,
 // Alg. 1).
+//
+// Layouts.  P is stored row-major ELL: the pw slots of fine row i at
+// i*pw .. i*pw+pw-1 (pw = 4 or 8, rows padded with zero values and column -1),
+// so one thread reads a whole row with 16-byte loads and a wavefront reads
+// 64 consecutive rows as one contiguous block.  J is stored slot-major
+// ([jw][n], entry o of row i at o*n + i); its neighbour is either i + off[o]
+// (the operator's rows use a few fixed column offsets, DIA) or an explicit
+// column.
 #include "internal.h"
 
 namespace msrsb {
 namespace {
+
+inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
 
 __device__ inline double wave_max(double v)
 {
@@ -17,17 +27,25 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+__device__ inline void eit_reduce(double emax, unsigned long long *eit_bits)
+{
+    emax = wave_max(emax);
+    if ((threadIdx.x & 63) == 0 && emax != 0.0)
+        atomicMax(eit_bits, static_cast<unsigned long long>(__double_as_longlong(emax)));
+}
+
 // Filter (eq. negoffdiag) and zero-row-sum diagonal (eq. Dhat_zero_rowsum):
 // per row, Dhat_ii = -sum_{j != i, same component} G_ij with
 // G_ij = min(A_ij, 0) when filtering; then J = I - omega Dhat^{-1} Ghat, i.e.
 // J_ii = 1 - omega, J_ij = -omega G_ij / Dhat_ii.  A row with Dhat_ii == 0 is
-// frozen (J_i = e_i).  J's pattern is A's restricted to same-component
-// entries (all of A's entries for scalar problems), in the same order.
+// frozen (J_i = e_i).  J's entries are A's same-component entries; they are
+// written to their ELL slot (the DIA offset slot, or the running position),
+// and absent slots are zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
     int n, int bs, int filter, double omega, const int *__restrict__ rp,
-    const int *__restrict__ ci, const double *__restrict__ a, const int *__restrict__ jrp,
-    T *__restrict__ jv)
+    const int *__restrict__ ci, const double *__restrict__ a, int jw, DiaOffsets joff,
+    int use_dia, T *__restrict__ jv)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -41,7 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
         if (filter && g > 0.0) g = 0.0;
         d -= g;
     }
-    int out = jrp[i];
+    for (int o = 0; o < jw; ++o) jv[static_cast<int64_t>(o) * n + i] = T(0);
+    int pos = 0;
     for (int e = e0; e < e1; ++e) {
         const int j = ci[e];
         if (j % bs != ic) continue;
@@ -55,88 +74,187 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
             if (filter && g > 0.0) g = 0.0;
             v = -omega * g / d;
         }
-        jv[out++] = static_cast<T>(v);
+        int slot = pos++;
+        if (use_dia) {
+            const int dlt = j - i;
+            for (int o = 0; o < joff.n; ++o)
+                if (joff.off[o] == dlt) slot = o;
+        }
+        jv[static_cast<int64_t>(slot) * n + i] = static_cast<T>(v);
     }
 }
 
 // Initial basis (Sec. 2.1): characteristic function of the coarse block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init_basis(int n, const int *__restrict__ prp,
-                                                       const int *__restrict__ pci,
+__global__ __launch_bounds__(kBlock) void k_init_basis(int n, int pw, const int *__restrict__ pcol,
                                                        const int *__restrict__ part,
                                                        T *__restrict__ p)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int pi = part[i];
-    for (int e = prp[i]; e < prp[i + 1]; ++e) p[e] = (pci[e] == pi) ? T(1) : T(0);
+    for (int s = 0; s < pw; ++s) {
+        const int64_t e = static_cast<int64_t>(i) * pw + s;
+        p[e] = (pcol[e] == pi) ? T(1) : T(0);
+    }
 }
 
-// One restricted smoothing iteration (eq. smoother, Alg. 1).  One thread per
-// fine row i holds row i's pattern (at most W coarse columns) in registers and
-// accumulates T_ij = sum_k J_ik P_kj over the J-neighbours k in ascending
-// order; entries of P_k* outside row i's pattern are dropped, which keeps
-// every basis function inside its support.  The row is then rescaled by its
-// FP64 sum so P stays a partition of unity, and |T - P_old| on interior rows
-// feeds e_it (wavefront max, then one 64-bit atomic max per wavefront).
+// One restricted smoothing iteration (eq. smoother, Alg. 1), slot-map form.
+//
+// For output slot s of row i (coarse column c_is) the restricted product is
+//   T_is = sum over J entries o of row i (ascending column) of
+//          J_io * P[k_o, slot of c_is in row k_o]
+// where the slot comes from a precomputed 4-bit map (0xF: c_is is not in row
+// k_o's pattern, the product is absent).  Products P_kj with j outside row
+// i's pattern never enter, which is the support restriction.  The row is then
+// rescaled by its FP64 sum so that P stays a partition of unity, and
+// |T - P_old| on interior rows feeds e_it.
+//
+// Each neighbour row of P is read whole with 16-byte loads and the needed
+// slot is selected in registers.
+template <typename T, int PW>
+__device__ inline void load_row(const T *__restrict__ p, int64_t row, T (&v)[PW])
+{
+    static_assert((PW * sizeof(T)) % 16 == 0, "rows are read in 16-byte pieces");
+    const uint4 *src = reinterpret_cast<const uint4 *>(p + row * PW);
+    uint4 *dst = reinterpret_cast<uint4 *>(v);
+#pragma unroll
+    for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) dst[q] = src[q];
+}
+
+template <typename T, int PW>
+__device__ inline void store_row(T *__restrict__ p, int64_t row, const T (&v)[PW])
+{
+    uint4 *dst = reinterpret_cast<uint4 *>(p + row * PW);
+    const uint4 *src = reinterpret_cast<const uint4 *>(v);
+#pragma unroll
+    for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) dst[q] = src[q];
+}
+
+template <typename T, int PW>
+__device__ inline T pick(const T (&v)[PW], uint32_t src)
+{
+    T r = T(0);
+#pragma unroll
+    for (int q = 0; q < PW; ++q) r = (src == static_cast<uint32_t>(q)) ? v[q] : r;
+    return r;
+}
+
+template <typename T, typename IDX, int PW>
+__global__ __launch_bounds__(kBlock) void k_smooth_map(
+    int n, int jw, DiaOffsets joff, const int *__restrict__ jcol, const T *__restrict__ jv,
+    const IDX *__restrict__ jmap, const uint32_t *__restrict__ tab, int ntab,
+    const T *__restrict__ pin, T *__restrict__ pout, const uint8_t *__restrict__ interior,
+    unsigned long long *__restrict__ eit_bits)
+{
+    // a one-byte map index selects from a table of at most 256 maps kept in LDS
+    __shared__ uint32_t stab[256];
+    if constexpr (sizeof(IDX) == 1) {
+        for (int t = threadIdx.x; t < ntab; t += blockDim.x) stab[t] = tab[t];
+        __syncthreads();
+    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double emax = 0.0;
+    if (i < n) {
+        T acc[PW];
+#pragma unroll
+        for (int s = 0; s < PW; ++s) acc[s] = T(0);
+        for (int o = 0; o < jw; ++o) {
+            const int64_t e = static_cast<int64_t>(o) * n + i;
+            uint32_t m;
+            if constexpr (sizeof(IDX) == 1)
+                m = stab[jmap[e]];
+            else if constexpr (sizeof(IDX) == 2)
+                m = tab[jmap[e]];
+            else
+                m = static_cast<uint32_t>(jmap[e]);
+            if (m == 0xFFFFFFFFu) continue;
+            const T w = jv[e];
+            const int k = jcol ? jcol[e] : i + joff.off[o];
+            T v[PW];
+            load_row<T, PW>(pin, k, v);
+#pragma unroll
+            for (int s = 0; s < PW; ++s) {
+                const uint32_t src = (m >> (4 * s)) & 0xFu;
+                if (src != 0xFu) acc[s] += w * pick<T, PW>(v, src);
+            }
+        }
+        double rs = 0.0;
+#pragma unroll
+        for (int s = 0; s < PW; ++s) rs += static_cast<double>(acc[s]);
+        T old[PW], out[PW];
+        load_row<T, PW>(pin, i, old);
+        const bool inner = eit_bits != nullptr && interior[i] != 0;
+#pragma unroll
+        for (int s = 0; s < PW; ++s) {
+            if (inner) {
+                const double dlt = fabs(static_cast<double>(acc[s]) - static_cast<double>(old[s]));
+                emax = (dlt > emax || dlt != dlt) ? dlt : emax;
+            }
+            out[s] = static_cast<T>(static_cast<double>(acc[s]) / rs);
+        }
+        store_row<T, PW>(pout, i, out);
+    }
+    if (eit_bits != nullptr) eit_reduce(emax, eit_bits);
+}
+
+// Fallback for rows wider than the slot maps allow: row i's pattern (W
+// slots) in registers, every entry of every neighbour row compared against it.
 template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_smooth(
-    int n, const int *__restrict__ jrp, const int *__restrict__ jci, const T *__restrict__ jv,
-    const int *__restrict__ prp, const int *__restrict__ pci, const T *__restrict__ pin,
+__global__ __launch_bounds__(kBlock) void k_smooth_cmp(
+    int n, int pw, int jw, DiaOffsets joff, const int *__restrict__ jcol,
+    const T *__restrict__ jv, const int *__restrict__ pcol, const T *__restrict__ pin,
     T *__restrict__ pout, const uint8_t *__restrict__ interior,
     unsigned long long *__restrict__ eit_bits)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double emax = 0.0;
     if (i < n) {
-        const int p0 = prp[i];
-        const int np = prp[i + 1] - p0;
         int col[W];
         T acc[W];
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            col[s] = (s < np) ? pci[p0 + s] : -1;
+            col[s] = (s < pw) ? pcol[static_cast<int64_t>(i) * pw + s] : -1;
             acc[s] = T(0);
         }
-        const int e1 = jrp[i + 1];
-        for (int e = jrp[i]; e < e1; ++e) {
-            const int k = jci[e];
+        for (int o = 0; o < jw; ++o) {
+            const int64_t e = static_cast<int64_t>(o) * n + i;
+            const int k = jcol ? jcol[e] : i + joff.off[o];
+            if (k < 0 || k >= n) continue;
             const T w = jv[e];
-            const int q1 = prp[k + 1];
-            for (int q = prp[k]; q < q1; ++q) {
-                const int c = pci[q];
-                const T wv = w * pin[q];
+            if (w == T(0)) continue;
+            for (int q = 0; q < pw; ++q) {
+                const int c = pcol[static_cast<int64_t>(k) * pw + q];
+                if (c < 0) break;
+                const T wv = w * pin[static_cast<int64_t>(k) * pw + q];
 #pragma unroll
                 for (int s = 0; s < W; ++s) acc[s] += (col[s] == c) ? wv : T(0);
             }
         }
         double rs = 0.0;
 #pragma unroll
-        for (int s = 0; s < W; ++s)
-            if (s < np) rs += static_cast<double>(acc[s]);
+        for (int s = 0; s < W; ++s) rs += static_cast<double>(acc[s]);
         const bool inner = eit_bits != nullptr && interior[i] != 0;
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            if (s < np) {
+            if (s < pw) {
+                const int64_t e = static_cast<int64_t>(i) * pw + s;
                 if (inner) {
-                    const double dlt = fabs(static_cast<double>(acc[s]) -
-                                            static_cast<double>(pin[p0 + s]));
+                    const double dlt =
+                        fabs(static_cast<double>(acc[s]) - static_cast<double>(pin[e]));
                     emax = (dlt > emax || dlt != dlt) ? dlt : emax;
                 }
-                pout[p0 + s] = static_cast<T>(static_cast<double>(acc[s]) / rs);
+                pout[e] = static_cast<T>(static_cast<double>(acc[s]) / rs);
             }
         }
     }
-    if (eit_bits != nullptr) {
-        emax = wave_max(emax);
-        if ((threadIdx.x & 63) == 0 && emax != 0.0)
-            atomicMax(eit_bits, static_cast<unsigned long long>(__double_as_longlong(emax)));
-    }
+    if (eit_bits != nullptr) eit_reduce(emax, eit_bits);
 }
 
-// Partial statistics of P: max |row sum - 1|, min and max entry.
+// Partial statistics of P: max |row sum - 1|, min and max entry (padding
+// slots hold zeros and are skipped through the column array).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_basis_stats(int n, const int *__restrict__ prp,
+__global__ __launch_bounds__(kBlock) void k_basis_stats(int n, int pw, const int *__restrict__ pcol,
                                                         const T *__restrict__ p,
                                                         double *__restrict__ partials)
 {
@@ -144,7 +262,9 @@ __global__ __launch_bounds__(kBlock) void k_basis_stats(int n, const int *__rest
     double err = 0.0, lo = 1e300, hi = -1e300;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int e = prp[i]; e < prp[i + 1]; ++e) {
+        for (int q = 0; q < pw; ++q) {
+            const int64_t e = static_cast<int64_t>(i) * pw + q;
+            if (pcol[e] < 0) continue;
             const double v = static_cast<double>(p[e]);
             s += v;
             lo = fmin(lo, v);
@@ -189,100 +309,179 @@ __global__ void k_basis_stats_final(int nb, const double *__restrict__ partials,
     out[2] = hi;
 }
 
-__global__ __launch_bounds__(kBlock) void k_f32_to_f64(int64_t m, const float *__restrict__ s,
-                                                       double *__restrict__ d)
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert(int64_t m, const S *__restrict__ s,
+                                                    D *__restrict__ d)
 {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < m) d[t] = static_cast<double>(s[t]);
+    if (t < m) d[t] = static_cast<D>(s[t]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_f64_to_f32(int64_t m, const double *__restrict__ s,
-                                                       float *__restrict__ d)
+// ELL <-> CSR for P (values in double on the CSR side)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ell_to_csr(int n, int pw, const int *__restrict__ prp,
+                                                       const T *__restrict__ pe,
+                                                       double *__restrict__ pc)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < m) d[t] = static_cast<float>(s[t]);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e0 = prp[i], np = prp[i + 1] - e0;
+    for (int s = 0; s < np; ++s) pc[e0 + s] = static_cast<double>(pe[static_cast<int64_t>(i) * pw + s]);
 }
 
-inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
-
-template <typename T, int W>
-void smooth_w(hipStream_t s, int n, const int *jrp, const int *jci, const T *jv, const int *prp,
-              const int *pci, const T *pin, T *pout, const uint8_t *interior,
-              unsigned long long *eit)
+__global__ __launch_bounds__(kBlock) void k_csr_to_ell(int n, int pw, const int *__restrict__ prp,
+                                                       const double *__restrict__ pc,
+                                                       double *__restrict__ pe)
 {
-    k_smooth<T, W><<<grid_for(n), kBlock, 0, s>>>(n, jrp, jci, jv, prp, pci, pin, pout, interior,
-                                                   eit);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e0 = prp[i], np = prp[i + 1] - e0;
+    for (int s = 0; s < pw; ++s)
+        pe[static_cast<int64_t>(i) * pw + s] = s < np ? pc[e0 + s] : 0.0;
+}
+
+// Slot maps (see k_smooth_map): one thread per fine row.
+__global__ __launch_bounds__(kBlock) void k_build_maps(int n, int pw, int jw, DiaOffsets joff,
+                                                       const int *__restrict__ jcol,
+                                                       const int *__restrict__ jrp,
+                                                       const int *__restrict__ jci,
+                                                       const int *__restrict__ pcol,
+                                                       uint32_t *__restrict__ maps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int o = 0; o < jw; ++o) {
+        const int64_t e = static_cast<int64_t>(o) * n + i;
+        const int k = jcol ? jcol[e] : i + joff.off[o];
+        bool present = false;
+        if (k >= 0 && k < n)
+            for (int q = jrp[i]; q < jrp[i + 1]; ++q)
+                if (jci[q] == k) present = true;
+        uint32_t m = 0xFFFFFFFFu;
+        if (present) {
+            for (int s = 0; s < pw && s < kMapWidth; ++s) {
+                const int c = pcol[static_cast<int64_t>(i) * pw + s];
+                uint32_t src = 0xFu;
+                if (c >= 0)
+                    for (int q = 0; q < pw; ++q)
+                        if (pcol[static_cast<int64_t>(k) * pw + q] == c) src = static_cast<uint32_t>(q);
+                m = (m & ~(0xFu << (4 * s))) | (src << (4 * s));
+            }
+        }
+        maps[e] = m;
+    }
+}
+
+inline int grid_n(int n) { return grid_for(n); }
+
+template <typename T, typename IDX>
+void smooth_map_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
+{
+    const IDX *idx = static_cast<const IDX *>(a.jmap_idx);
+    if (a.pw <= 4)
+        k_smooth_map<T, IDX, 4><<<grid_n(a.n), kBlock, 0, s>>>(
+            a.n, a.jw, a.joff, a.jcol, jv, idx, a.jmap_tab, a.jmap_ntab, pin, pout, a.interior,
+            a.eit);
+    else
+        k_smooth_map<T, IDX, 8><<<grid_n(a.n), kBlock, 0, s>>>(
+            a.n, a.jw, a.joff, a.jcol, jv, idx, a.jmap_tab, a.jmap_ntab, pin, pout, a.interior,
+            a.eit);
 }
 
 template <typename T>
-void smooth_t(hipStream_t s, int n, int maxw, const int *jrp, const int *jci, const T *jv,
-              const int *prp, const int *pci, const T *pin, T *pout, const uint8_t *interior,
-              unsigned long long *eit)
+void smooth_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
 {
-    if (maxw <= 4)
-        smooth_w<T, 4>(s, n, jrp, jci, jv, prp, pci, pin, pout, interior, eit);
-    else if (maxw <= 8)
-        smooth_w<T, 8>(s, n, jrp, jci, jv, prp, pci, pin, pout, interior, eit);
-    else if (maxw <= 16)
-        smooth_w<T, 16>(s, n, jrp, jci, jv, prp, pci, pin, pout, interior, eit);
+    switch (a.jmap_kind) {
+    case 1: smooth_map_t<T, uint8_t>(s, a, jv, pin, pout); return;
+    case 2: smooth_map_t<T, uint16_t>(s, a, jv, pin, pout); return;
+    case 3: smooth_map_t<T, uint32_t>(s, a, jv, pin, pout); return;
+    default: break;
+    }
+    if (a.pw <= 8)
+        k_smooth_cmp<T, 8><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
+                                                          a.pcol, pin, pout, a.interior, a.eit);
+    else if (a.pw <= 16)
+        k_smooth_cmp<T, 16><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
+                                                           a.pcol, pin, pout, a.interior, a.eit);
     else
-        smooth_w<T, 32>(s, n, jrp, jci, jv, prp, pci, pin, pout, interior, eit);
+        k_smooth_cmp<T, 32><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
+                                                           a.pcol, pin, pout, a.interior, a.eit);
 }
 
 }  // namespace
 
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
-                          const int *ci, const double *a, const int *jrp, double *jv64,
-                          float *jv32)
+                          const int *ci, const double *a, int jw, const DiaOffsets &joff,
+                          bool use_dia, double *jv64, float *jv32)
 {
     if (jv32)
-        k_filter_jacobi<float><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a, jrp,
-                                                              jv32);
+        k_filter_jacobi<float><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a, jw,
+                                                              joff, use_dia ? 1 : 0, jv32);
     else
         k_filter_jacobi<double><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a,
-                                                               jrp, jv64);
+                                                               jw, joff, use_dia ? 1 : 0, jv64);
 }
 
-void launch_init_basis(hipStream_t s, int n, const int *prp, const int *pci, const int *part,
+void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32)
 {
     if (p32)
-        k_init_basis<float><<<grid_for(n), kBlock, 0, s>>>(n, prp, pci, part, p32);
+        k_init_basis<float><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, part, p32);
     else
-        k_init_basis<double><<<grid_for(n), kBlock, 0, s>>>(n, prp, pci, part, p64);
+        k_init_basis<double><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, part, p64);
 }
 
-void launch_smooth(hipStream_t s, int n, int maxw, bool fp32, const int *jrp, const int *jci,
-                   const double *jv64, const float *jv32, const int *prp, const int *pci,
-                   const double *pin64, double *pout64, const float *pin32, float *pout32,
-                   const uint8_t *interior, unsigned long long *eit_bits)
+void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,
+                   const float *jv32, const double *pin64, double *pout64, const float *pin32,
+                   float *pout32)
 {
     if (fp32)
-        smooth_t<float>(s, n, maxw, jrp, jci, jv32, prp, pci, pin32, pout32, interior, eit_bits);
+        smooth_t<float>(s, a, jv32, pin32, pout32);
     else
-        smooth_t<double>(s, n, maxw, jrp, jci, jv64, prp, pci, pin64, pout64, interior,
-                         eit_bits);
+        smooth_t<double>(s, a, jv64, pin64, pout64);
 }
 
-void launch_basis_stats(hipStream_t s, int n, const int *prp, bool fp32, const double *p64,
-                        const float *p32, double *partials, double *out3)
+void launch_basis_stats(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
+                        const double *p64, const float *p32, double *partials, double *out3)
 {
     const int nb = 256;
     if (fp32)
-        k_basis_stats<float><<<nb, kBlock, 0, s>>>(n, prp, p32, partials);
+        k_basis_stats<float><<<nb, kBlock, 0, s>>>(n, pw, pcol, p32, partials);
     else
-        k_basis_stats<double><<<nb, kBlock, 0, s>>>(n, prp, p64, partials);
+        k_basis_stats<double><<<nb, kBlock, 0, s>>>(n, pw, pcol, p64, partials);
     k_basis_stats_final<<<1, 64, 0, s>>>(nb, partials, out3);
 }
 
 void launch_p_convert(hipStream_t s, int64_t m, const float *src, double *dst)
 {
-    if (m > 0) k_f32_to_f64<<<grid_for(m), kBlock, 0, s>>>(m, src, dst);
+    if (m > 0) k_convert<float, double><<<grid_for(m), kBlock, 0, s>>>(m, src, dst);
 }
 
 void launch_p_convert_down(hipStream_t s, int64_t m, const double *src, float *dst)
 {
-    if (m > 0) k_f64_to_f32<<<grid_for(m), kBlock, 0, s>>>(m, src, dst);
+    if (m > 0) k_convert<double, float><<<grid_for(m), kBlock, 0, s>>>(m, src, dst);
+}
+
+void launch_ell_to_csr(hipStream_t s, int n, int pw, const int *prp, bool fp32,
+                       const double *pe64, const float *pe32, double *pcsr)
+{
+    if (fp32)
+        k_ell_to_csr<float><<<grid_for(n), kBlock, 0, s>>>(n, pw, prp, pe32, pcsr);
+    else
+        k_ell_to_csr<double><<<grid_for(n), kBlock, 0, s>>>(n, pw, prp, pe64, pcsr);
+}
+
+void launch_csr_to_ell(hipStream_t s, int n, int pw, const int *prp, const double *pcsr,
+                       double *pe64)
+{
+    k_csr_to_ell<<<grid_for(n), kBlock, 0, s>>>(n, pw, prp, pcsr, pe64);
+}
+
+void launch_build_maps(hipStream_t s, int n, int pw, int jw, const DiaOffsets &joff,
+                       const int *jcol, const int *jrp, const int *jci, const int *pcol,
+                       uint32_t *maps)
+{
+    k_build_maps<<<grid_for(n), kBlock, 0, s>>>(n, pw, jw, joff, jcol, jrp, jci, pcol, maps);
 }
 
 }  // namespace msrsb

@@ -1,6 +1,8 @@
 // Coarse-level kernels: R = P^T values, the Galerkin operator A_c = R A P
 // (eq. lin_system_coarse, Alg. 2), the exact coarse solver M_c^{-1} = A_c^{-1}
 // and its application.
+#include <utility>
+
 #include "internal.h"
 
 namespace msrsb {
@@ -23,42 +25,49 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t m, double *__restrict__
 }
 
 // A_c row j = sum over fine rows i in the support of j (R row j, ascending
-// i) of P_ij * A_i* * P.  One wavefront per coarse row.  The coarse columns
+// i) of P_ij * A_i* * P.  One work-group per coarse row.  The coarse columns
 // reached by row j (its coarse neighbours) are found first and numbered in
-// ascending order in an LDS map; each lane then accumulates its share of the
-// fine rows into a private LDS column of per-neighbour partial sums, and the
-// 64 partial sums of every neighbour are added in lane order.  The result does
-// not depend on scheduling (no atomics), so it is bitwise reproducible.
-template <typename T>
-__global__ __launch_bounds__(64) void k_rap(int nc, int maxnb, const int *__restrict__ rrp,
-                                            const int *__restrict__ rci, const T *__restrict__ rv,
-                                            const int *__restrict__ rp,
+// ascending order in an LDS map; each thread then accumulates its share of
+// the fine rows into a private LDS column of per-neighbour partial sums, and
+// the partial sums of every neighbour are added in thread order.  No atomics
+// touch A_c, so it is bitwise reproducible.  The lower and upper bandwidths
+// of A_c are recorded for the coarse factorisation.
+template <typename T, int NT, bool DIA>
+__global__ __launch_bounds__(NT) void k_rap(int n, int nc, int maxnb, const int *__restrict__ rrp,
+                                            const int *__restrict__ rci,
+                                            const T *__restrict__ rv, const int *__restrict__ rp,
                                             const int *__restrict__ ci,
-                                            const double *__restrict__ a,
+                                            const double *__restrict__ a, DiaOffsets d,
+                                            const double *__restrict__ ad,
                                             const int *__restrict__ prp,
-                                            const int *__restrict__ pci, const T *__restrict__ pv,
-                                            double *__restrict__ ac, int *__restrict__ flag)
+                                            const int *__restrict__ pci,
+                                            const double *__restrict__ pv, double *__restrict__ ac,
+                                            int *__restrict__ flag, int *__restrict__ band)
 {
     extern __shared__ double smem[];
-    double *acc = smem;                                         // maxnb * 64
-    int *inv = reinterpret_cast<int *>(acc + maxnb * 64);       // maxnb
+    __shared__ int wsum[NT / 64];
+    double *acc = smem;                                         // maxnb * NT
+    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);       // maxnb
     short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
     const int j = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < nc; t += 64) map[t] = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ne = DIA ? d.n : 0;
+    for (int t = tid; t < nc; t += NT) map[t] = 0;
     __syncthreads();
     const int t0 = rrp[j], t1 = rrp[j + 1];
-    for (int t = t0 + lane; t < t1; t += 64) {
+    for (int t = t0 + tid; t < t1; t += NT) {
         const int i = rci[t];
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int k = ci[e];
+        const int e0 = DIA ? 0 : rp[i], e1 = DIA ? ne : rp[i + 1];
+        for (int e = e0; e < e1; ++e) {
+            const int k = DIA ? i + d.off[e] : ci[e];
+            if (DIA && (k < 0 || k >= n || ad[static_cast<int64_t>(e) * n + i] == 0.0)) continue;
             for (int q = prp[k]; q < prp[k + 1]; ++q) map[pci[q]] = 1;
         }
     }
     __syncthreads();
-    // number the marked coarse columns in ascending order (wavefront scan)
-    const int chunk = (nc + 63) / 64;
-    const int lo = lane * chunk, hi = min(nc, lo + chunk);
+    // number the marked coarse columns in ascending order (block scan)
+    const int chunk = (nc + NT - 1) / NT;
+    const int lo = tid * chunk, hi = min(nc, lo + chunk);
     int cnt = 0;
     for (int t = lo; t < hi; ++t) cnt += map[t];
     int pre = cnt;
@@ -67,12 +76,18 @@ __global__ __launch_bounds__(64) void k_rap(int nc, int maxnb, const int *__rest
         const int o = __shfl_up(pre, off, 64);
         if (lane >= off) pre += o;
     }
-    const int total = __shfl(pre, 63, 64);
+    if (lane == 63) wsum[wid] = pre;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        total += wsum[w];
+    }
     if (total > maxnb) {
-        if (lane == 0) flag[0] = 1;
+        if (tid == 0) flag[0] = 1;
         return;
     }
-    int slot = pre - cnt;
+    int slot = base + pre - cnt;
     __syncthreads();
     for (int t = lo; t < hi; ++t) {
         if (map[t]) {
@@ -82,26 +97,36 @@ __global__ __launch_bounds__(64) void k_rap(int nc, int maxnb, const int *__rest
             map[t] = -1;
         }
     }
-    for (int s = 0; s < total; ++s) acc[s * 64 + lane] = 0.0;
+    for (int s = 0; s < total; ++s) acc[s * NT + tid] = 0.0;
     __syncthreads();
-    for (int t = t0 + lane; t < t1; t += 64) {
+    for (int t = t0 + tid; t < t1; t += NT) {
         const int i = rci[t];
         const double pij = static_cast<double>(rv[t]);
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int k = ci[e];
-            const double pa = pij * a[e];
-            for (int q = prp[k]; q < prp[k + 1]; ++q) {
-                const int sl = map[pci[q]];
-                acc[sl * 64 + lane] += pa * static_cast<double>(pv[q]);
-            }
+        const int e0 = DIA ? 0 : rp[i], e1 = DIA ? ne : rp[i + 1];
+        for (int e = e0; e < e1; ++e) {
+            const int k = DIA ? i + d.off[e] : ci[e];
+            const double av = DIA ? ((k >= 0 && k < n) ? ad[static_cast<int64_t>(e) * n + i] : 0.0)
+                                  : a[e];
+            if (DIA && av == 0.0) continue;
+            const double pa = pij * av;
+            for (int q = prp[k]; q < prp[k + 1]; ++q)
+                acc[map[pci[q]] * NT + tid] += pa * pv[q];
         }
     }
     __syncthreads();
-    for (int s = lane; s < total; s += 64) {
+    int bl = 0, bu = 0;
+    for (int s = tid; s < total; s += NT) {
         double sum = 0.0;
-        for (int l = 0; l < 64; ++l) sum += acc[s * 64 + l];
-        ac[static_cast<int64_t>(j) * nc + inv[s]] = sum;
+        for (int l = 0; l < NT; ++l) sum += acc[s * NT + l];
+        const int col = inv[s];
+        ac[static_cast<int64_t>(j) * nc + col] = sum;
+        if (sum != 0.0) {
+            bl = max(bl, j - col);
+            bu = max(bu, col - j);
+        }
     }
+    if (bl > 0) atomicMax(band, bl);
+    if (bu > 0) atomicMax(band + 1, bu);
 }
 
 // ---------------------------------------------------------------------------
@@ -383,8 +408,306 @@ __global__ __launch_bounds__(kBlock) void k_gj_permute(int n, const double *__re
     Y[t] = X[static_cast<int64_t>(r) * n + colsrc[j]];
 }
 
-// y = M x, one wavefront per row; lanes stride over the columns and the 64
-// partial sums are added in a fixed butterfly order.
+// ---------------------------------------------------------------------------
+// Pivot-free block Gauss-Jordan, for a symmetric positive definite A_c (the
+// Galerkin operator of a symmetric positive definite A), in place on X.
+// For each 64-wide panel K (diagonal block D = X[K,K], G = D^{-1}):
+//   X[K,C] <- G X[K,C]                         (block row, C != K)
+//   X[R,C] <- X[R,C] - X[R,K] X[K,C]          (rank-64 update, R, C != K)
+//   X[R,K] <- -X[R,K] G,  X[K,K] <- G          (block column)
+// After the last panel X = A_c^{-1}.  Without pivoting the part of X not yet
+// eliminated keeps A_c's band: at panel K rows below k0 + 64 + bl have a zero
+// block column and columns right of k0 + 64 + bu a zero block row, so the
+// updates stop there (bl, bu = lower and upper bandwidth of A_c).
+// ---------------------------------------------------------------------------
+constexpr int kBP = 64;
+constexpr int kSuper = 128;  // columns per super-panel (a multiple of kBP)
+
+// G = D^{-1} by unblocked Gauss-Jordan in one wavefront: lane j keeps column
+// j of the 64 x 64 block in registers (rows past nb padded with the
+// identity).  Step c reads column c from lane c with a lane shuffle, so the loops
+// are fully unrolled and every register index is a constant.  Row c becomes
+// x_cj / d (1 / d in column c), every other row r becomes x_rj - x_rc x_cj / d
+// (-x_rc / d in column c).  Non-positive pivots set the flag.
+// one elimination step with a compile-time pivot index C; lane r holds row r
+// of the block, the pivot row is broadcast through LDS
+template <int C>
+__device__ __forceinline__ void gj_step(double (&v)[kBP], double *prow, int r, bool &bad)
+{
+    if (r == C) {
+#pragma unroll
+        for (int q = 0; q < kBP; q += 2)
+            *reinterpret_cast<double2 *>(prow + q) = double2{v[q], v[q + 1]};
+    }
+    __syncthreads();
+    double p[kBP];
+#pragma unroll
+    for (int q = 0; q < kBP; q += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(prow + q);
+        p[q] = t.x;
+        p[q + 1] = t.y;
+    }
+    __syncthreads();
+    const double d = p[C];
+    bad |= !(d > 0.0);
+    const double inv = 1.0 / d;
+    if (r == C) {
+#pragma unroll
+        for (int q = 0; q < kBP; ++q) v[q] = (q == C) ? inv : p[q] * inv;
+    } else {
+        const double f = v[C] * inv;
+#pragma unroll
+        for (int q = 0; q < kBP; ++q) v[q] = (q == C) ? -f : v[q] - f * p[q];
+    }
+}
+
+template <int... Cs>
+__device__ __forceinline__ void gj_all(double (&v)[kBP], double *prow, int r, bool &bad,
+                                       std::integer_sequence<int, Cs...>)
+{
+    (gj_step<Cs>(v, prow, r, bad), ...);
+}
+
+// G = D^{-1} by unblocked Gauss-Jordan in one wavefront: lane r keeps row r
+// of the 64 x 64 block in registers (rows and columns past nb padded with
+// the identity).  In step c the pivot row c is broadcast through LDS; row c
+// becomes x_cj / d (1 / d in column c) and every other row r becomes
+// x_rj - (x_rc / d) x_cj (-x_rc / d in column c).  The loops are fully
+// unrolled so every register index is a constant.  Non-positive pivots set
+// the flag.
+__global__ __launch_bounds__(64) void k_bgj_diag(const double *__restrict__ X, int n, int k0,
+                                                 int nb, double *__restrict__ G,
+                                                 int *__restrict__ flag)
+{
+    __shared__ __attribute__((aligned(16))) double prow[kBP];
+    const int r = threadIdx.x;
+    double v[kBP];
+#pragma unroll
+    for (int q = 0; q < kBP; ++q)
+        v[q] = (r < nb && q < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + q]
+                                  : (r == q ? 1.0 : 0.0);
+    bool bad = false;
+    gj_all(v, prow, r, bad, std::make_integer_sequence<int, kBP>{});
+    if (bad && r == 0) flag[0] = 1;
+    if (r < nb)
+#pragma unroll
+        for (int q = 0; q < kBP; ++q)
+            if (q < nb) G[r * kBP + q] = v[q];
+}
+
+// X[K, tile] <- G X[K, tile] for the column tiles left of cu other than K
+__global__ __launch_bounds__(256) void k_bgj_rowblock(double *__restrict__ X, int n, int k0,
+                                                      int nb, const double *__restrict__ G,
+                                                      int ct0)
+{
+    __shared__ double Gs[kBP][kBP + 1];
+    __shared__ double Xs[kBP][kBP + 1];
+    const int kt = k0 / kBP;
+    if (blockIdx.x == gridDim.x - 1) {  // the diagonal block becomes G
+        for (int e = threadIdx.x; e < nb * nb; e += 256)
+            X[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb] = G[(e / nb) * kBP + e % nb];
+        return;
+    }
+    const int tile = ct0 + blockIdx.x < kt ? ct0 + blockIdx.x : ct0 + blockIdx.x + 1;
+    const int c0 = tile * kBP;
+    for (int t = threadIdx.x; t < kBP * kBP; t += 256) {
+        const int r = t / kBP, c = t % kBP;
+        Gs[r][c] = (r < nb && c < nb) ? G[r * kBP + c] : 0.0;
+        Xs[r][c] = (r < nb && c0 + c < n) ? X[static_cast<int64_t>(k0 + r) * n + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int k = 0; k < nb; ++k) {
+        double g[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            g[u] = Gs[ty * 4 + u][k];
+            x[u] = Xs[k][tx * 4 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] += g[u] * x[w];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = ty * 4 + u;
+        if (r >= nb) continue;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int c = c0 + tx * 4 + w;
+            if (c < n) X[static_cast<int64_t>(k0 + r) * n + c] = acc[u][w];
+        }
+    }
+}
+
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+// acc (a wavefront's 32 x 32 quadrant at (wr, wc)) += A B for 64 x 64
+// operands in LDS, on the FP64 matrix cores
+__device__ inline void mfma_tile64(const double (*A)[kBP + 1], const double (*B)[kBP + 1],
+                                   mfma_f64x4 (&acc)[2][2], int wr, int wc, int li, int lk)
+{
+    for (int kk = 0; kk < kBP; kk += 4) {
+        const double a0 = A[wr + li][kk + lk], a1 = A[wr + 16 + li][kk + lk];
+        const double b0 = B[kk + lk][wc + li], b1 = B[kk + lk][wc + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+__device__ inline void zero_acc(mfma_f64x4 (&acc)[2][2])
+{
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// One 64-wide panel K inside a super-panel, for one row tile R != K (one
+// work-group per row tile below the band limit):
+//   X[R, t] -= X[R, K] (G X[K, t])   for the other column tiles t of the
+//                                    super-panel (G X[K, t] formed here from
+//                                    the unmodified X[K, t])
+//   X[R, K] <- -X[R, K] G
+// The row block K itself is updated afterwards by k_bgj_rowblock.
+__global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n, int k0, int nb,
+                                                   const double *__restrict__ G, int ct0, int nct)
+{
+    __shared__ double Gs[kBP][kBP + 1];
+    __shared__ double As[kBP][kBP + 1];  // X[R, K] before this panel
+    __shared__ double Ks[kBP][kBP + 1];  // X[K, t], then G X[K, t]
+    const int kt = k0 / kBP;
+    const int tr = blockIdx.x < kt ? blockIdx.x : blockIdx.x + 1;
+    const int r0 = tr * kBP;
+    for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
+        const int a = e / kBP, b = e % kBP;
+        Gs[a][b] = (a < nb && b < nb) ? G[a * kBP + b] : 0.0;
+        As[a][b] = (r0 + a < n && b < nb) ? X[static_cast<int64_t>(r0 + a) * n + k0 + b] : 0.0;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    mfma_f64x4 acc[2][2];
+    for (int u = 0; u < nct; ++u) {
+        const int tc = ct0 + u < kt ? ct0 + u : ct0 + u + 1;
+        const int c0 = tc * kBP;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
+            const int a = e / kBP, b = e % kBP;
+            Ks[a][b] = (a < nb && c0 + b < n) ? X[static_cast<int64_t>(k0 + a) * n + c0 + b] : 0.0;
+        }
+        __syncthreads();
+        zero_acc(acc);
+        mfma_tile64(Gs, Ks, acc, wr, wc, li, lk);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    Ks[wr + 16 * p + 4 * q + lk][wc + 16 * v + li] = acc[p][v][q];
+        __syncthreads();
+        zero_acc(acc);
+        mfma_tile64(As, Ks, acc, wr, wc, li, lk);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + wr + 16 * p + 4 * q + lk;
+                    const int c = c0 + wc + 16 * v + li;
+                    if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] -= acc[p][v][q];
+                }
+    }
+    __syncthreads();
+    zero_acc(acc);
+    mfma_tile64(As, Gs, acc, wr, wc, li, lk);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wr + 16 * p + 4 * q + lk;
+                const int c = wc + 16 * v + li;
+                if (r < n && c < nb) X[static_cast<int64_t>(r) * n + k0 + c] = -acc[p][v][q];
+            }
+}
+
+// Rows s0 .. s0+ns-1 of the columns outside the super-panel (up to c_hi) move
+// to B (ns x n) and are zeroed.
+__global__ __launch_bounds__(kBlock) void k_bgj_extract(double *__restrict__ X, int n, int s0,
+                                                        int ns, int c_hi, double *__restrict__ B)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    if (c >= c_hi || (c >= s0 && c < s0 + ns)) return;
+    const int64_t e = static_cast<int64_t>(s0 + t) * n + c;
+    B[static_cast<int64_t>(t) * n + c] = X[e];
+    X[e] = 0.0;
+}
+
+// X[R, C] += X[R, S] B[:, C] for row tiles below the band limit and column
+// tiles outside the super-panel S = [s0, s0 + ns) (ns a multiple of 64); the
+// super-panel's combined Gauss-Jordan transformation applied to the other
+// columns.  FP64 matrix cores, layout as in mfma_tile64.
+__global__ __launch_bounds__(256) void k_bgj_outer(double *__restrict__ X, int n, int s0, int ns,
+                                                   const double *__restrict__ B)
+{
+    __shared__ double As[kBP][kBP + 1];
+    __shared__ double Bs[kBP][kBP + 1];
+    const int st0 = s0 / kBP, nst = (ns + kBP - 1) / kBP;
+    const int tr = blockIdx.y;
+    const int tc = blockIdx.x < st0 ? blockIdx.x : blockIdx.x + nst;
+    const int r0 = tr * kBP, c0 = tc * kBP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    mfma_f64x4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < ns; kb += kBP) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kBP * kBP; t += 256) {
+            const int a = t / kBP, b = t % kBP;
+            As[a][b] = (r0 + a < n && kb + b < ns)
+                           ? X[static_cast<int64_t>(r0 + a) * n + s0 + kb + b] : 0.0;
+            Bs[a][b] = (kb + a < ns && c0 + b < n) ? B[static_cast<int64_t>(kb + a) * n + c0 + b]
+                                                    : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kBP; kk += 4) {
+            const double a0 = As[wr + li][kk + lk], a1 = As[wr + 16 + li][kk + lk];
+            const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wr + 16 * u + 4 * q + lk;
+                const int c = c0 + wc + 16 * v + li;
+                if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] += acc[u][v][q];
+            }
+}
+
+// y = M x, one wavefront per row; lanes stride over the columns (two per
+// 16-byte load when n is even) and the 64 partial sums are added in a fixed
+// butterfly order.
 __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double *__restrict__ M,
                                                  const double *__restrict__ x,
                                                  double *__restrict__ y)
@@ -394,7 +717,18 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double *__restrict
     if (row >= n) return;
     const double *mr = M + static_cast<int64_t>(row) * n;
     double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    if ((n & 1) == 0) {
+        const double2 *m2 = reinterpret_cast<const double2 *>(mr);
+        const double2 *x2 = reinterpret_cast<const double2 *>(x);
+        const int h = n >> 1;
+#pragma unroll 4
+        for (int c = lane; c < h; c += 64) {
+            const double2 a = m2[c], b = x2[c];
+            s += a.x * b.x + a.y * b.y;
+        }
+    } else {
+        for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) y[row] = s;
@@ -439,19 +773,44 @@ void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const
         k_gather<double><<<grid_for(m), kBlock, 0, s>>>(m, rsrc, p64, r64);
 }
 
-void launch_rap(hipStream_t s, int nc, int maxnb, const int *rrp, const int *rci, bool fp32,
-                const double *r64, const float *r32, const int *rp, const int *ci,
-                const double *a, const int *prp, const int *pci, const double *p64,
-                const float *p32, double *ac, int *flag)
+template <typename T, int NT>
+void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp, const int *rci,
+           const T *rv, const int *rp, const int *ci, const double *a, const DiaOffsets &d,
+           const double *ad, const int *prp, const int *pci, const double *pv, double *ac,
+           int *flag, int *band)
 {
-    const size_t shmem = sizeof(double) * maxnb * 64 + sizeof(int) * maxnb +
-                         sizeof(short) * static_cast<size_t>(nc) + 16;
-    if (fp32)
-        k_rap<float><<<nc, 64, shmem, s>>>(nc, maxnb, rrp, rci, r32, rp, ci, a, prp, pci, p32,
-                                           ac, flag);
+    if (d.n > 0)
+        k_rap<T, NT, true><<<nc, NT, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, rp, ci, a, d, ad, prp,
+                                                 pci, pv, ac, flag, band);
     else
-        k_rap<double><<<nc, 64, shmem, s>>>(nc, maxnb, rrp, rci, r64, rp, ci, a, prp, pci, p64,
-                                            ac, flag);
+        k_rap<T, NT, false><<<nc, NT, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, rp, ci, a, d, ad, prp,
+                                                  pci, pv, ac, flag, band);
+}
+
+void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
+                bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
+                const double *a, const DiaOffsets &d, const double *ad, const int *prp,
+                const int *pci, const double *pcsr, double *ac, int *flag, int *band)
+{
+    // 128 threads while the per-thread partial sums fit in 32 KB of LDS
+    const int nt = maxnb <= 32 ? 128 : 64;
+    const size_t shmem = sizeof(double) * maxnb * nt + sizeof(int) * maxnb +
+                         sizeof(short) * static_cast<size_t>(nc) + 16;
+    if (nt == 128) {
+        if (fp32)
+            rap_t<float, 128>(s, shmem, n, nc, maxnb, rrp, rci, r32, rp, ci, a, d, ad, prp, pci,
+                              pcsr, ac, flag, band);
+        else
+            rap_t<double, 128>(s, shmem, n, nc, maxnb, rrp, rci, r64, rp, ci, a, d, ad, prp, pci,
+                               pcsr, ac, flag, band);
+    } else {
+        if (fp32)
+            rap_t<float, 64>(s, shmem, n, nc, maxnb, rrp, rci, r32, rp, ci, a, d, ad, prp, pci,
+                             pcsr, ac, flag, band);
+        else
+            rap_t<double, 64>(s, shmem, n, nc, maxnb, rrp, rci, r64, rp, ci, a, d, ad, prp, pci,
+                              pcsr, ac, flag, band);
+    }
 }
 
 void launch_fill(hipStream_t s, int64_t m, double *x, double v)
@@ -498,6 +857,42 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
     }
     k_gj_colsrc<<<1, 64, 0, s>>>(n, piv, colsrc);
     k_gj_permute<<<grid_for(static_cast<int64_t>(n) * n), kBlock, 0, s>>>(n, X, colsrc, inv_out);
+    hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
+    return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;
+}
+
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu, double *G,
+                                double *B, int *flag, int *host_flag)
+{
+    if (n < 1 || n > kMaxCoarse) return MSRSB_E_ARG;
+    hipMemsetAsync(flag, 0, sizeof(int), s);
+    // super-panels of kSuper columns: their 64-wide panels are eliminated
+    // within the super-panel, then one rank-kSuper update carries the
+    // combined transformation to the other columns
+    for (int s0 = 0; s0 < n; s0 += kSuper) {
+        const int ns = min(kSuper, n - s0);
+        const int st0 = s0 / kBP, st1 = (s0 + ns + kBP - 1) / kBP;
+        for (int k0 = s0; k0 < s0 + ns; k0 += kBP) {
+            const int nb = min(kBP, n - k0);
+            const int rl = min(n, k0 + nb + bl);
+            const int rtiles = (rl + kBP - 1) / kBP;
+            k_bgj_diag<<<1, 64, 0, s>>>(X, n, k0, nb, G, flag);
+            const int inner = st1 - st0 - 1;  // super-panel column tiles other than K
+            if (rtiles > 1) k_bgj_inner<<<rtiles - 1, 256, 0, s>>>(X, n, k0, nb, G, st0, inner);
+            k_bgj_rowblock<<<inner + 1, 256, 0, s>>>(X, n, k0, nb, G, st0);
+        }
+        const int rl = min(n, s0 + ns + bl), cu = min(n, s0 + ns + bu);
+        const int rtiles = (rl + kBP - 1) / kBP, ctiles = (cu + kBP - 1) / kBP;
+        const int outer = ctiles - (st1 - st0);
+        if (outer > 0) {
+            // whole column tiles are extracted: the GEMM reads B up to the tile edge
+            const int c_hi = min(n, ctiles * kBP);
+            k_bgj_extract<<<dim3((c_hi + kBlock - 1) / kBlock, ns), kBlock, 0, s>>>(X, n, s0, ns,
+                                                                                   c_hi, B);
+            k_bgj_outer<<<dim3(outer, rtiles), 256, 0, s>>>(X, n, s0, ns, B);
+        }
+    }
     hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
     return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;

@@ -122,21 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restri
     if (threadIdx.x == 0) xc[j] = s;
 }
 
-// z += P w_c
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(int n, const int *__restrict__ prp,
-                                                        const int *__restrict__ pci,
-                                                        const T *__restrict__ pv,
-                                                        const double *__restrict__ wc,
-                                                        double *__restrict__ z)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int e = prp[i]; e < prp[i + 1]; ++e) s += static_cast<double>(pv[e]) * wc[pci[e]];
-    z[i] += s;
-}
-
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 double *__restrict__ part)
@@ -146,95 +131,6 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict_
         s += x[i] * y[i];
     s = block_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// r.z and r.(z - z_old) in one pass
-__global__ __launch_bounds__(kBlock) void k_dot2(int n, const double *__restrict__ r,
-                                                 const double *__restrict__ z,
-                                                 const double *__restrict__ zo,
-                                                 double *__restrict__ part)
-{
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        s0 += r[i] * z[i];
-        s1 += r[i] * (z[i] - zo[i]);
-    }
-    s0 = block_sum(s0);
-    s1 = block_sum(s1);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s0;
-        part[kReduceBlocks + blockIdx.x] = s1;
-    }
-}
-
-// q = A p and the partial sums of p.q
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, const int *__restrict__ rp,
-                                                     const int *__restrict__ ci,
-                                                     const double *__restrict__ a,
-                                                     const double *__restrict__ p,
-                                                     double *__restrict__ q,
-                                                     double *__restrict__ part)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (i < n) {
-        const double qi = row_dot(i, rp, ci, a, p);
-        q[i] = qi;
-        s = p[i] * qi;
-    }
-    s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// alpha = r.z / p.q, with the breakdown flag for p.q <= 0 or non-finite values
-__global__ void k_cg_alpha(double *scal)
-{
-    if (threadIdx.x != 0) return;
-    const double pq = scal[S_PQ], rz = scal[S_RZ_OLD];
-    const bool bad = !(pq > 0.0) || !isfinite(pq) || !isfinite(rz);
-    if (bad) scal[S_BREAK] = 1.0;
-    scal[S_ALPHA] = bad ? 0.0 : rz / pq;
-}
-
-// x += alpha p, r -= alpha q, partial sums of r.r
-__global__ __launch_bounds__(kBlock) void k_cg_update(int n, double *__restrict__ x,
-                                                      double *__restrict__ r,
-                                                      const double *__restrict__ p,
-                                                      const double *__restrict__ q,
-                                                      const double *__restrict__ scal,
-                                                      double *__restrict__ part)
-{
-    const double alpha = scal[S_ALPHA];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (i < n) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        s = ri * ri;
-    }
-    s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// flexible (Polak-Ribiere) beta = r.(z - z_old) / (r.z)_old
-__global__ void k_cg_beta(double *scal)
-{
-    if (threadIdx.x != 0) return;
-    const double rzo = scal[S_RZ_OLD];
-    const double b = scal[S_RZDIFF] / rzo;
-    if (!isfinite(b)) scal[S_BREAK] = 1.0;
-    scal[S_BETA] = isfinite(b) ? b : 0.0;
-    scal[S_RZ_OLD] = scal[S_RZ];
-}
-
-__global__ __launch_bounds__(kBlock) void k_p_update(int n, double *__restrict__ p,
-                                                     const double *__restrict__ z,
-                                                     const double *__restrict__ scal)
-{
-    const double beta = scal[S_BETA];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = z[i] + beta * p[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(int n, const double *__restrict__ x,
@@ -336,6 +232,352 @@ __global__ __launch_bounds__(kBlock) void k_scale_by_inv(int n, const double *__
     v[i] = nr > 0.0 ? w[i] / nr : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// DIA kernels: A stored as [noff][n] values on fixed column offsets; entries
+// a row does not have are zero.  Out-of-range neighbours are never loaded.
+// ---------------------------------------------------------------------------
+template <typename MT>
+__device__ inline MT dia_dot(int i, int n, const DiaOffsets &d, const MT *__restrict__ a,
+                             const double *__restrict__ x)
+{
+    MT s = MT(0);
+    for (int o = 0; o < d.n; ++o) {
+        const int k = i + d.off[o];
+        const MT av = a[static_cast<int64_t>(o) * n + i];
+        const double xv = (k >= 0 && k < n) ? x[k] : 0.0;
+        s += av * static_cast<MT>(xv);
+    }
+    return s;
+}
+
+// Per-block partial sums of NV values, stored at part[q * gridDim.x + block];
+// a one-block finishing kernel then adds them in block order, so the total
+// does not depend on scheduling.
+template <int NV>
+__device__ inline void block_partials(double (&v)[NV], double *__restrict__ part)
+{
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[q][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) t += sh[q][w];
+            part[static_cast<int64_t>(q) * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+// sums of the NV partial arrays (nb partials each) in a fixed order, then the
+// scalar update of the Krylov method; one block of kFinThreads threads
+constexpr int kFinThreads = 1024;
+
+template <int NV>
+__device__ inline void sum_partials_block(int nb, const double *__restrict__ part, double (&tot)[NV])
+{
+    __shared__ double sh[NV][kFinThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kFinThreads) x += part[static_cast<int64_t>(q) * nb + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[q][wid] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < kFinThreads / 64; ++w) t += sh[q][w];
+        tot[q] = t;
+    }
+}
+
+// alpha = (r.z)_old / (p.q), breakdown on p.q <= 0 or non-finite values
+__global__ __launch_bounds__(kFinThreads) void k_fin_alpha(int nb, const double *__restrict__ part,
+                                                           double *__restrict__ scal)
+{
+    double t[1];
+    sum_partials_block<1>(nb, part, t);
+    if (threadIdx.x != 0) return;
+    const double pq = t[0], rz = scal[S_RZ_OLD];
+    scal[S_PQ] = pq;
+    const bool bad = !(pq > 0.0) || !isfinite(pq) || !isfinite(rz);
+    if (bad) scal[S_BREAK] = 1.0;
+    scal[S_ALPHA] = bad ? 0.0 : rz / pq;
+}
+
+// r.r, also written with the breakdown flag to host-visible memory so the
+// host can test convergence without a copy
+__global__ __launch_bounds__(kFinThreads) void k_fin_rr(int nb, const double *__restrict__ part,
+                                                        double *__restrict__ scal,
+                                                        double *__restrict__ host_out)
+{
+    double t[1];
+    sum_partials_block<1>(nb, part, t);
+    if (threadIdx.x != 0) return;
+    scal[S_RR] = t[0];
+    host_out[0] = t[0];
+    host_out[1] = scal[S_BREAK];
+}
+
+// flexible (Polak-Ribiere) beta = r.(z - z_old) / (r.z)_old
+__global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *__restrict__ part,
+                                                          double *__restrict__ scal)
+{
+    double t[2];
+    sum_partials_block<2>(nb, part, t);
+    if (threadIdx.x != 0) return;
+    scal[S_RZ] = t[0];
+    scal[S_RZDIFF] = t[1];
+    const double b = t[1] / scal[S_RZ_OLD];
+    if (!isfinite(b)) scal[S_BREAK] = 1.0;
+    scal[S_BETA] = isfinite(b) ? b : 0.0;
+    scal[S_RZ_OLD] = t[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dia_spmv(int n, DiaOffsets d,
+                                                     const double *__restrict__ a,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = dia_dot(i, n, d, a, x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dia_residual(int n, DiaOffsets d,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ f,
+                                                         const double *__restrict__ x,
+                                                         double *__restrict__ r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = f[i] - dia_dot(i, n, d, a, x);
+}
+
+// z_out = z_in + dinv (v - A z_in), smoother matrix and arithmetic in MT
+template <typename MT>
+__global__ __launch_bounds__(kBlock) void k_dia_sweep(int n, DiaOffsets d, const MT *__restrict__ a,
+                                                      const MT *__restrict__ dinv,
+                                                      const double *__restrict__ v,
+                                                      const double *__restrict__ zin,
+                                                      double *__restrict__ zout)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const MT res = static_cast<MT>(v[i]) - dia_dot(i, n, d, a, zin);
+    zout[i] = zin[i] + static_cast<double>(dinv[i] * res);
+}
+
+// two sweeps from z = 0: z1 = dinv v, z2 = z1 + dinv (v - A z1), with z1 of
+// the neighbours recomputed on the fly
+template <typename MT>
+__global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
+                                                            const MT *__restrict__ a,
+                                                            const MT *__restrict__ dinv,
+                                                            const double *__restrict__ v,
+                                                            double *__restrict__ zout)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    MT s = MT(0);
+    for (int o = 0; o < d.n; ++o) {
+        const int k = i + d.off[o];
+        const MT av = a[static_cast<int64_t>(o) * n + i];
+        MT z1 = MT(0);
+        if (k >= 0 && k < n) z1 = static_cast<MT>(static_cast<double>(dinv[k] * static_cast<MT>(v[k])));
+        s += av * z1;
+    }
+    const double z1i = static_cast<double>(dinv[i] * static_cast<MT>(v[i]));
+    zout[i] = z1i + static_cast<double>(dinv[i] * (static_cast<MT>(v[i]) - s));
+}
+
+// last smoothing sweep of the preconditioner inside PCG, fused with the dot
+// products r.z and r.(z - z_old) and the flexible beta
+template <typename MT>
+__global__ __launch_bounds__(kBlock) void k_dia_sweep_dots(
+    int n, DiaOffsets d, const MT *__restrict__ a, const MT *__restrict__ dinv,
+    const double *__restrict__ r, const double *__restrict__ zin, double *__restrict__ zout,
+    const double *__restrict__ zold, double *__restrict__ part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < n) {
+        const MT res = static_cast<MT>(r[i]) - dia_dot(i, n, d, a, zin);
+        const double z = zin[i] + static_cast<double>(dinv[i] * res);
+        zout[i] = z;
+        v[0] = r[i] * z;
+        v[1] = r[i] * (z - zold[i]);
+    }
+    block_partials<2>(v, part);
+}
+
+// r.z and r.(z - z_old) with the flexible beta (when the last stage of the
+// preconditioner is not a fused DIA sweep)
+__global__ __launch_bounds__(kBlock) void k_dots_beta(int n, const double *__restrict__ r,
+                                                      const double *__restrict__ z,
+                                                      const double *__restrict__ zold,
+                                                      double *__restrict__ part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < n) {
+        v[0] = r[i] * z[i];
+        v[1] = r[i] * (z[i] - zold[i]);
+    }
+    block_partials<2>(v, part);
+}
+
+// p_new = z + beta p_old, q = A p_new, p_new.q and alpha = (r.z) / (p.q)
+template <bool DIA>
+__global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
+    int n, DiaOffsets d, const double *__restrict__ ad, const int *__restrict__ rp,
+    const int *__restrict__ ci, const double *__restrict__ a, const double *__restrict__ z,
+    const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ q,
+    double *__restrict__ part, const double *__restrict__ scal)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double beta = scal[S_BETA];
+    double v[1] = {0.0};
+    if (i < n) {
+        double s = 0.0;
+        if constexpr (DIA) {
+            for (int o = 0; o < d.n; ++o) {
+                const int k = i + d.off[o];
+                const double av = ad[static_cast<int64_t>(o) * n + i];
+                double pk = 0.0;
+                if (k >= 0 && k < n) pk = beta == 0.0 ? z[k] : z[k] + beta * pold[k];
+                s += av * pk;
+            }
+        } else {
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                const int k = ci[e];
+                s += a[e] * (beta == 0.0 ? z[k] : z[k] + beta * pold[k]);
+            }
+        }
+        const double pi = beta == 0.0 ? z[i] : z[i] + beta * pold[i];
+        pnew[i] = pi;
+        q[i] = s;
+        v[0] = pi * s;
+    }
+    block_partials<1>(v, part);
+}
+
+// x += alpha p, r -= alpha q, and r.r
+__global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict__ x,
+                                                       double *__restrict__ r,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ q,
+                                                       double *__restrict__ part,
+                                                       const double *__restrict__ scal)
+{
+    const double alpha = scal[S_ALPHA];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < n) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v[0] = ri * ri;
+    }
+    block_partials<1>(v, part);
+}
+
+// z (+)= P w_c with P in row-major ELL layout; a row (PW columns and
+// values) is read with 16-byte loads
+template <typename T, int PW>
+__global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const int *__restrict__ pcol,
+                                                        const T *__restrict__ pv,
+                                                        const double *__restrict__ wc,
+                                                        double *__restrict__ z, int zero)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int col[PW];
+    T val[PW];
+    {
+        const uint4 *cs = reinterpret_cast<const uint4 *>(pcol + static_cast<int64_t>(i) * PW);
+        uint4 *cd = reinterpret_cast<uint4 *>(col);
+#pragma unroll
+        for (int q = 0; q < PW / 4; ++q) cd[q] = cs[q];
+        const uint4 *vs = reinterpret_cast<const uint4 *>(pv + static_cast<int64_t>(i) * PW);
+        uint4 *vd = reinterpret_cast<uint4 *>(val);
+#pragma unroll
+        for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) vd[q] = vs[q];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < PW; ++q)
+        if (col[q] >= 0) s += static_cast<double>(val[q]) * wc[col[q]];
+    z[i] = zero ? s : z[i] + s;
+}
+
+// generic width (rows wider than 8)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_ell_w(int n, int pw, const int *__restrict__ pcol,
+                                                          const T *__restrict__ pv,
+                                                          const double *__restrict__ wc,
+                                                          double *__restrict__ z, int zero)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int q = 0; q < pw; ++q) {
+        const int64_t e = static_cast<int64_t>(i) * pw + q;
+        const int c = pcol[e];
+        if (c < 0) break;
+        s += static_cast<double>(pv[e]) * wc[c];
+    }
+    z[i] = zero ? s : z[i] + s;
+}
+
+// CSR -> DIA values (slot of every CSR entry precomputed), padding zeroed
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_csr_to_dia(int n, int noff, const int *__restrict__ rp,
+                                                       const int8_t *__restrict__ slot,
+                                                       const double *__restrict__ a,
+                                                       T *__restrict__ ad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int o = 0; o < noff; ++o) ad[static_cast<int64_t>(o) * n + i] = T(0);
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        ad[static_cast<int64_t>(slot[e]) * n + i] = static_cast<T>(a[e]);
+}
+
+// flag[0] = 1 unless A_ij == A_ji for every stored entry (and the transposed
+// entry exists)
+__global__ __launch_bounds__(kBlock) void k_check_symmetric(int n, const int *__restrict__ rp,
+                                                            const int *__restrict__ ci,
+                                                            const double *__restrict__ a,
+                                                            int *__restrict__ flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        int lo = rp[j], hi = rp[j + 1] - 1, found = -1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] == i) {
+                found = mid;
+                break;
+            }
+            if (ci[mid] < i) lo = mid + 1; else hi = mid - 1;
+        }
+        if (found < 0 || a[found] != a[e]) flag[0] = 1;
+    }
+}
+
 }  // namespace
 
 void launch_spmv(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
@@ -371,15 +613,6 @@ void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool
         k_restrict<double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
 }
 
-void launch_prolong_add(hipStream_t s, int n, const int *prp, const int *pci, bool fp32,
-                        const double *p64, const float *p32, const double *wc, double *z)
-{
-    if (fp32)
-        k_prolong_add<float><<<grid_for(n), kBlock, 0, s>>>(n, prp, pci, p32, wc, z);
-    else
-        k_prolong_add<double><<<grid_for(n), kBlock, 0, s>>>(n, prp, pci, p64, wc, z);
-}
-
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
                 double *out)
 {
@@ -388,38 +621,8 @@ void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *
     finish(s, nb, partials, out);
 }
 
-void launch_dot2(hipStream_t s, int n, const double *r, const double *z, const double *zold,
-                 double *partials, double *out_rz, double *out_rzdiff)
-{
-    const int nb = std::min(kReduceBlocks, std::max(1, grid_for(n)));
-    k_dot2<<<nb, kBlock, 0, s>>>(n, r, z, zold, partials);
-    finish(s, nb, partials, out_rz);
-    finish(s, nb, partials + kReduceBlocks, out_rzdiff);
-}
 
-void launch_spmv_dot(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
-                     const double *p, double *q, double *partials, double *out_pq)
-{
-    const int nb = grid_for(n);
-    k_spmv_dot<<<nb, kBlock, 0, s>>>(n, rp, ci, a, p, q, partials);
-    finish(s, nb, partials, out_pq);
-}
 
-void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                      const double *q, const double *scal, double *partials, double *out_rr)
-{
-    const int nb = grid_for(n);
-    k_cg_update<<<nb, kBlock, 0, s>>>(n, x, r, p, q, scal, partials);
-    finish(s, nb, partials, out_rr);
-}
-
-void launch_cg_alpha(hipStream_t s, double *scal) { k_cg_alpha<<<1, 64, 0, s>>>(scal); }
-void launch_cg_beta(hipStream_t s, double *scal) { k_cg_beta<<<1, 64, 0, s>>>(scal); }
-
-void launch_p_update(hipStream_t s, int n, double *p, const double *z, const double *scal)
-{
-    k_p_update<<<grid_for(n), kBlock, 0, s>>>(n, p, z, scal);
-}
 
 void launch_copy(hipStream_t s, int n, const double *x, double *y)
 {
@@ -465,6 +668,113 @@ void launch_norm_scale(hipStream_t s, int n, const double *w, double *vout, doub
 {
     launch_dot(s, n, w, w, partials, out_norm2);
     k_scale_by_inv<<<grid_for(n), kBlock, 0, s>>>(n, w, out_norm2, vout);
+}
+
+void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,
+                     double *y)
+{
+    k_dia_spmv<<<grid_for(n), kBlock, 0, s>>>(n, d, a, x, y);
+}
+
+void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
+                         const double *f, const double *x, double *r)
+{
+    k_dia_residual<<<grid_for(n), kBlock, 0, s>>>(n, d, a, f, x, r);
+}
+
+void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
+                      const float *a32, const double *dinv64, const float *dinv32,
+                      const double *v, const double *zin, double *zout, bool zero2)
+{
+    if (zero2) {
+        if (fp32)
+            k_dia_sweep2_zero<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zout);
+        else
+            k_dia_sweep2_zero<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zout);
+        return;
+    }
+    if (fp32)
+        k_dia_sweep<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zin, zout);
+    else
+        k_dia_sweep<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zin, zout);
+}
+
+void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
+                           const double *a64, const float *a32, const double *dinv64,
+                           const float *dinv32, const double *r, const double *zin, double *zout,
+                           const double *zold, double *part, double *scal)
+{
+    if (fp32)
+        k_dia_sweep_dots<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, r, zin, zout,
+                                                               zold, part);
+    else
+        k_dia_sweep_dots<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, r, zin, zout,
+                                                                zold, part);
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+}
+
+void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, const double *zold,
+                      double *part, double *scal)
+{
+    k_dots_beta<<<grid_for(n), kBlock, 0, s>>>(n, r, z, zold, part);
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+}
+
+void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *ad,
+                       const int *rp, const int *ci, const double *a, const double *z,
+                       const double *pold, double *pnew, double *q, double *part, double *scal)
+{
+    if (d.n > 0)
+        k_pcg_p_spmv<true><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
+                                                          part, scal);
+    else
+        k_pcg_p_spmv<false><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
+                                                           part, scal);
+    k_fin_alpha<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+}
+
+void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
+                       const double *q, double *part, double *scal, double *host_out)
+{
+    k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, x, r, p, q, part, scal);
+    k_fin_rr<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, host_out);
+}
+
+template <typename T>
+void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const T *pv, const double *wc,
+               double *z, bool zero)
+{
+    if (pw == 4)
+        k_prolong_ell<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, pcol, pv, wc, z, zero ? 1 : 0);
+    else if (pw == 8)
+        k_prolong_ell<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, pcol, pv, wc, z, zero ? 1 : 0);
+    else
+        k_prolong_ell_w<T><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, pv, wc, z, zero ? 1 : 0);
+}
+
+void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
+                        const double *p64, const float *p32, const double *wc, double *z,
+                        bool zero)
+{
+    if (fp32)
+        prolong_t<float>(s, n, pw, pcol, p32, wc, z, zero);
+    else
+        prolong_t<double>(s, n, pw, pcol, p64, wc, z, zero);
+}
+
+void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,
+                       const double *a, double *ad64, float *ad32)
+{
+    if (ad32)
+        k_csr_to_dia<float><<<grid_for(n), kBlock, 0, s>>>(n, noff, rp, slot, a, ad32);
+    else
+        k_csr_to_dia<double><<<grid_for(n), kBlock, 0, s>>>(n, noff, rp, slot, a, ad64);
+}
+
+void launch_check_symmetric(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
+                            int *flag)
+{
+    k_check_symmetric<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, a, flag);
 }
 
 }  // namespace msrsb

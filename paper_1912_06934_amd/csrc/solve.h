@@ -5,10 +5,18 @@
 
 namespace msrsb {
 
+// Buffers for the r.z dot products and flexible beta computed at the end of
+// a preconditioner application inside PCG.
+struct PcgDots {
+    const double *zold;
+    double *part;
+    double *scal;
+};
+
 msrsb_status ensure_workspace(msrsb_ctx *c);
 msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans);
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
-                     bool trans);
+                     bool trans, const PcgDots *dots);
 msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
                  msrsb_solve_info *info, bool trans);
 msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,

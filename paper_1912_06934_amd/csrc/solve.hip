@@ -2,6 +2,7 @@
 // the flexible Polak-Ribiere beta, right-preconditioned restarted GMRES).
 // All vector arithmetic runs in device kernels; the host only queues work and
 // reads the residual norm to decide when to stop.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -16,9 +17,9 @@ inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlo
 __global__ void k_fill_u64(unsigned long long *p) { p[0] = 0ull; }
 
 // --- GMRES small dense algebra (single thread; m <= 64) ---
-// Apply the previous Givens rotations to the new Hessenberg column h (j+2
-// entries: h[0..j] from the Gram-Schmidt, h[j+1] = ||w||^2 in nrm2), form the
-// new rotation, update g and write |g[j+1]| to res.
+// Apply the previous Givens rotations to the new Hessenberg column (h[0..j]
+// from the Gram-Schmidt, ||w||^2 in nrm2), form the new rotation, update g
+// and write |g[j+1]| and the rotated diagonal to res.
 __global__ void k_gmres_givens(int j, int m, double *__restrict__ H, const double *__restrict__ h,
                                const double *__restrict__ nrm2, double *__restrict__ cs,
                                double *__restrict__ sn, double *__restrict__ g,
@@ -76,10 +77,15 @@ __global__ void k_vec_add(int k, double *__restrict__ a, const double *__restric
     if (t < k) a[t] += b[t];
 }
 
+// The fine operator (A, or A^T for the transposed solve) in its CSR and,
+// when available, DIA forms, with the diagonal inverses of its smoothers.
 struct Op {
     const int *rp, *ci;
     const double *a;
     const float *a32;
+    DiaOffsets d;
+    const double *ad;
+    const float *ad32;
     const double *dj, *dl1;
     const float *dj32, *dl132;
 };
@@ -92,6 +98,9 @@ Op fine_op(msrsb_ctx *c, bool trans)
         o.ci = c->ci;
         o.a = c->a;
         o.a32 = c->a32;
+        o.d = c->a_off;
+        o.ad = c->a_dia;
+        o.ad32 = c->a_dia32;
         o.dj = c->dinv_jac;
         o.dl1 = c->dinv_l1;
         o.dj32 = c->dinv_jac32;
@@ -101,12 +110,31 @@ Op fine_op(msrsb_ctx *c, bool trans)
         o.ci = c->at_ci;
         o.a = c->at;
         o.a32 = c->at32;
+        o.d = c->at_off;
+        o.ad = c->at_dia;
+        o.ad32 = c->at_dia32;
         o.dj = c->dinv_jac_t;
         o.dl1 = c->dinv_l1_t;
         o.dj32 = c->dinv_jac32_t;
         o.dl132 = c->dinv_l1_32_t;
     }
     return o;
+}
+
+void op_residual(hipStream_t s, int n, const Op &o, const double *f, const double *x, double *r)
+{
+    if (o.d.n > 0)
+        launch_dia_residual(s, n, o.d, o.ad, f, x, r);
+    else
+        launch_residual(s, n, o.rp, o.ci, o.a, f, x, r);
+}
+
+void op_spmv(hipStream_t s, int n, const Op &o, const double *x, double *y)
+{
+    if (o.d.n > 0)
+        launch_dia_spmv(s, n, o.d, o.ad, x, y);
+    else
+        launch_spmv(s, n, o.rp, o.ci, o.a, x, y);
 }
 
 template <typename T>
@@ -119,25 +147,31 @@ msrsb_status dev_alloc(T **p, size_t count)
     return MSRSB_OK;
 }
 
-// one smoothing sweep z += M^{-1} (v - A z); zero: z is known to be zero
-// (then it is not read).  The result may land in *spare, in which case the
-// two pointers are exchanged.
+bool is_diag(int kind) { return kind == MSRSB_SMOOTH_JACOBI || kind == MSRSB_SMOOTH_L1JACOBI; }
+
+// one smoothing sweep z += M^{-1} (v - A z); with zero, z is known to be zero
+// and is not read.  The result may land in *spare, in which case the two
+// pointers are exchanged.
 void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, double **z,
            double **spare, bool zero, double *tmp)
 {
     hipStream_t s = c->stream;
     const int n = c->n;
-    if (kind == MSRSB_SMOOTH_JACOBI || kind == MSRSB_SMOOTH_L1JACOBI) {
+    if (is_diag(kind)) {
         const bool l1 = kind == MSRSB_SMOOTH_L1JACOBI;
-        launch_sweep(s, n, o.rp, o.ci, o.a, o.a32, l1 ? o.dl1 : o.dj, l1 ? o.dl132 : o.dj32, fp32,
-                     v, *z, *spare, zero);
+        const double *d64 = l1 ? o.dl1 : o.dj;
+        const float *d32 = l1 ? o.dl132 : o.dj32;
+        if (o.d.n > 0 && !zero)
+            launch_dia_sweep(s, n, o.d, fp32, o.ad, o.ad32, d64, d32, v, *z, *spare, false);
+        else
+            launch_sweep(s, n, o.rp, o.ci, o.a, o.a32, d64, d32, fp32, v, *z, *spare, zero);
         std::swap(*z, *spare);
     } else if (kind == MSRSB_SMOOTH_ILU0) {
         if (zero) {
             launch_copy(s, n, v, tmp);
             launch_fill(s, n, *z, 0.0);
         } else {
-            launch_residual(s, n, o.rp, o.ci, o.a, v, *z, tmp);
+            op_residual(s, n, o, v, *z, tmp);
         }
         launch_ilu0_apply(c, tmp, *z, nullptr);
     }
@@ -150,7 +184,7 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
     const size_t n = static_cast<size_t>(c->n);
     for (auto &p : c->w)
         if (dev_alloc(&p, n)) return MSRSB_E_NOMEM;
-    const size_t np = std::max<size_t>({n / kBlock + 2, 2 * static_cast<size_t>(kReduceBlocks),
+    const size_t np = std::max<size_t>({2 * (n / kBlock + 2), 2 * static_cast<size_t>(kReduceBlocks),
                                         64 * static_cast<size_t>(std::max(c->nc, 1)) + 64,
                                         static_cast<size_t>(64 * 66)});
     if (dev_alloc(&c->partials, np) || dev_alloc(&c->scal, S_COUNT) ||
@@ -158,7 +192,7 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
         dev_alloc(&c->eit_bits, 1) || dev_alloc(&c->dev_flag, 4))
         return MSRSB_E_NOMEM;
     if (!c->h_pinned && hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(double),
-                                      hipHostMallocDefault) != hipSuccess)
+                                      hipHostMallocCoherent) != hipSuccess)
         return MSRSB_E_NOMEM;
     return MSRSB_OK;
 }
@@ -174,16 +208,19 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
     const bool fp32 = o->fp32_smoother != 0;
     const size_t n = static_cast<size_t>(c->n);
     hipStream_t s = c->stream;
+    const int noff = trans ? c->at_off.n : c->a_off.n;
     if (!trans) {
         if (!c->smoother_valid || (fp32 && !c->smoother32_valid)) {
             if (dev_alloc(&c->dinv_jac, n) || dev_alloc(&c->dinv_l1, n)) return MSRSB_E_NOMEM;
             if (fp32 && (dev_alloc(&c->dinv_jac32, n) || dev_alloc(&c->dinv_l1_32, n) ||
                          dev_alloc(&c->a32, static_cast<size_t>(c->nnz))))
                 return MSRSB_E_NOMEM;
-            hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+            if (fp32 && noff > 0 && dev_alloc(&c->a_dia32, n * noff)) return MSRSB_E_NOMEM;
             launch_diag_inverses(s, c->n, c->rp, c->ci, c->a, c->dinv_jac, c->dinv_l1,
                                  fp32 ? c->dinv_jac32 : nullptr, fp32 ? c->dinv_l1_32 : nullptr,
                                  fp32 ? c->a32 : nullptr, c->nnz, c->dev_flag);
+            if (fp32 && noff > 0)
+                launch_csr_to_dia(s, c->n, noff, c->rp, c->a_slot, c->a, nullptr, c->a_dia32);
             c->smoother_valid = true;
             c->smoother32_valid = fp32;
         }
@@ -193,11 +230,14 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
             if (fp32 && (dev_alloc(&c->dinv_jac32_t, n) || dev_alloc(&c->dinv_l1_32_t, n) ||
                          dev_alloc(&c->at32, static_cast<size_t>(c->nnz))))
                 return MSRSB_E_NOMEM;
-            hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+            if (fp32 && noff > 0 && dev_alloc(&c->at_dia32, n * noff)) return MSRSB_E_NOMEM;
             launch_diag_inverses(s, c->n, c->at_rp, c->at_ci, c->at, c->dinv_jac_t, c->dinv_l1_t,
                                  fp32 ? c->dinv_jac32_t : nullptr,
                                  fp32 ? c->dinv_l1_32_t : nullptr, fp32 ? c->at32 : nullptr,
                                  c->nnz, c->dev_flag);
+            if (fp32 && noff > 0)
+                launch_csr_to_dia(s, c->n, noff, c->at_rp, c->at_slot, c->at, nullptr,
+                                  c->at_dia32);
             c->smoother_t_valid = true;
             c->smoother32_t_valid = fp32;
         }
@@ -213,10 +253,12 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
 }
 
 // z = B v (Alg. 4): z = 0; pre-smoothing; z += P M_c^{-1} R (v - A z);
-// post-smoothing.  With trans the preconditioner of A^T is applied: A^T,
-// smoothers of A^T, pre and post exchanged, and A_c^{-T}.
+// post-smoothing.  With trans the preconditioner of A^T is applied: A^T, the
+// smoothers of A^T, pre and post exchanged, and A_c^{-T}.  With dots (inside
+// PCG) the products r.z and r.(z - zold) and the flexible beta are formed as
+// well, fused into the last sweep when possible.
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
-                     bool trans)
+                     bool trans, const PcgDots *dots)
 {
     hipStream_t s = c->stream;
     const int n = c->n;
@@ -232,24 +274,39 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     if (post_k == MSRSB_SMOOTH_NONE) post_n = 0;
     double *z = c->w[8], *spare = c->w[9], *tmp = c->w[10];
     bool zero = true;
-    for (int t = 0; t < pre_n; ++t) {
+    int t = 0;
+    if (pre_n >= 2 && is_diag(pre_k) && op.d.n > 0) {
+        const bool l1 = pre_k == MSRSB_SMOOTH_L1JACOBI;
+        launch_dia_sweep(s, n, op.d, fp32, op.ad, op.ad32, l1 ? op.dl1 : op.dj,
+                         l1 ? op.dl132 : op.dj32, v, nullptr, z, true);
+        zero = false;
+        t = 2;
+    }
+    for (; t < pre_n; ++t) {
         sweep(c, op, pre_k, fp32, v, &z, &spare, zero, tmp);
         zero = false;
     }
     if (o->use_multiscale) {
         const double *res = v;
         if (!zero) {
-            launch_residual(s, n, op.rp, op.ci, op.a, v, z, tmp);
+            op_residual(s, n, op, v, z, tmp);
             res = tmp;
         }
         launch_restrict(s, c->nc, c->rrp, c->rci, c->p_is32, c->r64, c->r32, res, c->vc);
         launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
-        if (zero) launch_fill(s, n, z, 0.0);
-        launch_prolong_add(s, n, c->prp, c->pci, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
-                           c->wc, z);
+        launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
+                           c->wc, z, zero);
         zero = false;
     }
-    for (int t = 0; t < post_n; ++t) {
+    for (t = 0; t < post_n; ++t) {
+        const bool last = t == post_n - 1;
+        if (last && dots && is_diag(post_k) && op.d.n > 0 && !zero) {
+            const bool l1 = post_k == MSRSB_SMOOTH_L1JACOBI;
+            launch_dia_sweep_dots(s, n, op.d, fp32, op.ad, op.ad32, l1 ? op.dl1 : op.dj,
+                                  l1 ? op.dl132 : op.dj32, v, z, zout, dots->zold,
+                                  dots->part, dots->scal);
+            return;
+        }
         sweep(c, op, post_k, fp32, v, &z, &spare, zero, tmp);
         zero = false;
     }
@@ -257,6 +314,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         launch_fill(s, n, zout, 0.0);
     else
         launch_copy(s, n, z, zout);
+    if (dots)
+        launch_dots_beta(s, n, v, zout, dots->zold, dots->part, dots->scal);
 }
 
 static msrsb_status read_scalars(msrsb_ctx *c, int first, int count)
@@ -267,15 +326,18 @@ static msrsb_status read_scalars(msrsb_ctx *c, int first, int count)
 }
 
 // Preconditioned CG with flexible beta.  f, x device pointers (x = x0 on entry).
+// Convergence of iteration k is read on the host while iteration k+1's
+// preconditioner is already queued, so the device never waits for the host.
 msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
                  msrsb_solve_info *info, bool trans)
 {
     hipStream_t s = c->stream;
     const int n = c->n;
     const Op op = fine_op(c, trans);
-    double *r = c->w[0], *z = c->w[1], *zold = c->w[2], *p = c->w[3], *q = c->w[4];
+    double *r = c->w[0], *z = c->w[1], *zold = c->w[2], *p = c->w[3], *q = c->w[4],
+           *p2 = c->w[7];
     double *sc = c->scal;
-    hipMemsetAsync(sc, 0, S_COUNT * sizeof(double), s);
+    launch_fill(s, S_COUNT, sc, 0.0);
     launch_dot(s, n, f, f, c->partials, sc + S_FF);
     if (read_scalars(c, S_FF, 1)) return MSRSB_E_HIP;
     double fn = std::sqrt(c->h_pinned[0]);
@@ -285,12 +347,14 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
     msrsb_status rc = MSRSB_E_NOT_CONVERGED;
     bool restart = true;
     hipEvent_t ev;
-    hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return MSRSB_E_HIP;
     double *hist = info ? info->history : nullptr;
     const int hcap = info ? info->history_cap : 0;
+    PcgDots dots{zold, c->partials, sc};
+    volatile double *hmon = c->h_pinned + 8;  // r.r and breakdown flag, written by the device
     while (it <= o->max_iter) {
         if (restart) {
-            launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+            op_residual(s, n, op, f, x, r);
             launch_dot(s, n, r, r, c->partials, sc + S_RR);
             if (read_scalars(c, S_RR, 1)) { rc = MSRSB_E_HIP; break; }
             const double rr = c->h_pinned[0];
@@ -298,26 +362,22 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             if (!std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }
             if (rr <= thr2) { rc = MSRSB_OK; break; }
             if (it == o->max_iter) break;
-            apply_two_stage(c, o, r, z, trans);
-            launch_copy(s, n, z, p);
+            apply_two_stage(c, o, r, z, trans, nullptr);
             launch_dot(s, n, r, z, c->partials, sc + S_RZ_OLD);
+            launch_fill(s, 1, sc + S_BETA, 0.0);  // p = z
             restart = false;
         }
-        launch_spmv_dot(s, n, op.rp, op.ci, op.a, p, q, c->partials, sc + S_PQ);
-        launch_cg_alpha(s, sc);
-        launch_cg_update(s, n, x, r, p, q, sc, c->partials, sc + S_RR);
+        launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
+        std::swap(p, p2);
+        launch_pcg_update(s, n, x, r, p, q, c->partials, sc, c->h_pinned + 8);
         ++it;
-        hipMemcpyAsync(c->h_pinned, sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(c->h_pinned + 1, sc + S_BREAK, sizeof(double), hipMemcpyDeviceToHost, s);
         hipEventRecord(ev, s);
         // queue the next preconditioner application while the host waits
         std::swap(z, zold);
-        apply_two_stage(c, o, r, z, trans);
-        launch_dot2(s, n, r, z, zold, c->partials, sc + S_RZ, sc + S_RZDIFF);
-        launch_cg_beta(s, sc);
-        launch_p_update(s, n, p, z, sc);
+        dots.zold = zold;
+        apply_two_stage(c, o, r, z, trans, &dots);
         if (hipEventSynchronize(ev) != hipSuccess) { rc = MSRSB_E_HIP; break; }
-        const double rr = c->h_pinned[0], brk = c->h_pinned[1];
+        const double rr = hmon[0], brk = hmon[1];
         if (hist && it < hcap) hist[it] = std::sqrt(rr) / fn;
         if (brk != 0.0 || !std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }
         if (rr <= thr2) { restart = true; continue; }
@@ -325,7 +385,7 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
     }
     hipEventDestroy(ev);
     // true residual at exit
-    launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+    op_residual(s, n, op, f, x, r);
     launch_dot(s, n, r, r, c->partials, sc + S_TMP0);
     if (read_scalars(c, S_TMP0, 1)) return MSRSB_E_HIP;
     if (info) {
@@ -367,7 +427,7 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
     double *hist = info ? info->history : nullptr;
     const int hcap = info ? info->history_cap : 0;
     for (;;) {
-        launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+        op_residual(s, n, op, f, x, r);
         launch_dot(s, n, r, r, c->partials, sc + S_RR);
         if (read_scalars(c, S_RR, 1)) return MSRSB_E_HIP;
         const double beta = std::sqrt(c->h_pinned[0]);
@@ -378,12 +438,12 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
         launch_norm_scale(s, n, r, V, c->partials, sc + S_RR);
         k_gmres_init_g<<<1, 64, 0, s>>>(m, g, sc + S_RR);
         int j = 0;
-        bool done = false, brk = false;
+        bool brk = false;
         for (j = 0; j < m && it < o->max_iter; ++j) {
             const double *vj = V + static_cast<int64_t>(j) * n;
             double *vn = V + static_cast<int64_t>(j + 1) * n;
-            apply_two_stage(c, o, vj, zt, trans);
-            launch_spmv(s, n, op.rp, op.ci, op.a, zt, w);
+            apply_two_stage(c, o, vj, zt, trans, nullptr);
+            op_spmv(s, n, op, zt, w);
             // CGS2: h = V^T w; w -= V h; h2 = V^T w; w -= V h2; h += h2
             launch_multi_dot(s, n, j + 1, V, n, w, c->partials, hc);
             launch_multi_axpy(s, n, j + 1, V, n, hc, w, -1.0);
@@ -398,19 +458,18 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
             const double res = c->h_pinned[0], den = c->h_pinned[1];
             if (hist && it < hcap) hist[it] = res / fn;
             if (!std::isfinite(res) || !(den > 0.0)) { brk = true; break; }
-            if (res <= o->rtol * fn) { done = true; ++j; break; }
+            if (res <= o->rtol * fn) { ++j; break; }
         }
         if (j > 0) {
             k_gmres_solve<<<1, 64, 0, s>>>(j, m, H, g, y);
             launch_fill(s, n, w, 0.0);
             launch_multi_axpy(s, n, j, V, n, y, w, 1.0);
-            apply_two_stage(c, o, w, zt, trans);
+            apply_two_stage(c, o, w, zt, trans, nullptr);
             launch_axpy(s, n, 1.0, zt, x);
         }
         if (brk) { rc = MSRSB_E_BREAKDOWN; break; }
-        (void)done;
     }
-    launch_residual(s, n, op.rp, op.ci, op.a, f, x, r);
+    op_residual(s, n, op, f, x, r);
     launch_dot(s, n, r, r, c->partials, sc + S_TMP0);
     if (read_scalars(c, S_TMP0, 1)) return MSRSB_E_HIP;
     const double tr = std::sqrt(c->h_pinned[0]) / fn;

@@ -192,3 +192,46 @@ def test_adjoint_gradient_matches_oracle(torch_cuda):
     lam = orc.solve(gp, rtol=1e-12, pre=(2, 2), post=(2, 2), transpose=True)["x"]
     g_ref = oracle.tpfa_grad(cfg["dims"], cfg["h"], cfg["logk"], cfg["bc"], pr, lam)
     assert np.max(np.abs(g - g_ref)) <= 1e-8 * np.max(np.abs(g_ref))
+
+
+def _nonsymmetric(cfg, seed=0, amount=0.06):
+    A = sp.csr_matrix((cfg["a"], cfg["ci"], cfg["rp"])).tolil()
+    rng = np.random.default_rng(seed)
+    n = A.shape[0]
+    nx = cfg["dims"][0]
+    for i in range(n - 1):
+        if (i + 1) % nx:
+            A[i, i + 1] += amount * A[i, i] * rng.uniform()
+    A = A.tocsr()
+    A.sort_indices()
+    cfg.update(rp=A.indptr.astype(np.int32), ci=A.indices.astype(np.int32), a=A.data)
+    return cfg
+
+
+@pytest.mark.parametrize("case", [("c1", (96, 96), 4), ("c5", (48, 48, 48), 4)],
+                         ids=["2d-576coarse", "3d-1728coarse"])
+def test_coarse_inverse_many_panels(torch_cuda, case):
+    # coarse problems spanning several 128-column super-panels of the
+    # band-limited Gauss-Jordan inverse
+    cfg = tpfa_inputs(*case)
+    orc = oracle_setup(cfg, kmax=20)
+    s, _, _ = gpu_setup_tpfa(cfg, kmax=20)
+    assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
+    v = np.random.default_rng(3).standard_normal(cfg["rp"].size - 1)
+    z_ref = orc.apply(v)
+    z = np.zeros_like(v)
+    s.apply(v, z)
+    assert rel_max(z, z_ref) <= 1e-10
+
+
+def test_coarse_inverse_pivoting_nonsymmetric(torch_cuda):
+    # a non-symmetric operator takes the partial-pivoting Gauss-Jordan path
+    cfg = _nonsymmetric(tpfa_inputs("c1", (64, 64), 4))
+    orc = oracle_setup(cfg, kmax=20)
+    s, _ = gpu_setup_matrix(cfg, kmax=20)
+    assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
+    v = np.random.default_rng(4).standard_normal(cfg["rp"].size - 1)
+    z_ref = orc.apply(v, post=(1, 1))
+    z = np.zeros_like(v)
+    s.apply(v, z, post=(1, 1))
+    assert rel_max(z, z_ref) <= 1e-10
