@@ -190,9 +190,15 @@ typedef struct {
 } msrsb_coarse_opts;
 
 /* Alg. 2: R = P^T, A_c = R A P with the unfiltered A (eq.
- * lin_system_coarse), and the coarse solver M_c^{-1} = A_c^{-1} computed
- * exactly in FP64 (Gauss-Jordan with partial pivoting).  Synchronises.
- * Errors: E_STATE before setup_basis; E_COARSE_SINGULAR on a zero pivot. */
+ * lin_system_coarse), and the coarse solver M_c^{-1} = A_c^{-1} formed
+ * explicitly in FP64 (applied as a dense product).  When A is symmetric
+ * A_c is symmetric positive definite for the SPD problems of the paper and
+ * the inverse comes from blocked Gauss-Jordan without pivoting, confined to
+ * A_c's band until the fill spreads; a non-positive pivot falls back to
+ * Gauss-Jordan with partial pivoting, which is also used for non-symmetric
+ * A.  Synchronises.
+ * Errors: E_STATE before setup_basis; E_COARSE_SINGULAR on a zero pivot
+ * (pivoting form). */
 msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);
 /* Copy A_c out as a dense row-major nc x nc FP64 matrix. */
 msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *ctx, double *dense, int where);
@@ -233,9 +239,13 @@ msrsb_status msrsb_solve(msrsb_ctx *ctx, const double *f, double *u,
                          const msrsb_solve_opts *opts, msrsb_solve_info *info,
                          int where);
 
-/* Solve A^T lambda = g with the transposed preconditioner
- * B^T (pre and post smoothers exchanged, P A_c^{-T} P^T), e.g. the adjoint
- * system of a gradient computation. */
+/* Solve A^T lambda = g, e.g. the adjoint system of a gradient computation.
+ * The preconditioner is the two-stage preconditioner of A^T: A^T in the
+ * residuals, the smoothers built from A^T with the pre and post sweeps
+ * exchanged, and the coarse correction P A_c^{-T} P^T (P, R and the coarse
+ * inverse are reused).  For symmetric A, and for point Jacobi on any A, this
+ * is exactly B^T.  ILU(0) is not available here (E_ARG).  Other arguments and
+ * errors as msrsb_solve. */
 msrsb_status msrsb_solve_transpose(msrsb_ctx *ctx, const double *g, double *lambda,
                                    const msrsb_solve_opts *opts, msrsb_solve_info *info,
                                    int where);

@@ -470,7 +470,7 @@ msrsb_status msrsb_create(msrsb_ctx **out, int device, void *hip_stream)
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard g(device);
-    if (!dalloc(c->dev_flag, 4) || !dalloc(c->eit_bits, 1) || !dalloc(c->scal, S_COUNT)) {
+    if (!dalloc(c->dev_flag, 4) || !dalloc(c->eit_val, 1) || !dalloc(c->scal, S_COUNT)) {
         delete c;
         return MSRSB_E_NOMEM;
     }
@@ -491,7 +491,7 @@ void msrsb_destroy(msrsb_ctx *c)
     free_coarse(c);
     free_matrix(c);
     dfree(c->dev_flag);
-    dfree(c->eit_bits);
+    dfree(c->eit_val);
     dfree(c->scal);
     if (c->h_pinned) hipHostFree(c->h_pinned);
     for (int p = 0; p < MSRSB_N_PHASES; ++p)
@@ -834,14 +834,14 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     double e_last = -1.0;
     for (it = 0; it < o->max_iter; ++it) {
         const bool check = (it % o->check_every) == 0;
-        if (check) fill_u64_zero(s, c->eit_bits);
-        sa.eit = check ? c->eit_bits : nullptr;
+        sa.eit_part = check ? c->partials : nullptr;
+        sa.eit_out = c->eit_val;
         const int src = c->pcur, dst = 1 - c->pcur;
         launch_smooth(s, sa, fp32, c->jv, c->jv32, c->p64[src], c->p64[dst], c->p32[src],
                       c->p32[dst]);
         c->pcur = dst;
         if (check && o->tol >= 0.0) {
-            hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
+            hipMemcpyAsync(c->h_pinned, c->eit_val, sizeof(double), hipMemcpyDeviceToHost, s);
             if (hipStreamSynchronize(s) != hipSuccess)
                 return fail(c, MSRSB_E_HIP, "smoothing failed on the device");
             e_last = c->h_pinned[0];
@@ -853,7 +853,7 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     }
     phase_end(c, MSRSB_PHASE_SMOOTH);
     // last computed e_it, and P's statistics
-    hipMemcpyAsync(c->h_pinned, c->eit_bits, sizeof(double), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(c->h_pinned, c->eit_val, sizeof(double), hipMemcpyDeviceToHost, s);
     launch_basis_stats(s, c->n, c->pw, c->pcol_ell, fp32, c->p64[c->pcur], c->p32[c->pcur],
                        c->partials, c->scal + S_TMP0);
     hipMemcpyAsync(c->h_pinned + 1, c->scal + S_TMP0, 3 * sizeof(double), hipMemcpyDeviceToHost,

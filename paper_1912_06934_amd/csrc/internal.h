@@ -159,7 +159,7 @@ struct msrsb_ctx {
     double *gm_v = nullptr, *gm_h = nullptr;  // GMRES basis and small arrays
     int gm_cap = 0;
     double *h_pinned = nullptr;
-    unsigned long long *eit_bits = nullptr;
+    double *eit_val = nullptr;  // last e_it (device)
 
     // TPFA assembly description (set by msrsb_assemble_tpfa)
     bool tpfa = false;
@@ -175,6 +175,20 @@ struct msrsb_ctx {
 namespace msrsb {
 
 // ---- basis kernels (k_basis.hip) ----
+// Work-groups are dispatched to the eight XCDs in turn (group b to XCD b % 8)
+// and every XCD has its own L2.  Renumbering the groups so that each XCD walks
+// one contiguous range of rows keeps a stencil's neighbour rows (i +- nx,
+// i +- nx ny) in the L2 that already loaded them.
+__device__ __forceinline__ int xcd_group(int b, int g)
+{
+    const int q = g >> 3, r = g & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+__device__ __forceinline__ int xcd_row()
+{
+    return xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 struct SmoothArgs {
     int n = 0, pw = 0, jw = 0;
     DiaOffsets joff;
@@ -185,7 +199,8 @@ struct SmoothArgs {
     const uint32_t *jmap_tab = nullptr;
     int jmap_ntab = 0;
     const uint8_t *interior = nullptr;
-    unsigned long long *eit = nullptr;  // null: e_it not computed this iteration
+    double *eit_part = nullptr;  // per-work-group maxima; null: no e_it this iteration
+    double *eit_out = nullptr;   // e_it (one double)
 };
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,

@@ -27,11 +27,37 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
-__device__ inline void eit_reduce(double emax, unsigned long long *eit_bits)
+__device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// The work-group's max of the row deltas goes to part[blockIdx.x]; a
+// one-block kernel reduces the partials (no contended atomics).
+__device__ inline void eit_block(double emax, double *__restrict__ part)
 {
+    __shared__ double sh[kBlock / 64];
     emax = wave_max(emax);
-    if ((threadIdx.x & 63) == 0 && emax != 0.0)
-        atomicMax(eit_bits, static_cast<unsigned long long>(__double_as_longlong(emax)));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = emax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int w = 1; w < static_cast<int>(blockDim.x) / 64; ++w) m = nan_max(m, sh[w]);
+        part[blockIdx.x] = m;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_eit_final(int nb, const double *__restrict__ part,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sh[16];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024) m = nan_max(m, part[b]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int w = 1; w < 16; ++w) r = nan_max(r, sh[w]);
+        out[0] = r;
+    }
 }
 
 // Filter (eq. negoffdiag) and zero-row-sum diagonal (eq. Dhat_zero_rowsum):
@@ -112,71 +138,185 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(int n, int pw, const int 
 //
 // Each neighbour row of P is read whole with 16-byte loads and the needed
 // slot is selected in registers.
+// A row is moved as 16-byte vectors whose lanes are unpacked into (or packed
+// from) a register array; the array itself is never addressed as memory.
 template <typename T, int PW>
 __device__ inline void load_row(const T *__restrict__ p, int64_t row, T (&v)[PW])
 {
-    static_assert((PW * sizeof(T)) % 16 == 0, "rows are read in 16-byte pieces");
-    const uint4 *src = reinterpret_cast<const uint4 *>(p + row * PW);
-    uint4 *dst = reinterpret_cast<uint4 *>(v);
+    constexpr int L = 16 / sizeof(T);
+    static_assert(PW % L == 0, "rows are read in 16-byte pieces");
+    typedef T vec __attribute__((ext_vector_type(L)));
+    const vec *src = reinterpret_cast<const vec *>(p + row * PW);
 #pragma unroll
-    for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) dst[q] = src[q];
+    for (int q = 0; q < PW / L; ++q) {
+        const vec x = src[q];
+#pragma unroll
+        for (int j = 0; j < L; ++j) v[q * L + j] = x[j];
+    }
 }
 
 template <typename T, int PW>
 __device__ inline void store_row(T *__restrict__ p, int64_t row, const T (&v)[PW])
 {
-    uint4 *dst = reinterpret_cast<uint4 *>(p + row * PW);
-    const uint4 *src = reinterpret_cast<const uint4 *>(v);
+    constexpr int L = 16 / sizeof(T);
+    typedef T vec __attribute__((ext_vector_type(L)));
+    vec *dst = reinterpret_cast<vec *>(p + row * PW);
 #pragma unroll
-    for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) dst[q] = src[q];
+    for (int q = 0; q < PW / L; ++q) {
+        vec x;
+#pragma unroll
+        for (int j = 0; j < L; ++j) x[j] = v[q * L + j];
+        dst[q] = x;
+    }
 }
 
+// v[src] for src < PW by a select tree on the bits of src
 template <typename T, int PW>
 __device__ inline T pick(const T (&v)[PW], uint32_t src)
 {
-    T r = T(0);
-#pragma unroll
-    for (int q = 0; q < PW; ++q) r = (src == static_cast<uint32_t>(q)) ? v[q] : r;
-    return r;
+    static_assert(PW == 4 || PW == 8, "slot maps cover 4 or 8 slots");
+    const bool b0 = src & 1u, b1 = src & 2u;
+    const T a0 = b0 ? v[1] : v[0], a1 = b0 ? v[3] : v[2];
+    const T lo = b1 ? a1 : a0;
+    if constexpr (PW == 4) {
+        return lo;
+    } else {
+        const T a2 = b0 ? v[5] : v[4], a3 = b0 ? v[7] : v[6];
+        const T hi = b1 ? a3 : a2;
+        return (src & 4u) ? hi : lo;
+    }
 }
 
-template <typename T, typename IDX, int PW>
+// Map of J entry e: a one-byte index into the LDS table, a two-byte index
+// into the global table, or the map itself.
+template <typename IDX>
+__device__ __forceinline__ uint32_t map_of(const IDX *__restrict__ jmap, int64_t e,
+                                           const uint32_t *stab, const uint32_t *__restrict__ tab)
+{
+    if constexpr (sizeof(IDX) == 1)
+        return stab[jmap[e]];
+    else if constexpr (sizeof(IDX) == 2)
+        return tab[jmap[e]];
+    else
+        return static_cast<uint32_t>(jmap[e]);
+}
+
+// acc += w * (row v permuted by map m); absent slots (nibble 0xF) add zero
+template <typename T, int PW>
+__device__ __forceinline__ void accumulate(T (&acc)[PW], uint32_t m, T w, const T (&v)[PW])
+{
+#pragma unroll
+    for (int s = 0; s < PW; ++s) {
+        const uint32_t src = (m >> (4 * s)) & 0xFu;
+        acc[s] += ((src & 8u) ? T(0) : w) * pick<T, PW>(v, src);
+    }
+}
+
+// The same when the map is diagonal (every slot reads its own slot or
+// nothing), as for neighbours with the same support pattern: no selects.
+template <typename T, int PW>
+__device__ __forceinline__ void accumulate_diag(T (&acc)[PW], uint32_t m, T w, const T (&v)[PW])
+{
+#pragma unroll
+    for (int s = 0; s < PW; ++s) acc[s] += (((m >> (4 * s)) & 8u) ? T(0) : w) * v[s];
+}
+
+__host__ __device__ inline bool map_is_diag(uint32_t m)
+{
+    for (int s = 0; s < 8; ++s) {
+        const uint32_t src = (m >> (4 * s)) & 0xFu;
+        if (src != static_cast<uint32_t>(s) && src != 0xFu) return false;
+    }
+    return true;
+}
+
+// JW > 0: J has exactly JW slots per row, known at compile time, and the
+// neighbours are taken in chunks whose map indices, weights and rows are all
+// loaded before any is used (one wavefront keeps a whole chunk in flight).
+// JW == 0: any slot count, one neighbour at a time.
+template <typename T, typename IDX, int PW, int JW>
 __global__ __launch_bounds__(kBlock) void k_smooth_map(
     int n, int jw, DiaOffsets joff, const int *__restrict__ jcol, const T *__restrict__ jv,
     const IDX *__restrict__ jmap, const uint32_t *__restrict__ tab, int ntab,
     const T *__restrict__ pin, T *__restrict__ pout, const uint8_t *__restrict__ interior,
-    unsigned long long *__restrict__ eit_bits)
+    double *__restrict__ eit_part)
 {
-    // a one-byte map index selects from a table of at most 256 maps kept in LDS
+    // a one-byte map index selects from a table of at most 256 maps kept in
+    // LDS; the sign bit of sdiag marks diagonal maps
     __shared__ uint32_t stab[256];
+    __shared__ uint8_t sdiag[256];
     if constexpr (sizeof(IDX) == 1) {
-        for (int t = threadIdx.x; t < ntab; t += blockDim.x) stab[t] = tab[t];
+        for (int t = threadIdx.x; t < ntab; t += blockDim.x) {
+            const uint32_t m = tab[t];
+            stab[t] = m;
+            sdiag[t] = map_is_diag(m) ? 1 : 0;
+        }
         __syncthreads();
     }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     double emax = 0.0;
     if (i < n) {
         T acc[PW];
 #pragma unroll
         for (int s = 0; s < PW; ++s) acc[s] = T(0);
-        for (int o = 0; o < jw; ++o) {
-            const int64_t e = static_cast<int64_t>(o) * n + i;
-            uint32_t m;
-            if constexpr (sizeof(IDX) == 1)
-                m = stab[jmap[e]];
-            else if constexpr (sizeof(IDX) == 2)
-                m = tab[jmap[e]];
-            else
-                m = static_cast<uint32_t>(jmap[e]);
-            if (m == 0xFFFFFFFFu) continue;
-            const T w = jv[e];
-            const int k = jcol ? jcol[e] : i + joff.off[o];
-            T v[PW];
-            load_row<T, PW>(pin, k, v);
+        if constexpr (JW > 0) {
+            static_assert(sizeof(IDX) == 1, "fixed slot counts use the LDS map table");
+            // chunk: up to 9 FP32 rows or 4 FP64 rows in registers at once
+            constexpr int CMAX = sizeof(T) == 8 ? 4 : 9;
+            constexpr int CH = JW <= CMAX ? JW : CMAX;
+#pragma nounroll
+            for (int o0 = 0; o0 < JW; o0 += CH) {
+                uint32_t m[CH];
+                T w[CH];
+                int k[CH];
+                bool dg[CH];
 #pragma unroll
-            for (int s = 0; s < PW; ++s) {
-                const uint32_t src = (m >> (4 * s)) & 0xFu;
-                if (src != 0xFu) acc[s] += w * pick<T, PW>(v, src);
+                for (int u = 0; u < CH; ++u) {
+                    if (o0 + u >= JW) continue;
+                    const int64_t e = static_cast<int64_t>(o0 + u) * n + i;
+                    const int t = jmap[e];
+                    m[u] = stab[t];
+                    dg[u] = sdiag[t] != 0;
+                    w[u] = jv[e];
+                }
+                if (jcol) {
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+                        if (o0 + u < JW) k[u] = jcol[static_cast<int64_t>(o0 + u) * n + i];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+                        if (o0 + u < JW) k[u] = i + joff.off[o0 + u];
+                }
+                // an absent entry may point outside the matrix: read row i
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (o0 + u < JW && m[u] == 0xFFFFFFFFu) k[u] = i;
+                T v[CH][PW];
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (o0 + u < JW) load_row<T, PW>(pin, k[u], v[u]);
+                // a neighbour whose map is diagonal on every lane of the
+                // wavefront (same support pattern) skips the slot selects
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    if (o0 + u >= JW) continue;
+                    if (__all(dg[u]))
+                        accumulate_diag<T, PW>(acc, m[u], w[u], v[u]);
+                    else
+                        accumulate<T, PW>(acc, m[u], w[u], v[u]);
+                }
+            }
+        } else {
+            for (int o = 0; o < jw; ++o) {
+                const int64_t e = static_cast<int64_t>(o) * n + i;
+                const uint32_t m = map_of(jmap, e, stab, tab);
+                if (m == 0xFFFFFFFFu) continue;
+                const T w = jv[e];
+                const int k = jcol ? jcol[e] : i + joff.off[o];
+                T v[PW];
+                load_row<T, PW>(pin, k, v);
+                accumulate<T, PW>(acc, m, w, v);
             }
         }
         double rs = 0.0;
@@ -184,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         for (int s = 0; s < PW; ++s) rs += static_cast<double>(acc[s]);
         T old[PW], out[PW];
         load_row<T, PW>(pin, i, old);
-        const bool inner = eit_bits != nullptr && interior[i] != 0;
+        const bool inner = eit_part != nullptr && interior[i] != 0;
 #pragma unroll
         for (int s = 0; s < PW; ++s) {
             if (inner) {
@@ -195,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         }
         store_row<T, PW>(pout, i, out);
     }
-    if (eit_bits != nullptr) eit_reduce(emax, eit_bits);
+    if (eit_part != nullptr) eit_block(emax, eit_part);
 }
 
 // Fallback for rows wider than the slot maps allow: row i's pattern (W
@@ -205,9 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth_cmp(
     int n, int pw, int jw, DiaOffsets joff, const int *__restrict__ jcol,
     const T *__restrict__ jv, const int *__restrict__ pcol, const T *__restrict__ pin,
     T *__restrict__ pout, const uint8_t *__restrict__ interior,
-    unsigned long long *__restrict__ eit_bits)
+    double *__restrict__ eit_part)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     double emax = 0.0;
     if (i < n) {
         int col[W];
@@ -234,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_cmp(
         double rs = 0.0;
 #pragma unroll
         for (int s = 0; s < W; ++s) rs += static_cast<double>(acc[s]);
-        const bool inner = eit_bits != nullptr && interior[i] != 0;
+        const bool inner = eit_part != nullptr && interior[i] != 0;
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             if (s < pw) {
@@ -248,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_cmp(
             }
         }
     }
-    if (eit_bits != nullptr) eit_reduce(emax, eit_bits);
+    if (eit_part != nullptr) eit_block(emax, eit_part);
 }
 
 // Partial statistics of P: max |row sum - 1|, min and max entry (padding
@@ -374,18 +514,39 @@ __global__ __launch_bounds__(kBlock) void k_build_maps(int n, int pw, int jw, Di
 
 inline int grid_n(int n) { return grid_for(n); }
 
+template <typename T, typename IDX, int PW, int JW>
+void smooth_map_launch(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
+{
+    k_smooth_map<T, IDX, PW, JW><<<grid_n(a.n), kBlock, 0, s>>>(
+        a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx), a.jmap_tab,
+        a.jmap_ntab, pin, pout, a.interior, a.eit_part);
+}
+
+template <typename T, typename IDX, int PW>
+void smooth_map_pw(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
+{
+    if constexpr (sizeof(IDX) == 1) {
+        // the slot counts of 1D, 2D and 3D stencils and of the 27-point
+        // same-component pattern of trilinear elements
+        switch (a.jw) {
+        case 3: smooth_map_launch<T, IDX, PW, 3>(s, a, jv, pin, pout); return;
+        case 5: smooth_map_launch<T, IDX, PW, 5>(s, a, jv, pin, pout); return;
+        case 7: smooth_map_launch<T, IDX, PW, 7>(s, a, jv, pin, pout); return;
+        case 9: smooth_map_launch<T, IDX, PW, 9>(s, a, jv, pin, pout); return;
+        case 27: smooth_map_launch<T, IDX, PW, 27>(s, a, jv, pin, pout); return;
+        default: break;
+        }
+    }
+    smooth_map_launch<T, IDX, PW, 0>(s, a, jv, pin, pout);
+}
+
 template <typename T, typename IDX>
 void smooth_map_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
 {
-    const IDX *idx = static_cast<const IDX *>(a.jmap_idx);
     if (a.pw <= 4)
-        k_smooth_map<T, IDX, 4><<<grid_n(a.n), kBlock, 0, s>>>(
-            a.n, a.jw, a.joff, a.jcol, jv, idx, a.jmap_tab, a.jmap_ntab, pin, pout, a.interior,
-            a.eit);
+        smooth_map_pw<T, IDX, 4>(s, a, jv, pin, pout);
     else
-        k_smooth_map<T, IDX, 8><<<grid_n(a.n), kBlock, 0, s>>>(
-            a.n, a.jw, a.joff, a.jcol, jv, idx, a.jmap_tab, a.jmap_ntab, pin, pout, a.interior,
-            a.eit);
+        smooth_map_pw<T, IDX, 8>(s, a, jv, pin, pout);
 }
 
 template <typename T>
@@ -399,13 +560,13 @@ void smooth_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *
     }
     if (a.pw <= 8)
         k_smooth_cmp<T, 8><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
-                                                          a.pcol, pin, pout, a.interior, a.eit);
+                                                          a.pcol, pin, pout, a.interior, a.eit_part);
     else if (a.pw <= 16)
         k_smooth_cmp<T, 16><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
-                                                           a.pcol, pin, pout, a.interior, a.eit);
+                                                           a.pcol, pin, pout, a.interior, a.eit_part);
     else
         k_smooth_cmp<T, 32><<<grid_n(a.n), kBlock, 0, s>>>(a.n, a.pw, a.jw, a.joff, a.jcol, jv,
-                                                           a.pcol, pin, pout, a.interior, a.eit);
+                                                           a.pcol, pin, pout, a.interior, a.eit_part);
 }
 
 }  // namespace
@@ -439,6 +600,7 @@ void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *
         smooth_t<float>(s, a, jv32, pin32, pout32);
     else
         smooth_t<double>(s, a, jv64, pin64, pout64);
+    if (a.eit_part) k_eit_final<<<1, 1024, 0, s>>>(grid_n(a.n), a.eit_part, a.eit_out);
 }
 
 void launch_basis_stats(hipStream_t s, int n, int pw, const int *pcol, bool fp32,

@@ -3,6 +3,8 @@
 // of PCG and GMRES.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace msrsb {
 namespace {
 
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int *__restrict__ 
                                                  const double *__restrict__ x,
                                                  double *__restrict__ y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i < n) y[i] = row_dot(i, rp, ci, a, x);
 }
 
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(int n, const int *__restric
                                                      const double *__restrict__ x,
                                                      double *__restrict__ r)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i < n) r[i] = f[i] - row_dot(i, rp, ci, a, x);
 }
 
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep64(int n, const int *__restrict
                                                     const double *__restrict__ zin,
                                                     double *__restrict__ zout, int zero_start)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i >= n) return;
     if (zero_start) {
         zout[i] = dinv[i] * v[i];
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
                                                     const double *__restrict__ zin,
                                                     double *__restrict__ zout, int zero_start)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i >= n) return;
     if (zero_start) {
         zout[i] = static_cast<double>(dinv[i] * static_cast<float>(v[i]));
@@ -116,8 +118,24 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restri
 {
     const int j = blockIdx.x;
     double s = 0.0;
-    for (int t = rrp[j] + threadIdx.x; t < rrp[j + 1]; t += kBlock)
-        s += static_cast<double>(rv[t]) * x[rci[t]];
+    const int t1 = rrp[j + 1];
+    int t = rrp[j] + threadIdx.x;
+    // four entries per step: their indices, values and gathers in flight together
+    for (; t + 3 * kBlock < t1; t += 4 * kBlock) {
+        int c[4];
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = rci[t + u * kBlock];
+            v[u] = rv[t + u * kBlock];
+        }
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += static_cast<double>(v[u]) * xv[u];
+    }
+    for (; t < t1; t += kBlock) s += static_cast<double>(rv[t]) * x[rci[t]];
     s = block_sum(s);
     if (threadIdx.x == 0) xc[j] = s;
 }
@@ -234,18 +252,37 @@ __global__ __launch_bounds__(kBlock) void k_scale_by_inv(int n, const double *__
 
 // ---------------------------------------------------------------------------
 // DIA kernels: A stored as [noff][n] values on fixed column offsets; entries
-// a row does not have are zero.  Out-of-range neighbours are never loaded.
+// a row does not have are zero.  The kernels are instantiated for the
+// diagonal counts of common stencils (ND > 0, a compile-time constant) so
+// that all loads of a row are issued before the first product; ND == 0 takes
+// the count at run time.  A neighbour outside [0, n) reads row i instead and
+// the value is then replaced by zero.
 // ---------------------------------------------------------------------------
-template <typename MT>
-__device__ inline MT dia_dot(int i, int n, const DiaOffsets &d, const MT *__restrict__ a,
-                             const double *__restrict__ x)
+template <int ND, typename MT>
+__device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
+                                      const MT *__restrict__ a, const double *__restrict__ x)
 {
     MT s = MT(0);
-    for (int o = 0; o < d.n; ++o) {
-        const int k = i + d.off[o];
-        const MT av = a[static_cast<int64_t>(o) * n + i];
-        const double xv = (k >= 0 && k < n) ? x[k] : 0.0;
-        s += av * static_cast<MT>(xv);
+    if constexpr (ND > 0) {
+        MT av[ND];
+        double xv[ND];
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            const int k = i + d.off[o];
+            const bool in = k >= 0 && k < n;
+            av[o] = a[static_cast<int64_t>(o) * n + i];
+            const double t = x[in ? k : i];
+            xv[o] = in ? t : 0.0;
+        }
+#pragma unroll
+        for (int o = 0; o < ND; ++o) s += av[o] * static_cast<MT>(xv[o]);
+    } else {
+        for (int o = 0; o < d.n; ++o) {
+            const int k = i + d.off[o];
+            const MT av = a[static_cast<int64_t>(o) * n + i];
+            const double xv = (k >= 0 && k < n) ? x[k] : 0.0;
+            s += av * static_cast<MT>(xv);
+        }
     }
     return s;
 }
@@ -288,6 +325,7 @@ __device__ inline void sum_partials_block(int nb, const double *__restrict__ par
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         double x = 0.0;
+#pragma unroll 8
         for (int b = threadIdx.x; b < nb; b += kFinThreads) x += part[static_cast<int64_t>(q) * nb + b];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -345,57 +383,80 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *
     scal[S_RZ_OLD] = t[0];
 }
 
+template <int ND>
 __global__ __launch_bounds__(kBlock) void k_dia_spmv(int n, DiaOffsets d,
                                                      const double *__restrict__ a,
                                                      const double *__restrict__ x,
                                                      double *__restrict__ y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = dia_dot(i, n, d, a, x);
+    const int i = xcd_row();
+    if (i < n) y[i] = dia_dot<ND>(i, n, d, a, x);
 }
 
+template <int ND>
 __global__ __launch_bounds__(kBlock) void k_dia_residual(int n, DiaOffsets d,
                                                          const double *__restrict__ a,
                                                          const double *__restrict__ f,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ r)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) r[i] = f[i] - dia_dot(i, n, d, a, x);
+    const int i = xcd_row();
+    if (i < n) r[i] = f[i] - dia_dot<ND>(i, n, d, a, x);
 }
 
 // z_out = z_in + dinv (v - A z_in), smoother matrix and arithmetic in MT
-template <typename MT>
+template <int ND, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep(int n, DiaOffsets d, const MT *__restrict__ a,
                                                       const MT *__restrict__ dinv,
                                                       const double *__restrict__ v,
                                                       const double *__restrict__ zin,
                                                       double *__restrict__ zout)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i >= n) return;
-    const MT res = static_cast<MT>(v[i]) - dia_dot(i, n, d, a, zin);
+    const MT res = static_cast<MT>(v[i]) - dia_dot<ND>(i, n, d, a, zin);
     zout[i] = zin[i] + static_cast<double>(dinv[i] * res);
 }
 
 // two sweeps from z = 0: z1 = dinv v, z2 = z1 + dinv (v - A z1), with z1 of
 // the neighbours recomputed on the fly
-template <typename MT>
+template <int ND, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
                                                             const MT *__restrict__ a,
                                                             const MT *__restrict__ dinv,
                                                             const double *__restrict__ v,
                                                             double *__restrict__ zout)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i >= n) return;
     MT s = MT(0);
-    for (int o = 0; o < d.n; ++o) {
-        const int k = i + d.off[o];
-        const MT av = a[static_cast<int64_t>(o) * n + i];
-        MT z1 = MT(0);
-        if (k >= 0 && k < n) z1 = static_cast<MT>(static_cast<double>(dinv[k] * static_cast<MT>(v[k])));
-        s += av * z1;
+    if constexpr (ND > 0) {
+        MT av[ND], dk[ND];
+        double vk[ND];
+        bool in[ND];
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            const int k = i + d.off[o];
+            in[o] = k >= 0 && k < n;
+            const int kk = in[o] ? k : i;
+            av[o] = a[static_cast<int64_t>(o) * n + i];
+            dk[o] = dinv[kk];
+            vk[o] = v[kk];
+        }
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            const MT z1 = static_cast<MT>(static_cast<double>(dk[o] * static_cast<MT>(vk[o])));
+            s += av[o] * (in[o] ? z1 : MT(0));
+        }
+    } else {
+        for (int o = 0; o < d.n; ++o) {
+            const int k = i + d.off[o];
+            const MT av = a[static_cast<int64_t>(o) * n + i];
+            MT z1 = MT(0);
+            if (k >= 0 && k < n)
+                z1 = static_cast<MT>(static_cast<double>(dinv[k] * static_cast<MT>(v[k])));
+            s += av * z1;
+        }
     }
     const double z1i = static_cast<double>(dinv[i] * static_cast<MT>(v[i]));
     zout[i] = z1i + static_cast<double>(dinv[i] * (static_cast<MT>(v[i]) - s));
@@ -403,16 +464,16 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
 
 // last smoothing sweep of the preconditioner inside PCG, fused with the dot
 // products r.z and r.(z - z_old) and the flexible beta
-template <typename MT>
+template <int ND, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep_dots(
     int n, DiaOffsets d, const MT *__restrict__ a, const MT *__restrict__ dinv,
     const double *__restrict__ r, const double *__restrict__ zin, double *__restrict__ zout,
     const double *__restrict__ zold, double *__restrict__ part)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     double v[2] = {0.0, 0.0};
     if (i < n) {
-        const MT res = static_cast<MT>(r[i]) - dia_dot(i, n, d, a, zin);
+        const MT res = static_cast<MT>(r[i]) - dia_dot<ND>(i, n, d, a, zin);
         const double z = zin[i] + static_cast<double>(dinv[i] * res);
         zout[i] = z;
         v[0] = r[i] * z;
@@ -437,34 +498,65 @@ __global__ __launch_bounds__(kBlock) void k_dots_beta(int n, const double *__res
     block_partials<2>(v, part);
 }
 
-// p_new = z + beta p_old, q = A p_new, p_new.q and alpha = (r.z) / (p.q)
-template <bool DIA>
+// p_new = z + beta p_old, q = A p_new, p_new.q and alpha = (r.z) / (p.q).
+// DIA: ND as in dia_dot; ND < 0 is the CSR form.  beta == 0 (a restart)
+// never reads p_old.
+template <int ND>
 __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
     int n, DiaOffsets d, const double *__restrict__ ad, const int *__restrict__ rp,
     const int *__restrict__ ci, const double *__restrict__ a, const double *__restrict__ z,
     const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ q,
     double *__restrict__ part, const double *__restrict__ scal)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     const double beta = scal[S_BETA];
+    const bool restart = beta == 0.0;
     double v[1] = {0.0};
     if (i < n) {
         double s = 0.0;
-        if constexpr (DIA) {
+        if constexpr (ND > 0) {
+            double av[ND], pk[ND];
+            bool in[ND];
+            int kk[ND];
+#pragma unroll
+            for (int o = 0; o < ND; ++o) {
+                const int k = i + d.off[o];
+                in[o] = k >= 0 && k < n;
+                kk[o] = in[o] ? k : i;
+                av[o] = ad[static_cast<int64_t>(o) * n + i];
+            }
+            if (restart) {
+#pragma unroll
+                for (int o = 0; o < ND; ++o) pk[o] = z[kk[o]];
+            } else {
+                double po[ND];
+#pragma unroll
+                for (int o = 0; o < ND; ++o) {
+                    pk[o] = z[kk[o]];
+                    po[o] = pold[kk[o]];
+                }
+                // keep all loads ahead of the arithmetic (one round trip)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int o = 0; o < ND; ++o) pk[o] += beta * po[o];
+            }
+#pragma unroll
+            for (int o = 0; o < ND; ++o) s += av[o] * (in[o] ? pk[o] : 0.0);
+        } else if constexpr (ND == 0) {
             for (int o = 0; o < d.n; ++o) {
                 const int k = i + d.off[o];
                 const double av = ad[static_cast<int64_t>(o) * n + i];
                 double pk = 0.0;
-                if (k >= 0 && k < n) pk = beta == 0.0 ? z[k] : z[k] + beta * pold[k];
+                if (k >= 0 && k < n) pk = restart ? z[k] : z[k] + beta * pold[k];
                 s += av * pk;
             }
         } else {
             for (int e = rp[i]; e < rp[i + 1]; ++e) {
                 const int k = ci[e];
-                s += a[e] * (beta == 0.0 ? z[k] : z[k] + beta * pold[k]);
+                s += a[e] * (restart ? z[k] : z[k] + beta * pold[k]);
             }
         }
-        const double pi = beta == 0.0 ? z[i] : z[i] + beta * pold[i];
+        const double pi = restart ? z[i] : z[i] + beta * pold[i];
         pnew[i] = pi;
         q[i] = s;
         v[0] = pi * s;
@@ -505,19 +597,32 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const int *__rest
     int col[PW];
     T val[PW];
     {
-        const uint4 *cs = reinterpret_cast<const uint4 *>(pcol + static_cast<int64_t>(i) * PW);
-        uint4 *cd = reinterpret_cast<uint4 *>(col);
+        typedef int ivec __attribute__((ext_vector_type(4)));
+        constexpr int L = 16 / sizeof(T);
+        typedef T tvec __attribute__((ext_vector_type(L)));
+        const ivec *cs = reinterpret_cast<const ivec *>(pcol + static_cast<int64_t>(i) * PW);
+        const tvec *vs = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * PW);
 #pragma unroll
-        for (int q = 0; q < PW / 4; ++q) cd[q] = cs[q];
-        const uint4 *vs = reinterpret_cast<const uint4 *>(pv + static_cast<int64_t>(i) * PW);
-        uint4 *vd = reinterpret_cast<uint4 *>(val);
+        for (int q = 0; q < PW / 4; ++q) {
+            const ivec c = cs[q];
 #pragma unroll
-        for (int q = 0; q < static_cast<int>(PW * sizeof(T) / 16); ++q) vd[q] = vs[q];
+            for (int u = 0; u < 4; ++u) col[4 * q + u] = c[u];
+        }
+#pragma unroll
+        for (int q = 0; q < PW / L; ++q) {
+            const tvec v = vs[q];
+#pragma unroll
+            for (int u = 0; u < L; ++u) val[L * q + u] = v[u];
+        }
     }
+    // all gathers issued at once; padding slots (column -1) read entry 0 and
+    // contribute zero
+    double g[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) g[q] = wc[col[q] >= 0 ? col[q] : 0];
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < PW; ++q)
-        if (col[q] >= 0) s += static_cast<double>(val[q]) * wc[col[q]];
+    for (int q = 0; q < PW; ++q) s += col[q] >= 0 ? static_cast<double>(val[q]) * g[q] : 0.0;
     z[i] = zero ? s : z[i] + s;
 }
 
@@ -670,33 +775,58 @@ void launch_norm_scale(hipStream_t s, int n, const double *w, double *vout, doub
     k_scale_by_inv<<<grid_for(n), kBlock, 0, s>>>(n, w, out_norm2, vout);
 }
 
+// Calls f with std::integral_constant<int, ND>: the diagonal counts of 1D,
+// 2D and 3D point stencils and of the 9- and 27-point stencils get their own
+// instantiation, anything else the run-time form (ND = 0).
+template <typename F>
+void with_ndiag(int nd, F &&f)
+{
+    switch (nd) {
+    case 3: f(std::integral_constant<int, 3>{}); return;
+    case 5: f(std::integral_constant<int, 5>{}); return;
+    case 7: f(std::integral_constant<int, 7>{}); return;
+    case 9: f(std::integral_constant<int, 9>{}); return;
+    case 27: f(std::integral_constant<int, 27>{}); return;
+    default: f(std::integral_constant<int, 0>{}); return;
+    }
+}
+
 void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,
                      double *y)
 {
-    k_dia_spmv<<<grid_for(n), kBlock, 0, s>>>(n, d, a, x, y);
+    with_ndiag(d.n, [&](auto nd) {
+        k_dia_spmv<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(n, d, a, x, y);
+    });
 }
 
 void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
                          const double *f, const double *x, double *r)
 {
-    k_dia_residual<<<grid_for(n), kBlock, 0, s>>>(n, d, a, f, x, r);
+    with_ndiag(d.n, [&](auto nd) {
+        k_dia_residual<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(n, d, a, f, x, r);
+    });
 }
 
 void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
                       const float *a32, const double *dinv64, const float *dinv32,
                       const double *v, const double *zin, double *zout, bool zero2)
 {
-    if (zero2) {
-        if (fp32)
-            k_dia_sweep2_zero<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zout);
-        else
-            k_dia_sweep2_zero<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zout);
-        return;
-    }
-    if (fp32)
-        k_dia_sweep<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zin, zout);
-    else
-        k_dia_sweep<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zin, zout);
+    with_ndiag(d.n, [&](auto nd) {
+        constexpr int ND = decltype(nd)::value;
+        if (zero2) {
+            if (fp32)
+                k_dia_sweep2_zero<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v,
+                                                                            zout);
+            else
+                k_dia_sweep2_zero<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v,
+                                                                             zout);
+        } else if (fp32) {
+            k_dia_sweep<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zin, zout);
+        } else {
+            k_dia_sweep<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zin,
+                                                                   zout);
+        }
+    });
 }
 
 void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
@@ -704,12 +834,15 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                            const float *dinv32, const double *r, const double *zin, double *zout,
                            const double *zold, double *part, double *scal)
 {
-    if (fp32)
-        k_dia_sweep_dots<float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, r, zin, zout,
-                                                               zold, part);
-    else
-        k_dia_sweep_dots<double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, r, zin, zout,
-                                                                zold, part);
+    with_ndiag(d.n, [&](auto nd) {
+        constexpr int ND = decltype(nd)::value;
+        if (fp32)
+            k_dia_sweep_dots<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, r, zin,
+                                                                       zout, zold, part);
+        else
+            k_dia_sweep_dots<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, r, zin,
+                                                                        zout, zold, part);
+    });
     k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
 
@@ -725,11 +858,13 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
                        const double *pold, double *pnew, double *q, double *part, double *scal)
 {
     if (d.n > 0)
-        k_pcg_p_spmv<true><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
-                                                          part, scal);
+        with_ndiag(d.n, [&](auto nd) {
+            k_pcg_p_spmv<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, ad, rp, ci, a, z, pold, pnew, q, part, scal);
+        });
     else
-        k_pcg_p_spmv<false><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
-                                                           part, scal);
+        k_pcg_p_spmv<-1><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
+                                                        part, scal);
     k_fin_alpha<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
 

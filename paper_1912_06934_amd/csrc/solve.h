@@ -21,6 +21,5 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
                  msrsb_solve_info *info, bool trans);
 msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
                    msrsb_solve_info *info, bool trans);
-void fill_u64_zero(hipStream_t s, unsigned long long *p);
 
 }  // namespace msrsb

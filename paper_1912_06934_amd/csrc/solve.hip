@@ -14,8 +14,6 @@ namespace {
 
 inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
 
-__global__ void k_fill_u64(unsigned long long *p) { p[0] = 0ull; }
-
 // --- GMRES small dense algebra (single thread; m <= 64) ---
 // Apply the previous Givens rotations to the new Hessenberg column (h[0..j]
 // from the Gram-Schmidt, ||w||^2 in nrm2), form the new rotation, update g
@@ -189,7 +187,7 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
                                         static_cast<size_t>(64 * 66)});
     if (dev_alloc(&c->partials, np) || dev_alloc(&c->scal, S_COUNT) ||
         dev_alloc(&c->vc, std::max(c->nc, 1)) || dev_alloc(&c->wc, std::max(c->nc, 1)) ||
-        dev_alloc(&c->eit_bits, 1) || dev_alloc(&c->dev_flag, 4))
+        dev_alloc(&c->eit_val, 1) || dev_alloc(&c->dev_flag, 4))
         return MSRSB_E_NOMEM;
     if (!c->h_pinned && hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(double),
                                       hipHostMallocCoherent) != hipSuccess)
@@ -481,6 +479,5 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
     return rc;
 }
 
-void fill_u64_zero(hipStream_t s, unsigned long long *p) { k_fill_u64<<<1, 1, 0, s>>>(p); }
 
 }  // namespace msrsb
