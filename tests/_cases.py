@@ -13,6 +13,14 @@ def tpfa_inputs(name, dims=None, block=None, seed=None):
     return cfg
 
 
+def matrix_inputs(name, dims=None, block=None, seed=None):
+    """Workloads whose matrix is generated as CSR (MPFA-O, Q1 elasticity)."""
+    cfg = synth.make_config(name, dims=dims, block=block, seed=seed)
+    rp, ci, a = cfg["matrix"]
+    cfg.update(rp=rp, ci=ci, a=a, f=cfg["rhs"])
+    return cfg
+
+
 def oracle_setup(cfg, kmax=100, filt=True):
     m = oracle.Msrsb(cfg["rp"], cfg["ci"], cfg["a"], cfg.get("block_size", 1))
     s = cfg["supports"]
