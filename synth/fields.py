@@ -46,7 +46,9 @@ def gaussian_smoothed(dims, std_cells, rng, truncate=3.0):
     ker = np.exp(-0.5 * (t / std_cells) ** 2)
     ker /= ker.sum()
     for ax in range(g.ndim):
-        g = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="same"), ax, g)
+        # centred part of the full convolution (also for axes shorter than
+        # the kernel)
+        g = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="full")[r:r + v.size], ax, g)
     g = (g - g.mean()) / g.std()
     return g.ravel()
 

@@ -16,8 +16,8 @@ form the global boundary; every other cell is interior and counts in e_it.
 Vertex-centred (finite element).  Along an axis with N elements (N+1
 nodes), coarse vertex a sits at node v_a = a*b.  Its support is the open
 interval (v_{a-1}, v_{a+1}) with the ends extended past the domain.  The
-initial basis assigns node x to the nearest coarse vertex
-floor((2x + b) / (2b)) (ties to the higher vertex).  Nodes on a coarse
+initial basis assigns node x to the nearest coarse vertex (ties to the
+higher vertex; floor((2x + b) / (2b)) where the spacing is b).  Nodes on a coarse
 element face (x = v_a on some axis) are not interior.
 """
 import numpy as np
@@ -50,7 +50,11 @@ def _axis_vertices(N, b):
     hi = np.concatenate([verts[1:], [N + 1]])
     x = np.arange(N + 1)
     member = (x[:, None] > lo[None, :]) & (x[:, None] < hi[None, :])
-    part = np.clip((2 * x + b) // (2 * b), 0, M)
+    # nearest coarse vertex, ties to the higher one (equal to
+    # floor((2x + b) / 2b) where the spacing is b; also right for a shorter
+    # last coarse element)
+    dist = np.abs(x[:, None] - verts[None, :])
+    part = verts.size - 1 - np.argmin(dist[:, ::-1], axis=1)
     on_vert = np.isin(x, verts)
     return M + 1, member, part, on_vert
 

@@ -283,3 +283,49 @@ def test_mpfa_gmres_ilu0_solution(torch_cuda, case):
     i8 = s.solve(cfg["f"], u8, rtol=1e-8, max_iter=4000, **kw)
     assert abs(i8["iters"] - r8["iters"]) <= 2 + 0.05 * r8["iters"]
     assert i8["true_rel_res"] <= 1e-8
+
+
+# Q1 elasticity, 3 interleaved components, separate-displacement-component
+# filter, vertex-centred supports (ragged last coarse element on y and z)
+Q1_CASES = [("c3", (8, 8, 8), 4), ("c3", (12, 10, 9), 4), ("c3", (16, 16, 16), 8)]
+
+
+@pytest.mark.parametrize("case", Q1_CASES, ids=_id)
+def test_q1_sdc_basis_coarse_and_apply(torch_cuda, case):
+    cfg = matrix_inputs(*case)
+    orc = oracle_setup(cfg)
+    s, info = gpu_setup_matrix(cfg)
+    _, _, pv = s.get_prolongation()
+    assert rel_max(pv, orc.pv) <= 1e-12
+    assert 0.0 <= info["p_min"] and info["p_max"] <= 1.0
+    assert info["max_rowsum_err"] <= 8 * np.finfo(float).eps
+    assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
+    v = np.random.default_rng(5).standard_normal(cfg["rp"].size - 1)
+    z_ref = orc.apply(v, pre=(2, 2), post=(2, 2))
+    z = np.zeros_like(v)
+    s.apply(v, z, pre=(2, 2), post=(2, 2))
+    assert rel_max(z, z_ref) <= 1e-11
+
+
+@pytest.mark.parametrize("case", Q1_CASES, ids=_id)
+def test_q1_pcg_solution(torch_cuda, case):
+    cfg = matrix_inputs(*case)
+    orc = oracle_setup(cfg)
+    s, _ = gpu_setup_matrix(cfg)
+    kw = dict(pre=(2, 2), post=(2, 2))
+    ref = orc.solve(cfg["f"], rtol=1e-12, maxit=3000, **kw)
+    assert ref["status"] == 0
+    u = np.zeros(cfg["rp"].size - 1)
+    info = s.solve(cfg["f"], u, rtol=1e-12, max_iter=3000, **kw)
+    assert info["true_rel_res"] <= 1e-12
+    assert rel_max(u, ref["x"]) <= 1e-8
+    r8 = orc.solve(cfg["f"], rtol=1e-8, maxit=3000, **kw)
+    u8 = np.zeros_like(u)
+    i8 = s.solve(cfg["f"], u8, rtol=1e-8, max_iter=3000, **kw)
+    assert abs(i8["iters"] - r8["iters"]) <= 1
+    # the FP32 form (basis, smoother) solved to 1e-12 reaches the same u
+    s32, _ = gpu_setup_matrix(cfg, fp32_basis=True)
+    u32 = np.zeros_like(u)
+    i32 = s32.solve(cfg["f"], u32, rtol=1e-12, max_iter=3000, fp32_smoother=True, **kw)
+    assert i32["true_rel_res"] <= 1e-12
+    assert rel_max(u32, ref["x"]) <= 1e-8
