@@ -82,8 +82,8 @@ enum {
     MSRSB_PHASE_FACTOR = 4,      /* coarse factorisation (inverse of A_c) */
     MSRSB_PHASE_SOLVE = 5,       /* last msrsb_solve */
     MSRSB_PHASE_SOLVE_T = 6,     /* last msrsb_solve_transpose */
-    MSRSB_PHASE_GRAD = 7,        /* last msrsb_tpfa_adjoint_grad */
-    MSRSB_PHASE_ASSEMBLE = 8,    /* last msrsb_assemble_tpfa */
+    MSRSB_PHASE_GRAD = 7,        /* last adjoint gradient kernel */
+    MSRSB_PHASE_ASSEMBLE = 8,    /* last msrsb_assemble_tpfa / msrsb_assemble_q1 */
     MSRSB_PHASE_SMOOTHER_SETUP = 9, /* smoother data (diagonals, ILU(0)) */
     MSRSB_N_PHASES = 10
 };
@@ -260,6 +260,37 @@ msrsb_status msrsb_solve_transpose(msrsb_ctx *ctx, const double *g, double *lamb
  * msrsb_assemble_tpfa. */
 msrsb_status msrsb_tpfa_adjoint_grad(msrsb_ctx *ctx, const double *log_k, const double *p,
                                      const double *lambda, double *grad, int where);
+
+/* Q1 (bi/trilinear) finite element linear elasticity (App. "Linear
+ * elastostatics: Galerkin finite element formulation", eq.
+ * model_elastostatics_bilin_FE) on a Cartesian grid of dim = 2 (plane
+ * strain) or 3 dimensions: elems[d] equal elements of size h[d] per axis,
+ * Young's modulus E_e = exp(log_E[e]) per element (x fastest, prod(elems)
+ * values) and Poisson ratio nu in (-1, 1/2).  Nodes are numbered
+ * x + (nx+1)(y + (ny+1) z) and the dofs are interleaved, dof = dim*node + l.
+ * fixed (n = dim * #nodes bytes, may be NULL) marks homogeneous Dirichlet
+ * dofs, imposed by symmetric diagonalisation (Remark "FEM_Dir_BC"): their
+ * row and column are zero except for the diagonal.  Each row keeps the full
+ * pattern of its 3^dim neighbouring nodes (zeros included).  The result
+ * becomes the context's matrix with block_size = dim, as msrsb_set_matrix
+ * would set it (same pattern on a repeated call with the same grid: then it
+ * acts as msrsb_update_values and keeps P for a warm start).  Loads (the
+ * right-hand side) are the caller's.
+ * Errors: E_ARG for a bad dimension, grid, sizes or nu. */
+msrsb_status msrsb_assemble_q1(msrsb_ctx *ctx, int32_t dim, const int32_t elems[3],
+                               const double h[3], double nu, const double *log_E,
+                               const uint8_t *fixed, int where);
+
+/* Gradient with respect to log E of an objective through the elasticity
+ * system of the last msrsb_assemble_q1, given the displacement u and the
+ * adjoint lambda (A^T lambda = dJ/du), both n values:
+ *   grad_e = -E_e lambda_e^T K0_e u_e
+ * with K0_e the element stiffness for E = 1 and fixed dofs taken as zero
+ * (the right-hand side must not depend on E).  grad has prod(elems) values.
+ * (Derived from the element assembly; the paper has no adjoint.)
+ * Errors: E_STATE if A was not assembled by msrsb_assemble_q1. */
+msrsb_status msrsb_q1_adjoint_grad(msrsb_ctx *ctx, const double *u, const double *lambda,
+                                   double *grad, int where);
 
 /* Milliseconds of the last run of each phase (MSRSB_PHASE_*), measured
  * with HIP events on the context's stream.  Synchronises. */

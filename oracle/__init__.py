@@ -72,6 +72,7 @@ def _declare(L):
     L.orc_gmres.argtypes = [C.POINTER(Prec), _P, _P, _I, _D, _I, _P, _P, _P, _I]
     L.orc_tpfa.argtypes = [_I, _I, _I, _I, _D, _D, _D, _P, _P, _P, _P, _P, _P]
     L.orc_tpfa_grad.argtypes = [_I, _I, _I, _I, _D, _D, _D, _P, _P, _P, _P, _P]
+    L.orc_q1_grad.argtypes = [_I, _P, _P, _D, _P, _P, _P, _P, _P]
 
 
 def _p(a):
@@ -204,6 +205,18 @@ def tpfa_grad(dims, h, logk, bc, p, lam):
     hz = h[2] if len(h) > 2 else 1.0
     _check(lib().orc_tpfa_grad(dim, nx, ny, nz, h[0], h[1], hz, _p(_f64(logk)), _p(_f64(bc)),
                                _p(_f64(p)), _p(_f64(lam)), _p(g)), "tpfa_grad")
+    return g
+
+
+def q1_grad(elems, h, nu, logE, fixed, u, lam):
+    """dJ/dlog E per element for Q1 elasticity, given u and the adjoint."""
+    dim = len(elems)
+    el = _i32(list(elems) + [1] * (3 - dim))
+    hh = _f64(list(h)[:dim] + [1.0] * (3 - dim))
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    g = np.zeros(int(np.prod(elems)))
+    _check(lib().orc_q1_grad(dim, _p(el), _p(hh), float(nu), _p(_f64(logE)), _p(fx),
+                             _p(_f64(u)), _p(_f64(lam)), _p(g)), "q1_grad")
     return g
 
 

@@ -763,3 +763,82 @@ int orc_tpfa_grad(int dim, int nx, int ny, int nz, double hx, double hy, double 
     }
     return ORC_OK;
 }
+
+/* Gradient of an objective J(u) with respect to log E through the Q1
+ * elasticity system A(E) u = f with E-independent loads (App. "Linear
+ * elastostatics: Galerkin finite element formulation"): A = sum_e E_e K_e,
+ * so dJ/dlog E_e = -lambda^T (E_e K_e) u, with lambda solving A^T lambda =
+ * dJ/du.  Dofs fixed by symmetric diagonalisation are zero in u and
+ * lambda (homogeneous data, an objective on free dofs) and are skipped.
+ *
+ * The element matrix is integrated here directly from the bilinear form
+ *   a(v, u) = int lambda_L div v div u + 2 G eps(v) : eps(u),
+ * whose entry for v = N_a e_l, u = N_b e_m reads
+ *   lambda_L dN_a/dx_l dN_b/dx_m + G dN_a/dx_m dN_b/dx_l
+ *   + G delta_lm grad N_a . grad N_b,
+ * with 2-point Gauss quadrature per axis on the dim-cube of sizes h.  Nodes
+ * of element (ex, ey, ez) are (ex + bx, ey + by, ez + bz), local index
+ * bx + 2 by + 4 bz; dof = dim * node + l.  (Not in the paper, which has no
+ * adjoint.) */
+int orc_q1_grad(int dim, const int *elems, const double *h, double nu, const double *logE,
+                const unsigned char *fixed, const double *u, const double *lam, double *grad)
+{
+    if (dim != 2 && dim != 3) return ORC_EARG;
+    int ne[3] = {1, 1, 1}, nn[3] = {1, 1, 1};
+    for (int k = 0; k < dim; ++k) {
+        ne[k] = elems[k];
+        nn[k] = elems[k] + 1;
+    }
+    int nloc = 1 << dim, nd = dim * nloc;
+    double lamL = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), G = 1.0 / (2.0 * (1.0 + nu));
+    double K[24 * 24];
+    memset(K, 0, sizeof(K));
+    double gpt = 1.0 / sqrt(3.0);
+    double wdet = 1.0;
+    for (int k = 0; k < dim; ++k) wdet = wdet * (h[k] / 2.0);
+    for (int p = 0; p < nloc; ++p) {
+        double xi[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) xi[k] = (p >> k & 1) ? gpt : -gpt;
+        double dN[8][3];
+        for (int a = 0; a < nloc; ++a)
+            for (int k = 0; k < dim; ++k) {
+                /* d/dx_k of prod_m (1 + s_m xi_m)/2, with dxi/dx = 2/h */
+                double v = 1.0;
+                for (int m = 0; m < dim; ++m) {
+                    double sm = (a >> m & 1) ? 1.0 : -1.0;
+                    v = v * (m == k ? sm / 2.0 : (1.0 + sm * xi[m]) / 2.0);
+                }
+                dN[a][k] = v * 2.0 / h[k];
+            }
+        for (int a = 0; a < nloc; ++a)
+            for (int l = 0; l < dim; ++l)
+                for (int b = 0; b < nloc; ++b)
+                    for (int m = 0; m < dim; ++m) {
+                        double gg = 0.0;
+                        for (int k = 0; k < dim; ++k) gg = gg + dN[a][k] * dN[b][k];
+                        double v = lamL * dN[a][l] * dN[b][m] + G * dN[a][m] * dN[b][l];
+                        if (l == m) v = v + G * gg;
+                        K[(dim * a + l) * nd + dim * b + m] += v * wdet;
+                    }
+    }
+    int nel = ne[0] * ne[1] * ne[2];
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < nel; ++e) {
+        int o[3] = {e % ne[0], (e / ne[0]) % ne[1], e / (ne[0] * ne[1])};
+        double ue[24], le[24];
+        for (int a = 0; a < nloc; ++a) {
+            int node = (o[0] + (a & 1)) + nn[0] * ((o[1] + (a >> 1 & 1)) + nn[1] * (o[2] + (a >> 2 & 1)));
+            for (int l = 0; l < dim; ++l) {
+                int dof = dim * node + l;
+                int f = fixed ? fixed[dof] != 0 : 0;
+                ue[dim * a + l] = f ? 0.0 : u[dof];
+                le[dim * a + l] = f ? 0.0 : lam[dof];
+            }
+        }
+        double s = 0.0;
+        for (int i = 0; i < nd; ++i)
+            for (int j = 0; j < nd; ++j) s = s + le[i] * K[i * nd + j] * ue[j];
+        grad[e] = -exp(logE[e]) * s;
+    }
+    return ORC_OK;
+}

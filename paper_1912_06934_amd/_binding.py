@@ -85,6 +85,8 @@ SIGNATURES = [
     ("msrsb_solve_transpose", _ST,
      [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_int]),
     ("msrsb_tpfa_adjoint_grad", _ST, [_P, _P, _P, _P, _P, C.c_int]),
+    ("msrsb_assemble_q1", _ST, [_P, _I32, _P, _P, C.c_double, _P, _P, C.c_int]),
+    ("msrsb_q1_adjoint_grad", _ST, [_P, _P, _P, _P, C.c_int]),
     ("msrsb_get_timings", _ST, [_P, _P, _I32]),
 ]
 
@@ -213,6 +215,26 @@ class Msrsb:
         if isinstance(rhs_out, np.ndarray) and rhs_out is not k1:
             rhs_out[...] = k1
         return rhs_out
+
+    def assemble_q1(self, elems, h, nu, log_E, fixed=None):
+        """Q1 elasticity matrix from log E per element (block size = dim)."""
+        dim = len(elems)
+        d = (C.c_int32 * 3)(*(list(elems) + [1] * (3 - dim)))
+        hh = (C.c_double * 3)(*(list(h)[:dim] + [1.0] * (3 - dim)))
+        pe, w0, k0 = _ptr(log_E, np.float64)
+        pf, w1, k1 = _ptr(fixed, np.uint8)
+        self._check(self._lib.msrsb_assemble_q1(self._h, dim, d, hh, float(nu), pe, pf,
+                                                _where(w0, w1)), "assemble_q1")
+        self.n = dim * int(np.prod([e + 1 for e in elems]))
+
+    def q1_adjoint_grad(self, u, lam, grad):
+        a = [_ptr(u, np.float64), _ptr(lam, np.float64), _ptr(grad, np.float64)]
+        self._check(self._lib.msrsb_q1_adjoint_grad(self._h, a[0][0], a[1][0], a[2][0],
+                                                    _where(*[x[1] for x in a])),
+                    "q1_adjoint_grad")
+        if isinstance(grad, np.ndarray) and grad is not a[2][2]:
+            grad[...] = a[2][2]
+        return grad
 
     # -- coarse --
     def set_coarse(self, nc, part, sup_rowptr, sup_col, interior):

@@ -137,6 +137,10 @@ void free_matrix(msrsb_ctx *c)
     c->gm_cap = 0;
     dfree(c->partials);
     dfree(c->tlogk);
+    dfree(c->qk0);
+    dfree(c->qlogE);
+    dfree(c->qfixed);
+    c->q1 = false;
     dfree(c->a_slot);
     dfree(c->a_dia);
     dfree(c->a_dia32);
@@ -1056,6 +1060,121 @@ msrsb_status msrsb_tpfa_adjoint_grad(msrsb_ctx *c, const double *log_k, const do
     phase_end(c, MSRSB_PHASE_GRAD);
     if (where == MSRSB_HOST)
         hipMemcpyAsync(grad, dg, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "gradient failed on the device");
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_assemble_q1(msrsb_ctx *c, int32_t dim, const int32_t elems[3],
+                               const double h[3], double nu, const double *log_E,
+                               const uint8_t *fixed, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if ((dim != 2 && dim != 3) || !elems || !h || !log_E || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid Q1 arguments");
+    if (!(nu > -1.0 && nu < 0.5)) return fail(c, MSRSB_E_ARG, "Poisson ratio out of range");
+    int64_t nn = 1, nel = 1;
+    for (int k = 0; k < dim; ++k) {
+        if (elems[k] < 1 || !(h[k] > 0.0)) return fail(c, MSRSB_E_ARG, "invalid grid");
+        nn *= elems[k] + 1;
+        nel *= elems[k];
+    }
+    if (nn * dim > (1 << 27)) return fail(c, MSRSB_E_ARG, "grid too large");
+    const int n = static_cast<int>(nn * dim);
+    int ne[3] = {1, 1, 1}, nnd[3] = {1, 1, 1};
+    for (int k = 0; k < dim; ++k) {
+        ne[k] = elems[k];
+        nnd[k] = elems[k] + 1;
+    }
+    bool same = c->q1 && c->has_matrix && c->qdim == dim;
+    for (int k = 0; k < 3; ++k) same = same && c->qelems[k] == ne[k];
+    if (!same) {
+        // symbolic pattern: per row the 3^dim neighbouring nodes in ascending
+        // index, dim components each
+        std::vector<int> hrp(n + 1, 0), hci, dpos(n);
+        hci.reserve(static_cast<size_t>(n) * (dim == 3 ? 81 : 18));
+        const int zr = dim == 3 ? 1 : 0;
+        for (int node = 0; node < static_cast<int>(nn); ++node) {
+            const int x = node % nnd[0], y = (node / nnd[0]) % nnd[1], z = node / (nnd[0] * nnd[1]);
+            for (int l = 0; l < dim; ++l) {
+                const int r = dim * node + l;
+                for (int dz = -zr; dz <= zr; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int X = x + dx, Y = y + dy, Z = z + dz;
+                            if (X < 0 || Y < 0 || Z < 0 || X >= nnd[0] || Y >= nnd[1] || Z >= nnd[2])
+                                continue;
+                            const int nb = X + nnd[0] * (Y + nnd[1] * Z);
+                            for (int m = 0; m < dim; ++m) {
+                                if (dim * nb + m == r) dpos[r] = static_cast<int>(hci.size());
+                                hci.push_back(dim * nb + m);
+                            }
+                        }
+                hrp[r + 1] = static_cast<int>(hci.size());
+            }
+        }
+        const int64_t nnz = static_cast<int64_t>(hci.size());
+        free_coarse(c);
+        msrsb_status st = install_pattern(c, n, nnz, std::move(hrp), std::move(hci), dpos, dim);
+        if (st) return st;
+        c->q1 = true;
+        c->qdim = dim;
+        for (int k = 0; k < 3; ++k) c->qelems[k] = ne[k];
+    }
+    for (int k = 0; k < 3; ++k) c->qh[k] = k < dim ? h[k] : 1.0;
+    c->qnu = nu;
+    const int nd = dim << dim;
+    std::vector<double> k0(static_cast<size_t>(nd) * nd);
+    q1_element_stiffness(dim, c->qh, nu, k0.data());
+    if (!dalloc_keep(c->qk0, 24 * 24) || !dalloc_keep(c->qlogE, nel))
+        return fail(c, MSRSB_E_NOMEM, "allocation failed");
+    hipMemcpyAsync(c->qk0, k0.data(), k0.size() * sizeof(double), hipMemcpyHostToDevice,
+                   c->stream);
+    hipMemcpyAsync(c->qlogE, log_E, nel * sizeof(double), kind_in(where), c->stream);
+    if (fixed) {
+        if (!dalloc_keep(c->qfixed, n)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+        hipMemcpyAsync(c->qfixed, fixed, n, kind_in(where), c->stream);
+    } else {
+        dfree(c->qfixed);
+    }
+    phase_begin(c, MSRSB_PHASE_ASSEMBLE);
+    launch_q1_values(c->stream, dim, c->qelems, c->qk0, c->qlogE, c->qfixed, c->rp, c->a);
+    phase_end(c, MSRSB_PHASE_ASSEMBLE);
+    return refresh_values(c);
+}
+
+msrsb_status msrsb_q1_adjoint_grad(msrsb_ctx *c, const double *u, const double *lambda,
+                                   double *grad, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (!c->q1) return fail(c, MSRSB_E_STATE, "A was not assembled by msrsb_assemble_q1");
+    if (!u || !lambda || !grad || !valid_where(where))
+        return fail(c, MSRSB_E_ARG, "invalid vectors");
+    msrsb_status st = ensure_workspace(c);
+    if (st) return fail(c, st, "workspace allocation failed");
+    int64_t nel = 1;
+    for (int k = 0; k < c->qdim; ++k) nel *= c->qelems[k];
+    const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
+    const double *du = u, *dl = lambda;
+    double *dg = grad;
+    if (where == MSRSB_HOST) {
+        if (!dalloc_keep(c->w[11], std::max<int64_t>(c->n, nel)))
+            return fail(c, MSRSB_E_NOMEM, "allocation failed");
+        hipMemcpyAsync(c->w[8], u, bytes, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(c->w[9], lambda, bytes, hipMemcpyHostToDevice, c->stream);
+        du = c->w[8];
+        dl = c->w[9];
+        dg = c->w[11];
+    }
+    phase_begin(c, MSRSB_PHASE_GRAD);
+    launch_q1_grad(c->stream, c->qdim, c->qelems, c->qk0, c->qlogE, c->qfixed, du, dl, dg);
+    phase_end(c, MSRSB_PHASE_GRAD);
+    if (where == MSRSB_HOST)
+        hipMemcpyAsync(grad, dg, nel * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "gradient failed on the device");
     return MSRSB_OK;

@@ -167,6 +167,14 @@ struct msrsb_ctx {
     double th[3] = {1, 1, 1}, tbc[6] = {0, 0, 0, 0, 0, 0};
     double *tlogk = nullptr;
 
+    // Q1 elasticity description (set by msrsb_assemble_q1)
+    bool q1 = false;
+    int qdim = 0, qelems[3] = {1, 1, 1};
+    double qh[3] = {1, 1, 1}, qnu = 0.0;
+    double *qk0 = nullptr;       // element stiffness for E = 1, (dim 2^dim)^2
+    double *qlogE = nullptr;     // log E per element
+    uint8_t *qfixed = nullptr;   // Dirichlet flag per dof (null: none)
+
     // timings
     hipEvent_t ev_start[MSRSB_N_PHASES] = {}, ev_stop[MSRSB_N_PHASES] = {};
     bool ev_used[MSRSB_N_PHASES] = {};
@@ -302,5 +310,13 @@ void launch_tpfa_values(hipStream_t s, int dim, const int *dims, const double *h
                         double *rhs);
 void launch_tpfa_grad(hipStream_t s, int dim, const int *dims, const double *h, const double *bc,
                       const double *logk, const double *p, const double *lam, double *grad);
+
+// ---- Q1 elasticity (k_q1.hip) ----
+void q1_element_stiffness(int dim, const double *h, double nu, double *K);
+void launch_q1_values(hipStream_t s, int dim, const int *elems, const double *k0,
+                      const double *logE, const uint8_t *fixed, const int *rp, double *val);
+void launch_q1_grad(hipStream_t s, int dim, const int *elems, const double *k0,
+                    const double *logE, const uint8_t *fixed, const double *u, const double *lam,
+                    double *grad);
 
 }  // namespace msrsb

@@ -329,3 +329,56 @@ def test_q1_pcg_solution(torch_cuda, case):
     i32 = s32.solve(cfg["f"], u32, rtol=1e-12, max_iter=3000, fp32_smoother=True, **kw)
     assert i32["true_rel_res"] <= 1e-12
     assert rel_max(u32, ref["x"]) <= 1e-8
+
+
+@pytest.mark.parametrize("elems,h", [((12, 10, 9), (1 / 12, 1 / 10, 1 / 9)),
+                                     ((12, 12), (1 / 12, 20 / 12))], ids=["3d", "2d-stretched"])
+def test_q1_assembly_matches_generator(torch_cuda, elems, h):
+    from synth.q1 import q1_elasticity
+    from paper_1912_06934_amd import Msrsb
+    d = len(elems)
+    rng = np.random.default_rng(4)
+    logE = 1.5 * rng.standard_normal(int(np.prod(elems)))
+    n = d * int(np.prod([e + 1 for e in elems]))
+    fixed = np.zeros(n, dtype=np.uint8)
+    fixed[:d * (elems[0] + 1)] = 1                       # the y = 0 row / z = 0 ... first nodes
+    rp, ci, a = q1_elasticity(elems, h, np.exp(logE), 0.25, fixed.astype(bool))
+    s = Msrsb()
+    s.assemble_q1(elems, h, 0.25, logE, fixed)
+    grp, gci, ga = s.get_matrix()
+    assert np.array_equal(grp, rp) and np.array_equal(gci, ci)
+    assert np.max(np.abs(ga - a)) <= 1e-14 * np.max(np.abs(a))
+    G = sp.csr_matrix((ga, gci, grp))
+    assert (G - G.T).count_nonzero() == 0                # symmetric to the bit
+
+
+def test_q1_adjoint_gradient_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_06934_amd import MsrsbQ1Solve, Q1Problem
+    cfg = matrix_inputs("c3", (12, 10, 9), 4)
+    sup = cfg["supports"]
+    rng = np.random.default_rng(8)
+    free = np.nonzero(~cfg["fixed"])[0]
+    obs = np.sort(rng.choice(free, size=32, replace=False))
+    data = 1e-3 * rng.standard_normal(obs.size)
+    prob = Q1Problem(elems=cfg["dims"], h=cfg["h"], nu=cfg["nu"], loads=cfg["rhs"],
+                     fixed=cfg["fixed"].astype(np.uint8),
+                     coarse=dict(nc=sup["nc"], part=sup["part"], prp=sup["prp"], pci=sup["pci"],
+                                 interior=sup["interior"]),
+                     rtol=1e-12, max_iter=3000, fp32_basis=True)
+    lE = torch.tensor(cfg["logE"], device="cuda", requires_grad=True)
+    u = MsrsbQ1Solve.apply(lE, prob)
+    ob = torch.as_tensor(obs, device="cuda")
+    J = ((u[ob] - torch.as_tensor(data, device="cuda")) ** 2).sum()
+    J.backward()
+    g = lE.grad.cpu().numpy()
+    assert prob.last_forward["solve"]["true_rel_res"] <= 1e-12
+    assert prob.last_backward["solve"]["true_rel_res"] <= 1e-12
+    orc = oracle_setup(cfg)
+    ur = orc.solve(cfg["f"], rtol=1e-12, maxit=3000, pre=(2, 2), post=(2, 2))["x"]
+    assert rel_max(u.detach().cpu().numpy(), ur) <= 1e-8
+    gu = np.zeros_like(ur)
+    gu[obs] = 2 * (ur[obs] - data)
+    lam = orc.solve(gu, rtol=1e-12, maxit=3000, pre=(2, 2), post=(2, 2), transpose=True)["x"]
+    g_ref = oracle.q1_grad(cfg["dims"], cfg["h"], cfg["nu"], cfg["logE"], cfg["fixed"], ur, lam)
+    assert np.max(np.abs(g - g_ref)) <= 1e-8 * np.max(np.abs(g_ref))

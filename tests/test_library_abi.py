@@ -14,14 +14,15 @@ HEADER = os.path.join(ROOT, "include", "msrsb.h")
 def declared_symbols():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(msrsb_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(msrsb_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_paper_calls():
     names = declared_symbols()
     for must in ["msrsb_set_matrix", "msrsb_set_coarse", "msrsb_setup_basis",
                  "msrsb_build_coarse", "msrsb_apply_preconditioner", "msrsb_solve",
-                 "msrsb_solve_transpose", "msrsb_tpfa_adjoint_grad", "msrsb_assemble_tpfa"]:
+                 "msrsb_solve_transpose", "msrsb_tpfa_adjoint_grad", "msrsb_assemble_tpfa",
+                 "msrsb_assemble_q1", "msrsb_q1_adjoint_grad"]:
         assert must in names
 
 
@@ -30,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     lib = _binding.load()
     out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (msrsb_[a-z_]+)", out))
+    exported = set(re.findall(r"\bT (msrsb_[a-z0-9_]+)", out))
     missing = [s for s in declared_symbols() if s not in exported]
     assert not missing, missing
     for s in declared_symbols():

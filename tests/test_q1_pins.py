@@ -15,6 +15,10 @@
   nodes per direction, stretched 20 times in y.  The naive basis leaves
   [0, 1] within 20 iterations; the enhanced (SDC-filtered) basis converges
   to the bilinear interpolators of a homogeneous Cartesian problem.
+* The oracle's log-E adjoint gradient (element matrix integrated from the
+  index form of the bilinear form) against central finite differences of
+  the objective through direct solves of the generator's (Voigt-form)
+  matrices, per element and along a random direction.
 """
 import itertools
 
@@ -163,3 +167,43 @@ def test_naive_basis_diverges_sdc_basis_is_bilinear():
             hat = max(0.0, 1 - abs(x - cx) / 3) * max(0.0, 1 - abs(y - cy) / 3)
             err = max(err, abs(enh.pv[e] - hat))
     assert err <= 1e-10
+
+
+def _q1_objective(cfg, logE, obs, data):
+    import scipy.sparse.linalg as spl
+    rp, ci, a = q1_elasticity(cfg["dims"], cfg["h"], np.exp(logE), cfg["nu"], cfg["fixed"])
+    A = _csr(rp, ci, a).tocsc()
+    u = spl.spsolve(A, cfg["rhs"])
+    return float(np.sum((u[obs] - data) ** 2)), u, A
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 2), (4, 2, 3)])
+def test_oracle_q1_gradient_matches_finite_differences(dims):
+    """The oracle's log-E gradient (element matrix from the index form of the
+    bilinear form) against central differences of J through direct solves of
+    the generator's matrices (Voigt form), so neither side checks itself."""
+    import scipy.sparse.linalg as spl
+    cfg = synth.make_config("c3", dims=dims, block=2, seed=7)
+    n = cfg["rhs"].size
+    rng = np.random.default_rng(0)
+    free = np.nonzero(~cfg["fixed"])[0]
+    obs = np.sort(rng.choice(free, size=6, replace=False))
+    data = 1e-3 * rng.standard_normal(obs.size)
+    logE = cfg["logE"]
+    J0, u, A = _q1_objective(cfg, logE, obs, data)
+    gu = np.zeros(n)
+    gu[obs] = 2.0 * (u[obs] - data)
+    lam = spl.spsolve(A.T.tocsc(), gu)
+    g = oracle.q1_grad(dims, cfg["h"], cfg["nu"], logE, cfg["fixed"], u, lam)
+    step = 1e-5
+    for e in range(logE.size):
+        lp, lm = logE.copy(), logE.copy()
+        lp[e] += step
+        lm[e] -= step
+        fd = (_q1_objective(cfg, lp, obs, data)[0] - _q1_objective(cfg, lm, obs, data)[0]) / (2 * step)
+        assert abs(fd - g[e]) <= 1e-6 * np.max(np.abs(g)), (e, fd, g[e])
+    # a random direction over all elements
+    dvec = rng.standard_normal(logE.size)
+    fd = (_q1_objective(cfg, logE + step * dvec, obs, data)[0]
+          - _q1_objective(cfg, logE - step * dvec, obs, data)[0]) / (2 * step)
+    assert abs(fd - g @ dvec) <= 1e-6 * abs(g @ dvec)
