@@ -1,0 +1,179 @@
+"""Failure handling of the C ABI on the GPU: calls out of order, invalid
+inputs, a diverging basis, a Krylov breakdown, the iteration limit and an
+exactly singular coarse matrix.  Every case is an ordinary, in-bounds run
+whose error the host code detects and reports; nothing faults the device."""
+import numpy as np
+import pytest
+
+from _cases import tpfa_inputs
+
+pytestmark = pytest.mark.gpu
+
+E_ARG, E_STATE, E_BASIS_DIVERGED, E_COARSE_SINGULAR, E_BREAKDOWN, E_NOT_CONVERGED = \
+    -1, -2, -5, -6, -7, -8
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    from paper_1912_06934_amd import Msrsb, MsrsbError
+    return Msrsb, MsrsbError
+
+
+def _code(exc_info):
+    return exc_info.value.code
+
+
+def _laplace_1d(n):
+    """1D Laplacian with zero row sums (Neumann ends), integer entries."""
+    rp, ci, a = [0], [], []
+    for i in range(n):
+        if i > 0:
+            ci.append(i - 1)
+            a.append(-1.0)
+        ci.append(i)
+        a.append(2.0 if 0 < i < n - 1 else 1.0)
+        if i < n - 1:
+            ci.append(i + 1)
+            a.append(-1.0)
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32), np.array(a)
+
+
+def test_calls_out_of_order(lib):
+    Msrsb, MsrsbError = lib
+    s = Msrsb()
+    with pytest.raises(MsrsbError) as e:
+        s.set_coarse(1, np.zeros(4, np.int32), np.arange(5, dtype=np.int32),
+                     np.zeros(4, np.int32), np.ones(4, np.uint8))
+    assert _code(e) == E_STATE
+    rp, ci, a = _laplace_1d(8)
+    s.set_matrix(rp, ci, a)
+    with pytest.raises(MsrsbError) as e:
+        s.setup_basis(max_iter=1)
+    assert _code(e) == E_STATE
+    s.set_coarse(2, np.repeat(np.arange(2, dtype=np.int32), 4), np.arange(9, dtype=np.int32),
+                 np.repeat(np.arange(2, dtype=np.int32), 4), np.ones(8, np.uint8))
+    with pytest.raises(MsrsbError) as e:
+        s.build_coarse()
+    assert _code(e) == E_STATE
+    with pytest.raises(MsrsbError) as e:
+        s.solve(np.ones(8), np.zeros(8), pre=(1, 1))
+    assert _code(e) == E_STATE
+    with pytest.raises(MsrsbError) as e:
+        s.tpfa_adjoint_grad(np.zeros(8), np.zeros(8), np.zeros(8), np.zeros(8))
+    assert _code(e) == E_STATE
+    with pytest.raises(MsrsbError) as e:
+        s.q1_adjoint_grad(np.zeros(8), np.zeros(8), np.zeros(8))
+    assert _code(e) == E_STATE
+    # the smoother-only preconditioner needs no coarse level
+    z = np.zeros(8)
+    s.apply(np.ones(8), z, post=(1, 1), use_multiscale=False)
+    assert np.allclose(z, 1.0 / a[rp[:-1] + (np.arange(8) > 0)])
+
+
+def test_invalid_inputs(lib):
+    Msrsb, MsrsbError = lib
+    s = Msrsb()
+    rp, ci, a = _laplace_1d(6)
+    bad = ci.copy()
+    bad[1], bad[2] = bad[2], bad[1]                     # unsorted row 1
+    with pytest.raises(MsrsbError) as e:
+        s.set_matrix(rp, bad, a)
+    assert _code(e) == E_ARG
+    # a row without its diagonal
+    rp2 = np.array([0, 1, 2], np.int32)
+    with pytest.raises(MsrsbError) as e:
+        s.set_matrix(rp2, np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    assert _code(e) == E_ARG
+    with pytest.raises(MsrsbError) as e:                 # block size must divide n
+        s.set_matrix(rp, ci, a, block_size=4)
+    assert _code(e) == E_ARG
+    s.set_matrix(rp, ci, a)
+    part = np.array([0, 0, 0, 1, 1, 1], np.int32)
+    prp = np.arange(7, dtype=np.int32)
+    with pytest.raises(MsrsbError) as e:                 # part[i] not in row i's pattern
+        s.set_coarse(2, part, prp, np.array([0, 0, 1, 1, 1, 1], np.int32), np.ones(6, np.uint8))
+    assert _code(e) == E_ARG
+    with pytest.raises(MsrsbError) as e:                 # too many coarse unknowns
+        s.set_coarse(5000, part, prp, part, np.ones(6, np.uint8))
+    assert _code(e) == E_ARG
+
+
+def test_basis_divergence_is_reported(lib):
+    Msrsb, MsrsbError = lib
+    rp, ci, a = _laplace_1d(16)
+    a = a.copy()
+    a[5] = np.nan
+    s = Msrsb()
+    s.set_matrix(rp, ci, a)
+    part = np.repeat(np.arange(2, dtype=np.int32), 8)
+    s.set_coarse(2, part, np.arange(17, dtype=np.int32), part, np.ones(16, np.uint8))
+    with pytest.raises(MsrsbError) as e:            # the naive operator keeps the NaN
+        s.setup_basis(max_iter=10, filter=False)
+    assert _code(e) == E_BASIS_DIVERGED
+    # the naive basis on the perturbed, stretched MPFA-O grid grows without
+    # bound until it overflows; the filtered one stays a partition of unity
+    from synth.mpfa import perturbed_nodes, mpfa_o
+    import synth
+    X = perturbed_nodes((9, 9), np.random.default_rng(0), 0.4, lengths=(1.0, 10.0))
+    rp, ci, a = mpfa_o(X, np.eye(2)[None].repeat(81, 0))
+    sup = synth.cell_supports((9, 9), 3)
+    s = Msrsb()
+    s.set_matrix(rp, ci, a)
+    s.set_coarse(sup["nc"], sup["part"], sup["prp"], sup["pci"], sup["interior"])
+    with pytest.raises(MsrsbError) as e:
+        s.setup_basis(max_iter=20000, check_every=100, filter=False)
+    assert _code(e) == E_BASIS_DIVERGED
+    info = s.setup_basis(max_iter=1000, check_every=10, filter=True)
+    assert 0.0 <= info["p_min"] and info["p_max"] <= 1.0
+
+
+def test_breakdown_and_iteration_limit(lib):
+    Msrsb, MsrsbError = lib
+    cfg = tpfa_inputs("c1")
+    sup = cfg["supports"]
+    s = Msrsb()
+    s.set_matrix(cfg["rp"], cfg["ci"], cfg["a"])
+    s.set_coarse(sup["nc"], sup["part"], sup["prp"], sup["pci"], sup["interior"])
+    s.setup_basis(max_iter=20)
+    s.build_coarse()
+    n = cfg["rp"].size - 1
+    u = np.zeros(n)
+    with pytest.raises(MsrsbError) as e:
+        s.solve(cfg["f"], u, rtol=1e-12, max_iter=2, post=(1, 1))
+    assert _code(e) == E_NOT_CONVERGED
+    assert e.value.info["iters"] == 2 and np.all(np.isfinite(u))
+    assert e.value.info["true_rel_res"] > 1e-12
+    f = cfg["f"].copy()
+    f[3] = np.nan
+    with pytest.raises(MsrsbError) as e:
+        s.solve(f, np.zeros(n), post=(1, 1))
+    assert _code(e) == E_BREAKDOWN
+    # CG on a negative definite operator: p^T A p < 0
+    neg = Msrsb()
+    neg.set_matrix(cfg["rp"], cfg["ci"], -cfg["a"])
+    neg.set_coarse(sup["nc"], sup["part"], sup["prp"], sup["pci"], sup["interior"])
+    neg.setup_basis(max_iter=0)
+    neg.build_coarse()
+    with pytest.raises(MsrsbError) as e:
+        neg.solve(cfg["f"], np.zeros(n), post=(1, 1))
+    assert _code(e) == E_BREAKDOWN
+    # the library stays usable after the errors
+    u = np.zeros(n)
+    info = s.solve(cfg["f"], u, rtol=1e-8, post=(1, 1))
+    assert info["true_rel_res"] <= 1e-8
+
+
+def test_exactly_singular_coarse_matrix(lib):
+    Msrsb, MsrsbError = lib
+    rp, ci, a = _laplace_1d(8)
+    s = Msrsb()
+    s.set_matrix(rp, ci, a)
+    part = np.repeat(np.arange(2, dtype=np.int32), 4)
+    s.set_coarse(2, part, np.arange(9, dtype=np.int32), part, np.ones(8, np.uint8))
+    s.setup_basis(max_iter=0)        # P = characteristic functions: A_c = [[1,-1],[-1,1]]
+    with pytest.raises(MsrsbError) as e:
+        s.build_coarse()
+    assert _code(e) == E_COARSE_SINGULAR
