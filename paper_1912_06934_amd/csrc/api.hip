@@ -186,6 +186,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->wc);
     dfree(c->partials);
     dfree(c->pcol_ell);
+    dfree(c->pcol16);
     dfree(c->p_csr_tmp);
     dfree(c->band);
     if (c->jmap_idx) hipFree(c->jmap_idx);
@@ -267,6 +268,13 @@ msrsb_status refresh_values(msrsb_ctx *c)
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail(c, MSRSB_E_HIP, "value update failed");
     c->a_symmetric = flag == 0;
+    // symmetric stencil storage: the lower diagonals mirror the upper ones
+    {
+        const DiaOffsets &d = c->a_off;
+        bool pairs = d.n > 0 && (d.n & 1) && d.off[d.n / 2] == 0;
+        for (int o = 0; pairs && o < d.n; ++o) pairs = d.off[o] == -d.off[d.n - 1 - o];
+        c->a_off.sym = c->a_symmetric && pairs ? 1 : 0;
+    }
     c->smoother_valid = c->smoother32_valid = false;
     c->smoother_t_valid = c->smoother32_t_valid = false;
     c->ilu_valid = false;
@@ -432,7 +440,7 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
     if (st) return st;
     st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
-    if (trans && (st = ensure_transpose(c))) return st;
+    if (trans && !c->a_symmetric && (st = ensure_transpose(c))) return st;
     if ((st = ensure_smoother(c, o, trans))) return fail(c, st, c->err.empty() ? "smoother set-up failed" : c->err);
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
     // device buffers are used in place; host buffers are staged
@@ -715,6 +723,16 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     hipMemcpyAsync(c->rsrc, rsrc.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->pcol_ell, pcol.data(), pcol.size() * sizeof(int), hipMemcpyHostToDevice,
                    c->stream);
+    std::vector<uint16_t> pcol16;
+    if ((pw == 4 || pw == 8) && nc < 0xFFFF) {
+        pcol16.resize(pcol.size());
+        for (size_t t = 0; t < pcol.size(); ++t)
+            pcol16[t] = pcol[t] < 0 ? 0xFFFFu : static_cast<uint16_t>(pcol[t]);
+        if (!dalloc(c->pcol16, pcol16.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        hipMemcpyAsync(c->pcol16, pcol16.data(), pcol16.size() * sizeof(uint16_t),
+                       hipMemcpyHostToDevice, c->stream);
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "copying the coarse data failed");
     // slot maps of the smoothing product, stored as indices into a table of
@@ -946,8 +964,8 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
         launch_fill(s, nn, c->ac, 0.0);
         launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
-                   c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->ac, c->dev_flag,
-                   c->band);
+                   c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
+                   c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag, c->band);
         int hflag = 0;
         hipMemcpyAsync(&hflag, c->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(c->h_band, c->band, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -964,12 +982,14 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     phase_begin(c, MSRSB_PHASE_FACTOR);
     int hflag = 0;
     st = MSRSB_E_COARSE_SINGULAR;
+    c->acinv_sym = false;
     if (c->a_symmetric) {
         // symmetric positive definite A_c: band-limited Gauss-Jordan without
         // pivoting; a non-positive pivot falls back to partial pivoting
         hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
         st = coarse_inverse_spd(s, nc, c->acinv, c->h_band[0], c->h_band[1], c->spd_buf,
                                 c->spd_buf + 64 * 64, c->dev_flag, &hflag);
+        c->acinv_sym = st == MSRSB_OK;
     }
     if (st == MSRSB_E_COARSE_SINGULAR) {
         double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);

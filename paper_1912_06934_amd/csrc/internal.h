@@ -23,6 +23,9 @@ constexpr int kMapWidth = 8;          // P rows up to this width use slot maps
 struct DiaOffsets {
     int n = 0;
     int off[kMaxDiag] = {};
+    // 1: the operator is symmetric and its offsets come in +- pairs, so the
+    // lower diagonals may be read from the upper ones
+    int sym = 0;
 };
 
 // Device scalars of the Krylov drivers (one FP64 array on the device).
@@ -119,6 +122,7 @@ struct msrsb_ctx {
     // ascending coarse column order, padding = 0 / col -1
     int pw = 0;
     int *pcol_ell = nullptr;
+    uint16_t *pcol16 = nullptr;   // 16-bit copy for the prolongation (pw 4 or 8)
     double *p64[2] = {nullptr, nullptr};
     float *p32[2] = {nullptr, nullptr};
     int pcur = 0;          // which buffer holds the current P
@@ -135,6 +139,7 @@ struct msrsb_ctx {
 
     // coarse operator and its inverse
     double *ac = nullptr, *acinv = nullptr, *gj_b = nullptr;
+    bool acinv_sym = false;  // acinv came from the SPD (symmetric) path
     double *spd_buf = nullptr;  // diagonal-block inverse and super-panel rows (SPD path)
     int *piv = nullptr, *colsrc = nullptr, *dev_flag = nullptr;
 
@@ -236,7 +241,8 @@ void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
-                const int *pci, const double *pcsr, double *ac, int *flag, int *band);
+                const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
+                const double *pe64, const float *pe32, double *ac, int *flag, int *band);
 msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu, double *G,
                                 double *B, int *flag, int *host_flag);
 void launch_fill(hipStream_t s, int64_t m, double *x, double v);
@@ -268,7 +274,7 @@ void launch_gather_values(hipStream_t s, int64_t m, const int *src, const double
 void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,
                      double *y);
 void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
-                         const double *f, const double *x, double *r);
+                         const float *a32, const double *f, const double *x, double *r);
 void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
                       const float *a32, const double *dinv64, const float *dinv32,
                       const double *v, const double *zin, double *zout, bool zero2);
@@ -283,9 +289,9 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
                        const double *pold, double *pnew, double *q, double *part, double *scal);
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
                        const double *q, double *part, double *scal, double *host_out);
-void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
-                        const double *p64, const float *p32, const double *wc, double *z,
-                        bool zero);
+void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
+                        bool fp32, const double *p64, const float *p32, const double *wc,
+                        double *z, bool zero);
 void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,
                        const double *a, double *ad64, float *ad32);
 

@@ -129,6 +129,138 @@ __global__ __launch_bounds__(NT) void k_rap(int n, int nc, int maxnb, const int 
     if (bu > 0) atomicMax(band + 1, bu);
 }
 
+// The same product for a stencil A (ND diagonals, compile-time) and P in its
+// row-major ELL form (PW slots, 16-bit columns, 0xFFFF = padding, values in
+// T).  A fine row's ND coefficients and the ND neighbour rows of P (values
+// and columns) are all loaded before they are used.  The order of the sums
+// is that of k_rap (neighbours in offset order, slots in column order).
+template <typename PT>
+__device__ __forceinline__ void load_prow(const PT *__restrict__ p, const uint16_t *__restrict__ pc,
+                                          int64_t row, PT (&v)[8], uint16_t (&c)[8])
+{
+    typedef uint16_t cvec __attribute__((ext_vector_type(8)));
+    constexpr int L = 16 / sizeof(PT);
+    typedef PT tvec __attribute__((ext_vector_type(L)));
+    const cvec cc = *reinterpret_cast<const cvec *>(pc + row * 8);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = cc[u];
+    const tvec *vs = reinterpret_cast<const tvec *>(p + row * 8);
+#pragma unroll
+    for (int q = 0; q < 8 / L; ++q) {
+        const tvec x = vs[q];
+#pragma unroll
+        for (int u = 0; u < L; ++u) v[L * q + u] = x[u];
+    }
+}
+
+template <typename T, int NT, int ND>
+__global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
+                                                const int *__restrict__ rrp,
+                                                const int *__restrict__ rci,
+                                                const T *__restrict__ rv, DiaOffsets d,
+                                                const double *__restrict__ ad,
+                                                const uint16_t *__restrict__ pcol,
+                                                const T *__restrict__ pv, double *__restrict__ ac,
+                                                int *__restrict__ flag, int *__restrict__ band)
+{
+    extern __shared__ double smem[];
+    __shared__ int wsum[NT / 64];
+    double *acc = smem;                                         // maxnb * NT
+    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);       // maxnb
+    short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int t = tid; t < nc; t += NT) map[t] = 0;
+    __syncthreads();
+    const int t0 = rrp[j], t1 = rrp[j + 1];
+    for (int t = t0 + tid; t < t1; t += NT) {
+        const int i = rci[t];
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            const int k = i + d.off[o];
+            if (k < 0 || k >= n || ad[static_cast<int64_t>(o) * n + i] == 0.0) continue;
+            typedef uint16_t cvec __attribute__((ext_vector_type(8)));
+            const cvec cc = *reinterpret_cast<const cvec *>(pcol + static_cast<int64_t>(k) * 8);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (cc[u] != 0xFFFFu) map[cc[u]] = 1;
+        }
+    }
+    __syncthreads();
+    // number the marked coarse columns in ascending order (block scan)
+    const int chunk = (nc + NT - 1) / NT;
+    const int lo = tid * chunk, hi = min(nc, lo + chunk);
+    int cnt = 0;
+    for (int t = lo; t < hi; ++t) cnt += map[t];
+    int pre = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(pre, off, 64);
+        if (lane >= off) pre += o;
+    }
+    if (lane == 63) wsum[wid] = pre;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        total += wsum[w];
+    }
+    if (total > maxnb) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    int slot = base + pre - cnt;
+    __syncthreads();
+    for (int t = lo; t < hi; ++t) {
+        if (map[t]) {
+            inv[slot] = t;
+            map[t] = static_cast<short>(slot++);
+        } else {
+            map[t] = -1;
+        }
+    }
+    for (int s = 0; s < total; ++s) acc[s * NT + tid] = 0.0;
+    __syncthreads();
+    for (int t = t0 + tid; t < t1; t += NT) {
+        const int i = rci[t];
+        const double pij = static_cast<double>(rv[t]);
+        double av[ND];
+        T v[ND][8];
+        uint16_t cl[ND][8];
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            const int k = i + d.off[o];
+            const bool in = k >= 0 && k < n;
+            const double a = ad[static_cast<int64_t>(o) * n + i];
+            av[o] = in ? a : 0.0;
+            load_prow<T>(pv, pcol, in ? k : i, v[o], cl[o]);
+        }
+#pragma unroll
+        for (int o = 0; o < ND; ++o) {
+            if (av[o] == 0.0) continue;
+            const double pa = pij * av[o];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (cl[o][u] != 0xFFFFu)
+                    acc[map[cl[o][u]] * NT + tid] += pa * static_cast<double>(v[o][u]);
+        }
+    }
+    __syncthreads();
+    int bl = 0, bu = 0;
+    for (int s = tid; s < total; s += NT) {
+        double sum = 0.0;
+        for (int l = 0; l < NT; ++l) sum += acc[s * NT + l];
+        const int col = inv[s];
+        ac[static_cast<int64_t>(j) * nc + col] = sum;
+        if (sum != 0.0) {
+            bl = max(bl, j - col);
+            bu = max(bu, col - j);
+        }
+    }
+    if (bl > 0) atomicMax(band, bl);
+    if (bu > 0) atomicMax(band + 1, bu);
+}
+
 // ---------------------------------------------------------------------------
 // Exact coarse inverse by blocked Gauss-Jordan elimination with partial
 // pivoting, in place on a row-major n x n matrix X.
@@ -423,76 +555,81 @@ __global__ __launch_bounds__(kBlock) void k_gj_permute(int n, const double *__re
 constexpr int kBP = 64;
 constexpr int kSuper = 128;  // columns per super-panel (a multiple of kBP)
 
-// G = D^{-1} by unblocked Gauss-Jordan in one wavefront: lane j keeps column
-// j of the 64 x 64 block in registers (rows past nb padded with the
-// identity).  Step c reads column c from lane c with a lane shuffle, so the loops
-// are fully unrolled and every register index is a constant.  Row c becomes
-// x_cj / d (1 / d in column c), every other row r becomes x_rj - x_rc x_cj / d
-// (-x_rc / d in column c).  Non-positive pivots set the flag.
-// one elimination step with a compile-time pivot index C; lane r holds row r
-// of the block, the pivot row is broadcast through LDS
+// G = D^{-1} for the 64 x 64 diagonal block D by unblocked Gauss-Jordan
+// without pivoting, in four wavefronts: lane r of wavefront w keeps row r,
+// columns 16w .. 16w+15, in registers (rows and columns past nb padded with
+// the identity).  In step c the pivot row c and the pivot column c are
+// published through LDS (double-buffered, so one barrier per step); row c
+// becomes x_cj / d (1 / d in column c) and every other row r becomes
+// x_rj - (x_rc / d) x_cj (-x_rc / d in column c).  The steps are unrolled so
+// every register index is a constant.  Non-positive pivots set the flag.
+constexpr int kDiagCols = kBP / 4;
+
 template <int C>
-__device__ __forceinline__ void gj_step(double (&v)[kBP], double *prow, int r, bool &bad)
+__device__ __forceinline__ void gj_step(double (&v)[kDiagCols], double (*prow)[kBP],
+                                        double (*pcol)[kBP], int r, int w, bool &bad)
 {
+    constexpr int B = C & 1, WC = C / kDiagCols, QC = C % kDiagCols;
     if (r == C) {
 #pragma unroll
-        for (int q = 0; q < kBP; q += 2)
-            *reinterpret_cast<double2 *>(prow + q) = double2{v[q], v[q + 1]};
+        for (int q = 0; q < kDiagCols; q += 2)
+            *reinterpret_cast<double2 *>(&prow[B][kDiagCols * w + q]) = double2{v[q], v[q + 1]};
     }
+    if (w == WC) pcol[B][r] = v[QC];
     __syncthreads();
-    double p[kBP];
+    double p[kDiagCols];
 #pragma unroll
-    for (int q = 0; q < kBP; q += 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(prow + q);
+    for (int q = 0; q < kDiagCols; q += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(&prow[B][kDiagCols * w + q]);
         p[q] = t.x;
         p[q + 1] = t.y;
     }
-    __syncthreads();
-    const double d = p[C];
+    const double d = prow[B][C];
+    const double f = pcol[B][r];
     bad |= !(d > 0.0);
     const double inv = 1.0 / d;
+    const bool own = w == WC;
     if (r == C) {
 #pragma unroll
-        for (int q = 0; q < kBP; ++q) v[q] = (q == C) ? inv : p[q] * inv;
+        for (int q = 0; q < kDiagCols; ++q) v[q] = (own && q == QC) ? inv : p[q] * inv;
     } else {
-        const double f = v[C] * inv;
+        const double g = f * inv;
 #pragma unroll
-        for (int q = 0; q < kBP; ++q) v[q] = (q == C) ? -f : v[q] - f * p[q];
+        for (int q = 0; q < kDiagCols; ++q) v[q] = (own && q == QC) ? -g : v[q] - g * p[q];
     }
 }
 
 template <int... Cs>
-__device__ __forceinline__ void gj_all(double (&v)[kBP], double *prow, int r, bool &bad,
+__device__ __forceinline__ void gj_all(double (&v)[kDiagCols], double (*prow)[kBP],
+                                       double (*pcol)[kBP], int r, int w, bool &bad,
                                        std::integer_sequence<int, Cs...>)
 {
-    (gj_step<Cs>(v, prow, r, bad), ...);
+    (gj_step<Cs>(v, prow, pcol, r, w, bad), ...);
 }
 
-// G = D^{-1} by unblocked Gauss-Jordan in one wavefront: lane r keeps row r
-// of the 64 x 64 block in registers (rows and columns past nb padded with
-// the identity).  In step c the pivot row c is broadcast through LDS; row c
-// becomes x_cj / d (1 / d in column c) and every other row r becomes
-// x_rj - (x_rc / d) x_cj (-x_rc / d in column c).  The loops are fully
-// unrolled so every register index is a constant.  Non-positive pivots set
-// the flag.
-__global__ __launch_bounds__(64) void k_bgj_diag(const double *__restrict__ X, int n, int k0,
-                                                 int nb, double *__restrict__ G,
-                                                 int *__restrict__ flag)
+__global__ __launch_bounds__(256) void k_bgj_diag(const double *__restrict__ X, int n, int k0,
+                                                  int nb, double *__restrict__ G,
+                                                  int *__restrict__ flag)
 {
-    __shared__ __attribute__((aligned(16))) double prow[kBP];
-    const int r = threadIdx.x;
-    double v[kBP];
+    __shared__ __attribute__((aligned(16))) double prow[2][kBP];
+    __shared__ double pcol[2][kBP];
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[kDiagCols];
 #pragma unroll
-    for (int q = 0; q < kBP; ++q)
-        v[q] = (r < nb && q < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + q]
-                                  : (r == q ? 1.0 : 0.0);
+    for (int q = 0; q < kDiagCols; ++q) {
+        const int col = kDiagCols * w + q;
+        v[q] = (r < nb && col < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + col]
+                                    : (r == col ? 1.0 : 0.0);
+    }
     bool bad = false;
-    gj_all(v, prow, r, bad, std::make_integer_sequence<int, kBP>{});
-    if (bad && r == 0) flag[0] = 1;
+    gj_all(v, prow, pcol, r, w, bad, std::make_integer_sequence<int, kBP>{});
+    if (bad && threadIdx.x == 0) flag[0] = 1;
     if (r < nb)
 #pragma unroll
-        for (int q = 0; q < kBP; ++q)
-            if (q < nb) G[r * kBP + q] = v[q];
+        for (int q = 0; q < kDiagCols; ++q) {
+            const int col = kDiagCols * w + q;
+            if (col < nb) G[r * kBP + col] = v[q];
+        }
 }
 
 // X[K, tile] <- G X[K, tile] for the column tiles left of cu other than K
@@ -787,15 +924,47 @@ void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp
                                                   pci, pv, ac, flag, band);
 }
 
+template <typename T, int ND>
+void rap_ell_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
+               const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
+               const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band)
+{
+    k_rap_ell<T, 128, ND><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac,
+                                                 flag, band);
+}
+
+template <typename T>
+bool rap_ell(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
+             const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
+             const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band)
+{
+    switch (d.n) {
+    case 3: rap_ell_t<T, 3>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
+    case 5: rap_ell_t<T, 5>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
+    case 7: rap_ell_t<T, 7>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
+    case 9: rap_ell_t<T, 9>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
+    default: return false;
+    }
+}
+
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
-                const int *pci, const double *pcsr, double *ac, int *flag, int *band)
+                const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
+                const double *pe64, const float *pe32, double *ac, int *flag, int *band)
 {
     // 128 threads while the per-thread partial sums fit in 32 KB of LDS
     const int nt = maxnb <= 32 ? 128 : 64;
     const size_t shmem = sizeof(double) * maxnb * nt + sizeof(int) * maxnb +
                          sizeof(short) * static_cast<size_t>(nc) + 16;
+    // stencil A and 8-wide ELL P: the batched form
+    if (nt == 128 && d.n > 0 && pw == 8 && pcol16) {
+        const bool done = fp32 ? rap_ell<float>(s, shmem, n, nc, maxnb, rrp, rci, r32, d, ad,
+                                                pcol16, pe32, ac, flag, band)
+                               : rap_ell<double>(s, shmem, n, nc, maxnb, rrp, rci, r64, d, ad,
+                                                 pcol16, pe64, ac, flag, band);
+        if (done) return;
+    }
     if (nt == 128) {
         if (fp32)
             rap_t<float, 128>(s, shmem, n, nc, maxnb, rrp, rci, r32, rp, ci, a, d, ad, prp, pci,
@@ -877,7 +1046,7 @@ msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu,
             const int nb = min(kBP, n - k0);
             const int rl = min(n, k0 + nb + bl);
             const int rtiles = (rl + kBP - 1) / kBP;
-            k_bgj_diag<<<1, 64, 0, s>>>(X, n, k0, nb, G, flag);
+            k_bgj_diag<<<1, 256, 0, s>>>(X, n, k0, nb, G, flag);
             const int inner = st1 - st0 - 1;  // super-panel column tiles other than K
             if (rtiles > 1) k_bgj_inner<<<rtiles - 1, 256, 0, s>>>(X, n, k0, nb, G, st0, inner);
             k_bgj_rowblock<<<inner + 1, 256, 0, s>>>(X, n, k0, nb, G, st0);

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restri
                                                      const double *__restrict__ x,
                                                      double *__restrict__ xc)
 {
-    const int j = blockIdx.x;
+    // neighbouring coarse rows share fine rows: keep them on one XCD
+    const int j = xcd_group(blockIdx.x, gridDim.x);
     double s = 0.0;
     const int t1 = rrp[j + 1];
     int t = rrp[j] + threadIdx.x;
@@ -257,8 +258,23 @@ __global__ __launch_bounds__(kBlock) void k_scale_by_inv(int n, const double *__
 // that all loads of a row are issued before the first product; ND == 0 takes
 // the count at run time.  A neighbour outside [0, n) reads row i instead and
 // the value is then replaced by zero.
+//
+// SYM: A is symmetric with symmetric offsets (off[o] = -off[ND-1-o]); the
+// coefficient of a lower offset is read from the mirrored upper diagonal at
+// the neighbour's row, A(i, i+off) = A(i+off, i), so only the diagonal and
+// the upper diagonals stream from memory (the mirrored reads are rows that
+// the same work-group or its XCD neighbours just loaded).
 // ---------------------------------------------------------------------------
-template <int ND, typename MT>
+template <int ND, bool SYM, typename MT>
+__device__ __forceinline__ MT dia_coef(const MT *__restrict__ a, int o, int i, int kk, int n)
+{
+    if constexpr (SYM) {
+        if (o < ND / 2) return a[static_cast<int64_t>(ND - 1 - o) * n + kk];
+    }
+    return a[static_cast<int64_t>(o) * n + i];
+}
+
+template <int ND, bool SYM, typename MT>
 __device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
                                       const MT *__restrict__ a, const double *__restrict__ x)
 {
@@ -270,8 +286,9 @@ __device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
         for (int o = 0; o < ND; ++o) {
             const int k = i + d.off[o];
             const bool in = k >= 0 && k < n;
-            av[o] = a[static_cast<int64_t>(o) * n + i];
-            const double t = x[in ? k : i];
+            const int kk = in ? k : i;
+            av[o] = dia_coef<ND, SYM>(a, o, i, kk, n);
+            const double t = x[kk];
             xv[o] = in ? t : 0.0;
         }
 #pragma unroll
@@ -383,29 +400,31 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *
     scal[S_RZ_OLD] = t[0];
 }
 
-template <int ND>
+template <int ND, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_dia_spmv(int n, DiaOffsets d,
                                                      const double *__restrict__ a,
                                                      const double *__restrict__ x,
                                                      double *__restrict__ y)
 {
     const int i = xcd_row();
-    if (i < n) y[i] = dia_dot<ND>(i, n, d, a, x);
+    if (i < n) y[i] = dia_dot<ND, SYM>(i, n, d, a, x);
 }
 
-template <int ND>
+// r = f - A x; with MT = float the matrix values and the products are FP32
+// (the residual inside the preconditioner of the precision form)
+template <int ND, bool SYM, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_residual(int n, DiaOffsets d,
-                                                         const double *__restrict__ a,
+                                                         const MT *__restrict__ a,
                                                          const double *__restrict__ f,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ r)
 {
     const int i = xcd_row();
-    if (i < n) r[i] = f[i] - dia_dot<ND>(i, n, d, a, x);
+    if (i < n) r[i] = f[i] - static_cast<double>(dia_dot<ND, SYM>(i, n, d, a, x));
 }
 
 // z_out = z_in + dinv (v - A z_in), smoother matrix and arithmetic in MT
-template <int ND, typename MT>
+template <int ND, bool SYM, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep(int n, DiaOffsets d, const MT *__restrict__ a,
                                                       const MT *__restrict__ dinv,
                                                       const double *__restrict__ v,
@@ -414,13 +433,13 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep(int n, DiaOffsets d, const
 {
     const int i = xcd_row();
     if (i >= n) return;
-    const MT res = static_cast<MT>(v[i]) - dia_dot<ND>(i, n, d, a, zin);
+    const MT res = static_cast<MT>(v[i]) - dia_dot<ND, SYM>(i, n, d, a, zin);
     zout[i] = zin[i] + static_cast<double>(dinv[i] * res);
 }
 
 // two sweeps from z = 0: z1 = dinv v, z2 = z1 + dinv (v - A z1), with z1 of
 // the neighbours recomputed on the fly
-template <int ND, typename MT>
+template <int ND, bool SYM, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
                                                             const MT *__restrict__ a,
                                                             const MT *__restrict__ dinv,
@@ -439,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
             const int k = i + d.off[o];
             in[o] = k >= 0 && k < n;
             const int kk = in[o] ? k : i;
-            av[o] = a[static_cast<int64_t>(o) * n + i];
+            av[o] = dia_coef<ND, SYM>(a, o, i, kk, n);
             dk[o] = dinv[kk];
             vk[o] = v[kk];
         }
@@ -464,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
 
 // last smoothing sweep of the preconditioner inside PCG, fused with the dot
 // products r.z and r.(z - z_old) and the flexible beta
-template <int ND, typename MT>
+template <int ND, bool SYM, typename MT>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep_dots(
     int n, DiaOffsets d, const MT *__restrict__ a, const MT *__restrict__ dinv,
     const double *__restrict__ r, const double *__restrict__ zin, double *__restrict__ zout,
@@ -473,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep_dots(
     const int i = xcd_row();
     double v[2] = {0.0, 0.0};
     if (i < n) {
-        const MT res = static_cast<MT>(r[i]) - dia_dot<ND>(i, n, d, a, zin);
+        const MT res = static_cast<MT>(r[i]) - dia_dot<ND, SYM>(i, n, d, a, zin);
         const double z = zin[i] + static_cast<double>(dinv[i] * res);
         zout[i] = z;
         v[0] = r[i] * z;
@@ -499,9 +518,9 @@ __global__ __launch_bounds__(kBlock) void k_dots_beta(int n, const double *__res
 }
 
 // p_new = z + beta p_old, q = A p_new, p_new.q and alpha = (r.z) / (p.q).
-// DIA: ND as in dia_dot; ND < 0 is the CSR form.  beta == 0 (a restart)
-// never reads p_old.
-template <int ND>
+// DIA: ND and SYM as in dia_dot; ND < 0 is the CSR form.  beta == 0 (a
+// restart) never reads p_old.
+template <int ND, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
     int n, DiaOffsets d, const double *__restrict__ ad, const int *__restrict__ rp,
     const int *__restrict__ ci, const double *__restrict__ a, const double *__restrict__ z,
@@ -523,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
                 const int k = i + d.off[o];
                 in[o] = k >= 0 && k < n;
                 kk[o] = in[o] ? k : i;
-                av[o] = ad[static_cast<int64_t>(o) * n + i];
+                av[o] = dia_coef<ND, SYM>(ad, o, i, kk[o], n);
             }
             if (restart) {
 #pragma unroll
@@ -584,10 +603,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict
     block_partials<1>(v, part);
 }
 
-// z (+)= P w_c with P in row-major ELL layout; a row (PW columns and
-// values) is read with 16-byte loads
+// z (+)= P w_c with P in row-major ELL layout; a row's values are read with
+// 16-byte loads and its coarse columns are 16-bit (0xFFFF marks padding)
 template <typename T, int PW>
-__global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const int *__restrict__ pcol,
+__global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *__restrict__ pcol,
                                                         const T *__restrict__ pv,
                                                         const double *__restrict__ wc,
                                                         double *__restrict__ z, int zero)
@@ -597,17 +616,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const int *__rest
     int col[PW];
     T val[PW];
     {
-        typedef int ivec __attribute__((ext_vector_type(4)));
+        typedef uint16_t cvec __attribute__((ext_vector_type(PW)));
         constexpr int L = 16 / sizeof(T);
         typedef T tvec __attribute__((ext_vector_type(L)));
-        const ivec *cs = reinterpret_cast<const ivec *>(pcol + static_cast<int64_t>(i) * PW);
+        const cvec cs = *reinterpret_cast<const cvec *>(pcol + static_cast<int64_t>(i) * PW);
+#pragma unroll
+        for (int u = 0; u < PW; ++u) col[u] = cs[u] == 0xFFFFu ? -1 : static_cast<int>(cs[u]);
         const tvec *vs = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * PW);
-#pragma unroll
-        for (int q = 0; q < PW / 4; ++q) {
-            const ivec c = cs[q];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) col[4 * q + u] = c[u];
-        }
 #pragma unroll
         for (int q = 0; q < PW / L; ++q) {
             const tvec v = vs[q];
@@ -615,8 +630,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const int *__rest
             for (int u = 0; u < L; ++u) val[L * q + u] = v[u];
         }
     }
-    // all gathers issued at once; padding slots (column -1) read entry 0 and
-    // contribute zero
+    // all gathers issued at once; padding slots read entry 0 and contribute
+    // zero
     double g[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) g[q] = wc[col[q] >= 0 ? col[q] : 0];
@@ -775,35 +790,52 @@ void launch_norm_scale(hipStream_t s, int n, const double *w, double *vout, doub
     k_scale_by_inv<<<grid_for(n), kBlock, 0, s>>>(n, w, out_norm2, vout);
 }
 
-// Calls f with std::integral_constant<int, ND>: the diagonal counts of 1D,
-// 2D and 3D point stencils and of the 9- and 27-point stencils get their own
-// instantiation, anything else the run-time form (ND = 0).
-template <typename F>
-void with_ndiag(int nd, F &&f)
+// Calls f(std::integral_constant<int, ND>, std::bool_constant<SYM>): the
+// diagonal counts of 1D, 2D and 3D point stencils and of the 9- and 27-point
+// stencils get their own instantiation, anything else the run-time form
+// (ND = 0, full storage).
+template <int ND, typename F>
+void with_sym(const DiaOffsets &d, F &&f)
 {
-    switch (nd) {
-    case 3: f(std::integral_constant<int, 3>{}); return;
-    case 5: f(std::integral_constant<int, 5>{}); return;
-    case 7: f(std::integral_constant<int, 7>{}); return;
-    case 9: f(std::integral_constant<int, 9>{}); return;
-    case 27: f(std::integral_constant<int, 27>{}); return;
-    default: f(std::integral_constant<int, 0>{}); return;
+    if (d.sym)
+        f(std::integral_constant<int, ND>{}, std::true_type{});
+    else
+        f(std::integral_constant<int, ND>{}, std::false_type{});
+}
+
+template <typename F>
+void with_ndiag(const DiaOffsets &d, F &&f)
+{
+    switch (d.n) {
+    case 3: with_sym<3>(d, f); return;
+    case 5: with_sym<5>(d, f); return;
+    case 7: with_sym<7>(d, f); return;
+    case 9: with_sym<9>(d, f); return;
+    case 27: with_sym<27>(d, f); return;
+    default: f(std::integral_constant<int, 0>{}, std::false_type{}); return;
     }
 }
+
+#define MSRSB_DIA_ARGS(nd, sym) decltype(nd)::value, decltype(sym)::value
 
 void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,
                      double *y)
 {
-    with_ndiag(d.n, [&](auto nd) {
-        k_dia_spmv<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(n, d, a, x, y);
+    with_ndiag(d, [&](auto nd, auto sym) {
+        k_dia_spmv<MSRSB_DIA_ARGS(nd, sym)><<<grid_for(n), kBlock, 0, s>>>(n, d, a, x, y);
     });
 }
 
 void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
-                         const double *f, const double *x, double *r)
+                         const float *a32, const double *f, const double *x, double *r)
 {
-    with_ndiag(d.n, [&](auto nd) {
-        k_dia_residual<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(n, d, a, f, x, r);
+    with_ndiag(d, [&](auto nd, auto sym) {
+        if (a32)
+            k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a32, f, x, r);
+        else
+            k_dia_residual<MSRSB_DIA_ARGS(nd, sym), double><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a, f, x, r);
     });
 }
 
@@ -811,20 +843,20 @@ void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, cons
                       const float *a32, const double *dinv64, const float *dinv32,
                       const double *v, const double *zin, double *zout, bool zero2)
 {
-    with_ndiag(d.n, [&](auto nd) {
-        constexpr int ND = decltype(nd)::value;
+    with_ndiag(d, [&](auto nd, auto sym) {
         if (zero2) {
             if (fp32)
-                k_dia_sweep2_zero<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v,
-                                                                            zout);
+                k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float>
+                    <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zout);
             else
-                k_dia_sweep2_zero<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v,
-                                                                             zout);
+                k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), double>
+                    <<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zout);
         } else if (fp32) {
-            k_dia_sweep<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, zin, zout);
+            k_dia_sweep<MSRSB_DIA_ARGS(nd, sym), float><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a32, dinv32, v, zin, zout);
         } else {
-            k_dia_sweep<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, v, zin,
-                                                                   zout);
+            k_dia_sweep<MSRSB_DIA_ARGS(nd, sym), double><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a64, dinv64, v, zin, zout);
         }
     });
 }
@@ -834,14 +866,13 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                            const float *dinv32, const double *r, const double *zin, double *zout,
                            const double *zold, double *part, double *scal)
 {
-    with_ndiag(d.n, [&](auto nd) {
-        constexpr int ND = decltype(nd)::value;
+    with_ndiag(d, [&](auto nd, auto sym) {
         if (fp32)
-            k_dia_sweep_dots<ND, float><<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, r, zin,
-                                                                       zout, zold, part);
+            k_dia_sweep_dots<MSRSB_DIA_ARGS(nd, sym), float><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a32, dinv32, r, zin, zout, zold, part);
         else
-            k_dia_sweep_dots<ND, double><<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, r, zin,
-                                                                        zout, zold, part);
+            k_dia_sweep_dots<MSRSB_DIA_ARGS(nd, sym), double><<<grid_for(n), kBlock, 0, s>>>(
+                n, d, a64, dinv64, r, zin, zout, zold, part);
     });
     k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
@@ -858,13 +889,13 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
                        const double *pold, double *pnew, double *q, double *part, double *scal)
 {
     if (d.n > 0)
-        with_ndiag(d.n, [&](auto nd) {
-            k_pcg_p_spmv<decltype(nd)::value><<<grid_for(n), kBlock, 0, s>>>(
+        with_ndiag(d, [&](auto nd, auto sym) {
+            k_pcg_p_spmv<MSRSB_DIA_ARGS(nd, sym)><<<grid_for(n), kBlock, 0, s>>>(
                 n, d, ad, rp, ci, a, z, pold, pnew, q, part, scal);
         });
     else
-        k_pcg_p_spmv<-1><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew, q,
-                                                        part, scal);
+        k_pcg_p_spmv<-1, false><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew,
+                                                               q, part, scal);
     k_fin_alpha<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
 
@@ -876,25 +907,25 @@ void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double 
 }
 
 template <typename T>
-void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const T *pv, const double *wc,
-               double *z, bool zero)
+void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16, const T *pv,
+               const double *wc, double *z, bool zero)
 {
-    if (pw == 4)
-        k_prolong_ell<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, pcol, pv, wc, z, zero ? 1 : 0);
-    else if (pw == 8)
-        k_prolong_ell<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, pcol, pv, wc, z, zero ? 1 : 0);
+    if (pcol16 && pw == 4)
+        k_prolong_ell<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, pv, wc, z, zero ? 1 : 0);
+    else if (pcol16 && pw == 8)
+        k_prolong_ell<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, pv, wc, z, zero ? 1 : 0);
     else
         k_prolong_ell_w<T><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, pv, wc, z, zero ? 1 : 0);
 }
 
-void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
-                        const double *p64, const float *p32, const double *wc, double *z,
-                        bool zero)
+void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
+                        bool fp32, const double *p64, const float *p32, const double *wc,
+                        double *z, bool zero)
 {
     if (fp32)
-        prolong_t<float>(s, n, pw, pcol, p32, wc, z, zero);
+        prolong_t<float>(s, n, pw, pcol, pcol16, p32, wc, z, zero);
     else
-        prolong_t<double>(s, n, pw, pcol, p64, wc, z, zero);
+        prolong_t<double>(s, n, pw, pcol, pcol16, p64, wc, z, zero);
 }
 
 void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,

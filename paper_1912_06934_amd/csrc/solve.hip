@@ -91,7 +91,7 @@ struct Op {
 Op fine_op(msrsb_ctx *c, bool trans)
 {
     Op o;
-    if (!trans) {
+    if (!trans || c->a_symmetric) {  // A^T = A: share A's data
         o.rp = c->rp;
         o.ci = c->ci;
         o.a = c->a;
@@ -119,10 +119,13 @@ Op fine_op(msrsb_ctx *c, bool trans)
     return o;
 }
 
-void op_residual(hipStream_t s, int n, const Op &o, const double *f, const double *x, double *r)
+// r = f - A x; fp32 (inside the preconditioner of the precision form) uses
+// the FP32 copy of A's stencil values when there is one
+void op_residual(hipStream_t s, int n, const Op &o, const double *f, const double *x, double *r,
+                 bool fp32 = false)
 {
     if (o.d.n > 0)
-        launch_dia_residual(s, n, o.d, o.ad, f, x, r);
+        launch_dia_residual(s, n, o.d, o.ad, fp32 ? o.ad32 : nullptr, f, x, r);
     else
         launch_residual(s, n, o.rp, o.ci, o.a, f, x, r);
 }
@@ -206,6 +209,7 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
     const bool fp32 = o->fp32_smoother != 0;
     const size_t n = static_cast<size_t>(c->n);
     hipStream_t s = c->stream;
+    if (c->a_symmetric) trans = false;  // the smoothers of A^T are those of A
     const int noff = trans ? c->at_off.n : c->a_off.n;
     if (!trans) {
         if (!c->smoother_valid || (fp32 && !c->smoother32_valid)) {
@@ -287,12 +291,13 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     if (o->use_multiscale) {
         const double *res = v;
         if (!zero) {
-            op_residual(s, n, op, v, z, tmp);
+            op_residual(s, n, op, v, z, tmp, fp32);
             res = tmp;
         }
         launch_restrict(s, c->nc, c->rrp, c->rci, c->p_is32, c->r64, c->r32, res, c->vc);
-        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
-        launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
+        // the inverse from the SPD path is symmetric: no transposed product
+        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
+        launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
                            c->wc, z, zero);
         zero = false;
     }
