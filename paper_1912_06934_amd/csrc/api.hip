@@ -132,6 +132,7 @@ void free_matrix(msrsb_ctx *c)
     dfree(c->dinv_jac32_t);
     dfree(c->dinv_l1_32_t);
     for (auto &p : c->w) dfree(p);
+    for (auto &p : c->wf) dfree(p);
     dfree(c->gm_v);
     dfree(c->gm_h);
     c->gm_cap = 0;

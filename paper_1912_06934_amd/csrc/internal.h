@@ -159,6 +159,7 @@ struct msrsb_ctx {
 
     // Krylov workspace
     double *w[12] = {};
+    float *wf[3] = {};            // FP32 work vectors of the precision-form preconditioner
     double *vc = nullptr, *wc = nullptr;
     double *partials = nullptr, *scal = nullptr;
     double *gm_v = nullptr, *gm_h = nullptr;  // GMRES basis and small arrays
@@ -289,6 +290,13 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
                        const double *pold, double *pnew, double *q, double *part, double *scal);
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
                        const double *q, double *part, double *scal, double *host_out);
+void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
+                         const float *dinv32, const double *v, float *z1, float *tmp, int nc,
+                         const int *rrp, const int *rci, const float *r32, double *vc);
+void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
+                          const float *dinv32, const double *v, float *z1, float *z2, int pw,
+                          const uint16_t *pcol16, const float *p32, const double *wc,
+                          double *zout, const double *zold, double *partials, double *scal);
 void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
                         bool fp32, const double *p64, const float *p32, const double *wc,
                         double *z, bool zero);

@@ -681,14 +681,23 @@ __global__ __launch_bounds__(256) void k_bgj_rowblock(double *__restrict__ X, in
 
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 
+// LDS row stride (doubles) of the MFMA operand tiles: a 16 x 16 x 4 operand
+// read touches 16 rows x 4 k, which with a stride of 68 fall on 32 distinct
+// bank pairs (two lanes each, the minimum for 64 double loads)
+constexpr int kLds = kBP + 4;
+
 // acc (a wavefront's 32 x 32 quadrant at (wr, wc)) += A B for 64 x 64
-// operands in LDS, on the FP64 matrix cores
-__device__ inline void mfma_tile64(const double (*A)[kBP + 1], const double (*B)[kBP + 1],
+// operands in LDS on the FP64 matrix cores; A is stored by rows, A[row][k],
+// and B by columns, Bt[col][k].  Operand lane l of the 16 x 16 x 4
+// instruction holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register
+// q of lane l is D[4q + l / 16][l % 16].
+__device__ inline void mfma_tile64(const double (*A)[kLds], const double (*Bt)[kLds],
                                    mfma_f64x4 (&acc)[2][2], int wr, int wc, int li, int lk)
 {
+#pragma unroll 4
     for (int kk = 0; kk < kBP; kk += 4) {
         const double a0 = A[wr + li][kk + lk], a1 = A[wr + 16 + li][kk + lk];
-        const double b0 = B[kk + lk][wc + li], b1 = B[kk + lk][wc + 16 + li];
+        const double b0 = Bt[wc + li][kk + lk], b1 = Bt[wc + 16 + li][kk + lk];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -714,15 +723,18 @@ __device__ inline void zero_acc(mfma_f64x4 (&acc)[2][2])
 __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n, int k0, int nb,
                                                    const double *__restrict__ G, int ct0, int nct)
 {
-    __shared__ double Gs[kBP][kBP + 1];
-    __shared__ double As[kBP][kBP + 1];  // X[R, K] before this panel
-    __shared__ double Ks[kBP][kBP + 1];  // X[K, t], then G X[K, t]
+    __shared__ double Gs[kBP][kLds];  // G by rows
+    __shared__ double Gt[kBP][kLds];  // G by columns
+    __shared__ double As[kBP][kLds];  // X[R, K] before this panel, by rows
+    __shared__ double Kt[kBP][kLds];  // X[K, t] by columns, then (G X[K, t]) by columns
     const int kt = k0 / kBP;
     const int tr = blockIdx.x < kt ? blockIdx.x : blockIdx.x + 1;
     const int r0 = tr * kBP;
     for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
         const int a = e / kBP, b = e % kBP;
-        Gs[a][b] = (a < nb && b < nb) ? G[a * kBP + b] : 0.0;
+        const double g = (a < nb && b < nb) ? G[a * kBP + b] : 0.0;
+        Gs[a][b] = g;
+        Gt[b][a] = g;
         As[a][b] = (r0 + a < n && b < nb) ? X[static_cast<int64_t>(r0 + a) * n + k0 + b] : 0.0;
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -735,11 +747,11 @@ __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n
         __syncthreads();
         for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
             const int a = e / kBP, b = e % kBP;
-            Ks[a][b] = (a < nb && c0 + b < n) ? X[static_cast<int64_t>(k0 + a) * n + c0 + b] : 0.0;
+            Kt[b][a] = (a < nb && c0 + b < n) ? X[static_cast<int64_t>(k0 + a) * n + c0 + b] : 0.0;
         }
         __syncthreads();
         zero_acc(acc);
-        mfma_tile64(Gs, Ks, acc, wr, wc, li, lk);
+        mfma_tile64(Gs, Kt, acc, wr, wc, li, lk);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -747,10 +759,10 @@ __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n
             for (int v = 0; v < 2; ++v)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    Ks[wr + 16 * p + 4 * q + lk][wc + 16 * v + li] = acc[p][v][q];
+                    Kt[wc + 16 * v + li][wr + 16 * p + 4 * q + lk] = acc[p][v][q];
         __syncthreads();
         zero_acc(acc);
-        mfma_tile64(As, Ks, acc, wr, wc, li, lk);
+        mfma_tile64(As, Kt, acc, wr, wc, li, lk);
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -764,7 +776,7 @@ __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n
     }
     __syncthreads();
     zero_acc(acc);
-    mfma_tile64(As, Gs, acc, wr, wc, li, lk);
+    mfma_tile64(As, Gt, acc, wr, wc, li, lk);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -793,12 +805,14 @@ __global__ __launch_bounds__(kBlock) void k_bgj_extract(double *__restrict__ X, 
 // X[R, C] += X[R, S] B[:, C] for row tiles below the band limit and column
 // tiles outside the super-panel S = [s0, s0 + ns) (ns a multiple of 64); the
 // super-panel's combined Gauss-Jordan transformation applied to the other
-// columns.  FP64 matrix cores, layout as in mfma_tile64.
+// columns, on the FP64 matrix cores (mfma_tile64).  The next 64-deep chunk of
+// X[R, S] and B is loaded into registers while the current one is
+// multiplied, and the X[R, C] tile is fetched at the start.
 __global__ __launch_bounds__(256) void k_bgj_outer(double *__restrict__ X, int n, int s0, int ns,
                                                    const double *__restrict__ B)
 {
-    __shared__ double As[kBP][kBP + 1];
-    __shared__ double Bs[kBP][kBP + 1];
+    __shared__ double As[kBP][kLds];
+    __shared__ double Bt[kBP][kLds];
     const int st0 = s0 / kBP, nst = (ns + kBP - 1) / kBP;
     const int tr = blockIdx.y;
     const int tc = blockIdx.x < st0 ? blockIdx.x : blockIdx.x + nst;
@@ -806,29 +820,44 @@ __global__ __launch_bounds__(256) void k_bgj_outer(double *__restrict__ X, int n
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    mfma_f64x4 acc[2][2];
+    // the output tile, in the accumulator layout
+    double xo[2][2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wr + 16 * u + 4 * q + lk;
+                const int c = c0 + wc + 16 * v + li;
+                xo[u][v][q] = (r < n && c < n) ? X[static_cast<int64_t>(r) * n + c] : 0.0;
+            }
+    // thread t loads rows t / 64 + 4 k, column t % 64 of each 64 x 64 chunk
+    const int lr = threadIdx.x >> 6, lc = threadIdx.x & 63;
+    double ra[16], rb[16];
+    auto fetch = [&](int kb) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int a = lr + 4 * k;
+            ra[k] = (r0 + a < n && kb + lc < ns)
+                        ? X[static_cast<int64_t>(r0 + a) * n + s0 + kb + lc] : 0.0;
+            rb[k] = (kb + a < ns && c0 + lc < n) ? B[static_cast<int64_t>(kb + a) * n + c0 + lc]
+                                                 : 0.0;
+        }
+    };
+    mfma_f64x4 acc[2][2];
+    zero_acc(acc);
+    fetch(0);
     for (int kb = 0; kb < ns; kb += kBP) {
         __syncthreads();
-        for (int t = threadIdx.x; t < kBP * kBP; t += 256) {
-            const int a = t / kBP, b = t % kBP;
-            As[a][b] = (r0 + a < n && kb + b < ns)
-                           ? X[static_cast<int64_t>(r0 + a) * n + s0 + kb + b] : 0.0;
-            Bs[a][b] = (kb + a < ns && c0 + b < n) ? B[static_cast<int64_t>(kb + a) * n + c0 + b]
-                                                    : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            As[lr + 4 * k][lc] = ra[k];
+            Bt[lc][lr + 4 * k] = rb[k];
         }
         __syncthreads();
-        for (int kk = 0; kk < kBP; kk += 4) {
-            const double a0 = As[wr + li][kk + lk], a1 = As[wr + 16 + li][kk + lk];
-            const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
+        if (kb + kBP < ns) fetch(kb + kBP);
+        mfma_tile64(As, Bt, acc, wr, wc, li, lk);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -838,7 +867,7 @@ __global__ __launch_bounds__(256) void k_bgj_outer(double *__restrict__ X, int n
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + wr + 16 * u + 4 * q + lk;
                 const int c = c0 + wc + 16 * v + li;
-                if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] += acc[u][v][q];
+                if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] = xo[u][v][q] + acc[u][v][q];
             }
 }
 

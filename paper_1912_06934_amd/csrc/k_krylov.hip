@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
 }
 
 // v_c = R x with R = P^T stored by coarse rows: one work-group per coarse row
-template <typename T>
+template <typename T, typename XT>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restrict__ rrp,
                                                      const int *__restrict__ rci,
                                                      const T *__restrict__ rv,
-                                                     const double *__restrict__ x,
+                                                     const XT *__restrict__ x,
                                                      double *__restrict__ xc)
 {
     // neighbouring coarse rows share fine rows: keep them on one XCD
@@ -132,11 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restri
         }
         double xv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+        for (int u = 0; u < 4; ++u) xv[u] = static_cast<double>(x[c[u]]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) s += static_cast<double>(v[u]) * xv[u];
     }
-    for (; t < t1; t += kBlock) s += static_cast<double>(rv[t]) * x[rci[t]];
+    for (; t < t1; t += kBlock) s += static_cast<double>(rv[t]) * static_cast<double>(x[rci[t]]);
     s = block_sum(s);
     if (threadIdx.x == 0) xc[j] = s;
 }
@@ -274,9 +274,9 @@ __device__ __forceinline__ MT dia_coef(const MT *__restrict__ a, int o, int i, i
     return a[static_cast<int64_t>(o) * n + i];
 }
 
-template <int ND, bool SYM, typename MT>
+template <int ND, bool SYM, typename MT, typename XT>
 __device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
-                                      const MT *__restrict__ a, const double *__restrict__ x)
+                                      const MT *__restrict__ a, const XT *__restrict__ x)
 {
     MT s = MT(0);
     if constexpr (ND > 0) {
@@ -288,7 +288,7 @@ __device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
             const bool in = k >= 0 && k < n;
             const int kk = in ? k : i;
             av[o] = dia_coef<ND, SYM>(a, o, i, kk, n);
-            const double t = x[kk];
+            const double t = static_cast<double>(x[kk]);
             xv[o] = in ? t : 0.0;
         }
 #pragma unroll
@@ -297,7 +297,7 @@ __device__ __forceinline__ MT dia_dot(int i, int n, const DiaOffsets &d,
         for (int o = 0; o < d.n; ++o) {
             const int k = i + d.off[o];
             const MT av = a[static_cast<int64_t>(o) * n + i];
-            const double xv = (k >= 0 && k < n) ? x[k] : 0.0;
+            const double xv = (k >= 0 && k < n) ? static_cast<double>(x[k]) : 0.0;
             s += av * static_cast<MT>(xv);
         }
     }
@@ -412,39 +412,39 @@ __global__ __launch_bounds__(kBlock) void k_dia_spmv(int n, DiaOffsets d,
 
 // r = f - A x; with MT = float the matrix values and the products are FP32
 // (the residual inside the preconditioner of the precision form)
-template <int ND, bool SYM, typename MT>
+template <int ND, bool SYM, typename MT, typename XT = double, typename RT = double>
 __global__ __launch_bounds__(kBlock) void k_dia_residual(int n, DiaOffsets d,
                                                          const MT *__restrict__ a,
                                                          const double *__restrict__ f,
-                                                         const double *__restrict__ x,
-                                                         double *__restrict__ r)
+                                                         const XT *__restrict__ x,
+                                                         RT *__restrict__ r)
 {
     const int i = xcd_row();
-    if (i < n) r[i] = f[i] - static_cast<double>(dia_dot<ND, SYM>(i, n, d, a, x));
+    if (i < n) r[i] = static_cast<RT>(f[i] - static_cast<double>(dia_dot<ND, SYM>(i, n, d, a, x)));
 }
 
 // z_out = z_in + dinv (v - A z_in), smoother matrix and arithmetic in MT
-template <int ND, bool SYM, typename MT>
+template <int ND, bool SYM, typename MT, typename ZT = double>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep(int n, DiaOffsets d, const MT *__restrict__ a,
                                                       const MT *__restrict__ dinv,
                                                       const double *__restrict__ v,
-                                                      const double *__restrict__ zin,
-                                                      double *__restrict__ zout)
+                                                      const ZT *__restrict__ zin,
+                                                      ZT *__restrict__ zout)
 {
     const int i = xcd_row();
     if (i >= n) return;
     const MT res = static_cast<MT>(v[i]) - dia_dot<ND, SYM>(i, n, d, a, zin);
-    zout[i] = zin[i] + static_cast<double>(dinv[i] * res);
+    zout[i] = static_cast<ZT>(static_cast<double>(zin[i]) + static_cast<double>(dinv[i] * res));
 }
 
 // two sweeps from z = 0: z1 = dinv v, z2 = z1 + dinv (v - A z1), with z1 of
 // the neighbours recomputed on the fly
-template <int ND, bool SYM, typename MT>
+template <int ND, bool SYM, typename MT, typename ZT = double>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
                                                             const MT *__restrict__ a,
                                                             const MT *__restrict__ dinv,
                                                             const double *__restrict__ v,
-                                                            double *__restrict__ zout)
+                                                            ZT *__restrict__ zout)
 {
     const int i = xcd_row();
     if (i >= n) return;
@@ -478,22 +478,22 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
         }
     }
     const double z1i = static_cast<double>(dinv[i] * static_cast<MT>(v[i]));
-    zout[i] = z1i + static_cast<double>(dinv[i] * (static_cast<MT>(v[i]) - s));
+    zout[i] = static_cast<ZT>(z1i + static_cast<double>(dinv[i] * (static_cast<MT>(v[i]) - s)));
 }
 
 // last smoothing sweep of the preconditioner inside PCG, fused with the dot
 // products r.z and r.(z - z_old) and the flexible beta
-template <int ND, bool SYM, typename MT>
+template <int ND, bool SYM, typename MT, typename ZT = double>
 __global__ __launch_bounds__(kBlock) void k_dia_sweep_dots(
     int n, DiaOffsets d, const MT *__restrict__ a, const MT *__restrict__ dinv,
-    const double *__restrict__ r, const double *__restrict__ zin, double *__restrict__ zout,
+    const double *__restrict__ r, const ZT *__restrict__ zin, double *__restrict__ zout,
     const double *__restrict__ zold, double *__restrict__ part)
 {
     const int i = xcd_row();
     double v[2] = {0.0, 0.0};
     if (i < n) {
         const MT res = static_cast<MT>(r[i]) - dia_dot<ND, SYM>(i, n, d, a, zin);
-        const double z = zin[i] + static_cast<double>(dinv[i] * res);
+        const double z = static_cast<double>(zin[i]) + static_cast<double>(dinv[i] * res);
         zout[i] = z;
         v[0] = r[i] * z;
         v[1] = r[i] * (z - zold[i]);
@@ -605,11 +605,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict
 
 // z (+)= P w_c with P in row-major ELL layout; a row's values are read with
 // 16-byte loads and its coarse columns are 16-bit (0xFFFF marks padding)
-template <typename T, int PW>
+template <typename T, int PW, typename ZT = double>
 __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *__restrict__ pcol,
                                                         const T *__restrict__ pv,
                                                         const double *__restrict__ wc,
-                                                        double *__restrict__ z, int zero)
+                                                        ZT *__restrict__ z, int zero)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *_
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < PW; ++q) s += col[q] >= 0 ? static_cast<double>(val[q]) * g[q] : 0.0;
-    z[i] = zero ? s : z[i] + s;
+    z[i] = static_cast<ZT>(zero ? s : static_cast<double>(z[i]) + s);
 }
 
 // generic width (rows wider than 8)
@@ -728,9 +728,15 @@ void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool
                      const double *r64, const float *r32, const double *x, double *xc)
 {
     if (fp32)
-        k_restrict<float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
+        k_restrict<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
     else
-        k_restrict<double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
+        k_restrict<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
+}
+
+void launch_restrict_f32x(hipStream_t s, int nc, const int *rrp, const int *rci,
+                          const float *r32, const float *x, double *xc)
+{
+    k_restrict<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
 }
 
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
@@ -875,6 +881,44 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                 n, d, a64, dinv64, r, zin, zout, zold, part);
     });
     k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+}
+
+// The two-stage preconditioner of the precision form with FP32 intermediate
+// vectors (stencil A, l1/point-Jacobi x2 pre and post, 4- or 8-wide P): the
+// smoothing iterates, the residual fed to the restriction and the
+// prolongation's output are FP32; the final sweep writes the FP64 z and the
+// PCG dots.  _pre: z1 = two sweeps from zero, tmp = v - A z1, vc = R tmp.
+void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
+                         const float *dinv32, const double *v, float *z1, float *tmp, int nc,
+                         const int *rrp, const int *rci, const float *r32, double *vc)
+{
+    with_ndiag(d, [&](auto nd, auto sym) {
+        k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
+            n, d, a32, dinv32, v, z1);
+        k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
+            <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
+    });
+    k_restrict<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
+}
+
+// _post: z1 += P wc, z2 = sweep(z1), z = sweep(z2) with r.z, r.(z - zold)
+// and the flexible beta
+void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
+                          const float *dinv32, const double *v, float *z1, float *z2, int pw,
+                          const uint16_t *pcol16, const float *p32, const double *wc,
+                          double *zout, const double *zold, double *partials, double *scal)
+{
+    if (pw == 8)
+        k_prolong_ell<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, p32, wc, z1, 0);
+    else
+        k_prolong_ell<float, 4, float><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, p32, wc, z1, 0);
+    with_ndiag(d, [&](auto nd, auto sym) {
+        k_dia_sweep<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
+            n, d, a32, dinv32, v, z1, z2);
+        k_dia_sweep_dots<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
+            n, d, a32, dinv32, v, z2, zout, zold, partials);
+    });
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), partials, scal);
 }
 
 void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, const double *zold,

@@ -185,6 +185,8 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
     const size_t n = static_cast<size_t>(c->n);
     for (auto &p : c->w)
         if (dev_alloc(&p, n)) return MSRSB_E_NOMEM;
+    for (auto &p : c->wf)
+        if (dev_alloc(&p, n)) return MSRSB_E_NOMEM;
     const size_t np = std::max<size_t>({2 * (n / kBlock + 2), 2 * static_cast<size_t>(kReduceBlocks),
                                         64 * static_cast<size_t>(std::max(c->nc, 1)) + 64,
                                         static_cast<size_t>(64 * 66)});
@@ -275,6 +277,20 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     if (pre_k == MSRSB_SMOOTH_NONE) pre_n = 0;
     if (post_k == MSRSB_SMOOTH_NONE) post_n = 0;
     double *z = c->w[8], *spare = c->w[9], *tmp = c->w[10];
+    // precision form inside PCG with two Jacobi-type sweeps on each side of a
+    // stencil operator: FP32 intermediate vectors (launch_prec_f32_*)
+    if (fp32 && dots && o->use_multiscale && op.d.n > 0 && c->pcol16 && c->p_is32 &&
+        (c->pw == 4 || c->pw == 8) && is_diag(pre_k) && pre_n == 2 && pre_k == post_k &&
+        post_n == 2) {
+        const float *dinv = pre_k == MSRSB_SMOOTH_L1JACOBI ? op.dl132 : op.dj32;
+        float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
+        launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci, c->r32,
+                            c->vc);
+        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
+        launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
+                             c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal);
+        return;
+    }
     bool zero = true;
     int t = 0;
     if (pre_n >= 2 && is_diag(pre_k) && op.d.n > 0) {
