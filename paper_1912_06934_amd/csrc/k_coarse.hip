@@ -887,7 +887,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double *__restrict
         const double2 *m2 = reinterpret_cast<const double2 *>(mr);
         const double2 *x2 = reinterpret_cast<const double2 *>(x);
         const int h = n >> 1;
-#pragma unroll 4
+#pragma unroll 8
         for (int c = lane; c < h; c += 64) {
             const double2 a = m2[c], b = x2[c];
             s += a.x * b.x + a.y * b.y;

@@ -108,37 +108,41 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
     zout[i] = zin[i] + static_cast<double>(dinv[i] * (static_cast<float>(v[i]) - s));
 }
 
-// v_c = R x with R = P^T stored by coarse rows: one work-group per coarse row
+// v_c = R x with R = P^T stored by coarse rows: one wavefront per coarse
+// row (four rows per work-group, neighbouring coarse rows, which share fine
+// rows, on one XCD), eight entries per lane and step in flight, a butterfly
+// sum at the end.
 template <typename T, typename XT>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int *__restrict__ rrp,
-                                                     const int *__restrict__ rci,
-                                                     const T *__restrict__ rv,
-                                                     const XT *__restrict__ x,
-                                                     double *__restrict__ xc)
+__global__ __launch_bounds__(kBlock) void k_restrict_w(int nc, const int *__restrict__ rrp,
+                                                       const int *__restrict__ rci,
+                                                       const T *__restrict__ rv,
+                                                       const XT *__restrict__ x,
+                                                       double *__restrict__ xc)
 {
-    // neighbouring coarse rows share fine rows: keep them on one XCD
-    const int j = xcd_group(blockIdx.x, gridDim.x);
+    const int j = xcd_group(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= nc) return;
     double s = 0.0;
     const int t1 = rrp[j + 1];
-    int t = rrp[j] + threadIdx.x;
-    // four entries per step: their indices, values and gathers in flight together
-    for (; t + 3 * kBlock < t1; t += 4 * kBlock) {
-        int c[4];
-        T v[4];
+    int t = rrp[j] + lane;
+    for (; t + 7 * 64 < t1; t += 8 * 64) {
+        int c[8];
+        T v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = rci[t + u * kBlock];
-            v[u] = rv[t + u * kBlock];
+        for (int u = 0; u < 8; ++u) {
+            c[u] = rci[t + u * 64];
+            v[u] = rv[t + u * 64];
         }
-        double xv[4];
+        double xv[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = static_cast<double>(x[c[u]]);
+        for (int u = 0; u < 8; ++u) xv[u] = static_cast<double>(x[c[u]]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s += static_cast<double>(v[u]) * xv[u];
+        for (int u = 0; u < 8; ++u) s += static_cast<double>(v[u]) * xv[u];
     }
-    for (; t < t1; t += kBlock) s += static_cast<double>(rv[t]) * static_cast<double>(x[rci[t]]);
-    s = block_sum(s);
-    if (threadIdx.x == 0) xc[j] = s;
+    for (; t < t1; t += 64) s += static_cast<double>(rv[t]) * static_cast<double>(x[rci[t]]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) xc[j] = s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
@@ -728,15 +732,9 @@ void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool
                      const double *r64, const float *r32, const double *x, double *xc)
 {
     if (fp32)
-        k_restrict<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
+        k_restrict_w<float, double><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
     else
-        k_restrict<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
-}
-
-void launch_restrict_f32x(hipStream_t s, int nc, const int *rrp, const int *rci,
-                          const float *r32, const float *x, double *xc)
-{
-    k_restrict<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
+        k_restrict_w<double, double><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
 }
 
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
@@ -898,7 +896,7 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
-    k_restrict<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
+    k_restrict_w<float, float><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
 }
 
 // _post: z1 += P wc, z2 = sweep(z1), z = sweep(z2) with r.z, r.(z - zold)
