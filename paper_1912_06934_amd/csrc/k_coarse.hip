@@ -589,13 +589,15 @@ __device__ __forceinline__ void gj_step(double (&v)[kDiagCols], double (*prow)[k
     bad |= !(d > 0.0);
     const double inv = 1.0 / d;
     const bool own = w == WC;
-    if (r == C) {
+    // one branch-free form for the pivot row (base 0, factor -1/d) and the
+    // other rows (base x_rj, factor x_rc / d): v_j <- base_j - g p_j, and
+    // column c gets -g
+    const bool piv = r == C;
+    const double g = piv ? -inv : f * inv;
 #pragma unroll
-        for (int q = 0; q < kDiagCols; ++q) v[q] = (own && q == QC) ? inv : p[q] * inv;
-    } else {
-        const double g = f * inv;
-#pragma unroll
-        for (int q = 0; q < kDiagCols; ++q) v[q] = (own && q == QC) ? -g : v[q] - g * p[q];
+    for (int q = 0; q < kDiagCols; ++q) {
+        const double base = piv ? 0.0 : v[q];
+        v[q] = (own && q == QC) ? -g : base - g * p[q];
     }
 }
 
