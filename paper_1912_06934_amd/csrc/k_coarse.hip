@@ -555,83 +555,115 @@ __global__ __launch_bounds__(kBlock) void k_gj_permute(int n, const double *__re
 constexpr int kBP = 64;
 constexpr int kSuper = 128;  // columns per super-panel (a multiple of kBP)
 
-// G = D^{-1} for the 64 x 64 diagonal block D by unblocked Gauss-Jordan
-// without pivoting, in four wavefronts: lane r of wavefront w keeps row r,
-// columns 16w .. 16w+15, in registers (rows and columns past nb padded with
-// the identity).  In step c the pivot row c and the pivot column c are
-// published through LDS (double-buffered, so one barrier per step); row c
-// becomes x_cj / d (1 / d in column c) and every other row r becomes
-// x_rj - (x_rc / d) x_cj (-x_rc / d in column c).  The steps are unrolled so
-// every register index is a constant.  Non-positive pivots set the flag.
-constexpr int kDiagCols = kBP / 4;
+// G = D^{-1} for the 64 x 64 diagonal block D by Gauss-Jordan without
+// pivoting, blocked by 16 (the same elimination as the unblocked one, grouped
+// in four sub-panels P of 16 pivots; Q = the other 48 indices):
+//   M_PP <- G_P = M_PP^{-1}        (one wavefront, unblocked, below)
+//   H = G_P M_PQ,  M_QQ <- M_QQ - M_QP H,  M_QP <- -M_QP G_P,  M_PQ <- H
+// Rows and columns past nb are padded with the identity.  Non-positive pivots
+// set the flag.
+constexpr int kDS = kBP + 1;  // LDS row stride of the block
 
-template <int C>
-__device__ __forceinline__ void gj_step(double (&v)[kDiagCols], double (*prow)[kBP],
-                                        double (*pcol)[kBP], int r, int w, bool &bad)
+// Unblocked Gauss-Jordan on the 16 x 16 block at (o, o) of M in one
+// wavefront: lane l keeps row l / 4, columns 4 (l % 4) .. + 3 in registers
+// and takes the pivot row, the pivot and its own multiplier from the other
+// lanes by shuffles.  Row c becomes x_cj / d (1 / d in column c) and every
+// other row r becomes x_rj - (x_rc / d) x_cj (-x_rc / d in column c).
+__device__ inline void gj16(double (*M)[kDS], int o, int lane, bool &bad)
 {
-    constexpr int B = C & 1, WC = C / kDiagCols, QC = C % kDiagCols;
-    if (r == C) {
+    const int r = lane >> 2, q4 = lane & 3;
+    double a[4];
 #pragma unroll
-        for (int q = 0; q < kDiagCols; q += 2)
-            *reinterpret_cast<double2 *>(&prow[B][kDiagCols * w + q]) = double2{v[q], v[q + 1]};
-    }
-    if (w == WC) pcol[B][r] = v[QC];
-    __syncthreads();
-    double p[kDiagCols];
+    for (int j = 0; j < 4; ++j) a[j] = M[o + r][o + 4 * q4 + j];
 #pragma unroll
-    for (int q = 0; q < kDiagCols; q += 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(&prow[B][kDiagCols * w + q]);
-        p[q] = t.x;
-        p[q + 1] = t.y;
-    }
-    const double d = prow[B][C];
-    const double f = pcol[B][r];
-    bad |= !(d > 0.0);
-    const double inv = 1.0 / d;
-    const bool own = w == WC;
-    // one branch-free form for the pivot row (base 0, factor -1/d) and the
-    // other rows (base x_rj, factor x_rc / d): v_j <- base_j - g p_j, and
-    // column c gets -g
-    const bool piv = r == C;
-    const double g = piv ? -inv : f * inv;
+    for (int c = 0; c < 16; ++c) {
+        const int cq = c >> 2, cj = c & 3;
+        double pv[4];
 #pragma unroll
-    for (int q = 0; q < kDiagCols; ++q) {
-        const double base = piv ? 0.0 : v[q];
-        v[q] = (own && q == QC) ? -g : base - g * p[q];
+        for (int j = 0; j < 4; ++j) pv[j] = __shfl(a[j], 4 * c + q4, 64);
+        const double d = __shfl(a[cj], 4 * c + cq, 64);
+        const double f = __shfl(a[cj], 4 * r + cq, 64);
+        bad |= !(d > 0.0);
+        const double inv = 1.0 / d;
+        const bool piv = r == c;
+        const double g = piv ? -inv : f * inv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double base = piv ? 0.0 : a[j];
+            a[j] = (4 * q4 + j == c) ? -g : base - g * pv[j];
+        }
     }
-}
-
-template <int... Cs>
-__device__ __forceinline__ void gj_all(double (&v)[kDiagCols], double (*prow)[kBP],
-                                       double (*pcol)[kBP], int r, int w, bool &bad,
-                                       std::integer_sequence<int, Cs...>)
-{
-    (gj_step<Cs>(v, prow, pcol, r, w, bad), ...);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[o + r][o + 4 * q4 + j] = a[j];
 }
 
 __global__ __launch_bounds__(256) void k_bgj_diag(const double *__restrict__ X, int n, int k0,
                                                   int nb, double *__restrict__ G,
                                                   int *__restrict__ flag)
 {
-    __shared__ __attribute__((aligned(16))) double prow[2][kBP];
-    __shared__ double pcol[2][kBP];
-    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double v[kDiagCols];
-#pragma unroll
-    for (int q = 0; q < kDiagCols; ++q) {
-        const int col = kDiagCols * w + q;
-        v[q] = (r < nb && col < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + col]
-                                    : (r == col ? 1.0 : 0.0);
+    __shared__ double M[kBP][kDS];
+    __shared__ double H[16][kDS];   // G_P M_PQ
+    __shared__ double Cp[kBP][17];  // M_QP before the sub-panel (column block P)
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    #pragma unroll
+    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
+        const int e = t + 256 * it_;
+        const int r = e / kBP, c = e % kBP;
+        M[r][c] = (r < nb && c < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + c]
+                                     : (r == c ? 1.0 : 0.0);
     }
+    __syncthreads();
     bool bad = false;
-    gj_all(v, prow, pcol, r, w, bad, std::make_integer_sequence<int, kBP>{});
-    if (bad && threadIdx.x == 0) flag[0] = 1;
-    if (r < nb)
+    for (int p = 0; p < 4; ++p) {
+        const int o = 16 * p;
+        if (w == 0) gj16(M, o, lane, bad);
+        __syncthreads();
+        // H = G_P M_PQ (columns outside P) and a copy of the column block P
+        #pragma unroll
+        for (int it_ = 0; it_ < (16 * kBP) / 256; ++it_) {
+            const int e = t + 256 * it_;
+            const int k = e / kBP, j = e % kBP;
+            if (j >= o && j < o + 16) continue;
+            double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < kDiagCols; ++q) {
-            const int col = kDiagCols * w + q;
-            if (col < nb) G[r * kBP + col] = v[q];
+            for (int m = 0; m < 16; ++m) s += M[o + k][o + m] * M[o + m][j];
+            H[k][j] = s;
         }
+        #pragma unroll
+        for (int it_ = 0; it_ < (kBP * 16) / 256; ++it_) {
+            const int e = t + 256 * it_;
+            const int r = e / 16, k = e % 16;
+            Cp[r][k] = M[r][o + k];
+        }
+        __syncthreads();
+        // column j of the rows outside P: M_rj -= M_rP H_Pj, or -M_rP G_P in P;
+        // the rows of P take H
+        {
+            const int j = lane;
+            const bool inP = j >= o && j < o + 16;
+            double hc[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) hc[k] = inP ? M[o + k][j] : H[k][j];
+            for (int r = w; r < kBP; r += 4) {
+                if (r >= o && r < o + 16) {
+                    if (!inP) M[r][j] = H[r - o][j];
+                    continue;
+                }
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) s += Cp[r][k] * hc[k];
+                M[r][j] = inP ? -s : M[r][j] - s;
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) flag[0] = 1;
+    #pragma unroll
+    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
+        const int e = t + 256 * it_;
+        const int r = e / kBP, c = e % kBP;
+        if (r < nb && c < nb) G[r * kBP + c] = M[r][c];
+    }
 }
 
 // X[K, tile] <- G X[K, tile] for the column tiles left of cu other than K
@@ -649,7 +681,9 @@ __global__ __launch_bounds__(256) void k_bgj_rowblock(double *__restrict__ X, in
     }
     const int tile = ct0 + blockIdx.x < kt ? ct0 + blockIdx.x : ct0 + blockIdx.x + 1;
     const int c0 = tile * kBP;
-    for (int t = threadIdx.x; t < kBP * kBP; t += 256) {
+    #pragma unroll
+    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
+        const int t = threadIdx.x + 256 * it_;
         const int r = t / kBP, c = t % kBP;
         Gs[r][c] = (r < nb && c < nb) ? G[r * kBP + c] : 0.0;
         Xs[r][c] = (r < nb && c0 + c < n) ? X[static_cast<int64_t>(k0 + r) * n + c0 + c] : 0.0;
@@ -732,7 +766,9 @@ __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n
     const int kt = k0 / kBP;
     const int tr = blockIdx.x < kt ? blockIdx.x : blockIdx.x + 1;
     const int r0 = tr * kBP;
-    for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
+    #pragma unroll
+    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
+        const int e = threadIdx.x + 256 * it_;
         const int a = e / kBP, b = e % kBP;
         const double g = (a < nb && b < nb) ? G[a * kBP + b] : 0.0;
         Gs[a][b] = g;
@@ -747,7 +783,9 @@ __global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n
         const int tc = ct0 + u < kt ? ct0 + u : ct0 + u + 1;
         const int c0 = tc * kBP;
         __syncthreads();
-        for (int e = threadIdx.x; e < kBP * kBP; e += 256) {
+        #pragma unroll
+        for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
+            const int e = threadIdx.x + 256 * it_;
             const int a = e / kBP, b = e % kBP;
             Kt[b][a] = (a < nb && c0 + b < n) ? X[static_cast<int64_t>(k0 + a) * n + c0 + b] : 0.0;
         }
