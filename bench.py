@@ -193,7 +193,7 @@ def main():
     per_launch_s = results["fp32"]["smooth_ms"] / KMAX / 1e3
     achieved = bytes_it / per_launch_s / 1e9
     peak = 8000.0
-    roofline = dict(kernel="k_smooth_map<float, unsigned char, 8, 7> (restricted smoothing, FP32 basis)",
+    roofline = dict(kernel="k_smooth_map<float, unsigned char, 8, 7, true> (restricted smoothing, FP32 basis)",
                     bound="hbm", achieved=round(achieved, 1), peak=peak, unit="GB/s",
                     frac=round(achieved / peak, 4),
                     traffic=traffic_record("k_smooth_f32_c4"),

@@ -820,9 +820,13 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
             !dalloc_keep(c->p64[1], pm) || !dalloc_keep(c->r64, c->pnnz))
             return fail(c, MSRSB_E_NOMEM, "allocation of the FP64 basis failed");
     }
+    // factored J (s_i and the upper diagonals of the filtered A) for a
+    // symmetric stencil with the slot counts the smoothing kernel specialises
+    const bool jsym = c->j_dia && c->bs == 1 && c->a_off.sym && c->jmap_kind == 1 &&
+                      (c->jw == 3 || c->jw == 5 || c->jw == 7 || c->jw == 9 || c->jw == 27);
     phase_begin(c, MSRSB_PHASE_FILTER);
     launch_filter_jacobi(s, c->n, c->bs, o->filter, o->omega, c->rp, c->ci, c->a, c->jw, c->j_off,
-                         c->j_dia, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
+                         c->j_dia, jsym, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
     phase_end(c, MSRSB_PHASE_FILTER);
     phase_begin(c, MSRSB_PHASE_INIT);
     const bool warm = o->warm_start && c->has_basis;
@@ -852,6 +856,8 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     sa.jmap_tab = c->jmap_tab;
     sa.jmap_ntab = c->jmap_ntab;
     sa.interior = c->interior;
+    sa.sym = jsym;
+    sa.omega = o->omega;
     phase_begin(c, MSRSB_PHASE_SMOOTH);
     int it = 0;
     double e_last = -1.0;

@@ -215,10 +215,12 @@ struct SmoothArgs {
     const uint8_t *interior = nullptr;
     double *eit_part = nullptr;  // per-work-group maxima; null: no e_it this iteration
     double *eit_out = nullptr;   // e_it (one double)
+    bool sym = false;            // J stored factored (k_filter_jacobi's sym form)
+    double omega = 0.0;
 };
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
-                          bool use_dia, double *jv64, float *jv32);
+                          bool use_dia, bool sym, double *jv64, float *jv32);
 void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32);
 void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,

@@ -67,11 +67,17 @@ __global__ __launch_bounds__(1024) void k_eit_final(int nb, const double *__rest
 // frozen (J_i = e_i).  J's entries are A's same-component entries; they are
 // written to their ELL slot (the DIA offset slot, or the running position),
 // and absent slots are zero.
+//
+// sym (a symmetric stencil A, so Ghat is symmetric): J is kept factored,
+// J_ij = s_i Ghat_ij with s_i = -omega / Dhat_ii (0 for a frozen row), and
+// only s (in the diagonal slot) and the upper diagonals of Ghat are stored;
+// the smoothing step reads Ghat_{i,i-o} = Ghat_{i-o,i} from the neighbour's
+// row and J_ii = 1 - omega (1 where s_i = 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
     int n, int bs, int filter, double omega, const int *__restrict__ rp,
     const int *__restrict__ ci, const double *__restrict__ a, int jw, DiaOffsets joff,
-    int use_dia, T *__restrict__ jv)
+    int use_dia, int sym, T *__restrict__ jv)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -91,7 +97,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
         const int j = ci[e];
         if (j % bs != ic) continue;
         double v;
-        if (d == 0.0) {
+        if (sym) {
+            if (j < i) continue;
+            if (j == i) {
+                v = d == 0.0 ? 0.0 : -omega / d;
+            } else {
+                v = a[e];
+                if (filter && v > 0.0) v = 0.0;
+            }
+        } else if (d == 0.0) {
             v = (j == i) ? 1.0 : 0.0;
         } else if (j == i) {
             v = 1.0 - omega;
@@ -221,6 +235,24 @@ __device__ __forceinline__ void accumulate_diag(T (&acc)[PW], uint32_t m, T w, c
     for (int s = 0; s < PW; ++s) acc[s] += (((m >> (4 * s)) & 8u) ? T(0) : w) * v[s];
 }
 
+// The same through LDS: the neighbour row is written slot-major into this
+// thread's column of sb ([PW + 1][kBlock], row PW zero) and read back at the
+// mapped slots (an absent slot reads the zero row), so the permutation costs
+// one address and one LDS read per slot instead of a select tree.  Each
+// thread touches only its own column: no barrier is needed.
+template <typename T, int PW>
+__device__ __forceinline__ void accumulate_lds(T (&acc)[PW], uint32_t m, T w, const T (&v)[PW],
+                                               T *sb)
+{
+#pragma unroll
+    for (int t = 0; t < PW; ++t) sb[t * kBlock] = v[t];
+#pragma unroll
+    for (int s = 0; s < PW; ++s) {
+        const uint32_t src = (m >> (4 * s)) & 0xFu;
+        acc[s] += w * sb[min(src, static_cast<uint32_t>(PW)) * kBlock];
+    }
+}
+
 __host__ __device__ inline bool map_is_diag(uint32_t m)
 {
     for (int s = 0; s < 8; ++s) {
@@ -234,17 +266,24 @@ __host__ __device__ inline bool map_is_diag(uint32_t m)
 // neighbours are taken in chunks whose map indices, weights and rows are all
 // loaded before any is used (one wavefront keeps a whole chunk in flight).
 // JW == 0: any slot count, one neighbour at a time.
-template <typename T, typename IDX, int PW, int JW>
+// SYM (JW > 0, stencil J stored factored by k_filter_jacobi's sym form):
+// J_io = s_i Ghat_up[JW-1-o][i+off_o] below the diagonal, s_i Ghat_up[o][i]
+// above it, and 1 - omega (1 for a frozen row) on it.
+template <typename T, typename IDX, int PW, int JW, bool SYM = false>
 __global__ __launch_bounds__(kBlock) void k_smooth_map(
     int n, int jw, DiaOffsets joff, const int *__restrict__ jcol, const T *__restrict__ jv,
     const IDX *__restrict__ jmap, const uint32_t *__restrict__ tab, int ntab,
     const T *__restrict__ pin, T *__restrict__ pout, const uint8_t *__restrict__ interior,
-    double *__restrict__ eit_part)
+    double *__restrict__ eit_part, double omega)
 {
     // a one-byte map index selects from a table of at most 256 maps kept in
     // LDS; the sign bit of sdiag marks diagonal maps
     __shared__ uint32_t stab[256];
     __shared__ uint8_t sdiag[256];
+    // per-thread columns for the permutation of neighbour rows (JW > 0)
+    __shared__ T sperm[JW > 0 ? (PW + 1) * kBlock : 1];
+    T *sb = sperm + (JW > 0 ? threadIdx.x : 0);
+    if constexpr (JW > 0) sb[PW * kBlock] = T(0);
     if constexpr (sizeof(IDX) == 1) {
         for (int t = threadIdx.x; t < ntab; t += blockDim.x) {
             const uint32_t m = tab[t];
@@ -261,6 +300,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         for (int s = 0; s < PW; ++s) acc[s] = T(0);
         if constexpr (JW > 0) {
             static_assert(sizeof(IDX) == 1, "fixed slot counts use the LDS map table");
+            constexpr int MID = JW / 2;
+            T si = T(0), jd = T(0);
+            if constexpr (SYM) {
+                si = jv[static_cast<int64_t>(MID) * n + i];
+                jd = si == T(0) ? T(1) : static_cast<T>(1.0 - omega);
+            }
             // chunk: up to 9 FP32 rows or 4 FP64 rows in registers at once
             constexpr int CMAX = sizeof(T) == 8 ? 4 : 9;
             constexpr int CH = JW <= CMAX ? JW : CMAX;
@@ -273,11 +318,26 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     if (o0 + u >= JW) continue;
-                    const int64_t e = static_cast<int64_t>(o0 + u) * n + i;
+                    const int o = o0 + u;
+                    const int64_t e = static_cast<int64_t>(o) * n + i;
                     const int t = jmap[e];
                     m[u] = stab[t];
                     dg[u] = sdiag[t] != 0;
-                    w[u] = jv[e];
+                    if constexpr (SYM) {
+                        // an absent neighbour's mirrored slot is zero by
+                        // pattern symmetry; one beyond the ends reads row i
+                        const int kn = i + joff.off[o];
+                        const bool in = kn >= 0 && kn < n;
+                        if (o < MID) {
+                            const T g = jv[static_cast<int64_t>(JW - 1 - o) * n + (in ? kn : i)];
+                            w[u] = in ? si * g : T(0);
+                        } else if (o == MID)
+                            w[u] = jd;
+                        else
+                            w[u] = si * jv[e];
+                    } else {
+                        w[u] = jv[e];
+                    }
                 }
                 if (jcol) {
 #pragma unroll
@@ -304,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
                     if (__all(dg[u]))
                         accumulate_diag<T, PW>(acc, m[u], w[u], v[u]);
                     else
-                        accumulate<T, PW>(acc, m[u], w[u], v[u]);
+                        accumulate_lds<T, PW>(acc, m[u], w[u], v[u], sb);
                 }
             }
         } else {
@@ -325,13 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         T old[PW], out[PW];
         load_row<T, PW>(pin, i, old);
         const bool inner = eit_part != nullptr && interior[i] != 0;
+        const double rinv = 1.0 / rs;
 #pragma unroll
         for (int s = 0; s < PW; ++s) {
             if (inner) {
                 const double dlt = fabs(static_cast<double>(acc[s]) - static_cast<double>(old[s]));
                 emax = (dlt > emax || dlt != dlt) ? dlt : emax;
             }
-            out[s] = static_cast<T>(static_cast<double>(acc[s]) / rs);
+            out[s] = static_cast<T>(static_cast<double>(acc[s]) * rinv);
         }
         store_row<T, PW>(pout, i, out);
     }
@@ -374,6 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_cmp(
         double rs = 0.0;
 #pragma unroll
         for (int s = 0; s < W; ++s) rs += static_cast<double>(acc[s]);
+        const double rinv = 1.0 / rs;
         const bool inner = eit_part != nullptr && interior[i] != 0;
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -384,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_cmp(
                         fabs(static_cast<double>(acc[s]) - static_cast<double>(pin[e]));
                     emax = (dlt > emax || dlt != dlt) ? dlt : emax;
                 }
-                pout[e] = static_cast<T>(static_cast<double>(acc[s]) / rs);
+                pout[e] = static_cast<T>(static_cast<double>(acc[s]) * rinv);
             }
         }
     }
@@ -517,9 +579,17 @@ inline int grid_n(int n) { return grid_for(n); }
 template <typename T, typename IDX, int PW, int JW>
 void smooth_map_launch(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *pout)
 {
+    if constexpr (JW > 0) {
+        if (a.sym) {
+            k_smooth_map<T, IDX, PW, JW, true><<<grid_n(a.n), kBlock, 0, s>>>(
+                a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx), a.jmap_tab,
+                a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega);
+            return;
+        }
+    }
     k_smooth_map<T, IDX, PW, JW><<<grid_n(a.n), kBlock, 0, s>>>(
         a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx), a.jmap_tab,
-        a.jmap_ntab, pin, pout, a.interior, a.eit_part);
+        a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega);
 }
 
 template <typename T, typename IDX, int PW>
@@ -573,14 +643,16 @@ void smooth_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *
 
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
-                          bool use_dia, double *jv64, float *jv32)
+                          bool use_dia, bool sym, double *jv64, float *jv32)
 {
     if (jv32)
         k_filter_jacobi<float><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a, jw,
-                                                              joff, use_dia ? 1 : 0, jv32);
+                                                              joff, use_dia ? 1 : 0, sym ? 1 : 0,
+                                                              jv32);
     else
         k_filter_jacobi<double><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a,
-                                                               jw, joff, use_dia ? 1 : 0, jv64);
+                                                               jw, joff, use_dia ? 1 : 0,
+                                                               sym ? 1 : 0, jv64);
 }
 
 void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
