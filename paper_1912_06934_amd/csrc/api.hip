@@ -713,7 +713,7 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         !dalloc(c->rsrc, pnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
         !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
         !dalloc(c->colsrc, nc) || !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2) ||
-        !dalloc(c->spd_buf, 64 * 64 + 128 * static_cast<size_t>(nc)))
+        !dalloc(c->spd_buf, static_cast<size_t>((nc + 63) / 64) * 64 * 64))
         return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
     hipMemcpyAsync(c->part, hpart.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->prp, hprp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
@@ -990,16 +990,16 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     int hflag = 0;
     st = MSRSB_E_COARSE_SINGULAR;
     c->acinv_sym = false;
+    double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
     if (c->a_symmetric) {
-        // symmetric positive definite A_c: band-limited Gauss-Jordan without
-        // pivoting; a non-positive pivot falls back to partial pivoting
+        // symmetric positive definite A_c: band Cholesky, W = L^{-1} and
+        // W^T W; a non-positive pivot falls back to partial pivoting
         hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
-        st = coarse_inverse_spd(s, nc, c->acinv, c->h_band[0], c->h_band[1], c->spd_buf,
-                                c->spd_buf + 64 * 64, c->dev_flag, &hflag);
+        st = coarse_inverse_spd(s, nc, c->acinv, std::max(c->h_band[0], c->h_band[1]), c->spd_buf,
+                                work, c->dev_flag, &hflag);
         c->acinv_sym = st == MSRSB_OK;
     }
     if (st == MSRSB_E_COARSE_SINGULAR) {
-        double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
         hipMemcpyAsync(work, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
         st = coarse_inverse(s, nc, work, c->acinv, c->gj_b, c->piv, c->colsrc, c->dev_flag,
                             &hflag);

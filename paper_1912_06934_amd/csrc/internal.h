@@ -140,7 +140,7 @@ struct msrsb_ctx {
     // coarse operator and its inverse
     double *ac = nullptr, *acinv = nullptr, *gj_b = nullptr;
     bool acinv_sym = false;  // acinv came from the SPD (symmetric) path
-    double *spd_buf = nullptr;  // diagonal-block inverse and super-panel rows (SPD path)
+    double *spd_buf = nullptr;  // inverse Cholesky factors of the diagonal blocks (SPD path)
     int *piv = nullptr, *colsrc = nullptr, *dev_flag = nullptr;
 
     // smoothers (diagonal inverses of A, and of A^T for the transposed solve)
@@ -246,8 +246,8 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band);
-msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu, double *G,
-                                double *B, int *flag, int *host_flag);
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
+                                int *flag, int *host_flag);
 void launch_fill(hipStream_t s, int64_t m, double *x, double v);
 msrsb_status coarse_inverse(hipStream_t s, int nc, double *ac_work, double *inv_out,
                             double *bbuf, int *piv, int *colsrc, int *flag, int *host_flag);

@@ -306,8 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
                 si = jv[static_cast<int64_t>(MID) * n + i];
                 jd = si == T(0) ? T(1) : static_cast<T>(1.0 - omega);
             }
-            // chunk: up to 9 FP32 rows or 4 FP64 rows in registers at once
-            constexpr int CMAX = sizeof(T) == 8 ? 4 : 9;
+            // chunk: up to 9 FP32 rows or 7 FP64 rows in registers at once
+            constexpr int CMAX = sizeof(T) == 8 ? 7 : 9;
             constexpr int CH = JW <= CMAX ? JW : CMAX;
 #pragma nounroll
             for (int o0 = 0; o0 < JW; o0 += CH) {

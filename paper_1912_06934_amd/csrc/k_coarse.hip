@@ -541,179 +541,23 @@ __global__ __launch_bounds__(kBlock) void k_gj_permute(int n, const double *__re
 }
 
 // ---------------------------------------------------------------------------
-// Pivot-free block Gauss-Jordan, for a symmetric positive definite A_c (the
-// Galerkin operator of a symmetric positive definite A), in place on X.
-// For each 64-wide panel K (diagonal block D = X[K,K], G = D^{-1}):
-//   X[K,C] <- G X[K,C]                         (block row, C != K)
-//   X[R,C] <- X[R,C] - X[R,K] X[K,C]          (rank-64 update, R, C != K)
-//   X[R,K] <- -X[R,K] G,  X[K,K] <- G          (block column)
-// After the last panel X = A_c^{-1}.  Without pivoting the part of X not yet
-// eliminated keeps A_c's band: at panel K rows below k0 + 64 + bl have a zero
-// block column and columns right of k0 + 64 + bu a zero block row, so the
-// updates stop there (bl, bu = lower and upper bandwidth of A_c).
+// Inverse of a symmetric positive definite A_c (the Galerkin operator of a
+// symmetric positive definite A) through its Cholesky factor, A_c = L L^T:
+//   1. band Cholesky by 64-wide panels K (k0 = 64 K): the diagonal block's
+//      inverse factor Linv_K = L_KK^{-1}, then for the row tiles R1 >= R2
+//      inside the band below K
+//        L_R = X[R, K] Linv_K^T,   X[R1, R2] -= L_R1 L_R2^T,
+//      with L_R^T kept in the (otherwise unused) upper triangle at X[K, R];
+//      A_c's lower bandwidth bl bounds the band, which the factor keeps;
+//   2. W = L^{-1} (lower triangular) by strips of 16 columns, each strip a
+//      forward substitution down the row tiles I:
+//        W[I, S] = Linv_I (E[I, S] - sum over band tiles K < I of L[I, K] W[K, S]);
+//   3. A_c^{-1} = W^T W, lower tiles formed on the FP64 matrix cores and
+//      mirrored, so the inverse is exactly symmetric.
+// A non-positive (or non-finite) pivot sets the flag: A_c is not positive
+// definite and the caller falls back to Gauss-Jordan with pivoting.
 // ---------------------------------------------------------------------------
-constexpr int kBP = 64;
-constexpr int kSuper = 128;  // columns per super-panel (a multiple of kBP)
-
-// G = D^{-1} for the 64 x 64 diagonal block D by Gauss-Jordan without
-// pivoting, blocked by 16 (the same elimination as the unblocked one, grouped
-// in four sub-panels P of 16 pivots; Q = the other 48 indices):
-//   M_PP <- G_P = M_PP^{-1}        (one wavefront, unblocked, below)
-//   H = G_P M_PQ,  M_QQ <- M_QQ - M_QP H,  M_QP <- -M_QP G_P,  M_PQ <- H
-// Rows and columns past nb are padded with the identity.  Non-positive pivots
-// set the flag.
-constexpr int kDS = kBP + 1;  // LDS row stride of the block
-
-// Unblocked Gauss-Jordan on the 16 x 16 block at (o, o) of M in one
-// wavefront: lane l keeps row l / 4, columns 4 (l % 4) .. + 3 in registers
-// and takes the pivot row, the pivot and its own multiplier from the other
-// lanes by shuffles.  Row c becomes x_cj / d (1 / d in column c) and every
-// other row r becomes x_rj - (x_rc / d) x_cj (-x_rc / d in column c).
-__device__ inline void gj16(double (*M)[kDS], int o, int lane, bool &bad)
-{
-    const int r = lane >> 2, q4 = lane & 3;
-    double a[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) a[j] = M[o + r][o + 4 * q4 + j];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int cq = c >> 2, cj = c & 3;
-        double pv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) pv[j] = __shfl(a[j], 4 * c + q4, 64);
-        const double d = __shfl(a[cj], 4 * c + cq, 64);
-        const double f = __shfl(a[cj], 4 * r + cq, 64);
-        bad |= !(d > 0.0);
-        const double inv = 1.0 / d;
-        const bool piv = r == c;
-        const double g = piv ? -inv : f * inv;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double base = piv ? 0.0 : a[j];
-            a[j] = (4 * q4 + j == c) ? -g : base - g * pv[j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) M[o + r][o + 4 * q4 + j] = a[j];
-}
-
-__global__ __launch_bounds__(256) void k_bgj_diag(const double *__restrict__ X, int n, int k0,
-                                                  int nb, double *__restrict__ G,
-                                                  int *__restrict__ flag)
-{
-    __shared__ double M[kBP][kDS];
-    __shared__ double H[16][kDS];   // G_P M_PQ
-    __shared__ double Cp[kBP][17];  // M_QP before the sub-panel (column block P)
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    #pragma unroll
-    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
-        const int e = t + 256 * it_;
-        const int r = e / kBP, c = e % kBP;
-        M[r][c] = (r < nb && c < nb) ? X[static_cast<int64_t>(k0 + r) * n + k0 + c]
-                                     : (r == c ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    bool bad = false;
-    for (int p = 0; p < 4; ++p) {
-        const int o = 16 * p;
-        if (w == 0) gj16(M, o, lane, bad);
-        __syncthreads();
-        // H = G_P M_PQ (columns outside P) and a copy of the column block P
-        #pragma unroll
-        for (int it_ = 0; it_ < (16 * kBP) / 256; ++it_) {
-            const int e = t + 256 * it_;
-            const int k = e / kBP, j = e % kBP;
-            if (j >= o && j < o + 16) continue;
-            double s = 0.0;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) s += M[o + k][o + m] * M[o + m][j];
-            H[k][j] = s;
-        }
-        #pragma unroll
-        for (int it_ = 0; it_ < (kBP * 16) / 256; ++it_) {
-            const int e = t + 256 * it_;
-            const int r = e / 16, k = e % 16;
-            Cp[r][k] = M[r][o + k];
-        }
-        __syncthreads();
-        // column j of the rows outside P: M_rj -= M_rP H_Pj, or -M_rP G_P in P;
-        // the rows of P take H
-        {
-            const int j = lane;
-            const bool inP = j >= o && j < o + 16;
-            double hc[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) hc[k] = inP ? M[o + k][j] : H[k][j];
-            for (int r = w; r < kBP; r += 4) {
-                if (r >= o && r < o + 16) {
-                    if (!inP) M[r][j] = H[r - o][j];
-                    continue;
-                }
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) s += Cp[r][k] * hc[k];
-                M[r][j] = inP ? -s : M[r][j] - s;
-            }
-        }
-        __syncthreads();
-    }
-    if (bad) flag[0] = 1;
-    #pragma unroll
-    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
-        const int e = t + 256 * it_;
-        const int r = e / kBP, c = e % kBP;
-        if (r < nb && c < nb) G[r * kBP + c] = M[r][c];
-    }
-}
-
-// X[K, tile] <- G X[K, tile] for the column tiles left of cu other than K
-__global__ __launch_bounds__(256) void k_bgj_rowblock(double *__restrict__ X, int n, int k0,
-                                                      int nb, const double *__restrict__ G,
-                                                      int ct0)
-{
-    __shared__ double Gs[kBP][kBP + 1];
-    __shared__ double Xs[kBP][kBP + 1];
-    const int kt = k0 / kBP;
-    if (blockIdx.x == gridDim.x - 1) {  // the diagonal block becomes G
-        for (int e = threadIdx.x; e < nb * nb; e += 256)
-            X[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb] = G[(e / nb) * kBP + e % nb];
-        return;
-    }
-    const int tile = ct0 + blockIdx.x < kt ? ct0 + blockIdx.x : ct0 + blockIdx.x + 1;
-    const int c0 = tile * kBP;
-    #pragma unroll
-    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
-        const int t = threadIdx.x + 256 * it_;
-        const int r = t / kBP, c = t % kBP;
-        Gs[r][c] = (r < nb && c < nb) ? G[r * kBP + c] : 0.0;
-        Xs[r][c] = (r < nb && c0 + c < n) ? X[static_cast<int64_t>(k0 + r) * n + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
-    for (int k = 0; k < nb; ++k) {
-        double g[4], x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            g[u] = Gs[ty * 4 + u][k];
-            x[u] = Xs[k][tx * 4 + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) acc[u][w] += g[u] * x[w];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = ty * 4 + u;
-        if (r >= nb) continue;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int c = c0 + tx * 4 + w;
-            if (c < n) X[static_cast<int64_t>(k0 + r) * n + c] = acc[u][w];
-        }
-    }
-}
+constexpr int kBP = 64;  // panel width
 
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 
@@ -749,166 +593,385 @@ __device__ inline void zero_acc(mfma_f64x4 (&acc)[2][2])
         for (int v = 0; v < 2; ++v) acc[u][v] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
 }
 
-// One 64-wide panel K inside a super-panel, for one row tile R != K (one
-// work-group per row tile below the band limit):
-//   X[R, t] -= X[R, K] (G X[K, t])   for the other column tiles t of the
-//                                    super-panel (G X[K, t] formed here from
-//                                    the unmodified X[K, t])
-//   X[R, K] <- -X[R, K] G
-// The row block K itself is updated afterwards by k_bgj_rowblock.
-__global__ __launch_bounds__(256) void k_bgj_inner(double *__restrict__ X, int n, int k0, int nb,
-                                                   const double *__restrict__ G, int ct0, int nct)
+// acc (quadrant layout of mfma_tile64) into T[row][col] (or T[col][row])
+__device__ inline void acc_to_lds(const mfma_f64x4 (&acc)[2][2], double (*T)[kLds], bool trans,
+                                  int wr, int wc, int li, int lk)
 {
-    __shared__ double Gs[kBP][kLds];  // G by rows
-    __shared__ double Gt[kBP][kLds];  // G by columns
-    __shared__ double As[kBP][kLds];  // X[R, K] before this panel, by rows
-    __shared__ double Kt[kBP][kLds];  // X[K, t] by columns, then (G X[K, t]) by columns
-    const int kt = k0 / kBP;
-    const int tr = blockIdx.x < kt ? blockIdx.x : blockIdx.x + 1;
-    const int r0 = tr * kBP;
-    #pragma unroll
-    for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
-        const int e = threadIdx.x + 256 * it_;
-        const int a = e / kBP, b = e % kBP;
-        const double g = (a < nb && b < nb) ? G[a * kBP + b] : 0.0;
-        Gs[a][b] = g;
-        Gt[b][a] = g;
-        As[a][b] = (r0 + a < n && b < nb) ? X[static_cast<int64_t>(r0 + a) * n + k0 + b] : 0.0;
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    const int li = lane & 15, lk = lane >> 4;
-    mfma_f64x4 acc[2][2];
-    for (int u = 0; u < nct; ++u) {
-        const int tc = ct0 + u < kt ? ct0 + u : ct0 + u + 1;
-        const int c0 = tc * kBP;
-        __syncthreads();
-        #pragma unroll
-        for (int it_ = 0; it_ < (kBP * kBP) / 256; ++it_) {
-            const int e = threadIdx.x + 256 * it_;
-            const int a = e / kBP, b = e % kBP;
-            Kt[b][a] = (a < nb && c0 + b < n) ? X[static_cast<int64_t>(k0 + a) * n + c0 + b] : 0.0;
-        }
-        __syncthreads();
-        zero_acc(acc);
-        mfma_tile64(Gs, Kt, acc, wr, wc, li, lk);
-        __syncthreads();
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int v = 0; v < 2; ++v)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    Kt[wc + 16 * v + li][wr + 16 * p + 4 * q + lk] = acc[p][v][q];
-        __syncthreads();
-        zero_acc(acc);
-        mfma_tile64(As, Kt, acc, wr, wc, li, lk);
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int v = 0; v < 2; ++v)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + wr + 16 * p + 4 * q + lk;
-                    const int c = c0 + wc + 16 * v + li;
-                    if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] -= acc[p][v][q];
-                }
-    }
-    __syncthreads();
-    zero_acc(acc);
-    mfma_tile64(As, Gt, acc, wr, wc, li, lk);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wr + 16 * p + 4 * q + lk;
-                const int c = wc + 16 * v + li;
-                if (r < n && c < nb) X[static_cast<int64_t>(r) * n + k0 + c] = -acc[p][v][q];
+                const int r = wr + 16 * p + 4 * q + lk, c = wc + 16 * v + li;
+                if (trans)
+                    T[c][r] = acc[p][v][q];
+                else
+                    T[r][c] = acc[p][v][q];
             }
 }
 
-// Rows s0 .. s0+ns-1 of the columns outside the super-panel (up to c_hi) move
-// to B (ns x n) and are zeroed.
-__global__ __launch_bounds__(kBlock) void k_bgj_extract(double *__restrict__ X, int n, int s0,
-                                                        int ns, int c_hi, double *__restrict__ B)
+// lower-triangle pair (a, b), a >= b, of linear index t = a (a + 1) / 2 + b
+__device__ inline void tri_pair(int t, int &a, int &b)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y;
-    if (c >= c_hi || (c >= s0 && c < s0 + ns)) return;
-    const int64_t e = static_cast<int64_t>(s0 + t) * n + c;
-    B[static_cast<int64_t>(t) * n + c] = X[e];
-    X[e] = 0.0;
+    int x = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (x * (x + 1) / 2 > t) --x;
+    while ((x + 1) * (x + 2) / 2 <= t) ++x;
+    a = x;
+    b = t - x * (x + 1) / 2;
 }
 
-// X[R, C] += X[R, S] B[:, C] for row tiles below the band limit and column
-// tiles outside the super-panel S = [s0, s0 + ns) (ns a multiple of 64); the
-// super-panel's combined Gauss-Jordan transformation applied to the other
-// columns, on the FP64 matrix cores (mfma_tile64).  The next 64-deep chunk of
-// X[R, S] and B is loaded into registers while the current one is
-// multiplied, and the X[R, C] tile is fetched at the start.
-__global__ __launch_bounds__(256) void k_bgj_outer(double *__restrict__ X, int n, int s0, int ns,
-                                                   const double *__restrict__ B)
+__device__ inline double readlane_d(double v, int lane)
 {
-    __shared__ double As[kBP][kLds];
-    __shared__ double Bt[kBP][kLds];
-    const int st0 = s0 / kBP, nst = (ns + kBP - 1) / kBP;
-    const int tr = blockIdx.y;
-    const int tc = blockIdx.x < st0 ? blockIdx.x : blockIdx.x + nst;
-    const int r0 = tr * kBP, c0 = tc * kBP;
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Linv = L^{-1} for a 64 x 64 diagonal block D = L L^T, from Gaussian
+// elimination without pivoting on [D | I]: with D = L_u diag(u) L_u^T (L_u
+// unit lower triangular, u the pivots) the right half ends as L_u^{-1}, and
+// Linv = diag(u)^{-1/2} L_u^{-1}.  Column j of the left half is dead once
+// step j has used it, and column j of the right half is born at step j, so
+// both share one register slot: lane r of wavefront w keeps row r, slots
+// 16 w .. 16 w + 15 (m on entry: D's entries).
+//
+// The pivots are taken four at a time.  The wavefront owning the four
+// columns runs the four unblocked steps on them alone (pivot u_k, the
+// multipliers m_rk = x_rk / u_k of every row, slot k turned into -m_rk) and
+// publishes the multipliers; lanes k .. k + 3 of every wavefront publish
+// their rows.  After one barrier every wavefront applies the four steps to
+// its other slots: the pivot rows as they stood at their step,
+// P_t = x_(k+t) - sum_(t' < t) m_(k+t, k+t') P_t', then x_r -= m_(r, k+t) P_t
+// in step order, the same operations as the unblocked elimination.
+// Non-positive or non-finite pivots set *flag.
+struct CholInvSmem {
+    double msh[2][4][kBP];   // multipliers of a block of four pivots (by parity)
+    double prow[2][4][kBP];  // the block's pivot rows before the block
+    double piv[kBP];
+};
+
+__device__ inline void chol_inv_regs(double (&m)[16], CholInvSmem &sm, double *__restrict__ Linv,
+                                     int *__restrict__ flag)
+{
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    bool bad = false;
+    // blocks 4 ow + i: the slots s0 = 4 i are fixed at compile time, the
+    // owning wavefront ow and the pivot rows k are uniform run-time values
+#pragma unroll 1
+    for (int ow = 0; ow < kBP / 16; ++ow)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = 16 * ow + 4 * i, par = i & 1, s0 = 4 * i;
+        if (lane >= k && lane < k + 4) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) sm.prow[par][lane - k][16 * w + s] = m[s];
+        }
+        if (w == ow) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int kt = k + t;
+                const double p = readlane_d(m[s0 + t], kt);
+                bad |= !(p > 0.0) || !isfinite(p);
+                const double mult = lane > kt ? m[s0 + t] / p : 0.0;
+                sm.msh[par][t][lane] = mult;
+                if (lane == 0) sm.piv[kt] = p;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u == t) continue;
+                    const double pk = readlane_d(m[s0 + u], kt);
+                    m[s0 + u] -= mult * pk;
+                }
+                m[s0 + t] = lane > kt ? -mult : (lane == kt ? 1.0 : m[s0 + t]);
+            }
+        }
+        __syncthreads();
+        double mr[4], mk[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            mr[t] = sm.msh[par][t][lane];
+#pragma unroll
+            for (int u = t + 1; u < 4; ++u) mk[u][t] = sm.msh[par][t][k + u];
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            if (w == ow && s >= s0 && s < s0 + 4) continue;
+            const int j = 16 * w + s;
+            double P[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                double v = sm.prow[par][t][j];
+#pragma unroll
+                for (int u = 0; u < t; ++u) v -= mk[t][u] * P[u];
+                P[t] = v;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) m[s] -= mr[t] * P[t];
+        }
+    }
+    const double rs = 1.0 / sqrt(sm.piv[lane]);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int j = 16 * w + s;
+        Linv[lane * kBP + j] = j <= lane ? m[s] * rs : 0.0;
+    }
+    if (bad) flag[0] = 1;
+}
+
+// Linv for the diagonal block X[K, K] (its lower triangle, mirrored; rows
+// and columns past nb padded with the identity)
+__global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ X, int n, int k0,
+                                                  int nb, double *__restrict__ Linv,
+                                                  int *__restrict__ flag)
+{
+    __shared__ CholInvSmem sm;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double m[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int j = 16 * w + s, r = lane;
+        double v = r == j ? 1.0 : 0.0;
+        if (r < nb && j < nb) {
+            const int hi = r > j ? r : j, lo = r > j ? j : r;
+            v = X[static_cast<int64_t>(k0 + hi) * n + k0 + lo];
+        }
+        m[s] = v;
+    }
+    chol_inv_regs(m, sm, Linv, flag);
+}
+
+// Panel K of the band Cholesky for the lower tile pairs (R1, R2) of the band
+// below it, R1 >= R2 >= rt0 = K + 1 (one work-group per pair):
+//   L_R1 = X[R1, K] Linv^T, L_R2 = X[R2, K] Linv^T, X[R1, R2] -= L_R1 L_R2^T;
+// the diagonal pairs store L_R^T at X[K, R] (upper triangle, read by the
+// forward substitution).  X[R, K] itself is left as it was: other pairs of
+// the same launch read it.  All operands and the output tile are fetched
+// before the first product.  With Lnext set, the pair (K+1, K+1) (block 0,
+// dispatched first) goes on to invert the freshly updated diagonal block of
+// the next panel (nbn rows) into Lnext.
+__global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int n, int k0, int nb,
+                                                     int rt0, const double *__restrict__ Linv,
+                                                     double *__restrict__ Lnext, int nbn,
+                                                     int *__restrict__ flag)
+{
+    __shared__ double Ls[kBP][kLds];  // Linv by rows: the B operand of X[R, K] Linv^T
+    __shared__ double A1[kBP][kLds];  // X[R1, K], then L_R1 (by rows)
+    __shared__ double A2[kBP][kLds];  // X[R2, K], then L_R2 (by rows)
+    __shared__ CholInvSmem sm;
+    int a, b;
+    tri_pair(blockIdx.x, a, b);
+    const int r1 = (rt0 + a) * kBP, r2 = (rt0 + b) * kBP;
+    const bool diag = a == b;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    {
+        double gl[16], g1[16], g2[16];
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = t + 256 * it;
+            const int r = e / kBP, c = e % kBP;
+            gl[it] = Linv[e];
+            g1[it] = (r1 + r < n && c < nb) ? X[static_cast<int64_t>(r1 + r) * n + k0 + c] : 0.0;
+            g2[it] = (!diag && r2 + r < n && c < nb) ? X[static_cast<int64_t>(r2 + r) * n + k0 + c]
+                                                     : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = t + 256 * it;
+            const int r = e / kBP, c = e % kBP;
+            Ls[r][c] = gl[it];
+            A1[r][c] = g1[it];
+            if (!diag) A2[r][c] = g2[it];
+        }
+    }
     // the output tile, in the accumulator layout
     double xo[2][2][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wr + 16 * u + 4 * q + lk;
-                const int c = c0 + wc + 16 * v + li;
-                xo[u][v][q] = (r < n && c < n) ? X[static_cast<int64_t>(r) * n + c] : 0.0;
+                const int r = r1 + wr + 16 * p + 4 * q + lk, c = r2 + wc + 16 * v + li;
+                xo[p][v][q] = (r < n && c < n) ? X[static_cast<int64_t>(r) * n + c] : 0.0;
             }
-    // thread t loads rows t / 64 + 4 k, column t % 64 of each 64 x 64 chunk
+    __syncthreads();
+    mfma_f64x4 acc1[2][2], acc2[2][2];
+    zero_acc(acc1);
+    mfma_tile64(A1, Ls, acc1, wr, wc, li, lk);
+    if (!diag) {
+        zero_acc(acc2);
+        mfma_tile64(A2, Ls, acc2, wr, wc, li, lk);
+    }
+    __syncthreads();
+    acc_to_lds(acc1, A1, false, wr, wc, li, lk);
+    if (!diag) acc_to_lds(acc2, A2, false, wr, wc, li, lk);
+    __syncthreads();
+    zero_acc(acc1);
+    mfma_tile64(A1, diag ? A1 : A2, acc1, wr, wc, li, lk);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xo[p][v][q] -= acc1[p][v][q];
+                const int r = r1 + wr + 16 * p + 4 * q + lk, c = r2 + wc + 16 * v + li;
+                if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] = xo[p][v][q];
+            }
+    if (!diag) return;
+    // L_R^T at X[K, R]: row c of the tile holds column c of L_R
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = t + 256 * it;
+        const int c = e / kBP, r = e % kBP;
+        if (c < nb && r1 + r < n) X[static_cast<int64_t>(k0 + c) * n + r1 + r] = A1[r][c];
+    }
+    if (Lnext == nullptr || blockIdx.x != 0) return;
+    // the next panel's diagonal block, now final: its inverse factor
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) A2[wr + 16 * p + 4 * q + lk][wc + 16 * v + li] = xo[p][v][q];
+    __syncthreads();
+    double m[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int j = 16 * w + s, r = lane;
+        const int hi = r > j ? r : j, lo = r > j ? j : r;
+        m[s] = (r < nbn && j < nbn) ? A2[hi][lo] : (r == j ? 1.0 : 0.0);
+    }
+    chol_inv_regs(m, sm, Lnext, flag);
+}
+
+// W = L^{-1}, one strip of 16 columns S = [c0, c0 + 16) per work-group (the
+// strips are independent).  Row tile I of the strip, from the strip's own
+// panel down: wavefront w forms rows 16 w .. 16 w + 15 of
+//   sum over K in [max(jp, I - tb), I) of L[I, K] W[K, S]
+// (L[I, K] read transposed from the upper triangle of X, W[K, S] written by
+// this work-group at an earlier step), subtracts it from the identity's
+// block, and multiplies by Linv_I.  Entries of W above the diagonal come out
+// as exact zeros (Linv_I is lower triangular).
+__global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, int n, int tb,
+                                                const double *__restrict__ Linv,
+                                                double *__restrict__ W)
+{
+    __shared__ double Rs[kBP][17];  // right-hand block, rows k, 16 columns
+    const int c0 = 16 * blockIdx.x;
+    const int jp = c0 / kBP, nt = (n + kBP - 1) / kBP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool cin = c0 + li < n;
+    for (int I = jp; I < nt; ++I) {
+        const int r0 = I * kBP;
+        const int ra = r0 + 16 * w + li;  // this lane's A-operand row
+        mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int K = max(jp, I - tb); K < I; ++K) {
+            const int q0 = K * kBP;
+            double av[16], bv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int row = q0 + 4 * u + lk;
+                av[u] = (row < n && ra < n) ? X[static_cast<int64_t>(row) * n + ra] : 0.0;
+                bv[u] = (row < n && cin) ? W[static_cast<int64_t>(row) * n + c0 + li] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 16 * w + 4 * q + lk;
+            Rs[row][li] = (r0 + row == c0 + li ? 1.0 : 0.0) - acc[q];
+        }
+        __syncthreads();
+        const double *Li = Linv + static_cast<int64_t>(I) * kBP * kBP;
+        mfma_f64x4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < kBP; kk += 4) {
+            const double a = Li[(16 * w + li) * kBP + kk + lk];
+            const double b = Rs[kk + lk][li];
+            o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, o, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = r0 + 16 * w + 4 * q + lk;
+            if (row < n && cin) W[static_cast<int64_t>(row) * n + c0 + li] = o[q];
+        }
+        // Rs is reused and the next tile reads this one's W from memory
+        __syncthreads();
+    }
+}
+
+// X = W^T W for the lower tile pairs (I, J), I >= J (one work-group per
+// pair, the longest sums first): X[I, J] = sum over K >= I of W[K, I]^T
+// W[K, J] on the FP64 matrix cores, the next 64-deep chunk fetched into
+// registers while the current one is multiplied; the tile is written at
+// (I, J) and, through LDS, transposed at (J, I).
+__global__ __launch_bounds__(256) void k_chol_wtw(const double *__restrict__ W, int n,
+                                                  double *__restrict__ X)
+{
+    __shared__ double As[kBP][kLds];  // W[K, I] by columns (A[r][k] = W[q0 + k][i0 + r])
+    __shared__ double Bt[kBP][kLds];  // W[K, J] by columns
+    int I, J;
+    tri_pair(blockIdx.x, I, J);
+    const int nt = (n + kBP - 1) / kBP;
+    const int i0 = I * kBP, j0 = J * kBP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
     const int lr = threadIdx.x >> 6, lc = threadIdx.x & 63;
     double ra[16], rb[16];
-    auto fetch = [&](int kb) {
+    auto fetch = [&](int K) {
+        const int q0 = K * kBP;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int a = lr + 4 * k;
-            ra[k] = (r0 + a < n && kb + lc < ns)
-                        ? X[static_cast<int64_t>(r0 + a) * n + s0 + kb + lc] : 0.0;
-            rb[k] = (kb + a < ns && c0 + lc < n) ? B[static_cast<int64_t>(kb + a) * n + c0 + lc]
-                                                 : 0.0;
+        for (int u = 0; u < 16; ++u) {
+            const int row = q0 + lr + 4 * u;
+            ra[u] = (row < n && i0 + lc < n) ? W[static_cast<int64_t>(row) * n + i0 + lc] : 0.0;
+            rb[u] = (row < n && j0 + lc < n) ? W[static_cast<int64_t>(row) * n + j0 + lc] : 0.0;
         }
     };
     mfma_f64x4 acc[2][2];
     zero_acc(acc);
-    fetch(0);
-    for (int kb = 0; kb < ns; kb += kBP) {
+    fetch(I);
+    for (int K = I; K < nt; ++K) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            As[lr + 4 * k][lc] = ra[k];
-            Bt[lc][lr + 4 * k] = rb[k];
+        for (int u = 0; u < 16; ++u) {
+            As[lc][lr + 4 * u] = ra[u];
+            Bt[lc][lr + 4 * u] = rb[u];
         }
         __syncthreads();
-        if (kb + kBP < ns) fetch(kb + kBP);
+        if (K + 1 < nt) fetch(K + 1);
         mfma_tile64(As, Bt, acc, wr, wc, li, lk);
     }
+    // (I, J) directly; for I == J only its lower triangle, so that both
+    // triangles come from the same values
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wr + 16 * u + 4 * q + lk;
-                const int c = c0 + wc + 16 * v + li;
-                if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] = xo[u][v][q] + acc[u][v][q];
+                const int r = wr + 16 * p + 4 * q + lk, c = wc + 16 * v + li;
+                if (i0 + r < n && j0 + c < n && (I != J || r >= c))
+                    X[static_cast<int64_t>(i0 + r) * n + j0 + c] = acc[p][v][q];
             }
+    __syncthreads();
+    acc_to_lds(acc, As, true, wr, wc, li, lk);  // As[c][r] = X[I, J][r][c]
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < (kBP * kBP) / 256; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int c = e / kBP, r = e % kBP;
+        if (j0 + c < n && i0 + r < n && (I != J || r > c))
+            X[static_cast<int64_t>(j0 + c) * n + i0 + r] = As[c][r];
+    }
 }
 
 // y = M x, one wavefront per row; lanes stride over the columns (two per
@@ -1100,37 +1163,32 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
     return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;
 }
 
-msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, int bu, double *G,
-                                double *B, int *flag, int *host_flag)
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
+                                int *flag, int *host_flag)
 {
     if (n < 1 || n > kMaxCoarse) return MSRSB_E_ARG;
     hipMemsetAsync(flag, 0, sizeof(int), s);
-    // super-panels of kSuper columns: their 64-wide panels are eliminated
-    // within the super-panel, then one rank-kSuper update carries the
-    // combined transformation to the other columns
-    for (int s0 = 0; s0 < n; s0 += kSuper) {
-        const int ns = min(kSuper, n - s0);
-        const int st0 = s0 / kBP, st1 = (s0 + ns + kBP - 1) / kBP;
-        for (int k0 = s0; k0 < s0 + ns; k0 += kBP) {
-            const int nb = min(kBP, n - k0);
-            const int rl = min(n, k0 + nb + bl);
-            const int rtiles = (rl + kBP - 1) / kBP;
-            k_bgj_diag<<<1, 256, 0, s>>>(X, n, k0, nb, G, flag);
-            const int inner = st1 - st0 - 1;  // super-panel column tiles other than K
-            if (rtiles > 1) k_bgj_inner<<<rtiles - 1, 256, 0, s>>>(X, n, k0, nb, G, st0, inner);
-            k_bgj_rowblock<<<inner + 1, 256, 0, s>>>(X, n, k0, nb, G, st0);
-        }
-        const int rl = min(n, s0 + ns + bl), cu = min(n, s0 + ns + bu);
-        const int rtiles = (rl + kBP - 1) / kBP, ctiles = (cu + kBP - 1) / kBP;
-        const int outer = ctiles - (st1 - st0);
-        if (outer > 0) {
-            // whole column tiles are extracted: the GEMM reads B up to the tile edge
-            const int c_hi = min(n, ctiles * kBP);
-            k_bgj_extract<<<dim3((c_hi + kBlock - 1) / kBlock, ns), kBlock, 0, s>>>(X, n, s0, ns,
-                                                                                   c_hi, B);
-            k_bgj_outer<<<dim3(outer, rtiles), 256, 0, s>>>(X, n, s0, ns, B);
+    const int nt = (n + kBP - 1) / kBP;
+    // row tiles below a panel that the band reaches
+    const int tb = min(nt - 1, (max(bl, 0) + kBP - 1) / kBP);
+    // each panel's update also inverts the next panel's diagonal block, which
+    // it finalises; a panel without band rows below it leaves the next block
+    // untouched, and that block is inverted on its own
+    bool have_inv = false;
+    for (int K = 0; K < nt; ++K) {
+        const int k0 = K * kBP, nb = min(kBP, n - k0);
+        double *li = Linv + static_cast<int64_t>(K) * kBP * kBP;
+        if (!have_inv) k_chol_inv<<<1, 256, 0, s>>>(X, n, k0, nb, li, flag);
+        const int T = min(nt - 1, K + tb) - K;
+        have_inv = T > 0;
+        if (T > 0) {
+            const int nbn = min(kBP, n - k0 - kBP);
+            k_chol_update<<<T * (T + 1) / 2, 256, 0, s>>>(X, n, k0, nb, K + 1, li, li + kBP * kBP,
+                                                          nbn, flag);
         }
     }
+    k_chol_w<<<(n + 15) / 16, 256, 0, s>>>(X, n, tb, Linv, W);
+    k_chol_wtw<<<nt * (nt + 1) / 2, 256, 0, s>>>(W, n, X);
     hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
     return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;

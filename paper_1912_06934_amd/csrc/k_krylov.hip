@@ -108,41 +108,43 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
     zout[i] = zin[i] + static_cast<double>(dinv[i] * (static_cast<float>(v[i]) - s));
 }
 
-// v_c = R x with R = P^T stored by coarse rows: one wavefront per coarse
-// row (four rows per work-group, neighbouring coarse rows, which share fine
-// rows, on one XCD), eight entries per lane and step in flight, a butterfly
-// sum at the end.
+// v_c = R x with R = P^T stored by coarse rows: one work-group per coarse
+// row (neighbouring coarse rows, which share fine rows, on one XCD).  A step
+// takes up to 16 entries per lane, all of them loaded (positions beyond the
+// row end re-read its last entry and are skipped) before their x values are
+// gathered, so a coarse row of up to 4,096 entries costs two round trips.
+// Each lane sums its entries in order, then a fixed butterfly and wavefront
+// order combine the lanes, so the result is reproducible.
 template <typename T, typename XT>
-__global__ __launch_bounds__(kBlock) void k_restrict_w(int nc, const int *__restrict__ rrp,
+__global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__restrict__ rrp,
                                                        const int *__restrict__ rci,
                                                        const T *__restrict__ rv,
                                                        const XT *__restrict__ x,
                                                        double *__restrict__ xc)
 {
-    const int j = xcd_group(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    constexpr int U = 16;
+    const int j = xcd_group(blockIdx.x, gridDim.x);
     if (j >= nc) return;
     double s = 0.0;
     const int t1 = rrp[j + 1];
-    int t = rrp[j] + lane;
-    for (; t + 7 * 64 < t1; t += 8 * 64) {
-        int c[8];
-        T v[8];
+    for (int t = rrp[j] + threadIdx.x; t < t1; t += U * kBlock) {
+        int c[U];
+        T v[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            c[u] = rci[t + u * 64];
-            v[u] = rv[t + u * 64];
+        for (int u = 0; u < U; ++u) {
+            const int e = min(t + u * kBlock, t1 - 1);
+            c[u] = rci[e];
+            v[u] = rv[e];
         }
-        double xv[8];
+        double xv[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = static_cast<double>(x[c[u]]);
+        for (int u = 0; u < U; ++u) xv[u] = static_cast<double>(x[c[u]]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += static_cast<double>(v[u]) * xv[u];
+        for (int u = 0; u < U; ++u)
+            if (t + u * kBlock < t1) s += static_cast<double>(v[u]) * xv[u];
     }
-    for (; t < t1; t += 64) s += static_cast<double>(rv[t]) * static_cast<double>(x[rci[t]]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) xc[j] = s;
+    s = block_sum(s);
+    if (threadIdx.x == 0) xc[j] = s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
@@ -565,6 +567,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
             }
 #pragma unroll
             for (int o = 0; o < ND; ++o) s += av[o] * (in[o] ? pk[o] : 0.0);
+            // p_new at row i is the zero offset's entry (no second round trip)
+            double pc = pk[0];
+#pragma unroll
+            for (int o = 1; o < ND; ++o)
+                if (d.off[o] == 0) pc = pk[o];
+            pnew[i] = pc;
+            q[i] = s;
+            v[0] = pc * s;
         } else if constexpr (ND == 0) {
             for (int o = 0; o < d.n; ++o) {
                 const int k = i + d.off[o];
@@ -579,10 +589,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
                 s += a[e] * (restart ? z[k] : z[k] + beta * pold[k]);
             }
         }
-        const double pi = restart ? z[i] : z[i] + beta * pold[i];
-        pnew[i] = pi;
-        q[i] = s;
-        v[0] = pi * s;
+        if constexpr (ND <= 0) {
+            const double pi = restart ? z[i] : z[i] + beta * pold[i];
+            pnew[i] = pi;
+            q[i] = s;
+            v[0] = pi * s;
+        }
     }
     block_partials<1>(v, part);
 }
@@ -732,9 +744,9 @@ void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool
                      const double *r64, const float *r32, const double *x, double *xc)
 {
     if (fp32)
-        k_restrict_w<float, double><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
+        k_restrict_b<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
     else
-        k_restrict_w<double, double><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
+        k_restrict_b<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
 }
 
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
@@ -896,7 +908,7 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
-    k_restrict_w<float, float><<<(nc + 3) / 4, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
+    k_restrict_b<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
 }
 
 // _post: z1 += P wc, z2 = sweep(z1), z = sweep(z2) with r.z, r.(z - zold)

@@ -209,11 +209,12 @@ def _nonsymmetric(cfg, seed=0, amount=0.06):
     return cfg
 
 
-@pytest.mark.parametrize("case", [("c1", (96, 96), 4), ("c5", (48, 48, 48), 4)],
-                         ids=["2d-576coarse", "3d-1728coarse"])
+@pytest.mark.parametrize("case", [("c1", (96, 96), 4), ("c5", (48, 48, 48), 4),
+                                  ("c1", (100, 92), 4), ("c5", (44, 40, 36), 4)],
+                         ids=["2d-576coarse", "3d-1728coarse", "2d-575coarse", "3d-990coarse"])
 def test_coarse_inverse_many_panels(torch_cuda, case):
-    # coarse problems spanning several 128-column super-panels of the
-    # band-limited Gauss-Jordan inverse
+    # coarse problems spanning many 64-wide panels of the band Cholesky
+    # inverse, with whole and ragged last panels
     cfg = tpfa_inputs(*case)
     orc = oracle_setup(cfg, kmax=20)
     s, _, _ = gpu_setup_tpfa(cfg, kmax=20)
