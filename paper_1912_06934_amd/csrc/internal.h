@@ -290,8 +290,10 @@ void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, co
 void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *ad,
                        const int *rp, const int *ci, const double *a, const double *z,
                        const double *pold, double *pnew, double *q, double *part, double *scal);
+// host_out: the r.r mailbox ([0] r.r, [1] breakdown flag, [2] = tag once both
+// are written)
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part, double *scal, double *host_out);
+                       const double *q, double *part, double *scal, double *host_out, int tag);
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const float *r32, double *vc);

@@ -849,14 +849,16 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int
     chol_inv_regs(m, sm, Lnext, flag);
 }
 
-// W = L^{-1}, one strip of 16 columns S = [c0, c0 + 16) per work-group (the
-// strips are independent).  Row tile I of the strip, from the strip's own
-// panel down: wavefront w forms rows 16 w .. 16 w + 15 of
+// W = L^{-1} (row-major), one strip of 16 columns S = [c0, c0 + 16) per
+// work-group (the strips are independent).
+// Row tile I of the strip, from the strip's own panel down: wavefront w
+// forms rows 16 w .. 16 w + 15 of
 //   sum over K in [max(jp, I - tb), I) of L[I, K] W[K, S]
 // (L[I, K] read transposed from the upper triangle of X, W[K, S] written by
-// this work-group at an earlier step), subtracts it from the identity's
-// block, and multiplies by Linv_I.  Entries of W above the diagonal come out
-// as exact zeros (Linv_I is lower triangular).
+// this work-group at an earlier step; the operands of the next K tile are
+// loaded while the current one is multiplied), subtracts it from the
+// identity's block, and multiplies by Linv_I.  Entries of W above the
+// diagonal come out as exact zeros (Linv_I is lower triangular).
 __global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, int n, int tb,
                                                 const double *__restrict__ Linv,
                                                 double *__restrict__ W)
@@ -870,19 +872,33 @@ __global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, in
     for (int I = jp; I < nt; ++I) {
         const int r0 = I * kBP;
         const int ra = r0 + 16 * w + li;  // this lane's A-operand row
-        mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int K = max(jp, I - tb); K < I; ++K) {
+        const double *Li = Linv + static_cast<int64_t>(I) * kBP * kBP;
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = Li[(16 * w + li) * kBP + 4 * u + lk];
+        auto load = [&](int K, double (&av)[16], double (&bv)[16]) {
             const int q0 = K * kBP;
-            double av[16], bv[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int row = q0 + 4 * u + lk;
                 av[u] = (row < n && ra < n) ? X[static_cast<int64_t>(row) * n + ra] : 0.0;
                 bv[u] = (row < n && cin) ? W[static_cast<int64_t>(row) * n + c0 + li] : 0.0;
             }
+        };
+        mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        double a0[16], b0[16], a1[16], b1[16];
+        const int kb = max(jp, I - tb);
+        if (kb < I) load(kb, a0, b0);
+        for (int K = kb; K < I; K += 2) {
+            if (K + 1 < I) load(K + 1, a1, b1);
 #pragma unroll
             for (int u = 0; u < 16; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc, 0, 0, 0);
+            if (K + 1 >= I) break;
+            if (K + 2 < I) load(K + 2, a0, b0);
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -890,14 +906,10 @@ __global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, in
             Rs[row][li] = (r0 + row == c0 + li ? 1.0 : 0.0) - acc[q];
         }
         __syncthreads();
-        const double *Li = Linv + static_cast<int64_t>(I) * kBP * kBP;
         mfma_f64x4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < kBP; kk += 4) {
-            const double a = Li[(16 * w + li) * kBP + kk + lk];
-            const double b = Rs[kk + lk][li];
-            o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, o, 0, 0, 0);
-        }
+        for (int u = 0; u < 16; ++u)
+            o = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[u], Rs[4 * u + lk][li], o, 0, 0, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = r0 + 16 * w + 4 * q + lk;

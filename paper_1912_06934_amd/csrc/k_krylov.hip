@@ -377,11 +377,13 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(int nb, const double 
     scal[S_ALPHA] = bad ? 0.0 : rz / pq;
 }
 
-// r.r, also written with the breakdown flag to host-visible memory so the
-// host can test convergence without a copy
+// r.r, also written with the breakdown flag to a host mailbox (coherent
+// pinned memory) so that the host can test convergence without a copy or an
+// event: the values first, then (after a system-scope fence) the iteration
+// tag the host waits for
 __global__ __launch_bounds__(kFinThreads) void k_fin_rr(int nb, const double *__restrict__ part,
                                                         double *__restrict__ scal,
-                                                        double *__restrict__ host_out)
+                                                        double *__restrict__ host_out, double tag)
 {
     double t[1];
     sum_partials_block<1>(nb, part, t);
@@ -389,6 +391,8 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rr(int nb, const double *__
     scal[S_RR] = t[0];
     host_out[0] = t[0];
     host_out[1] = scal[S_BREAK];
+    __threadfence_system();
+    host_out[2] = tag;
 }
 
 // flexible (Polak-Ribiere) beta = r.(z - z_old) / (r.z)_old
@@ -954,10 +958,10 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
 }
 
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part, double *scal, double *host_out)
+                       const double *q, double *part, double *scal, double *host_out, int tag)
 {
     k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, x, r, p, q, part, scal);
-    k_fin_rr<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, host_out);
+    k_fin_rr<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, host_out, tag);
 }
 
 template <typename T>

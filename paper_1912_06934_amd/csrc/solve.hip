@@ -3,6 +3,8 @@
 // All vector arithmetic runs in device kernels; the host only queues work and
 // reads the residual norm to decide when to stop.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -337,6 +339,31 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         launch_dots_beta(s, n, v, zout, dots->zold, dots->part, dots->scal);
 }
 
+// Wait until the device has tagged the r.r mailbox mb with iteration tag
+// (mb[2]).  Only plain reads of pinned memory while the device works: a
+// stream query puts a marker into the stream, and the barrier behind it
+// leaves the device idle for several microseconds.  After a second without
+// the tag the stream is queried, and if it has finished or failed without
+// the tag arriving the wait reports failure instead of spinning on.
+static bool wait_mailbox(hipStream_t s, volatile double *mb, int tag)
+{
+    const double want = tag;
+    auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 1;; ++spin) {
+        if (mb[2] == want) break;
+        if ((spin & 0xFFFFu) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+            if (hipStreamQuery(s) != hipErrorNotReady) {
+                if (mb[2] == want) break;
+                return false;
+            }
+            t0 = std::chrono::steady_clock::now();
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return true;
+}
+
 static msrsb_status read_scalars(msrsb_ctx *c, int first, int count)
 {
     hipMemcpyAsync(c->h_pinned, c->scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
@@ -364,13 +391,13 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
     const double thr2 = (o->rtol * fn) * (o->rtol * fn);
     int it = 0;
     msrsb_status rc = MSRSB_E_NOT_CONVERGED;
-    bool restart = true;
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return MSRSB_E_HIP;
+    bool restart = true, queued = false;
     double *hist = info ? info->history : nullptr;
     const int hcap = info ? info->history_cap : 0;
     PcgDots dots{zold, c->partials, sc};
-    volatile double *hmon = c->h_pinned + 8;  // r.r and breakdown flag, written by the device
+    // r.r, the breakdown flag and the iteration tag, written by the device
+    volatile double *hmon = c->h_pinned + 8;
+    hmon[2] = -1.0;
     while (it <= o->max_iter) {
         if (restart) {
             op_residual(s, n, op, f, x, r);
@@ -383,26 +410,36 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             if (it == o->max_iter) break;
             apply_two_stage(c, o, r, z, trans, nullptr);
             launch_dot(s, n, r, z, c->partials, sc + S_RZ_OLD);
-            launch_fill(s, 1, sc + S_BETA, 0.0);  // p = z
+            launch_fill(s, 1, sc + S_BETA, 0.0);   // p = z
+            launch_fill(s, 1, sc + S_BREAK, 0.0);  // a queued-ahead step may have set it
             restart = false;
+            queued = false;
         }
-        launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
-        std::swap(p, p2);
-        launch_pcg_update(s, n, x, r, p, q, c->partials, sc, c->h_pinned + 8);
+        if (!queued) {
+            launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
+            std::swap(p, p2);
+        }
         ++it;
-        hipEventRecord(ev, s);
-        // queue the next preconditioner application while the host waits
+        launch_pcg_update(s, n, x, r, p, q, c->partials, sc, c->h_pinned + 8, it);
+        // queue the next preconditioner application, and the next step's
+        // p = z + beta p, q = A p (neither touches x or r, so the work is
+        // merely dropped if this step turns out to be the last), while the
+        // host waits for r.r
         std::swap(z, zold);
         dots.zold = zold;
         apply_two_stage(c, o, r, z, trans, &dots);
-        if (hipEventSynchronize(ev) != hipSuccess) { rc = MSRSB_E_HIP; break; }
+        queued = it < o->max_iter;
+        if (queued) {
+            launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
+            std::swap(p, p2);
+        }
+        if (!wait_mailbox(s, hmon, it)) { rc = MSRSB_E_HIP; break; }
         const double rr = hmon[0], brk = hmon[1];
         if (hist && it < hcap) hist[it] = std::sqrt(rr) / fn;
         if (brk != 0.0 || !std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }
         if (rr <= thr2) { restart = true; continue; }
         if (it >= o->max_iter) break;
     }
-    hipEventDestroy(ev);
     // true residual at exit
     op_residual(s, n, op, f, x, r);
     launch_dot(s, n, r, r, c->partials, sc + S_TMP0);
