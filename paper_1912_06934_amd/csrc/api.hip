@@ -137,6 +137,7 @@ void free_matrix(msrsb_ctx *c)
     dfree(c->gm_h);
     c->gm_cap = 0;
     dfree(c->partials);
+    dfree(c->partials_rr);
     dfree(c->tlogk);
     dfree(c->qk0);
     dfree(c->qlogE);
@@ -186,6 +187,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->vc);
     dfree(c->wc);
     dfree(c->partials);
+    dfree(c->partials_rr);
     dfree(c->pcol_ell);
     dfree(c->pcol16);
     dfree(c->p_csr_tmp);

@@ -162,6 +162,7 @@ struct msrsb_ctx {
     float *wf[3] = {};            // FP32 work vectors of the precision-form preconditioner
     double *vc = nullptr, *wc = nullptr;
     double *partials = nullptr, *scal = nullptr;
+    double *partials_rr = nullptr;  // r.r partials of the PCG update
     double *gm_v = nullptr, *gm_h = nullptr;  // GMRES basis and small arrays
     int gm_cap = 0;
     double *h_pinned = nullptr;
@@ -284,23 +285,27 @@ void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, cons
 void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                            const double *a64, const float *a32, const double *dinv64,
                            const float *dinv32, const double *r, const double *zin, double *zout,
-                           const double *zold, double *part, double *scal);
+                           const double *zold, double *part, double *scal,
+                           const double *part_rr, double *host_out, int tag);
+// beta and, with host_out, the step's r.r mailbox (see k_fin_beta)
 void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, const double *zold,
-                      double *part, double *scal);
+                      double *part, double *scal, const double *part_rr, double *host_out,
+                      int tag);
 void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *ad,
                        const int *rp, const int *ci, const double *a, const double *z,
                        const double *pold, double *pnew, double *q, double *part, double *scal);
-// host_out: the r.r mailbox ([0] r.r, [1] breakdown flag, [2] = tag once both
-// are written)
+// x += alpha p, r -= alpha q; the r.r partials (one per block) go to
+// part_rr and are summed by the step's k_fin_beta
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part, double *scal, double *host_out, int tag);
+                       const double *q, double *part_rr, double *scal);
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const float *r32, double *vc);
 void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,
-                          double *zout, const double *zold, double *partials, double *scal);
+                          double *zout, const double *zold, double *partials, double *scal,
+                          const double *part_rr, double *host_out, int tag);
 void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
                         bool fp32, const double *p64, const float *p32, const double *wc,
                         double *z, bool zero);

@@ -29,8 +29,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t m, double *__restrict__
 // reached by row j (its coarse neighbours) are found first and numbered in
 // ascending order in an LDS map; each thread then accumulates its share of
 // the fine rows into a private LDS column of per-neighbour partial sums, and
-// the partial sums of every neighbour are added in thread order.  No atomics
-// touch A_c, so it is bitwise reproducible.  The lower and upper bandwidths
+// the partial sums of every neighbour are added in thread order.  The column
+// updates are LDS atomic adds: a thread's adds to one address land in
+// program order (so the sums are reproducible), but unlike a load-add-store
+// they do not have to wait for one another when two products may share a
+// column.  No atomics touch A_c, so it is bitwise reproducible.  The lower and upper bandwidths
 // of A_c are recorded for the coarse factorisation.
 template <typename T, int NT, bool DIA>
 __global__ __launch_bounds__(NT) void k_rap(int n, int nc, int maxnb, const int *__restrict__ rrp,
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(NT) void k_rap(int n, int nc, int maxnb, const int 
             if (DIA && av == 0.0) continue;
             const double pa = pij * av;
             for (int q = prp[k]; q < prp[k + 1]; ++q)
-                acc[map[pci[q]] * NT + tid] += pa * pv[q];
+                atomicAdd(&acc[map[pci[q]] * NT + tid], pa * pv[q]);
         }
     }
     __syncthreads();
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (cl[o][u] != 0xFFFFu)
-                    acc[map[cl[o][u]] * NT + tid] += pa * static_cast<double>(v[o][u]);
+                    atomicAdd(&acc[map[cl[o][u]] * NT + tid], pa * static_cast<double>(v[o][u]));
         }
     }
     __syncthreads();

@@ -340,16 +340,20 @@ __device__ inline void block_partials(double (&v)[NV], double *__restrict__ part
 // scalar update of the Krylov method; one block of kFinThreads threads
 constexpr int kFinThreads = 1024;
 
+// The block's sums of NV partial arrays of nb entries: array q starts at
+// part + q * nb, or, for q = NV - 1 when last is given, at last.
 template <int NV>
-__device__ inline void sum_partials_block(int nb, const double *__restrict__ part, double (&tot)[NV])
+__device__ inline void sum_partials_block(int nb, const double *__restrict__ part, double (&tot)[NV],
+                                          const double *__restrict__ last = nullptr)
 {
     __shared__ double sh[NV][kFinThreads / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
+        const double *src = (q == NV - 1 && last) ? last : part + static_cast<int64_t>(q) * nb;
         double x = 0.0;
 #pragma unroll 8
-        for (int b = threadIdx.x; b < nb; b += kFinThreads) x += part[static_cast<int64_t>(q) * nb + b];
+        for (int b = threadIdx.x; b < nb; b += kFinThreads) x += src[b];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         if (lane == 0) sh[q][wid] = x;
@@ -377,30 +381,21 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(int nb, const double 
     scal[S_ALPHA] = bad ? 0.0 : rz / pq;
 }
 
-// r.r, also written with the breakdown flag to a host mailbox (coherent
-// pinned memory) so that the host can test convergence without a copy or an
-// event: the values first, then (after a system-scope fence) the iteration
-// tag the host waits for
-__global__ __launch_bounds__(kFinThreads) void k_fin_rr(int nb, const double *__restrict__ part,
-                                                        double *__restrict__ scal,
-                                                        double *__restrict__ host_out, double tag)
-{
-    double t[1];
-    sum_partials_block<1>(nb, part, t);
-    if (threadIdx.x != 0) return;
-    scal[S_RR] = t[0];
-    host_out[0] = t[0];
-    host_out[1] = scal[S_BREAK];
-    __threadfence_system();
-    host_out[2] = tag;
-}
-
-// flexible (Polak-Ribiere) beta = r.(z - z_old) / (r.z)_old
+// flexible (Polak-Ribiere) beta = r.(z - z_old) / (r.z)_old from the
+// partials [0, nb) of r.z and [nb, 2 nb) of r.(z - z_old).  With host_out
+// (inside PCG) also r.r of the step's residual update, from the partials
+// part_rr: written with the breakdown flag to a host mailbox (coherent
+// pinned memory), the values first and then, after a system-scope fence,
+// the iteration tag the host waits for.
 __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *__restrict__ part,
-                                                          double *__restrict__ scal)
+                                                          double *__restrict__ scal,
+                                                          const double *__restrict__ part_rr,
+                                                          double *__restrict__ host_out,
+                                                          double tag)
 {
-    double t[2];
-    sum_partials_block<2>(nb, part, t);
+    // r.z, r.(z - z_old) and (inside PCG) r.r in one pass
+    double t[3];
+    sum_partials_block<3>(nb, part, t, host_out != nullptr ? part_rr : part);
     if (threadIdx.x != 0) return;
     scal[S_RZ] = t[0];
     scal[S_RZDIFF] = t[1];
@@ -408,6 +403,12 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *
     if (!isfinite(b)) scal[S_BREAK] = 1.0;
     scal[S_BETA] = isfinite(b) ? b : 0.0;
     scal[S_RZ_OLD] = t[0];
+    if (host_out == nullptr) return;
+    scal[S_RR] = t[2];
+    host_out[0] = t[2];
+    host_out[1] = scal[S_BREAK];
+    __threadfence_system();
+    host_out[2] = tag;
 }
 
 template <int ND, bool SYM>
@@ -884,7 +885,8 @@ void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, cons
 void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                            const double *a64, const float *a32, const double *dinv64,
                            const float *dinv32, const double *r, const double *zin, double *zout,
-                           const double *zold, double *part, double *scal)
+                           const double *zold, double *part, double *scal,
+                           const double *part_rr, double *host_out, int tag)
 {
     with_ndiag(d, [&](auto nd, auto sym) {
         if (fp32)
@@ -894,7 +896,7 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
             k_dia_sweep_dots<MSRSB_DIA_ARGS(nd, sym), double><<<grid_for(n), kBlock, 0, s>>>(
                 n, d, a64, dinv64, r, zin, zout, zold, part);
     });
-    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, part_rr, host_out, tag);
 }
 
 // The two-stage preconditioner of the precision form with FP32 intermediate
@@ -920,7 +922,8 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
 void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,
-                          double *zout, const double *zold, double *partials, double *scal)
+                          double *zout, const double *zold, double *partials, double *scal,
+                          const double *part_rr, double *host_out, int tag)
 {
     if (pw == 8)
         k_prolong_ell<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, p32, wc, z1, 0);
@@ -932,14 +935,15 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
         k_dia_sweep_dots<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
             n, d, a32, dinv32, v, z2, zout, zold, partials);
     });
-    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), partials, scal);
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), partials, scal, part_rr, host_out, tag);
 }
 
 void launch_dots_beta(hipStream_t s, int n, const double *r, const double *z, const double *zold,
-                      double *part, double *scal)
+                      double *part, double *scal, const double *part_rr, double *host_out,
+                      int tag)
 {
     k_dots_beta<<<grid_for(n), kBlock, 0, s>>>(n, r, z, zold, part);
-    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
+    k_fin_beta<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, part_rr, host_out, tag);
 }
 
 void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *ad,
@@ -958,10 +962,9 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
 }
 
 void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part, double *scal, double *host_out, int tag)
+                       const double *q, double *part_rr, double *scal)
 {
-    k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, x, r, p, q, part, scal);
-    k_fin_rr<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal, host_out, tag);
+    k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, x, r, p, q, part_rr, scal);
 }
 
 template <typename T>

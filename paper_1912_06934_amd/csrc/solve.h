@@ -11,6 +11,9 @@ struct PcgDots {
     const double *zold;
     double *part;
     double *scal;
+    const double *part_rr;  // r.r partials of the step's update
+    double *host_out;       // r.r mailbox of the step (null: beta only)
+    int tag;           // the step's iteration number
 };
 
 msrsb_status ensure_workspace(msrsb_ctx *c);

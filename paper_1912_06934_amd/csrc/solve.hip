@@ -192,7 +192,8 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
     const size_t np = std::max<size_t>({2 * (n / kBlock + 2), 2 * static_cast<size_t>(kReduceBlocks),
                                         64 * static_cast<size_t>(std::max(c->nc, 1)) + 64,
                                         static_cast<size_t>(64 * 66)});
-    if (dev_alloc(&c->partials, np) || dev_alloc(&c->scal, S_COUNT) ||
+    if (dev_alloc(&c->partials, np) || dev_alloc(&c->partials_rr, n / kBlock + 2) ||
+        dev_alloc(&c->scal, S_COUNT) ||
         dev_alloc(&c->vc, std::max(c->nc, 1)) || dev_alloc(&c->wc, std::max(c->nc, 1)) ||
         dev_alloc(&c->eit_val, 1) || dev_alloc(&c->dev_flag, 4))
         return MSRSB_E_NOMEM;
@@ -290,7 +291,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
                             c->vc);
         launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
-                             c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal);
+                             c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
+                             dots->part_rr, dots->host_out, dots->tag);
         return;
     }
     bool zero = true;
@@ -325,7 +327,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
             const bool l1 = post_k == MSRSB_SMOOTH_L1JACOBI;
             launch_dia_sweep_dots(s, n, op.d, fp32, op.ad, op.ad32, l1 ? op.dl1 : op.dj,
                                   l1 ? op.dl132 : op.dj32, v, z, zout, dots->zold,
-                                  dots->part, dots->scal);
+                                  dots->part, dots->scal, dots->part_rr, dots->host_out,
+                                  dots->tag);
             return;
         }
         sweep(c, op, post_k, fp32, v, &z, &spare, zero, tmp);
@@ -336,7 +339,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     else
         launch_copy(s, n, z, zout);
     if (dots)
-        launch_dots_beta(s, n, v, zout, dots->zold, dots->part, dots->scal);
+        launch_dots_beta(s, n, v, zout, dots->zold, dots->part, dots->scal, dots->part_rr,
+                         dots->host_out, dots->tag);
 }
 
 // Wait until the device has tagged the r.r mailbox mb with iteration tag
@@ -394,7 +398,7 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
     bool restart = true, queued = false;
     double *hist = info ? info->history : nullptr;
     const int hcap = info ? info->history_cap : 0;
-    PcgDots dots{zold, c->partials, sc};
+    PcgDots dots{zold, c->partials, sc, c->partials_rr, c->h_pinned + 8, 0};
     // r.r, the breakdown flag and the iteration tag, written by the device
     volatile double *hmon = c->h_pinned + 8;
     hmon[2] = -1.0;
@@ -420,13 +424,14 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             std::swap(p, p2);
         }
         ++it;
-        launch_pcg_update(s, n, x, r, p, q, c->partials, sc, c->h_pinned + 8, it);
+        launch_pcg_update(s, n, x, r, p, q, c->partials_rr, sc);
         // queue the next preconditioner application, and the next step's
         // p = z + beta p, q = A p (neither touches x or r, so the work is
         // merely dropped if this step turns out to be the last), while the
         // host waits for r.r
         std::swap(z, zold);
         dots.zold = zold;
+        dots.tag = it;
         apply_two_stage(c, o, r, z, trans, &dots);
         queued = it < o->max_iter;
         if (queued) {
