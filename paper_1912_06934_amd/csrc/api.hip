@@ -176,6 +176,8 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rrp);
     dfree(c->rci);
     dfree(c->rsrc);
+    dfree(c->roff16);
+    dfree(c->rbase);
     dfree(c->r64);
     dfree(c->r32);
     dfree(c->ac);
@@ -696,9 +698,14 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     for (int i = 0; i < n; ++i)
         for (int e = hprp[i]; e < hprp[i + 1]; ++e)
             pcol[static_cast<size_t>(i) * pw + (e - hprp[i])] = hpci[e];
-    std::vector<int> rrp(nc + 1, 0), rci(pnnz), rsrc(pnnz);
-    for (int64_t e = 0; e < pnnz; ++e) rrp[hpci[e] + 1]++;
-    for (int jj = 0; jj < nc; ++jj) rrp[jj + 1] += rrp[jj];
+    // rows padded to multiples of 64 entries: a pad repeats the row's last
+    // column with value 0 (rsrc = -1)
+    std::vector<int> rlen(nc, 0);
+    for (int64_t e = 0; e < pnnz; ++e) rlen[hpci[e]]++;
+    std::vector<int> rrp(nc + 1, 0);
+    for (int jj = 0; jj < nc; ++jj) rrp[jj + 1] = rrp[jj] + (rlen[jj] + 63) / 64 * 64;
+    const int64_t rnnz = rrp[nc];
+    std::vector<int> rci(rnnz), rsrc(rnnz, -1);
     {
         std::vector<int> pos(rrp.begin(), rrp.end() - 1);
         for (int i = 0; i < n; ++i)
@@ -708,11 +715,27 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                 rsrc[pos[jj]] = i * pw + (e - hprp[i]);
                 pos[jj]++;
             }
+        for (int jj = 0; jj < nc; ++jj)
+            for (int t = pos[jj]; t < rrp[jj + 1]; ++t) rci[t] = rci[t - 1];
     }
+    // 16-bit column offsets when every 64-entry group spans fewer than 2^16 rows
+    bool r16 = true;
+    std::vector<int> rbase(rnnz / 64);
+    std::vector<uint16_t> roff(rnnz);
+    for (int64_t g = 0; g < rnnz / 64 && r16; ++g) {
+        rbase[g] = rci[64 * g];
+        for (int u = 0; u < 64; ++u) {
+            const int d = rci[64 * g + u] - rbase[g];
+            if (d < 0 || d > 0xFFFF) { r16 = false; break; }
+            roff[64 * g + u] = static_cast<uint16_t>(d);
+        }
+    }
+    c->rnnz = rnnz;
     const size_t nn = static_cast<size_t>(nc) * nc;
     if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
-        !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, pnnz) ||
-        !dalloc(c->rsrc, pnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
+        !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, rnnz) ||
+        !dalloc(c->rsrc, rnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
+        (r16 && (!dalloc(c->roff16, rnnz) || !dalloc(c->rbase, rnnz / 64))) ||
         !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
         !dalloc(c->colsrc, nc) || !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2) ||
         !dalloc(c->spd_buf, static_cast<size_t>((nc + 63) / 64) * 64 * 64))
@@ -722,8 +745,14 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     hipMemcpyAsync(c->pci, hpci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->interior, hint.data(), n, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->rrp, rrp.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
-    hipMemcpyAsync(c->rci, rci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
-    hipMemcpyAsync(c->rsrc, rsrc.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->rci, rci.data(), rnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->rsrc, rsrc.data(), rnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (r16) {
+        hipMemcpyAsync(c->roff16, roff.data(), rnnz * sizeof(uint16_t), hipMemcpyHostToDevice,
+                       c->stream);
+        hipMemcpyAsync(c->rbase, rbase.data(), rnnz / 64 * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+    }
     hipMemcpyAsync(c->pcol_ell, pcol.data(), pcol.size() * sizeof(int), hipMemcpyHostToDevice,
                    c->stream);
     std::vector<uint16_t> pcol16;
@@ -815,11 +844,11 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     const size_t jm = static_cast<size_t>(c->jw) * c->n, pm = static_cast<size_t>(c->pw) * c->n;
     if (fp32) {
         if (!dalloc_keep(c->jv32, jm) || !dalloc_keep(c->p32[0], pm) ||
-            !dalloc_keep(c->p32[1], pm) || !dalloc_keep(c->r32, c->pnnz))
+            !dalloc_keep(c->p32[1], pm) || !dalloc_keep(c->r32, c->rnnz))
             return fail(c, MSRSB_E_NOMEM, "allocation of the FP32 basis failed");
     } else {
         if (!dalloc_keep(c->jv, jm) || !dalloc_keep(c->p64[0], pm) ||
-            !dalloc_keep(c->p64[1], pm) || !dalloc_keep(c->r64, c->pnnz))
+            !dalloc_keep(c->p64[1], pm) || !dalloc_keep(c->r64, c->rnnz))
             return fail(c, MSRSB_E_NOMEM, "allocation of the FP64 basis failed");
     }
     // factored J (s_i and the upper diagonals of the filtered A) for a
@@ -914,7 +943,7 @@ msrsb_status msrsb_set_prolongation(msrsb_ctx *c, const double *val, int where)
     if (!val || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid values");
     const size_t pm = static_cast<size_t>(c->pw) * c->n;
     if (!dalloc_keep(c->p64[0], pm) || !dalloc_keep(c->p64[1], pm) ||
-        !dalloc_keep(c->r64, c->pnnz) || !dalloc_keep(c->p_csr_tmp, c->pnnz))
+        !dalloc_keep(c->r64, c->rnnz) || !dalloc_keep(c->p_csr_tmp, c->pnnz))
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     c->pcur = 0;
     c->p_is32 = false;
@@ -959,13 +988,13 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     msrsb_status st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
     const bool fp32 = c->p_is32;
-    if (fp32 ? !dalloc_keep(c->r32, c->pnnz) : !dalloc_keep(c->r64, c->pnnz))
+    if (fp32 ? !dalloc_keep(c->r32, c->rnnz) : !dalloc_keep(c->r64, c->rnnz))
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     const int nc = c->nc;
     const int64_t nn = static_cast<int64_t>(nc) * nc;
     if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
     phase_begin(c, MSRSB_PHASE_RAP);
-    launch_gather_r(s, c->pnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
+    launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
     launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
                       c->p_csr_tmp);
     for (;;) {

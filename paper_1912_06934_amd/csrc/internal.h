@@ -130,7 +130,14 @@ struct msrsb_ctx {
     double *p_csr_tmp = nullptr;  // CSR copy for msrsb_get_prolongation
 
     // R = P^T (CSR over coarse rows) with the source index into P
+    // R = P^T by coarse rows, each row padded to a multiple of 64 entries
+    // (pads repeat the row's last column with value 0, rsrc = -1); rnnz
+    // entries in all.  With roff16, the columns are also kept as 16-bit
+    // offsets from a base per 64-entry group (rbase), for the restriction.
     int *rrp = nullptr, *rci = nullptr, *rsrc = nullptr;
+    uint16_t *roff16 = nullptr;
+    int *rbase = nullptr;
+    int64_t rnnz = 0;
     double *r64 = nullptr;
     float *r32 = nullptr;
     int rmaxnb = 0;  // max coarse neighbours of a coarse row (RAP)
@@ -263,8 +270,10 @@ void launch_residual(hipStream_t s, int n, const int *rp, const int *ci, const d
 void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
                   const float *a32, const double *dinv, const float *dinv32, bool fp32,
                   const double *v, const double *zin, double *zout, bool zero_start);
-void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool fp32,
-                     const double *r64, const float *r32, const double *x, double *xc);
+// xc = R x; columns from rci, or (roff16 non-null) rbase[e / 64] + roff16[e]
+void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
+                     const uint16_t *roff16, const int *rbase, bool fp32, const double *r64,
+                     const float *r32, const double *x, double *xc);
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
                 double *out);
 void launch_copy(hipStream_t s, int n, const double *x, double *y);
@@ -300,7 +309,8 @@ void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double 
                        const double *q, double *part_rr, double *scal);
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
-                         const int *rrp, const int *rci, const float *r32, double *vc);
+                         const int *rrp, const int *rci, const uint16_t *roff16,
+                         const int *rbase, const float *r32, double *vc);
 void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,

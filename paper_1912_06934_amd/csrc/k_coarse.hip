@@ -10,12 +10,16 @@ namespace {
 
 inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
 
+// r[t] = p[src[t]], or 0 where src[t] < 0 (R's row padding)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t m, const int *__restrict__ src,
                                                    const T *__restrict__ p, T *__restrict__ r)
 {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < m) r[t] = p[src[t]];
+    if (t < m) {
+        const int e = src[t];
+        r[t] = e >= 0 ? p[e] : T(0);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t m, double *__restrict__ x, double v)

@@ -108,16 +108,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
     zout[i] = zin[i] + static_cast<double>(dinv[i] * (static_cast<float>(v[i]) - s));
 }
 
-// v_c = R x with R = P^T stored by coarse rows: one work-group per coarse
-// row (neighbouring coarse rows, which share fine rows, on one XCD).  A step
-// takes up to 16 entries per lane, all of them loaded (positions beyond the
-// row end re-read its last entry and are skipped) before their x values are
-// gathered, so a coarse row of up to 4,096 entries costs two round trips.
-// Each lane sums its entries in order, then a fixed butterfly and wavefront
-// order combine the lanes, so the result is reproducible.
-template <typename T, typename XT>
+// v_c = R x with R = P^T stored by coarse rows (padded to 64-entry groups,
+// pads of value 0): one work-group per coarse row (neighbouring coarse rows,
+// which share fine rows, on one XCD).  With R16 the columns are read as
+// 16-bit offsets from the group's base (a wavefront's 64 entries share one
+// group).  A step takes up to 16 entries per lane, all of them loaded
+// (positions beyond the row end re-read its last entry and are skipped)
+// before their x values are gathered, so a coarse row of up to 4,096
+// entries costs two round trips.  Each lane sums its entries in order, then
+// a fixed butterfly and wavefront order combine the lanes, so the result is
+// reproducible.
+template <typename T, typename XT, bool R16>
 __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__restrict__ rrp,
                                                        const int *__restrict__ rci,
+                                                       const uint16_t *__restrict__ roff,
+                                                       const int *__restrict__ rbase,
                                                        const T *__restrict__ rv,
                                                        const XT *__restrict__ x,
                                                        double *__restrict__ xc)
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__rest
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = min(t + u * kBlock, t1 - 1);
-            c[u] = rci[e];
+            c[u] = R16 ? rbase[e >> 6] + static_cast<int>(roff[e]) : rci[e];
             v[u] = rv[e];
         }
         double xv[U];
@@ -745,13 +750,25 @@ void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const doub
                                                  zero_start ? 1 : 0);
 }
 
-void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci, bool fp32,
-                     const double *r64, const float *r32, const double *x, double *xc)
+void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
+                     const uint16_t *roff16, const int *rbase, bool fp32, const double *r64,
+                     const float *r32, const double *x, double *xc)
 {
-    if (fp32)
-        k_restrict_b<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, x, xc);
-    else
-        k_restrict_b<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r64, x, xc);
+    if (fp32) {
+        if (roff16)
+            k_restrict_b<float, double, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
+                                                                    r32, x, xc);
+        else
+            k_restrict_b<float, double, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
+                                                                     r32, x, xc);
+    } else {
+        if (roff16)
+            k_restrict_b<double, double, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
+                                                                     r64, x, xc);
+        else
+            k_restrict_b<double, double, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16,
+                                                                      rbase, r64, x, xc);
+    }
 }
 
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
@@ -906,7 +923,8 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
 // PCG dots.  _pre: z1 = two sweeps from zero, tmp = v - A z1, vc = R tmp.
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
-                         const int *rrp, const int *rci, const float *r32, double *vc)
+                         const int *rrp, const int *rci, const uint16_t *roff16,
+                         const int *rbase, const float *r32, double *vc)
 {
     with_ndiag(d, [&](auto nd, auto sym) {
         k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
@@ -914,7 +932,12 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
-    k_restrict_b<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, rci, r32, tmp, vc);
+    if (roff16)
+        k_restrict_b<float, float, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, r32,
+                                                               tmp, vc);
+    else
+        k_restrict_b<float, float, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, r32,
+                                                                tmp, vc);
 }
 
 // _post: z1 += P wc, z2 = sweep(z1), z = sweep(z2) with r.z, r.(z - zold)

@@ -287,8 +287,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         post_n == 2) {
         const float *dinv = pre_k == MSRSB_SMOOTH_L1JACOBI ? op.dl132 : op.dj32;
         float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
-        launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci, c->r32,
-                            c->vc);
+        launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci,
+                            c->roff16, c->rbase, c->r32, c->vc);
         launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
                              c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
@@ -314,7 +314,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
             op_residual(s, n, op, v, z, tmp, fp32);
             res = tmp;
         }
-        launch_restrict(s, c->nc, c->rrp, c->rci, c->p_is32, c->r64, c->r32, res, c->vc);
+        launch_restrict(s, c->nc, c->rrp, c->rci, c->roff16, c->rbase, c->p_is32, c->r64, c->r32,
+                        res, c->vc);
         // the inverse from the SPD path is symmetric: no transposed product
         launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
         launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
