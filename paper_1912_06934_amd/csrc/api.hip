@@ -182,6 +182,8 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->r32);
     dfree(c->ac);
     dfree(c->acinv);
+    dfree(c->acinv_pk);
+    dfree(c->symv_part);
     dfree(c->gj_b);
     dfree(c->spd_buf);
     dfree(c->piv);
@@ -732,9 +734,12 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     }
     c->rnnz = rnnz;
     const size_t nn = static_cast<size_t>(nc) * nc;
+    const int ntc = (nc + 63) / 64, ntri = ntc * (ntc + 1) / 2;
     if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
         !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, rnnz) ||
         !dalloc(c->rsrc, rnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
+        !dalloc(c->acinv_pk, static_cast<size_t>(ntri) * 64 * 64) ||
+        !dalloc(c->symv_part, static_cast<size_t>(ntri) * 128) ||
         (r16 && (!dalloc(c->roff16, rnnz) || !dalloc(c->rbase, rnnz / 64))) ||
         !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
         !dalloc(c->colsrc, nc) || !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2) ||
@@ -857,7 +862,10 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
                       (c->jw == 3 || c->jw == 5 || c->jw == 7 || c->jw == 9 || c->jw == 27);
     phase_begin(c, MSRSB_PHASE_FILTER);
     launch_filter_jacobi(s, c->n, c->bs, o->filter, o->omega, c->rp, c->ci, c->a, c->jw, c->j_off,
-                         c->j_dia, jsym, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr);
+                         c->j_dia, jsym, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr,
+                         // A's DIA copy when it has J's offsets (scalar A: J's pattern is A's)
+                         c->bs == 1 && c->a_off.n == c->jw && c->a_off.n > 0 ? c->a_dia
+                                                                            : nullptr);
     phase_end(c, MSRSB_PHASE_FILTER);
     phase_begin(c, MSRSB_PHASE_INIT);
     const bool warm = o->warm_start && c->has_basis;
@@ -995,9 +1003,13 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
     phase_begin(c, MSRSB_PHASE_RAP);
     launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
-    launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
-                      c->p_csr_tmp);
+    bool have_csr = false;  // the CSR copy of P, for the general RAP only
     for (;;) {
+        if (!have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16)) {
+            launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
+                              c->p_csr_tmp);
+            have_csr = true;
+        }
         hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
         hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
         launch_fill(s, nn, c->ac, 0.0);
@@ -1027,7 +1039,7 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         // W^T W; a non-positive pivot falls back to partial pivoting
         hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
         st = coarse_inverse_spd(s, nc, c->acinv, std::max(c->h_band[0], c->h_band[1]), c->spd_buf,
-                                work, c->dev_flag, &hflag);
+                                work, c->acinv_pk, c->dev_flag, &hflag);
         c->acinv_sym = st == MSRSB_OK;
     }
     if (st == MSRSB_E_COARSE_SINGULAR) {

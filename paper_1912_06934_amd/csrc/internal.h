@@ -146,6 +146,10 @@ struct msrsb_ctx {
 
     // coarse operator and its inverse
     double *ac = nullptr, *acinv = nullptr, *gj_b = nullptr;
+    // the SPD path's inverse: lower 64 x 64 tiles (I >= J) packed in
+    // I (I + 1) / 2 + J order, each row-major and whole (diagonal tiles hold
+    // both triangles, zeros past nc); and the partials of its product
+    double *acinv_pk = nullptr, *symv_part = nullptr;
     bool acinv_sym = false;  // acinv came from the SPD (symmetric) path
     double *spd_buf = nullptr;  // inverse Cholesky factors of the diagonal blocks (SPD path)
     int *piv = nullptr, *colsrc = nullptr, *dev_flag = nullptr;
@@ -228,7 +232,8 @@ struct SmoothArgs {
 };
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
-                          bool use_dia, bool sym, double *jv64, float *jv32);
+                          bool use_dia, bool sym, double *jv64, float *jv32,
+                          const double *ad = nullptr);
 void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32);
 void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,
@@ -249,13 +254,18 @@ void launch_build_maps(hipStream_t s, int n, int pw, int jw, const DiaOffsets &j
 // ---- coarse kernels (k_coarse.hip) ----
 void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const double *p64,
                      const float *p32, double *r64, float *r32);
+// whether launch_rap takes the stencil/ELL form (which needs no CSR copy of P)
+bool rap_uses_ell(int maxnb, const DiaOffsets &d, int pw, const uint16_t *pcol16);
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band);
 msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
-                                int *flag, int *host_flag);
+                                double *pk, int *flag, int *host_flag);
+// y = S x for the symmetric S in the packed lower-tile form (acinv_pk)
+void launch_symv_packed(hipStream_t s, int n, const double *pk, const double *x, double *y,
+                        double *part);
 void launch_fill(hipStream_t s, int64_t m, double *x, double v);
 msrsb_status coarse_inverse(hipStream_t s, int nc, double *ac_work, double *inv_out,
                             double *bbuf, int *piv, int *colsrc, int *flag, int *host_flag);

@@ -126,17 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
 
 // Initial basis (Sec. 2.1): characteristic function of the coarse block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init_basis(int n, int pw, const int *__restrict__ pcol,
+__global__ __launch_bounds__(kBlock) void k_init_basis(int64_t m, int pw,
+                                                       const int *__restrict__ pcol,
                                                        const int *__restrict__ part,
                                                        T *__restrict__ p)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int pi = part[i];
-    for (int s = 0; s < pw; ++s) {
-        const int64_t e = static_cast<int64_t>(i) * pw + s;
-        p[e] = (pcol[e] == pi) ? T(1) : T(0);
-    }
+    // one ELL entry per thread (coalesced stores)
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    p[e] = (pcol[e] == part[e / pw]) ? T(1) : T(0);
 }
 
 // One restricted smoothing iteration (eq. smoother, Alg. 1), slot-map form.
@@ -495,20 +493,82 @@ __global__ __launch_bounds__(kBlock) void k_basis_stats(int n, int pw, const int
     }
 }
 
-__global__ void k_basis_stats_final(int nb, const double *__restrict__ partials,
-                                    double *__restrict__ out)
+// The same for 4- or 8-wide rows, one ELL entry per thread (coalesced): a
+// row is PW consecutive lanes, its sum formed by a butterfly over them.
+template <typename T, int PW>
+__global__ __launch_bounds__(kBlock) void k_basis_stats_e(int64_t m, const int *__restrict__ pcol,
+                                                          const T *__restrict__ p,
+                                                          double *__restrict__ partials)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double sh[3][kBlock];
     double err = 0.0, lo = 1e300, hi = -1e300;
-    for (int b = 0; b < nb; ++b) {
+    // the stride is a multiple of PW, so a lane keeps its slot
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < m;
+         e += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const bool real = pcol[e] >= 0;
+        const double v = real ? static_cast<double>(p[e]) : 0.0;
+        if (real) {
+            lo = fmin(lo, v);
+            hi = fmax(hi, v);
+        }
+        double s = v;
+#pragma unroll
+        for (int off = 1; off < PW; off <<= 1) s += __shfl_xor(s, off, 64);
+        if ((threadIdx.x & (PW - 1)) == 0) {
+            const double d = fabs(s - 1.0);
+            err = (d > err || d != d) ? d : err;
+        }
+    }
+    sh[0][threadIdx.x] = err;
+    sh[1][threadIdx.x] = lo;
+    sh[2][threadIdx.x] = hi;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            const double o = sh[0][threadIdx.x + st];
+            sh[0][threadIdx.x] = (o > sh[0][threadIdx.x] || o != o) ? o : sh[0][threadIdx.x];
+            sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + st]);
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = sh[0][0];
+        partials[3 * blockIdx.x + 1] = sh[1][0];
+        partials[3 * blockIdx.x + 2] = sh[2][0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_basis_stats_final(int nb,
+                                                              const double *__restrict__ partials,
+                                                              double *__restrict__ out)
+{
+    __shared__ double sh[3][kBlock];
+    double err = 0.0, lo = 1e300, hi = -1e300;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
         const double o = partials[3 * b];
         err = (o > err || o != o) ? o : err;
         lo = fmin(lo, partials[3 * b + 1]);
         hi = fmax(hi, partials[3 * b + 2]);
     }
-    out[0] = err;
-    out[1] = lo;
-    out[2] = hi;
+    sh[0][threadIdx.x] = err;
+    sh[1][threadIdx.x] = lo;
+    sh[2][threadIdx.x] = hi;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            const double o = sh[0][threadIdx.x + st];
+            sh[0][threadIdx.x] = (o > sh[0][threadIdx.x] || o != o) ? o : sh[0][threadIdx.x];
+            sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + st]);
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0];
+        out[1] = sh[1][0];
+        out[2] = sh[2][0];
+    }
 }
 
 template <typename S, typename D>
@@ -641,10 +701,66 @@ void smooth_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *
 
 }  // namespace
 
+// The same for a scalar stencil A whose DIA copy (ad, [jw][n], absent
+// entries zero) has J's offsets: A is read diagonal by diagonal (coalesced)
+// instead of row by row.  Dhat sums the off-diagonals in offset order, which
+// is column order, so the values equal k_filter_jacobi's.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_filter_jacobi_dia(int n, int filter, double omega,
+                                                              const double *__restrict__ ad,
+                                                              DiaOffsets joff, int sym,
+                                                              T *__restrict__ jv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int jw = joff.n;
+    int mid = 0;
+    for (int o = 0; o < jw; ++o)
+        if (joff.off[o] == 0) mid = o;
+    double d = 0.0;
+    for (int o = 0; o < jw; ++o) {
+        if (o == mid) continue;
+        double g = ad[static_cast<int64_t>(o) * n + i];
+        if (filter && g > 0.0) g = 0.0;
+        d -= g;
+    }
+    for (int o = 0; o < jw; ++o) {
+        double v;
+        if (sym) {
+            if (o < mid) {
+                v = 0.0;
+            } else if (o == mid) {
+                v = d == 0.0 ? 0.0 : -omega / d;
+            } else {
+                v = ad[static_cast<int64_t>(o) * n + i];
+                if (filter && v > 0.0) v = 0.0;
+            }
+        } else if (d == 0.0) {
+            v = o == mid ? 1.0 : 0.0;
+        } else if (o == mid) {
+            v = 1.0 - omega;
+        } else {
+            double g = ad[static_cast<int64_t>(o) * n + i];
+            if (filter && g > 0.0) g = 0.0;
+            v = g == 0.0 ? 0.0 : -omega * g / d;
+        }
+        jv[static_cast<int64_t>(o) * n + i] = static_cast<T>(v);
+    }
+}
+
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
-                          bool use_dia, bool sym, double *jv64, float *jv32)
+                          bool use_dia, bool sym, double *jv64, float *jv32, const double *ad)
 {
+    if (ad && use_dia && bs == 1) {
+        if (jv32)
+            k_filter_jacobi_dia<float><<<grid_for(n), kBlock, 0, s>>>(n, filter, omega, ad, joff,
+                                                                      sym ? 1 : 0, jv32);
+        else
+            k_filter_jacobi_dia<double><<<grid_for(n), kBlock, 0, s>>>(n, filter, omega, ad, joff,
+                                                                       sym ? 1 : 0, jv64);
+        return;
+    }
     if (jv32)
         k_filter_jacobi<float><<<grid_for(n), kBlock, 0, s>>>(n, bs, filter, omega, rp, ci, a, jw,
                                                               joff, use_dia ? 1 : 0, sym ? 1 : 0,
@@ -658,10 +774,11 @@ void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega
 void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32)
 {
+    const int64_t m = static_cast<int64_t>(n) * pw;
     if (p32)
-        k_init_basis<float><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, part, p32);
+        k_init_basis<float><<<grid_for(m), kBlock, 0, s>>>(m, pw, pcol, part, p32);
     else
-        k_init_basis<double><<<grid_for(n), kBlock, 0, s>>>(n, pw, pcol, part, p64);
+        k_init_basis<double><<<grid_for(m), kBlock, 0, s>>>(m, pw, pcol, part, p64);
 }
 
 void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,
@@ -678,12 +795,24 @@ void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *
 void launch_basis_stats(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
                         const double *p64, const float *p32, double *partials, double *out3)
 {
-    const int nb = 256;
-    if (fp32)
+    const int64_t m = static_cast<int64_t>(n) * pw;
+    const int nb = std::min(2048, std::max(1, grid_for(pw == 4 || pw == 8 ? m : n)));
+    if (pw == 8) {
+        if (fp32)
+            k_basis_stats_e<float, 8><<<nb, kBlock, 0, s>>>(m, pcol, p32, partials);
+        else
+            k_basis_stats_e<double, 8><<<nb, kBlock, 0, s>>>(m, pcol, p64, partials);
+    } else if (pw == 4) {
+        if (fp32)
+            k_basis_stats_e<float, 4><<<nb, kBlock, 0, s>>>(m, pcol, p32, partials);
+        else
+            k_basis_stats_e<double, 4><<<nb, kBlock, 0, s>>>(m, pcol, p64, partials);
+    } else if (fp32) {
         k_basis_stats<float><<<nb, kBlock, 0, s>>>(n, pw, pcol, p32, partials);
-    else
+    } else {
         k_basis_stats<double><<<nb, kBlock, 0, s>>>(n, pw, pcol, p64, partials);
-    k_basis_stats_final<<<1, 64, 0, s>>>(nb, partials, out3);
+    }
+    k_basis_stats_final<<<1, kBlock, 0, s>>>(nb, partials, out3);
 }
 
 void launch_p_convert(hipStream_t s, int64_t m, const float *src, double *dst)

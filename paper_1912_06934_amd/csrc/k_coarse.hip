@@ -927,13 +927,15 @@ __global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, in
     }
 }
 
-// X = W^T W for the lower tile pairs (I, J), I >= J (one work-group per
-// pair, the longest sums first): X[I, J] = sum over K >= I of W[K, I]^T
-// W[K, J] on the FP64 matrix cores, the next 64-deep chunk fetched into
-// registers while the current one is multiplied; the tile is written at
-// (I, J) and, through LDS, transposed at (J, I).
+// A_c^{-1} = W^T W for the lower tile pairs (I, J), I >= J (one work-group
+// per pair, the longest sums first): tile (I, J) = sum over K >= I of
+// W[K, I]^T W[K, J] on the FP64 matrix cores, the next 64-deep chunk fetched
+// into registers while the current one is multiplied.  The tile goes whole
+// into the packed lower-tile array pk (zeros past n); a diagonal tile's
+// upper triangle is its lower one transposed through LDS, so the inverse is
+// exactly symmetric.
 __global__ __launch_bounds__(256) void k_chol_wtw(const double *__restrict__ W, int n,
-                                                  double *__restrict__ X)
+                                                  double *__restrict__ pk)
 {
     __shared__ double As[kBP][kLds];  // W[K, I] by columns (A[r][k] = W[q0 + k][i0 + r])
     __shared__ double Bt[kBP][kLds];  // W[K, J] by columns
@@ -969,28 +971,112 @@ __global__ __launch_bounds__(256) void k_chol_wtw(const double *__restrict__ W, 
         if (K + 1 < nt) fetch(K + 1);
         mfma_tile64(As, Bt, acc, wr, wc, li, lk);
     }
-    // (I, J) directly; for I == J only its lower triangle, so that both
-    // triangles come from the same values
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int v = 0; v < 2; ++v)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = wr + 16 * p + 4 * q + lk, c = wc + 16 * v + li;
-                if (i0 + r < n && j0 + c < n && (I != J || r >= c))
-                    X[static_cast<int64_t>(i0 + r) * n + j0 + c] = acc[p][v][q];
-            }
     __syncthreads();
-    acc_to_lds(acc, As, true, wr, wc, li, lk);  // As[c][r] = X[I, J][r][c]
+    acc_to_lds(acc, As, false, wr, wc, li, lk);  // As[r][c] = tile[r][c]
     __syncthreads();
+    double *tile = pk + static_cast<int64_t>(blockIdx.x) * kBP * kBP;
 #pragma unroll
     for (int it = 0; it < (kBP * kBP) / 256; ++it) {
         const int e = threadIdx.x + 256 * it;
-        const int c = e / kBP, r = e % kBP;
-        if (j0 + c < n && i0 + r < n && (I != J || r > c))
-            X[static_cast<int64_t>(j0 + c) * n + i0 + r] = As[c][r];
+        const int r = e / kBP, c = e % kBP;
+        double v = (I != J || r >= c) ? As[r][c] : As[c][r];
+        if (i0 + r >= n || j0 + c >= n) v = 0.0;
+        tile[e] = v;
     }
+}
+
+// y = S x for a symmetric S held as packed lower 64 x 64 tiles.  Tile t =
+// (I, J) (one work-group each): thread (g, h) = (t / 16, t % 16) holds rows
+// 4g .. 4g + 3 and columns 4h .. 4h + 3 of the tile; the row partials
+// S_IJ x_J (16 lanes per row group) and, off the diagonal, the column
+// partials S_IJ^T x_I (16 row groups per column group, across the four
+// wavefronts through LDS) are reduced in a fixed order and written to
+// part[t][0][.] and part[t][1][.].
+__global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ pk, int n,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ part)
+{
+    __shared__ double sh[4][kBP];
+    int I, J;
+    tri_pair(blockIdx.x, I, J);
+    const int t = threadIdx.x, g = t >> 4, h = t & 15;
+    const int lane = t & 63, w = t >> 6;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const d4 *tile = reinterpret_cast<const d4 *>(pk + static_cast<int64_t>(blockIdx.x) * kBP * kBP);
+    d4 m[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) m[a] = tile[(4 * g + a) * (kBP / 4) + h];
+    double xj[4], xi[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int cj = J * kBP + 4 * h + b, ri = I * kBP + 4 * g + b;
+        xj[b] = cj < n ? x[cj] : 0.0;
+        xi[b] = ri < n ? x[ri] : 0.0;
+    }
+    double* out = part + static_cast<int64_t>(blockIdx.x) * 2 * kBP;
+    // rows: sum over the 16 lanes of a row group
+    double rs[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = m[a][0] * xj[0];
+        v += m[a][1] * xj[1];
+        v += m[a][2] * xj[2];
+        v += m[a][3] * xj[3];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        rs[a] = v;
+    }
+    if (h == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) out[4 * g + a] = rs[a];
+    }
+    if (I == J) return;
+    // columns: the four row groups of a wavefront by shuffles, then the
+    // four wavefronts in order through LDS
+    double cs[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        double v = m[0][b] * xi[0];
+        v += m[1][b] * xi[1];
+        v += m[2][b] * xi[2];
+        v += m[3][b] * xi[3];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        cs[b] = v;
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sh[w][4 * h + b] = cs[b];
+    }
+    __syncthreads();
+    if (t < kBP) out[kBP + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+}
+
+// y_I = sum over J <= I of the row partials of tile (I, J) and over J > I
+// of the column partials of tile (J, I), in order of J (all partials of a
+// row loaded before the sum: nt <= kMaxCoarse / 64 = 64)
+__global__ __launch_bounds__(kBP) void k_symv_final(const double *__restrict__ part, int n,
+                                                    double *__restrict__ y)
+{
+    constexpr int kMaxTiles = kMaxCoarse / kBP;
+    const int I = blockIdx.x, r = threadIdx.x, nt = gridDim.x;
+    const int row = I * kBP + r;
+    if (row >= n) return;
+    double v[kMaxTiles];
+#pragma unroll
+    for (int J = 0; J < kMaxTiles; ++J) {
+        int64_t e = 0;
+        if (J <= I)
+            e = (static_cast<int64_t>(I) * (I + 1) / 2 + J) * 2 * kBP + r;
+        else if (J < nt)
+            e = (static_cast<int64_t>(J) * (J + 1) / 2 + I) * 2 * kBP + kBP + r;
+        v[J] = J < nt ? part[e] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int J = 0; J < kMaxTiles; ++J)
+        if (J < nt) s += v[J];
+    y[row] = s;
 }
 
 // y = M x, one wavefront per row; lanes stride over the columns (two per
@@ -1098,6 +1184,12 @@ bool rap_ell(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *r
     }
 }
 
+bool rap_uses_ell(int maxnb, const DiaOffsets &d, int pw, const uint16_t *pcol16)
+{
+    return maxnb <= 32 && pw == 8 && pcol16 &&
+           (d.n == 3 || d.n == 5 || d.n == 7 || d.n == 9);
+}
+
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
@@ -1183,7 +1275,7 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
 }
 
 msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
-                                int *flag, int *host_flag)
+                                double *pk, int *flag, int *host_flag)
 {
     if (n < 1 || n > kMaxCoarse) return MSRSB_E_ARG;
     hipMemsetAsync(flag, 0, sizeof(int), s);
@@ -1207,10 +1299,18 @@ msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double 
         }
     }
     k_chol_w<<<(n + 15) / 16, 256, 0, s>>>(X, n, tb, Linv, W);
-    k_chol_wtw<<<nt * (nt + 1) / 2, 256, 0, s>>>(W, n, X);
+    k_chol_wtw<<<nt * (nt + 1) / 2, 256, 0, s>>>(W, n, pk);
     hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
     return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;
+}
+
+void launch_symv_packed(hipStream_t s, int n, const double *pk, const double *x, double *y,
+                        double *part)
+{
+    const int nt = (n + kBP - 1) / kBP;
+    k_symv_tiles<<<nt * (nt + 1) / 2, 256, 0, s>>>(pk, n, x, part);
+    k_symv_final<<<nt, kBP, 0, s>>>(part, n, y);
 }
 
 void launch_gemv(hipStream_t s, int n, const double *m, const double *x, double *y, bool trans,

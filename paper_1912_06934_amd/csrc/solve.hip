@@ -191,7 +191,8 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
         if (dev_alloc(&p, n)) return MSRSB_E_NOMEM;
     const size_t np = std::max<size_t>({2 * (n / kBlock + 2), 2 * static_cast<size_t>(kReduceBlocks),
                                         64 * static_cast<size_t>(std::max(c->nc, 1)) + 64,
-                                        static_cast<size_t>(64 * 66)});
+                                        static_cast<size_t>(64 * 66),
+                                        static_cast<size_t>(3 * 2048)});
     if (dev_alloc(&c->partials, np) || dev_alloc(&c->partials_rr, n / kBlock + 2) ||
         dev_alloc(&c->scal, S_COUNT) ||
         dev_alloc(&c->vc, std::max(c->nc, 1)) || dev_alloc(&c->wc, std::max(c->nc, 1)) ||
@@ -264,6 +265,16 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
 // smoothers of A^T, pre and post exchanged, and A_c^{-T}.  With dots (inside
 // PCG) the products r.z and r.(z - zold) and the flexible beta are formed as
 // well, fused into the last sweep when possible.
+// wc = A_c^{-1} vc (A_c^{-T} for trans): the SPD path's symmetric inverse
+// from its packed lower tiles, otherwise the dense product
+static void coarse_apply(msrsb_ctx *c, bool trans)
+{
+    if (c->acinv_sym)
+        launch_symv_packed(c->stream, c->nc, c->acinv_pk, c->vc, c->wc, c->symv_part);
+    else
+        launch_gemv(c->stream, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
+}
+
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
                      bool trans, const PcgDots *dots)
 {
@@ -289,7 +300,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
         launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci,
                             c->roff16, c->rbase, c->r32, c->vc);
-        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
+        coarse_apply(c, trans);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
                              c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
                              dots->part_rr, dots->host_out, dots->tag);
@@ -316,8 +327,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         }
         launch_restrict(s, c->nc, c->rrp, c->rci, c->roff16, c->rbase, c->p_is32, c->r64, c->r32,
                         res, c->vc);
-        // the inverse from the SPD path is symmetric: no transposed product
-        launch_gemv(s, c->nc, c->acinv, c->vc, c->wc, trans && !c->acinv_sym, c->partials);
+        coarse_apply(c, trans);
         launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
                            c->wc, z, zero);
         zero = false;
