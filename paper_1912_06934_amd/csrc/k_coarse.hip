@@ -636,116 +636,226 @@ __device__ inline double readlane_d(double v, int lane)
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-// Linv = L^{-1} for a 64 x 64 diagonal block D = L L^T, from Gaussian
-// elimination without pivoting on [D | I]: with D = L_u diag(u) L_u^T (L_u
-// unit lower triangular, u the pivots) the right half ends as L_u^{-1}, and
-// Linv = diag(u)^{-1/2} L_u^{-1}.  Column j of the left half is dead once
-// step j has used it, and column j of the right half is born at step j, so
-// both share one register slot: lane r of wavefront w keeps row r, slots
-// 16 w .. 16 w + 15 (m on entry: D's entries).
-//
-// The pivots are taken four at a time.  The wavefront owning the four
-// columns runs the four unblocked steps on them alone (pivot u_k, the
-// multipliers m_rk = x_rk / u_k of every row, slot k turned into -m_rk) and
-// publishes the multipliers; lanes k .. k + 3 of every wavefront publish
-// their rows.  After one barrier every wavefront applies the four steps to
-// its other slots: the pivot rows as they stood at their step,
-// P_t = x_(k+t) - sum_(t' < t) m_(k+t, k+t') P_t', then x_r -= m_(r, k+t) P_t
-// in step order, the same operations as the unblocked elimination.
-// Non-positive or non-finite pivots set *flag.
-struct CholInvSmem {
-    double msh[2][4][kBP];   // multipliers of a block of four pivots (by parity)
-    double prow[2][4][kBP];  // the block's pivot rows before the block
-    double piv[kBP];
-};
+// ---- inverse Cholesky factor of a 64 x 64 diagonal block -----------------
+// Linv = L^{-1} for a symmetric positive definite D = L L^T held in LDS,
+// blocked by 16 x 16 blocks (i, j = 0 .. 3), right-looking:
+//   for k = 0 .. 3:  Li_kk = L_kk^{-1} of the current D_kk (one wavefront);
+//                    L_ik = D_ik Li_kk^T (i > k);
+//                    D_ij -= L_ik L_jk^T (k < j <= i),
+// then the blocks below the diagonal of L^{-1}, by distance from it,
+//   Li_ij = -Li_ii (sum over j <= m < i of L_im Li_mj).
+// The 16 x 16 products run on the FP64 matrix cores; the diagonal blocks are
+// factored by Gaussian elimination on [D_kk | I] (below).
 
-__device__ inline void chol_inv_regs(double (&m)[16], CholInvSmem &sm, double *__restrict__ Linv,
-                                     int *__restrict__ flag)
+// Reciprocal by Newton-Raphson refinement of the hardware estimate: two
+// steps r <- r + r (1 - p r) from v_rcp_f64 (about 2^-23 relative error)
+// give the reciprocal to within about an ulp.
+__device__ __forceinline__ double recip_nr(double p)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+
+// One wavefront: Li block (kb, kb) = L_kk^{-1} of the 16 x 16 block (kb, kb)
+// of D (lower triangle read).  Gaussian elimination without pivoting on
+// [D_kk | I]: with D_kk = L_u diag(u) L_u^T (L_u unit lower triangular) the
+// right half ends as L_u^{-1}, and L^{-1} = diag(u)^{-1/2} L_u^{-1}.  Column c
+// of the left half is dead after step c and column c of the right half is
+// born at step c, so both share one slot.  Lane r + 16 g holds row r, slots
+// 4 g .. 4 g + 3.  Returns true on a non-positive or non-finite pivot.
+__device__ inline bool chol_inv16(const double (*D)[kLds], double (*Li)[kLds], int kb, int lane)
+{
+    const int r = lane & 15, g = lane >> 4, o = 16 * kb;
+    double m[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = 4 * g + s;
+        m[s] = c <= r ? D[o + r][o + c] : D[o + c][o + r];
+    }
     bool bad = false;
-    // blocks 4 ow + i: the slots s0 = 4 i are fixed at compile time, the
-    // owning wavefront ow and the pivot rows k are uniform run-time values
-#pragma unroll 1
-    for (int ow = 0; ow < kBP / 16; ++ow)
+    double ur = 1.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int k = 16 * ow + 4 * i, par = i & 1, s0 = 4 * i;
-        if (lane >= k && lane < k + 4) {
+    for (int k = 0; k < 16; ++k) {
+        const int gk = k >> 2, sk = k & 3;
+        const double p = readlane_d(m[sk], k + 16 * gk);
+        bad |= !(p > 0.0) || !isfinite(p);
+        if (r == k) ur = p;
+        const double rp = recip_nr(p);
+        // x_rk of this lane's row and the pivot row's entries of its slots
+        const double xrk = __shfl(m[sk], r + 16 * gk, 64);
+        double pk[4];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) sm.prow[par][lane - k][16 * w + s] = m[s];
+        for (int s = 0; s < 4; ++s) pk[s] = __shfl(m[s], k + 16 * g, 64);
+        const double mult = r > k ? xrk * rp : 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s == sk && g == gk)
+                m[s] = r > k ? -mult : (r == k ? 1.0 : m[s]);
+            else
+                m[s] = fma(-mult, pk[s], m[s]);
         }
-        if (w == ow) {
+    }
+    const double rs = 1.0 / sqrt(ur);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int kt = k + t;
-                const double p = readlane_d(m[s0 + t], kt);
-                bad |= !(p > 0.0) || !isfinite(p);
-                const double mult = lane > kt ? m[s0 + t] / p : 0.0;
-                sm.msh[par][t][lane] = mult;
-                if (lane == 0) sm.piv[kt] = p;
+    for (int s = 0; s < 4; ++s) {
+        const int c = 4 * g + s;
+        Li[o + r][o + c] = c <= r ? m[s] * rs : 0.0;
+    }
+    return bad;
+}
+
+// acc += (-)A B for 16 x 16 blocks in LDS: A at (ar, ac) by rows; B at
+// (br, bc) by rows, or (bt) B^T at (br, bc) by rows.  Lane l supplies
+// A[l % 16][kk + l / 16] and B[kk + l / 16][l % 16] at k-steps kk = 0, 4,
+// 8, 12; result register q of lane l is row 4 q + l / 16, column l % 16.
+__device__ inline mfma_f64x4 mfma16(const double (*A)[kLds], int ar, int ac, bool neg,
+                                    const double (*B)[kLds], int br, int bc, bool bt,
+                                    mfma_f64x4 acc, int li, int lk)
+{
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (u == t) continue;
-                    const double pk = readlane_d(m[s0 + u], kt);
-                    m[s0 + u] -= mult * pk;
+    for (int kk = 0; kk < 16; kk += 4) {
+        const double av = A[ar + li][ac + kk + lk];
+        const double b = bt ? B[br + li][bc + kk + lk] : B[br + kk + lk][bc + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(neg ? -av : av, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// acc += (-)A B with B a 16 x 16 result held in registers (result register q
+// of lane l is B's row 4 q + l / 16, column l % 16: B's k-step q operand)
+__device__ inline mfma_f64x4 mfma16_breg(const double (*A)[kLds], int ar, int ac, bool neg,
+                                         const mfma_f64x4 &B, mfma_f64x4 acc, int li, int lk)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double av = A[ar + li][ac + 4 * q + lk];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(neg ? -av : av, B[q], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ inline mfma_f64x4 load_blk(const double (*T)[kLds], int r0, int c0, int li, int lk)
+{
+    mfma_f64x4 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = T[r0 + 4 * q + lk][c0 + li];
+    return v;
+}
+
+__device__ inline void store_blk(double (*T)[kLds], int r0, int c0, const mfma_f64x4 &v, int li,
+                                 int lk)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T[r0 + 4 * q + lk][c0 + li] = v[q];
+}
+
+// orders one wavefront's LDS writes before its own later LDS reads
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// D_ij -= L_ik L_jk^T (L's blocks stored in D's place)
+__device__ inline void schur_blk(double (*D)[kLds], int i, int j, int k, int li, int lk)
+{
+    mfma_f64x4 acc = load_blk(D, 16 * i, 16 * j, li, lk);
+    acc = mfma16(D, 16 * i, 16 * k, true, D, 16 * j, 16 * k, true, acc, li, lk);
+    store_blk(D, 16 * i, 16 * j, acc, li, lk);
+}
+
+// Called by all 256 threads; D (64 x 64, symmetric positive definite, lower
+// triangle read) is overwritten by L's blocks and Schur complements, Li
+// receives L^{-1} on and below the diagonal (the blocks above it are not
+// written).  Returns true in every thread when a pivot was not positive.
+__device__ __forceinline__ bool chol_inv64(double (*D)[kLds], double (*Li)[kLds])
+{
+    __shared__ int bad_any;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    bool bad = false;
+    if (threadIdx.x == 0) bad_any = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // wavefront 0 factors D_kk (already final: it updated it itself);
+        // the others finish the previous step's Schur updates meanwhile
+        if (w == 0) {
+            bad |= chol_inv16(D, Li, k, lane);
+        } else if (k > 0) {
+            int t = 0;
+#pragma unroll
+            for (int i = k; i < 4; ++i)
+#pragma unroll
+                for (int j = k; j <= i; ++j) {
+                    if (i == k && j == k) continue;
+                    if (t++ % 3 == w - 1) schur_blk(D, i, j, k - 1, li, lk);
                 }
-                m[s0 + t] = lane > kt ? -mult : (lane == kt ? 1.0 : m[s0 + t]);
+        }
+        __syncthreads();
+        if (k == 3) break;
+        // L_ik = D_ik Li_kk^T by wavefront i - k - 1; wavefront 0 goes on to
+        // D_{k+1,k+1} -= L_{k+1,k} L_{k+1,k}^T, the next step's diagonal block
+        const int i = k + 1 + w;
+        if (i < 4) {
+            mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mfma16(D, 16 * i, 16 * k, false, Li, 16 * k, 16 * k, true, acc, li, lk);
+            store_blk(D, 16 * i, 16 * k, acc, li, lk);
+            if (w == 0) {
+                wave_lds_sync();
+                schur_blk(D, k + 1, k + 1, k, li, lk);
             }
         }
         __syncthreads();
-        double mr[4], mk[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            mr[t] = sm.msh[par][t][lane];
-#pragma unroll
-            for (int u = t + 1; u < 4; ++u) mk[u][t] = sm.msh[par][t][k + u];
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            if (w == ow && s >= s0 && s < s0 + 4) continue;
-            const int j = 16 * w + s;
-            double P[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                double v = sm.prow[par][t][j];
-#pragma unroll
-                for (int u = 0; u < t; ++u) v -= mk[t][u] * P[u];
-                P[t] = v;
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) m[s] -= mr[t] * P[t];
-        }
     }
-    const double rs = 1.0 / sqrt(sm.piv[lane]);
+    // off-diagonal blocks of L^{-1}, one block per wavefront, by distance
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int j = 16 * w + s;
-        Linv[lane * kBP + j] = j <= lane ? m[s] * rs : 0.0;
+    for (int d = 1; d < 4; ++d) {
+        const int j = w, i = w + d;
+        if (i < 4) {
+            mfma_f64x4 sacc = {0.0, 0.0, 0.0, 0.0};
+            for (int mm = j; mm < i; ++mm)
+                sacc = mfma16(D, 16 * i, 16 * mm, false, Li, 16 * mm, 16 * j, false, sacc, li, lk);
+            mfma_f64x4 res = {0.0, 0.0, 0.0, 0.0};
+            res = mfma16_breg(Li, 16 * i, 16 * i, true, sacc, res, li, lk);
+            store_blk(Li, 16 * i, 16 * j, res, li, lk);
+        }
+        __syncthreads();
     }
-    if (bad) flag[0] = 1;
+    if (bad) bad_any = 1;
+    __syncthreads();
+    return bad_any != 0;
 }
 
-// Linv for the diagonal block X[K, K] (its lower triangle, mirrored; rows
-// and columns past nb padded with the identity)
+// Linv (global, 64 x 64 row-major) from Li: the lower triangle, zeros above
+__device__ inline void store_linv(const double (*Li)[kLds], double *__restrict__ Linv)
+{
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int r = e / kBP, c = e % kBP;
+        Linv[e] = c <= r ? Li[r][c] : 0.0;
+    }
+}
+
+// Linv for the diagonal block X[K, K] (its lower triangle; rows and columns
+// past nb padded with the identity)
 __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ X, int n, int k0,
                                                   int nb, double *__restrict__ Linv,
                                                   int *__restrict__ flag)
 {
-    __shared__ CholInvSmem sm;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double m[16];
+    __shared__ double Dm[kBP][kLds];
+    __shared__ double Li[kBP][kLds];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int j = 16 * w + s, r = lane;
-        double v = r == j ? 1.0 : 0.0;
-        if (r < nb && j < nb) {
-            const int hi = r > j ? r : j, lo = r > j ? j : r;
-            v = X[static_cast<int64_t>(k0 + hi) * n + k0 + lo];
-        }
-        m[s] = v;
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int r = e / kBP, c = e % kBP;
+        double v = r == c ? 1.0 : 0.0;
+        if (r < nb && c < nb && c <= r) v = X[static_cast<int64_t>(k0 + r) * n + k0 + c];
+        Dm[r][c] = v;
     }
-    chol_inv_regs(m, sm, Linv, flag);
+    __syncthreads();
+    const bool bad = chol_inv64(Dm, Li);
+    store_linv(Li, Linv);
+    if (bad && threadIdx.x == 0) flag[0] = 1;
 }
 
 // Panel K of the band Cholesky for the lower tile pairs (R1, R2) of the band
@@ -765,7 +875,6 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int
     __shared__ double Ls[kBP][kLds];  // Linv by rows: the B operand of X[R, K] Linv^T
     __shared__ double A1[kBP][kLds];  // X[R1, K], then L_R1 (by rows)
     __shared__ double A2[kBP][kLds];  // X[R2, K], then L_R2 (by rows)
-    __shared__ CholInvSmem sm;
     int a, b;
     tri_pair(blockIdx.x, a, b);
     const int r1 = (rt0 + a) * kBP, r2 = (rt0 + b) * kBP;
@@ -838,22 +947,21 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int
         if (c < nb && r1 + r < n) X[static_cast<int64_t>(k0 + c) * n + r1 + r] = A1[r][c];
     }
     if (Lnext == nullptr || blockIdx.x != 0) return;
-    // the next panel's diagonal block, now final: its inverse factor
+    // the next panel's diagonal block, now final: its inverse factor (rows
+    // and columns past nbn padded with the identity; Ls is free again)
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) A2[wr + 16 * p + 4 * q + lk][wc + 16 * v + li] = xo[p][v][q];
+            for (int q = 0; q < 4; ++q) {
+                const int r = wr + 16 * p + 4 * q + lk, c = wc + 16 * v + li;
+                A2[r][c] = (r < nbn && c < nbn) ? xo[p][v][q] : (r == c ? 1.0 : 0.0);
+            }
     __syncthreads();
-    double m[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int j = 16 * w + s, r = lane;
-        const int hi = r > j ? r : j, lo = r > j ? j : r;
-        m[s] = (r < nbn && j < nbn) ? A2[hi][lo] : (r == j ? 1.0 : 0.0);
-    }
-    chol_inv_regs(m, sm, Lnext, flag);
+    const bool bad = chol_inv64(A2, Ls);
+    store_linv(Ls, Lnext);
+    if (bad && t == 0) flag[0] = 1;
 }
 
 // W = L^{-1} (row-major), one strip of 16 columns S = [c0, c0 + 16) per
