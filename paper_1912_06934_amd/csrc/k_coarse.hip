@@ -858,6 +858,79 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ X, 
     if (bad && threadIdx.x == 0) flag[0] = 1;
 }
 
+// W = L^{-1} (row-major) by strips of 16 columns S = [c0, c0 + 16) and row
+// tiles I from the strip's own panel down (a forward substitution).  Row
+// tile I of a strip: wavefront w forms rows 16 w .. 16 w + 15 of
+//   sum over K in [max(jp, I - tb), I) of L[I, K] W[K, S]
+// (L[I, K] read transposed from the upper triangle of X, W[K, S] finished
+// earlier; the operands of the next K tile are loaded while the current one
+// is multiplied), subtracts it from the identity's block, and multiplies by
+// Linv_I.  Entries of W above the diagonal come out as exact zeros (Linv_I is
+// lower triangular).  Rs: 64 x 17 doubles of LDS.
+__device__ inline void w_row_tile(const double *__restrict__ X, int n, int tb,
+                                  const double *__restrict__ LinvI, double *__restrict__ W, int c0,
+                                  int I, double (*Rs)[17])
+{
+    const int jp = c0 / kBP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool cin = c0 + li < n;
+    const int r0 = I * kBP;
+    const int ra = r0 + 16 * w + li;  // this lane's A-operand row
+    double lv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = LinvI[(16 * w + li) * kBP + 4 * u + lk];
+    auto load = [&](int K, double (&av)[16], double (&bv)[16]) {
+        const int q0 = K * kBP;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int row = q0 + 4 * u + lk;
+            av[u] = (row < n && ra < n) ? X[static_cast<int64_t>(row) * n + ra] : 0.0;
+            bv[u] = (row < n && cin) ? W[static_cast<int64_t>(row) * n + c0 + li] : 0.0;
+        }
+    };
+    mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    double a0[16], b0[16], a1[16], b1[16];
+    const int kb = max(jp, I - tb);
+    if (kb < I) load(kb, a0, b0);
+    for (int K = kb; K < I; K += 2) {
+        if (K + 1 < I) load(K + 1, a1, b1);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc, 0, 0, 0);
+        if (K + 1 >= I) break;
+        if (K + 2 < I) load(K + 2, a0, b0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = 16 * w + 4 * q + lk;
+        Rs[row][li] = (r0 + row == c0 + li ? 1.0 : 0.0) - acc[q];
+    }
+    __syncthreads();
+    mfma_f64x4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[u], Rs[4 * u + lk][li], o, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = r0 + 16 * w + 4 * q + lk;
+        if (row < n && cin) W[static_cast<int64_t>(row) * n + c0 + li] = o[q];
+    }
+}
+
+// Row tile I of W for every strip that reaches it (one work-group per strip,
+// strips 0 .. gridDim.x - 1), when no panel update carries it
+__global__ __launch_bounds__(256) void k_chol_w_row(const double *__restrict__ X, int n, int tb,
+                                                    const double *__restrict__ LinvI,
+                                                    double *__restrict__ W, int I)
+{
+    __shared__ double Rs[kBP][17];
+    w_row_tile(X, n, tb, LinvI, W, 16 * blockIdx.x, I, Rs);
+}
+
 // Panel K of the band Cholesky for the lower tile pairs (R1, R2) of the band
 // below it, R1 >= R2 >= rt0 = K + 1 (one work-group per pair):
 //   L_R1 = X[R1, K] Linv^T, L_R2 = X[R2, K] Linv^T, X[R1, R2] -= L_R1 L_R2^T;
@@ -870,11 +943,20 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ X, 
 __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int n, int k0, int nb,
                                                      int rt0, const double *__restrict__ Linv,
                                                      double *__restrict__ Lnext, int nbn,
-                                                     int *__restrict__ flag)
+                                                     int *__restrict__ flag, int npairs, int tb,
+                                                     double *__restrict__ W)
 {
     __shared__ double Ls[kBP][kLds];  // Linv by rows: the B operand of X[R, K] Linv^T
     __shared__ double A1[kBP][kLds];  // X[R1, K], then L_R1 (by rows)
     __shared__ double A2[kBP][kLds];  // X[R2, K], then L_R2 (by rows)
+    if (static_cast<int>(blockIdx.x) >= npairs) {
+        // the work-groups after the pairs: row tile K of W, one strip each
+        // (W's earlier row tiles and L's band tiles left of panel K are
+        // final; this launch writes neither)
+        w_row_tile(X, n, tb, Linv, W, 16 * (blockIdx.x - npairs), rt0 - 1,
+                   reinterpret_cast<double (*)[17]>(&A1[0][0]));
+        return;
+    }
     int a, b;
     tri_pair(blockIdx.x, a, b);
     const int r1 = (rt0 + a) * kBP, r2 = (rt0 + b) * kBP;
@@ -962,77 +1044,6 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int
     const bool bad = chol_inv64(A2, Ls);
     store_linv(Ls, Lnext);
     if (bad && t == 0) flag[0] = 1;
-}
-
-// W = L^{-1} (row-major), one strip of 16 columns S = [c0, c0 + 16) per
-// work-group (the strips are independent).
-// Row tile I of the strip, from the strip's own panel down: wavefront w
-// forms rows 16 w .. 16 w + 15 of
-//   sum over K in [max(jp, I - tb), I) of L[I, K] W[K, S]
-// (L[I, K] read transposed from the upper triangle of X, W[K, S] written by
-// this work-group at an earlier step; the operands of the next K tile are
-// loaded while the current one is multiplied), subtracts it from the
-// identity's block, and multiplies by Linv_I.  Entries of W above the
-// diagonal come out as exact zeros (Linv_I is lower triangular).
-__global__ __launch_bounds__(256) void k_chol_w(const double *__restrict__ X, int n, int tb,
-                                                const double *__restrict__ Linv,
-                                                double *__restrict__ W)
-{
-    __shared__ double Rs[kBP][17];  // right-hand block, rows k, 16 columns
-    const int c0 = 16 * blockIdx.x;
-    const int jp = c0 / kBP, nt = (n + kBP - 1) / kBP;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const bool cin = c0 + li < n;
-    for (int I = jp; I < nt; ++I) {
-        const int r0 = I * kBP;
-        const int ra = r0 + 16 * w + li;  // this lane's A-operand row
-        const double *Li = Linv + static_cast<int64_t>(I) * kBP * kBP;
-        double lv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) lv[u] = Li[(16 * w + li) * kBP + 4 * u + lk];
-        auto load = [&](int K, double (&av)[16], double (&bv)[16]) {
-            const int q0 = K * kBP;
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int row = q0 + 4 * u + lk;
-                av[u] = (row < n && ra < n) ? X[static_cast<int64_t>(row) * n + ra] : 0.0;
-                bv[u] = (row < n && cin) ? W[static_cast<int64_t>(row) * n + c0 + li] : 0.0;
-            }
-        };
-        mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        double a0[16], b0[16], a1[16], b1[16];
-        const int kb = max(jp, I - tb);
-        if (kb < I) load(kb, a0, b0);
-        for (int K = kb; K < I; K += 2) {
-            if (K + 1 < I) load(K + 1, a1, b1);
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc, 0, 0, 0);
-            if (K + 1 >= I) break;
-            if (K + 2 < I) load(K + 2, a0, b0);
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = 16 * w + 4 * q + lk;
-            Rs[row][li] = (r0 + row == c0 + li ? 1.0 : 0.0) - acc[q];
-        }
-        __syncthreads();
-        mfma_f64x4 o = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            o = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[u], Rs[4 * u + lk][li], o, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = r0 + 16 * w + 4 * q + lk;
-            if (row < n && cin) W[static_cast<int64_t>(row) * n + c0 + li] = o[q];
-        }
-        // Rs is reused and the next tile reads this one's W from memory
-        __syncthreads();
-    }
 }
 
 // A_c^{-1} = W^T W for the lower tile pairs (I, J), I >= J (one work-group
@@ -1392,21 +1403,28 @@ msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double 
     const int tb = min(nt - 1, (max(bl, 0) + kBP - 1) / kBP);
     // each panel's update also inverts the next panel's diagonal block, which
     // it finalises; a panel without band rows below it leaves the next block
-    // untouched, and that block is inverted on its own
+    // untouched, and that block is inverted on its own.  Row tile K of W =
+    // L^{-1} rides along with panel K's update (extra work-groups, which run
+    // beside the diagonal inversion), or gets a launch of its own.
     bool have_inv = false;
     for (int K = 0; K < nt; ++K) {
         const int k0 = K * kBP, nb = min(kBP, n - k0);
         double *li = Linv + static_cast<int64_t>(K) * kBP * kBP;
         if (!have_inv) k_chol_inv<<<1, 256, 0, s>>>(X, n, k0, nb, li, flag);
         const int T = min(nt - 1, K + tb) - K;
+        // strips of 16 columns left of the end of panel K
+        const int nstrips = (min(n, k0 + kBP) + 15) / 16;
         have_inv = T > 0;
         if (T > 0) {
             const int nbn = min(kBP, n - k0 - kBP);
-            k_chol_update<<<T * (T + 1) / 2, 256, 0, s>>>(X, n, k0, nb, K + 1, li, li + kBP * kBP,
-                                                          nbn, flag);
+            const int npairs = T * (T + 1) / 2;
+            k_chol_update<<<npairs + nstrips, 256, 0, s>>>(X, n, k0, nb, K + 1, li,
+                                                           li + kBP * kBP, nbn, flag, npairs, tb,
+                                                           W);
+        } else {
+            k_chol_w_row<<<nstrips, 256, 0, s>>>(X, n, tb, li, W, K);
         }
     }
-    k_chol_w<<<(n + 15) / 16, 256, 0, s>>>(X, n, tb, Linv, W);
     k_chol_wtw<<<nt * (nt + 1) / 2, 256, 0, s>>>(W, n, pk);
     hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
