@@ -897,6 +897,9 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     sa.interior = c->interior;
     sa.sym = jsym;
     sa.omega = o->omega;
+    // FP64 rows overflow an XCD's L2 between a row's two z-neighbour reads
+    // in the plain order; FP32 rows fit, and measure no faster tiled
+    if (c->j_dia && !fp32) sa.go = grid_order_for(c->n, c->j_off);
     phase_begin(c, MSRSB_PHASE_SMOOTH);
     int it = 0;
     double e_last = -1.0;

@@ -215,6 +215,31 @@ __device__ __forceinline__ int xcd_row()
     return xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 }
 
+// Work-group order of a sweep over a 3D grid (rows numbered x fastest):
+// the y lines are cut into eight slabs, one per XCD, and each XCD walks its
+// slab layer by layer in z, kBlock rows of one layer per work-group.  The
+// rows that a row's z-neighbours share an L2 with are then read a few
+// dispatch steps apart rather than a whole grid plane apart.  nx == 0: the
+// plain order (as xcd_row).
+struct GridOrder {
+    int nx = 0, ny = 0, nz = 0;
+    int lines = 0;  // y lines per slab (ny / 8)
+    int bps = 0;    // work-groups per slab layer (lines * nx / kBlock)
+};
+// first row of this work-group (uniform: kept in a scalar register)
+__device__ __forceinline__ int grid_row0(const GridOrder &g)
+{
+    const int q = xcd_group(blockIdx.x, gridDim.x);
+    if (g.nx == 0) return __builtin_amdgcn_readfirstlane(q * kBlock);
+    const int sub = q % g.bps, rest = q / g.bps;
+    const int z = rest % g.nz, st = rest / g.nz;
+    return __builtin_amdgcn_readfirstlane((z * g.ny + st * g.lines) * g.nx + sub * kBlock);
+}
+// The order for n rows with DIA offsets d, when d is the 7-point stencil
+// {-nx ny, -nx, -1, 0, 1, nx, nx ny} of an nx x ny x nz grid whose slabs
+// split into whole work-groups (then the grid has exactly n / kBlock of them)
+GridOrder grid_order_for(int n, const DiaOffsets &d);
+
 struct SmoothArgs {
     int n = 0, pw = 0, jw = 0;
     DiaOffsets joff;
@@ -229,6 +254,7 @@ struct SmoothArgs {
     double *eit_out = nullptr;   // e_it (one double)
     bool sym = false;            // J stored factored (k_filter_jacobi's sym form)
     double omega = 0.0;
+    GridOrder go;                // work-group order (nx == 0: plain)
 };
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,

@@ -24,7 +24,9 @@ pytestmark = pytest.mark.gpu
 CASES = [("c1", None, None),                 # 32^2, 16 coarse blocks (full size)
          ("c1", (37, 29), 8),                # partial coarse blocks on both axes
          ("c5", (24, 20, 18), 8),            # 3D, ragged last blocks
-         ("c4", (32, 32, 32), 8)]            # layered channels
+         ("c4", (32, 32, 32), 8),            # layered channels
+         ("c4", (32, 64, 12), 8)]            # slabs of whole work-groups: the
+                                             # z-walking smoothing order
 
 
 @pytest.fixture(scope="module")
@@ -125,8 +127,9 @@ def test_deterministic(torch_cuda):
         assert np.array_equal(x, y)
 
 
-def test_fp32_basis_form(torch_cuda):
-    cfg = tpfa_inputs("c4", (32, 32, 32), 8)
+@pytest.mark.parametrize("dims", [(32, 32, 32), (32, 64, 12)], ids=["32x32x32", "32x64x12"])
+def test_fp32_basis_form(torch_cuda, dims):
+    cfg = tpfa_inputs("c4", dims, 8)
     orc = oracle_setup(cfg)
     s, rhs, info = gpu_setup_tpfa(cfg, fp32_basis=True)
     _, _, pv = s.get_prolongation()
