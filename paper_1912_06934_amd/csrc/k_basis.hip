@@ -296,6 +296,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
     }
     const int i = grid_row0(go) + static_cast<int>(threadIdx.x);
     double emax = 0.0;
+    // FP64 rows leave through LDS (below); out stays zero past n
+    constexpr bool kStream = JW > 0 && sizeof(T) == 8;
+    T out[PW];
+#pragma unroll
+    for (int s = 0; s < PW; ++s) out[s] = T(0);
     if (i < n) {
         T acc[PW];
 #pragma unroll
@@ -384,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         double rs = 0.0;
 #pragma unroll
         for (int s = 0; s < PW; ++s) rs += static_cast<double>(acc[s]);
-        T old[PW], out[PW];
+        T old[PW];
         load_row<T, PW>(pin, i, old);
         const bool inner = eit_part != nullptr && interior[i] != 0;
         const double rinv = 1.0 / rs;
@@ -396,11 +401,33 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
             }
             out[s] = static_cast<T>(static_cast<double>(acc[s]) * rinv);
         }
+        if constexpr (!kStream) store_row<T, PW>(pout, i, out);
+    }
+    if constexpr (kStream) {
         // FP64 rows are written as streaming stores: they are not read again
         // in this iteration, and keeping them out of the L2 leaves room for
         // the neighbour rows one grid plane apart (FP32 rows fit either way,
-        // and measure faster with plain stores)
-        store_row<T, PW, sizeof(T) == 8>(pout, i, out);
+        // and measure faster with plain stores).  A streaming store reaches
+        // memory as written, so the wavefront's 64 rows (consecutive) are
+        // first transposed through the threads' LDS columns, which the
+        // accumulation no longer needs: each store instruction then covers
+        // 1 KB of whole cache lines instead of 16 bytes of each of 64 rows.
+        constexpr int L = 16 / sizeof(T), CH = PW / L;
+        typedef T vec __attribute__((ext_vector_type(L)));
+#pragma unroll
+        for (int t = 0; t < PW; ++t) sb[t * kBlock] = out[t];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+        const int64_t row0 = static_cast<int64_t>(i) - lane;  // the wavefront's first row
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int piece = q * 64 + lane, r = piece / CH, c = piece % CH;
+            vec x;
+#pragma unroll
+            for (int l = 0; l < L; ++l) x[l] = sperm[(c * L + l) * kBlock + wbase + r];
+            if (row0 + r < n)
+                __builtin_nontemporal_store(x, reinterpret_cast<vec *>(pout + (row0 + r) * PW) + c);
+        }
     }
     if (eit_part != nullptr) eit_block(emax, eit_part);
 }
