@@ -210,9 +210,12 @@ __device__ __forceinline__ int xcd_group(int b, int g)
     const int q = g >> 3, r = g & 7, x = b & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
 }
+// (for kernels launched with kBlock threads per work-group: the constant
+// stands in for blockDim.x, which is read from the dispatch packet by a
+// vector load that every wavefront would wait for before its first real one)
 __device__ __forceinline__ int xcd_row()
 {
-    return xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    return xcd_group(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
 }
 
 // Work-group order of a sweep over a 3D grid (rows numbered x fastest):

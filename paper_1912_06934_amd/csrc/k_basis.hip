@@ -39,7 +39,7 @@ __device__ inline void eit_block(double emax, double *__restrict__ part)
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = sh[0];
-        for (int w = 1; w < static_cast<int>(blockDim.x) / 64; ++w) m = nan_max(m, sh[w]);
+        for (int w = 1; w < kBlock / 64; ++w) m = nan_max(m, sh[w]);
         part[blockIdx.x] = m;
     }
 }
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi(
     const int *__restrict__ ci, const double *__restrict__ a, int jw, DiaOffsets joff,
     int use_dia, int sym, T *__restrict__ jv)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int e0 = rp[i], e1 = rp[i + 1];
     const int ic = i % bs;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(int64_t m, int pw,
                                                        T *__restrict__ p)
 {
     // one ELL entry per thread (coalesced stores)
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (e >= m) return;
     p[e] = (pcol[e] == part[e / pw]) ? T(1) : T(0);
 }
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
     T *sb = sperm + (JW > 0 ? threadIdx.x : 0);
     if constexpr (JW > 0) sb[PW * kBlock] = T(0);
     if constexpr (sizeof(IDX) == 1) {
-        for (int t = threadIdx.x; t < ntab; t += blockDim.x) {
+        for (int t = threadIdx.x; t < ntab; t += kBlock) {
             const uint32_t m = tab[t];
             stab[t] = m;
             sdiag[t] = map_is_diag(m) ? 1 : 0;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_basis_stats(int n, int pw, const int
 {
     __shared__ double sh[3][kBlock];
     double err = 0.0, lo = 1e300, hi = -1e300;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         double s = 0.0;
         for (int q = 0; q < pw; ++q) {
             const int64_t e = static_cast<int64_t>(i) * pw + q;
@@ -610,7 +610,7 @@ template <typename S, typename D>
 __global__ __launch_bounds__(kBlock) void k_convert(int64_t m, const S *__restrict__ s,
                                                     D *__restrict__ d)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t < m) d[t] = static_cast<D>(s[t]);
 }
 
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_to_csr(int n, int pw, const int 
                                                        const T *__restrict__ pe,
                                                        double *__restrict__ pc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int e0 = prp[i], np = prp[i + 1] - e0;
     for (int s = 0; s < np; ++s) pc[e0 + s] = static_cast<double>(pe[static_cast<int64_t>(i) * pw + s]);
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_to_ell(int n, int pw, const int 
                                                        const double *__restrict__ pc,
                                                        double *__restrict__ pe)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int e0 = prp[i], np = prp[i + 1] - e0;
     for (int s = 0; s < pw; ++s)
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_build_maps(int n, int pw, int jw, Di
                                                        const int *__restrict__ pcol,
                                                        uint32_t *__restrict__ maps)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     for (int o = 0; o < jw; ++o) {
         const int64_t e = static_cast<int64_t>(o) * n + i;
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi_dia(int n, int filter,
                                                               DiaOffsets joff, int sym,
                                                               T *__restrict__ jv)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int jw = joff.n;
     int mid = 0;

@@ -15,7 +15,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t m, const int *__restrict__ src,
                                                    const T *__restrict__ p, T *__restrict__ r)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t < m) {
         const int e = src[t];
         r[t] = e >= 0 ? p[e] : T(0);
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t m, const int *__restr
 
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t m, double *__restrict__ x, double v)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t < m) x[t] = v;
 }
 
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_leaf_update(double *__restrict__ 
                                                            int nb, int kl, int lw,
                                                            const double *__restrict__ bbuf)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int r = static_cast<int>(t / kPanel), cc = static_cast<int>(t % kPanel);
     if (r >= n || cc >= nb) return;
     const int col = k0 + cc;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_swap_extract(double *__restrict__
                                                             int nb, const int *__restrict__ piv,
                                                             double *__restrict__ B)
 {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.x * kBlock + threadIdx.x;
     if (col >= n || (col >= k0 && col < k0 + nb)) return;
     for (int c = 0; c < nb; ++c) {
         const int k = k0 + c, p = piv[k];
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_permute(int n, const double *__re
                                                        const int *__restrict__ colsrc,
                                                        double *__restrict__ Y)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t >= static_cast<int64_t>(n) * n) return;
     const int r = static_cast<int>(t / n), j = static_cast<int>(t % n);
     Y[t] = X[static_cast<int64_t>(r) * n + colsrc[j]];
@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double *__restrict
                                                  const double *__restrict__ x,
                                                  double *__restrict__ y)
 {
-    const int row = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int row = (blockIdx.x * kBlock + threadIdx.x) / 64;
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
     const double *mr = M + static_cast<int64_t>(row) * n;
@@ -1234,7 +1234,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_t_partial(int n, const double *
                                                            const double *__restrict__ x,
                                                            double *__restrict__ part)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
     const int seg = blockIdx.y;
     if (c >= n) return;
     const int rows = (n + kGemvSeg - 1) / kGemvSeg;
@@ -1247,7 +1247,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_t_partial(int n, const double *
 __global__ __launch_bounds__(kBlock) void k_gemv_t_final(int n, const double *__restrict__ part,
                                                          double *__restrict__ y)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= n) return;
     double s = 0.0;
     for (int seg = 0; seg < kGemvSeg; ++seg) s += part[static_cast<int64_t>(seg) * n + c];

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict_
                                                 double *__restrict__ part)
 {
     double s = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         s += x[i] * y[i];
     s = block_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -166,14 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict_
 __global__ __launch_bounds__(kBlock) void k_copy(int n, const double *__restrict__ x,
                                                  double *__restrict__ y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) y[i] = x[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_axpy(int n, double alpha, const double *__restrict__ x,
                                                  double *__restrict__ y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) y[i] += alpha * x[i];
 }
 
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_inverses(int n, const int *__re
                                                           float *__restrict__ a32,
                                                           int *__restrict__ flag)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double d = 0.0, l1 = 0.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_values(int64_t m, const int *
                                                           const double *__restrict__ a,
                                                           double *__restrict__ out)
 {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t < m) out[t] = a[src[t]];
 }
 
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_multi_dot(int n, const double *__res
     const int t = blockIdx.y;
     const double *vt = V + static_cast<int64_t>(t) * ldv;
     double s = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         s += vt[i] * w[i];
     s = block_sum(s);
     if (threadIdx.x == 0) part[static_cast<int64_t>(t) * gridDim.x + blockIdx.x] = s;
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_multi_axpy(int n, int k, const doubl
                                                        int64_t ldv, const double *__restrict__ h,
                                                        double *__restrict__ w, double sign)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int t = 0; t < k; ++t) s += h[t] * V[static_cast<int64_t>(t) * ldv + i];
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_by_inv(int n, const double *__
                                                          const double *__restrict__ nrm2,
                                                          double *__restrict__ v)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const double nr = sqrt(nrm2[0]);
     v[i] = nr > 0.0 ? w[i] / nr : 0.0;
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_beta(int n, const double *__res
                                                       const double *__restrict__ zold,
                                                       double *__restrict__ part)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (i < n) {
         v[0] = r[i] * z[i];
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict
                                                        const double *__restrict__ scal)
 {
     const double alpha = scal[S_ALPHA];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (i < n) {
         x[i] += alpha * p[i];
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *_
                                                         const double *__restrict__ wc,
                                                         ZT *__restrict__ z, int zero)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int col[PW];
     T val[PW];
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell_w(int n, int pw, const i
                                                           const double *__restrict__ wc,
                                                           double *__restrict__ z, int zero)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int q = 0; q < pw; ++q) {
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_to_dia(int n, int noff, const in
                                                        const double *__restrict__ a,
                                                        T *__restrict__ ad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     for (int o = 0; o < noff; ++o) ad[static_cast<int64_t>(o) * n + i] = T(0);
     for (int e = rp[i]; e < rp[i + 1]; ++e)
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_check_symmetric(int n, const int *__
                                                             const double *__restrict__ a,
                                                             int *__restrict__ flag)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
