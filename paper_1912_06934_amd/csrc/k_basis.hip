@@ -286,6 +286,60 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
     __shared__ T sperm[JW > 0 ? (PW + 1) * kBlock : 1];
     T *sb = sperm + (JW > 0 ? threadIdx.x : 0);
     if constexpr (JW > 0) sb[PW * kBlock] = T(0);
+    const int i = grid_row0(go) + static_cast<int>(threadIdx.x);
+    // chunk: up to 9 FP32 rows or 7 FP64 rows in registers at once
+    constexpr int CMAX = sizeof(T) == 8 ? 7 : 9;
+    constexpr int MID = JW / 2;
+    // When one chunk holds every neighbour, all of the row's global loads
+    // (map indices, weights, neighbour rows) are issued before the map table
+    // is staged, so the two memory round trips overlap.  The rows are read
+    // before the maps are known: an absent neighbour reads any row inside the
+    // matrix (its contribution is zero), one past the ends reads row i.
+    constexpr bool kOne = JW > 0 && JW <= CMAX;
+    constexpr int N1 = kOne ? JW : 1;
+    int t1[N1];
+    T w1[N1], v1[N1][PW];
+    if constexpr (kOne) {
+        if (i < n) {
+            // the neighbour rows first, then the map indices and J values
+            // (all loads in flight before any arithmetic waits on one)
+            int k[JW];
+            if (jcol) {
+#pragma unroll
+                for (int o = 0; o < JW; ++o) k[o] = jcol[static_cast<int64_t>(o) * n + i];
+            } else {
+#pragma unroll
+                for (int o = 0; o < JW; ++o) k[o] = i + joff.off[o];
+            }
+#pragma unroll
+            for (int o = 0; o < JW; ++o) {
+                const int kk = (k[o] >= 0 && k[o] < n) ? k[o] : i;
+                load_row<T, PW>(pin, kk, v1[o]);
+            }
+            // J values as stored (the weights are formed after the table)
+            T jraw[JW];
+#pragma unroll
+            for (int o = 0; o < JW; ++o) {
+                const int64_t e = static_cast<int64_t>(o) * n + i;
+                t1[o] = jmap[e];
+                if constexpr (SYM) {
+                    // the lower coefficients mirror the neighbour's upper
+                    // ones; an absent neighbour's mirrored slot is zero by
+                    // pattern symmetry, one beyond the ends reads row i
+                    const int kn = i + joff.off[o];
+                    const bool in = kn >= 0 && kn < n;
+                    if (o < MID)
+                        jraw[o] = jv[static_cast<int64_t>(JW - 1 - o) * n + (in ? kn : i)];
+                    else
+                        jraw[o] = jv[e];
+                } else {
+                    jraw[o] = jv[e];
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < JW; ++o) w1[o] = jraw[o];
+        }
+    }
     if constexpr (sizeof(IDX) == 1) {
         for (int t = threadIdx.x; t < ntab; t += kBlock) {
             const uint32_t m = tab[t];
@@ -294,7 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         }
         __syncthreads();
     }
-    const int i = grid_row0(go) + static_cast<int>(threadIdx.x);
     double emax = 0.0;
     // FP64 rows leave through LDS (below); out stays zero past n
     constexpr bool kStream = JW > 0 && sizeof(T) == 8;
@@ -305,16 +358,40 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         T acc[PW];
 #pragma unroll
         for (int s = 0; s < PW; ++s) acc[s] = T(0);
-        if constexpr (JW > 0) {
+        if constexpr (kOne) {
             static_assert(sizeof(IDX) == 1, "fixed slot counts use the LDS map table");
-            constexpr int MID = JW / 2;
+            if constexpr (SYM) {
+                // J = s_i Ghat: w1 holds the raw upper coefficients (the
+                // neighbour's for the lower slots) and s_i in the middle
+                const T si = w1[MID];
+#pragma unroll
+                for (int o = 0; o < JW; ++o) {
+                    const int kn = i + joff.off[o];
+                    const bool in = kn >= 0 && kn < n;
+                    if (o < MID)
+                        w1[o] = in ? si * w1[o] : T(0);
+                    else if (o > MID)
+                        w1[o] = si * w1[o];
+                }
+                w1[MID] = si == T(0) ? T(1) : static_cast<T>(1.0 - omega);
+            }
+            // a neighbour whose map is diagonal on every lane of the
+            // wavefront (same support pattern) skips the slot selects
+#pragma unroll
+            for (int o = 0; o < JW; ++o) {
+                const uint32_t m = stab[t1[o]];
+                if (__all(sdiag[t1[o]] != 0))
+                    accumulate_diag<T, PW>(acc, m, w1[o], v1[o]);
+                else
+                    accumulate_lds<T, PW>(acc, m, w1[o], v1[o], sb);
+            }
+        } else if constexpr (JW > 0) {
+            static_assert(sizeof(IDX) == 1, "fixed slot counts use the LDS map table");
             T si = T(0), jd = T(0);
             if constexpr (SYM) {
                 si = jv[static_cast<int64_t>(MID) * n + i];
                 jd = si == T(0) ? T(1) : static_cast<T>(1.0 - omega);
             }
-            // chunk: up to 9 FP32 rows or 7 FP64 rows in registers at once
-            constexpr int CMAX = sizeof(T) == 8 ? 7 : 9;
             constexpr int CH = JW <= CMAX ? JW : CMAX;
 #pragma nounroll
             for (int o0 = 0; o0 < JW; o0 += CH) {
