@@ -180,18 +180,38 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
     for (int t = tid; t < nc; t += NT) map[t] = 0;
     __syncthreads();
     const int t0 = rrp[j], t1 = rrp[j + 1];
-    for (int t = t0 + tid; t < t1; t += NT) {
-        const int i = rci[t];
+    // entries t and t + NT of a thread at once; a neighbour's columns are
+    // read whether or not its coefficient is zero (the test comes after), so
+    // every load of both entries is in flight together
+    typedef uint16_t cvec __attribute__((ext_vector_type(8)));
+    for (int t = t0 + tid; t < t1; t += 2 * NT) {
+        int ii[2];
+        bool ok[2];
 #pragma unroll
-        for (int o = 0; o < ND; ++o) {
-            const int k = i + d.off[o];
-            if (k < 0 || k >= n || ad[static_cast<int64_t>(o) * n + i] == 0.0) continue;
-            typedef uint16_t cvec __attribute__((ext_vector_type(8)));
-            const cvec cc = *reinterpret_cast<const cvec *>(pcol + static_cast<int64_t>(k) * 8);
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (cc[u] != 0xFFFFu) map[cc[u]] = 1;
+        for (int q = 0; q < 2; ++q) {
+            ok[q] = t + q * NT < t1;
+            ii[q] = rci[ok[q] ? t + q * NT : t];
         }
+        double av[2][ND];
+        cvec cc[2][ND];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int o = 0; o < ND; ++o) {
+                const int k = ii[q] + d.off[o];
+                const bool in = k >= 0 && k < n;
+                av[q][o] = in && ok[q] ? ad[static_cast<int64_t>(o) * n + ii[q]] : 0.0;
+                cc[q][o] = *reinterpret_cast<const cvec *>(pcol + static_cast<int64_t>(in ? k : ii[q]) * 8);
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int o = 0; o < ND; ++o) {
+                if (av[q][o] == 0.0) continue;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (cc[q][o][u] != 0xFFFFu) map[cc[q][o][u]] = 1;
+            }
     }
     __syncthreads();
     // number the marked coarse columns in ascending order (block scan)
@@ -228,29 +248,44 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
     }
     for (int s = 0; s < total; ++s) acc[s * NT + tid] = 0.0;
     __syncthreads();
-    for (int t = t0 + tid; t < t1; t += NT) {
-        const int i = rci[t];
-        const double pij = static_cast<double>(rv[t]);
-        double av[ND];
-        T v[ND][8];
-        uint16_t cl[ND][8];
+    // UA entries of a thread per round (t, t + NT, ...), their loads all in
+    // flight together; the sums are taken in the same entry order as one at
+    // a time (UA = 1 for FP64 rows, which would not fit in registers twice)
+    constexpr int UA = sizeof(T) == 4 ? 2 : 1;
+    for (int t = t0 + tid; t < t1; t += UA * NT) {
+        int ii[UA];
+        double pij[UA];
 #pragma unroll
-        for (int o = 0; o < ND; ++o) {
-            const int k = i + d.off[o];
-            const bool in = k >= 0 && k < n;
-            const double a = ad[static_cast<int64_t>(o) * n + i];
-            av[o] = in ? a : 0.0;
-            load_prow<T>(pv, pcol, in ? k : i, v[o], cl[o]);
+        for (int q = 0; q < UA; ++q) {
+            const bool ok = t + q * NT < t1;
+            ii[q] = rci[ok ? t + q * NT : t];
+            pij[q] = ok ? static_cast<double>(rv[t + q * NT]) : 0.0;
         }
+        double av[UA][ND];
+        T v[UA][ND][8];
+        uint16_t cl[UA][ND][8];
 #pragma unroll
-        for (int o = 0; o < ND; ++o) {
-            if (av[o] == 0.0) continue;
-            const double pa = pij * av[o];
+        for (int q = 0; q < UA; ++q)
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (cl[o][u] != 0xFFFFu)
-                    atomicAdd(&acc[map[cl[o][u]] * NT + tid], pa * static_cast<double>(v[o][u]));
-        }
+            for (int o = 0; o < ND; ++o) {
+                const int k = ii[q] + d.off[o];
+                const bool in = k >= 0 && k < n;
+                const double a = ad[static_cast<int64_t>(o) * n + ii[q]];
+                av[q][o] = in ? a : 0.0;
+                load_prow<T>(pv, pcol, in ? k : ii[q], v[q][o], cl[q][o]);
+            }
+#pragma unroll
+        for (int q = 0; q < UA; ++q)
+#pragma unroll
+            for (int o = 0; o < ND; ++o) {
+                if (av[q][o] == 0.0 || pij[q] == 0.0) continue;
+                const double pa = pij[q] * av[q][o];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (cl[q][o][u] != 0xFFFFu)
+                        atomicAdd(&acc[map[cl[q][o][u]] * NT + tid],
+                                  pa * static_cast<double>(v[q][o][u]));
+            }
     }
     __syncthreads();
     int bl = 0, bu = 0;
