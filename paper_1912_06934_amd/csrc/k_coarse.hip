@@ -180,22 +180,23 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
     for (int t = tid; t < nc; t += NT) map[t] = 0;
     __syncthreads();
     const int t0 = rrp[j], t1 = rrp[j + 1];
-    // entries t and t + NT of a thread at once; a neighbour's columns are
+    // entries t, t + NT, ... (UM of them) of a thread at once; a neighbour's columns are
     // read whether or not its coefficient is zero (the test comes after), so
-    // every load of both entries is in flight together
+    // every load of those entries is in flight together
     typedef uint16_t cvec __attribute__((ext_vector_type(8)));
-    for (int t = t0 + tid; t < t1; t += 2 * NT) {
-        int ii[2];
-        bool ok[2];
+    constexpr int UM = 4;
+    for (int t = t0 + tid; t < t1; t += UM * NT) {
+        int ii[UM];
+        bool ok[UM];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < UM; ++q) {
             ok[q] = t + q * NT < t1;
             ii[q] = rci[ok[q] ? t + q * NT : t];
         }
-        double av[2][ND];
-        cvec cc[2][ND];
+        double av[UM][ND];
+        cvec cc[UM][ND];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < UM; ++q)
 #pragma unroll
             for (int o = 0; o < ND; ++o) {
                 const int k = ii[q] + d.off[o];
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                 cc[q][o] = *reinterpret_cast<const cvec *>(pcol + static_cast<int64_t>(in ? k : ii[q]) * 8);
             }
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < UM; ++q)
 #pragma unroll
             for (int o = 0; o < ND; ++o) {
                 if (av[q][o] == 0.0) continue;
