@@ -193,10 +193,11 @@ typedef struct {
  * lin_system_coarse), and the coarse solver M_c^{-1} = A_c^{-1} formed
  * explicitly in FP64 (applied as a dense product).  When A is symmetric
  * A_c is symmetric positive definite for the SPD problems of the paper and
- * the inverse comes from blocked Gauss-Jordan without pivoting, confined to
- * A_c's band until the fill spreads; a non-positive pivot falls back to
- * Gauss-Jordan with partial pivoting, which is also used for non-symmetric
- * A.  Synchronises.
+ * the inverse comes from its Cholesky factor, A_c^{-1} = L^{-T} L^{-1} (a
+ * band Cholesky, L^{-1} by forward substitution, the product on the FP64
+ * matrix cores), kept as its lower 64 x 64 tiles; a non-positive pivot falls
+ * back to Gauss-Jordan with partial pivoting, which is also used for
+ * non-symmetric A.  Synchronises.
  * Errors: E_STATE before setup_basis; E_COARSE_SINGULAR on a zero pivot
  * (pivoting form). */
 msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);

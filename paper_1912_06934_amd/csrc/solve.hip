@@ -14,8 +14,6 @@
 namespace msrsb {
 namespace {
 
-inline int grid_for(int64_t m) { return static_cast<int>((m + kBlock - 1) / kBlock); }
-
 // --- GMRES small dense algebra (single thread; m <= 64) ---
 // Apply the previous Givens rotations to the new Hessenberg column (h[0..j]
 // from the Gram-Schmidt, ||w||^2 in nrm2), form the new rotation, update g
