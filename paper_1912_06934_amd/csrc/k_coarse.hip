@@ -1089,11 +1089,16 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ X, int
 // into the packed lower-tile array pk (zeros past n); a diagonal tile's
 // upper triangle is its lower one transposed through LDS, so the inverse is
 // exactly symmetric.
+// LDS row stride of the WtW chunks, stored as loaded (row k of the chunk,
+// 64 columns): the 16 x 4 transposed operand reads of a half-wavefront fall
+// on distinct bank pairs, and so do the row-wise stores
+constexpr int kLdsW = kBP + 16;
+
 __global__ __launch_bounds__(256) void k_chol_wtw(const double *__restrict__ W, int n,
                                                   double *__restrict__ pk)
 {
-    __shared__ double As[kBP][kLds];  // W[K, I] by columns (A[r][k] = W[q0 + k][i0 + r])
-    __shared__ double Bt[kBP][kLds];  // W[K, J] by columns
+    __shared__ double As[kBP][kLdsW];  // As[k][r] = W[q0 + k][i0 + r]
+    __shared__ double Bs[kBP][kLdsW];  // Bs[k][c] = W[q0 + k][j0 + c]
     int I, J;
     tri_pair(blockIdx.x, I, J);
     const int nt = (n + kBP - 1) / kBP;
@@ -1119,15 +1124,32 @@ __global__ __launch_bounds__(256) void k_chol_wtw(const double *__restrict__ W, 
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            As[lc][lr + 4 * u] = ra[u];
-            Bt[lc][lr + 4 * u] = rb[u];
+            As[lr + 4 * u][lc] = ra[u];
+            Bs[lr + 4 * u][lc] = rb[u];
         }
         __syncthreads();
         if (K + 1 < nt) fetch(K + 1);
-        mfma_tile64(As, Bt, acc, wr, wc, li, lk);
+        // C[r][c] += sum_k As[k][r] Bs[k][c]: operand lane l supplies
+        // A[l % 16][kk + l / 16] = As[kk + l / 16][row] and likewise for B
+#pragma unroll 4
+        for (int kk = 0; kk < kBP; kk += 4) {
+            const double a0 = As[kk + lk][wr + li], a1 = As[kk + lk][wr + 16 + li];
+            const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
     }
     __syncthreads();
-    acc_to_lds(acc, As, false, wr, wc, li, lk);  // As[r][c] = tile[r][c]
+    // the tile through LDS (As, reused with its own stride)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                As[wr + 16 * p + 4 * q + lk][wc + 16 * v + li] = acc[p][v][q];
     __syncthreads();
     double *tile = pk + static_cast<int64_t>(blockIdx.x) * kBP * kBP;
 #pragma unroll
