@@ -196,6 +196,9 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->pcol16);
     dfree(c->p_csr_tmp);
     dfree(c->band);
+    dfree(c->rap_cols);
+    dfree(c->rap_ncol);
+    c->rap_cols_valid = false;
     if (c->jmap_idx) hipFree(c->jmap_idx);
     c->jmap_idx = nullptr;
     dfree(c->jmap_tab);
@@ -829,6 +832,20 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         }
     }
     c->rmaxnb = c->bs == 1 ? 32 : kMaxCoarseNeighbours;
+    // the column pattern of R A P (symbolic part of the Galerkin product):
+    // it depends on the patterns of A and P only, both fixed from here on
+    // (build_coarse checks it against A's current values)
+    c->rap_cols_valid = false;
+    if (rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16) && c->a_dia) {
+        if (!dalloc(c->rap_cols, static_cast<size_t>(nc) * kMaxCoarseNeighbours) ||
+            !dalloc(c->rap_ncol, nc))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        launch_rap_cols(c->stream, c->n, nc, c->rrp, c->rci, c->a_off, c->a_dia, c->pcol16,
+                        c->rap_cols, c->rap_ncol);
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return fail(c, MSRSB_E_HIP, "coarse pattern failed on the device");
+        c->rap_cols_valid = true;
+    }
     c->has_coarse = true;
     c->has_basis = c->has_coarse_op = false;
     return MSRSB_OK;
@@ -1007,24 +1024,36 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     phase_begin(c, MSRSB_PHASE_RAP);
     launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
     bool have_csr = false;  // the CSR copy of P, for the general RAP only
+    bool lists_rebuilt = false;
     for (;;) {
         if (!have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16)) {
             launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
                               c->p_csr_tmp);
             have_csr = true;
         }
-        hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
+        hipMemsetAsync(c->dev_flag, 0, 2 * sizeof(int), s);
         hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
         launch_fill(s, nn, c->ac, 0.0);
         launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
-                   c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag, c->band);
-        int hflag = 0;
-        hipMemcpyAsync(&hflag, c->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+                   c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag, c->band,
+                   c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol);
+        int hflag[2] = {0, 0};
+        hipMemcpyAsync(hflag, c->dev_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(c->h_band, c->band, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (hipStreamSynchronize(s) != hipSuccess)
             return fail(c, MSRSB_E_HIP, "coarse operator failed on the device");
-        if (!hflag) break;
+        if (hflag[1]) {
+            // A gained a nonzero outside the column lists: form them again
+            // from A's current values and repeat the product
+            if (lists_rebuilt)
+                return fail(c, MSRSB_E_HIP, "coarse operator pattern is inconsistent");
+            launch_rap_cols(s, c->n, nc, c->rrp, c->rci, c->a_off, c->a_dia, c->pcol16,
+                            c->rap_cols, c->rap_ncol);
+            lists_rebuilt = true;
+            continue;
+        }
+        if (!hflag[0]) break;
         if (c->rmaxnb >= kMaxCoarseNeighbours)
             return fail(c, MSRSB_E_ARG, "a coarse row has more than " +
                                             std::to_string(kMaxCoarseNeighbours) +

@@ -141,6 +141,10 @@ struct msrsb_ctx {
     double *r64 = nullptr;
     float *r32 = nullptr;
     int rmaxnb = 0;  // max coarse neighbours of a coarse row (RAP)
+    // R A P's column lists by coarse row, formed once per pattern when the
+    // ELL form of the RAP applies ([nc][kMaxCoarseNeighbours] and counts)
+    int *rap_cols = nullptr, *rap_ncol = nullptr;
+    bool rap_cols_valid = false;
     int *band = nullptr;  // lower and upper bandwidth of A_c (device)
     int h_band[2] = {0, 0};
 
@@ -289,7 +293,13 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
-                const double *pe64, const float *pe32, double *ac, int *flag, int *band);
+                const double *pe64, const float *pe32, double *ac, int *flag, int *band,
+                const int *cols = nullptr, const int *ncol = nullptr);
+// the column lists of R A P by coarse row (ELL form only; see k_rap_cols):
+// cols [nc][kMaxCoarseNeighbours], ncol [nc]
+void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,
+                     const DiaOffsets &d, const double *ad, const uint16_t *pcol16, int *cols,
+                     int *ncol);
 msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
                                 double *pk, int *flag, int *host_flag);
 // y = S x for the symmetric S in the packed lower-tile form (acinv_pk)

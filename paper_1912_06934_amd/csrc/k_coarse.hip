@@ -160,29 +160,26 @@ __device__ __forceinline__ void load_prow(const PT *__restrict__ p, const uint16
     }
 }
 
-template <typename T, int NT, int ND>
-__global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
-                                                const int *__restrict__ rrp,
-                                                const int *__restrict__ rci,
-                                                const T *__restrict__ rv, DiaOffsets d,
-                                                const double *__restrict__ ad,
-                                                const uint16_t *__restrict__ pcol,
-                                                const T *__restrict__ pv, double *__restrict__ ac,
-                                                int *__restrict__ flag, int *__restrict__ band)
+// The coarse columns of row j of R A P (stencil A with ND diagonals, ELL P):
+// the columns of P's rows k = i + off that row i of R reaches through a
+// nonzero A_ik, marked in map (nc entries of LDS) and numbered in ascending
+// order, map[c] = slot or -1 and inv[slot] = c.  Returns their count (in
+// every thread); the numbering is done only when the count fits cap.
+// Called by all NT threads.
+template <int NT, int ND>
+__device__ inline int rap_columns(int n, int nc, int j, int cap, const int *__restrict__ rrp,
+                                  const int *__restrict__ rci, const DiaOffsets &d,
+                                  const double *__restrict__ ad,
+                                  const uint16_t *__restrict__ pcol, short *map, int *inv)
 {
-    extern __shared__ double smem[];
     __shared__ int wsum[NT / 64];
-    double *acc = smem;                                         // maxnb * NT
-    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);       // maxnb
-    short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
-    const int j = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int t = tid; t < nc; t += NT) map[t] = 0;
     __syncthreads();
     const int t0 = rrp[j], t1 = rrp[j + 1];
-    // entries t, t + NT, ... (UM of them) of a thread at once; a neighbour's columns are
-    // read whether or not its coefficient is zero (the test comes after), so
-    // every load of those entries is in flight together
+    // entries t, t + NT, ... (UM of them) of a thread at once; a neighbour's
+    // columns are read whether or not its coefficient is zero (the test comes
+    // after), so every load of those entries is in flight together
     typedef uint16_t cvec __attribute__((ext_vector_type(8)));
     constexpr int UM = 4;
     for (int t = t0 + tid; t < t1; t += UM * NT) {
@@ -233,10 +230,7 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
         if (w < wid) base += wsum[w];
         total += wsum[w];
     }
-    if (total > maxnb) {
-        if (tid == 0) flag[0] = 1;
-        return;
-    }
+    if (total > cap) return total;
     int slot = base + pre - cnt;
     __syncthreads();
     for (int t = lo; t < hi; ++t) {
@@ -247,8 +241,81 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
             map[t] = -1;
         }
     }
+    return total;
+}
+
+// The column lists of R A P by coarse row, once per pattern (set-up of the
+// coarse space): cols[j * kMaxCoarseNeighbours + s], s < ncol[j], ascending
+// (a row with more columns stores its count only).
+template <int ND>
+__global__ __launch_bounds__(128) void k_rap_cols(int n, int nc, const int *__restrict__ rrp,
+                                                  const int *__restrict__ rci, DiaOffsets d,
+                                                  const double *__restrict__ ad,
+                                                  const uint16_t *__restrict__ pcol,
+                                                  int *__restrict__ cols, int *__restrict__ ncol)
+{
+    extern __shared__ double smem[];
+    int *inv = reinterpret_cast<int *>(smem);                        // kMaxCoarseNeighbours
+    short *map = reinterpret_cast<short *>(inv + kMaxCoarseNeighbours);  // nc
+    const int j = blockIdx.x;
+    const int total = rap_columns<128, ND>(n, nc, j, kMaxCoarseNeighbours, rrp, rci, d, ad, pcol,
+                                           map, inv);
+    __syncthreads();
+    if (total <= kMaxCoarseNeighbours)
+        for (int s = threadIdx.x; s < total; s += 128)
+            cols[static_cast<int64_t>(j) * kMaxCoarseNeighbours + s] = inv[s];
+    if (threadIdx.x == 0) ncol[j] = total;
+}
+
+// The numeric product: with column lists (cols, ncol from k_rap_cols) the
+// row's columns are installed in the LDS map directly; without, they are
+// marked here as above.  A contribution to a column outside a list (A's
+// values gained a nonzero since the lists were formed) sets flag[1], and
+// the caller rebuilds the lists and repeats; more columns than maxnb set
+// flag[0].
+template <typename T, int NT, int ND>
+__global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
+                                                const int *__restrict__ rrp,
+                                                const int *__restrict__ rci,
+                                                const T *__restrict__ rv, DiaOffsets d,
+                                                const double *__restrict__ ad,
+                                                const uint16_t *__restrict__ pcol,
+                                                const T *__restrict__ pv, double *__restrict__ ac,
+                                                int *__restrict__ flag, int *__restrict__ band,
+                                                const int *__restrict__ cols,
+                                                const int *__restrict__ ncol)
+{
+    extern __shared__ double smem[];
+    double *acc = smem;                                         // maxnb * NT
+    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);       // maxnb
+    short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    int total;
+    if (cols != nullptr) {
+        total = ncol[j];
+        if (total > maxnb) {
+            if (tid == 0) flag[0] = 1;
+            return;
+        }
+        for (int t = tid; t < nc; t += NT) map[t] = -1;
+        __syncthreads();
+        for (int s = tid; s < total; s += NT) {
+            const int c = cols[static_cast<int64_t>(j) * kMaxCoarseNeighbours + s];
+            inv[s] = c;
+            map[c] = static_cast<short>(s);
+        }
+    } else {
+        total = rap_columns<NT, ND>(n, nc, j, maxnb, rrp, rci, d, ad, pcol, map, inv);
+        if (total > maxnb) {
+            if (tid == 0) flag[0] = 1;
+            return;
+        }
+    }
     for (int s = 0; s < total; ++s) acc[s * NT + tid] = 0.0;
     __syncthreads();
+    const int t0 = rrp[j], t1 = rrp[j + 1];
+    bool miss = false;
     // UA entries of a thread per round (t, t + NT, ...), their loads all in
     // flight together; the sums are taken in the same entry order as one at
     // a time (UA = 1 for FP64 rows, which would not fit in registers twice)
@@ -282,12 +349,18 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                 if (av[q][o] == 0.0 || pij[q] == 0.0) continue;
                 const double pa = pij[q] * av[q][o];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (cl[q][o][u] != 0xFFFFu)
-                        atomicAdd(&acc[map[cl[q][o][u]] * NT + tid],
-                                  pa * static_cast<double>(v[q][o][u]));
+                for (int u = 0; u < 8; ++u) {
+                    if (cl[q][o][u] == 0xFFFFu) continue;
+                    const int sl = map[cl[q][o][u]];
+                    const double prod = pa * static_cast<double>(v[q][o][u]);
+                    if (sl >= 0)
+                        atomicAdd(&acc[sl * NT + tid], prod);
+                    else if (prod != 0.0)
+                        miss = true;
+                }
             }
     }
+    if (miss) flag[1] = 1;
     __syncthreads();
     int bl = 0, bu = 0;
     for (int s = tid; s < total; s += NT) {
@@ -1341,22 +1414,32 @@ void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp
 template <typename T, int ND>
 void rap_ell_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
                const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
-               const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band)
+               const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
+               const int *cols, const int *ncol)
 {
     k_rap_ell<T, 128, ND><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac,
-                                                 flag, band);
+                                                 flag, band, cols, ncol);
 }
 
 template <typename T>
 bool rap_ell(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
              const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
-             const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band)
+             const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
+             const int *cols, const int *ncol)
 {
     switch (d.n) {
-    case 3: rap_ell_t<T, 3>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
-    case 5: rap_ell_t<T, 5>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
-    case 7: rap_ell_t<T, 7>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
-    case 9: rap_ell_t<T, 9>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band); return true;
+    case 3: rap_ell_t<T, 3>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
+                            cols, ncol);
+        return true;
+    case 5: rap_ell_t<T, 5>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
+                            cols, ncol);
+        return true;
+    case 7: rap_ell_t<T, 7>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
+                            cols, ncol);
+        return true;
+    case 9: rap_ell_t<T, 9>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
+                            cols, ncol);
+        return true;
     default: return false;
     }
 }
@@ -1367,11 +1450,26 @@ bool rap_uses_ell(int maxnb, const DiaOffsets &d, int pw, const uint16_t *pcol16
            (d.n == 3 || d.n == 5 || d.n == 7 || d.n == 9);
 }
 
+void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,
+                     const DiaOffsets &d, const double *ad, const uint16_t *pcol16, int *cols,
+                     int *ncol)
+{
+    const size_t shmem = sizeof(int) * kMaxCoarseNeighbours + sizeof(short) * nc + 16;
+    switch (d.n) {
+    case 3: k_rap_cols<3><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
+    case 5: k_rap_cols<5><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
+    case 7: k_rap_cols<7><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
+    case 9: k_rap_cols<9><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
+    default: break;
+    }
+}
+
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
-                const double *pe64, const float *pe32, double *ac, int *flag, int *band)
+                const double *pe64, const float *pe32, double *ac, int *flag, int *band,
+                const int *cols, const int *ncol)
 {
     // 128 threads while the per-thread partial sums fit in 32 KB of LDS
     const int nt = maxnb <= 32 ? 128 : 64;
@@ -1380,9 +1478,9 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
     // stencil A and 8-wide ELL P: the batched form
     if (nt == 128 && d.n > 0 && pw == 8 && pcol16) {
         const bool done = fp32 ? rap_ell<float>(s, shmem, n, nc, maxnb, rrp, rci, r32, d, ad,
-                                                pcol16, pe32, ac, flag, band)
+                                                pcol16, pe32, ac, flag, band, cols, ncol)
                                : rap_ell<double>(s, shmem, n, nc, maxnb, rrp, rci, r64, d, ad,
-                                                 pcol16, pe64, ac, flag, band);
+                                                 pcol16, pe64, ac, flag, band, cols, ncol);
         if (done) return;
     }
     if (nt == 128) {

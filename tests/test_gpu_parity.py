@@ -65,6 +65,29 @@ def test_basis_and_coarse_operator_match_oracle(torch_cuda, case):
     assert rel_max(ac, orc.ac) <= 1e-12
 
 
+def test_coarse_pattern_follows_value_changes(torch_cuda):
+    """The column lists of R A P are formed with the coarse space, from A's
+    values at that time.  Formed on a diagonal A, they miss every coupling
+    through a neighbour; once the full values are in place, the product must
+    still reach all of A_c (the lists are formed again)."""
+    from paper_1912_06934_amd import Msrsb
+    cfg = tpfa_inputs("c5", (24, 20, 18), 8)
+    orc = oracle_setup(cfg)
+    rp, ci, a = cfg["rp"], cfg["ci"], cfg["a"]
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    s = Msrsb(device=0)
+    s.set_matrix(rp, ci, np.where(ci == rows, a, 0.0))
+    sup = cfg["supports"]
+    s.set_coarse(sup["nc"], sup["part"], sup["prp"], sup["pci"], sup["interior"])
+    s.update_values(a)
+    s.setup_basis(max_iter=100)
+    s.build_coarse()
+    ac = s.get_coarse_matrix()
+    assert rel_max(ac, orc.ac) <= 1e-12
+    s.build_coarse()
+    assert np.array_equal(s.get_coarse_matrix(), ac)
+
+
 @pytest.mark.parametrize("case", CASES, ids=_id)
 @pytest.mark.parametrize("smoother", [((0, 0), (1, 1)), ((2, 2), (2, 2)), ((1, 1), (0, 0))],
                          ids=["jac-post", "l1x2", "jac-pre"])
