@@ -1303,30 +1303,37 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ p
 }
 
 // y_I = sum over J <= I of the row partials of tile (I, J) and over J > I
-// of the column partials of tile (J, I), in order of J (all partials of a
-// row loaded before the sum: nt <= kMaxCoarse / 64 = 64)
-__global__ __launch_bounds__(kBP) void k_symv_final(const double *__restrict__ part, int n,
-                                                    double *__restrict__ y)
+// of the column partials of tile (J, I): four threads per row (one
+// wavefront per quarter of J) each add their quarter in order of J, all its
+// partials loaded first (nt <= kMaxCoarse / 64 = 64), then the quarters are
+// added in order.
+__global__ __launch_bounds__(256) void k_symv_final(const double *__restrict__ part, int n,
+                                                   double *__restrict__ y)
 {
     constexpr int kMaxTiles = kMaxCoarse / kBP;
-    const int I = blockIdx.x, r = threadIdx.x, nt = gridDim.x;
-    const int row = I * kBP + r;
-    if (row >= n) return;
-    double v[kMaxTiles];
+    constexpr int kQ = kMaxTiles / 4;
+    __shared__ double sh[4][kBP];
+    const int I = blockIdx.x, nt = gridDim.x;
+    const int r = threadIdx.x & 63, qd = threadIdx.x >> 6;
+    double v[kQ];
 #pragma unroll
-    for (int J = 0; J < kMaxTiles; ++J) {
+    for (int u = 0; u < kQ; ++u) {
+        const int J = qd * kQ + u;
         int64_t e = 0;
         if (J <= I)
             e = (static_cast<int64_t>(I) * (I + 1) / 2 + J) * 2 * kBP + r;
         else if (J < nt)
             e = (static_cast<int64_t>(J) * (J + 1) / 2 + I) * 2 * kBP + kBP + r;
-        v[J] = J < nt ? part[e] : 0.0;
+        v[u] = J < nt ? part[e] : 0.0;
     }
     double s = 0.0;
 #pragma unroll
-    for (int J = 0; J < kMaxTiles; ++J)
-        if (J < nt) s += v[J];
-    y[row] = s;
+    for (int u = 0; u < kQ; ++u) s += v[u];
+    sh[qd][r] = s;
+    __syncthreads();
+    const int row = I * kBP + threadIdx.x;
+    if (threadIdx.x < kBP && row < n)
+        y[row] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
 }
 
 // y = M x, one wavefront per row; lanes stride over the columns (two per
@@ -1592,7 +1599,7 @@ void launch_symv_packed(hipStream_t s, int n, const double *pk, const double *x,
 {
     const int nt = (n + kBP - 1) / kBP;
     k_symv_tiles<<<nt * (nt + 1) / 2, 256, 0, s>>>(pk, n, x, part);
-    k_symv_final<<<nt, kBP, 0, s>>>(part, n, y);
+    k_symv_final<<<nt, 256, 0, s>>>(part, n, y);
 }
 
 void launch_gemv(hipStream_t s, int n, const double *m, const double *x, double *y, bool trans,
