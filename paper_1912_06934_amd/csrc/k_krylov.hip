@@ -376,10 +376,12 @@ __device__ inline void sum_partials_block(int nb, const double *__restrict__ par
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(int nb, const double *__restrict__ part,
                                                            double *__restrict__ scal)
 {
+    // the scalar read first, so that its load overlaps the partials' loads
+    const double rz = scal[S_RZ_OLD];
     double t[1];
     sum_partials_block<1>(nb, part, t);
     if (threadIdx.x != 0) return;
-    const double pq = t[0], rz = scal[S_RZ_OLD];
+    const double pq = t[0];
     scal[S_PQ] = pq;
     const bool bad = !(pq > 0.0) || !isfinite(pq) || !isfinite(rz);
     if (bad) scal[S_BREAK] = 1.0;
@@ -398,20 +400,23 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *
                                                           double *__restrict__ host_out,
                                                           double tag)
 {
+    // the scalars read first, so that their loads overlap the partials' loads
+    const double rz_old = scal[S_RZ_OLD], brk = scal[S_BREAK];
     // r.z, r.(z - z_old) and (inside PCG) r.r in one pass
     double t[3];
     sum_partials_block<3>(nb, part, t, host_out != nullptr ? part_rr : part);
     if (threadIdx.x != 0) return;
     scal[S_RZ] = t[0];
     scal[S_RZDIFF] = t[1];
-    const double b = t[1] / scal[S_RZ_OLD];
-    if (!isfinite(b)) scal[S_BREAK] = 1.0;
-    scal[S_BETA] = isfinite(b) ? b : 0.0;
+    const double b = t[1] / rz_old;
+    const bool bad = !isfinite(b);
+    if (bad) scal[S_BREAK] = 1.0;
+    scal[S_BETA] = bad ? 0.0 : b;
     scal[S_RZ_OLD] = t[0];
     if (host_out == nullptr) return;
     scal[S_RR] = t[2];
     host_out[0] = t[2];
-    host_out[1] = scal[S_BREAK];
+    host_out[1] = bad ? 1.0 : brk;
     __threadfence_system();
     host_out[2] = tag;
 }
