@@ -614,6 +614,80 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv(
     block_partials<1>(v, part);
 }
 
+// The DIA form of the kernel above with the work-group's own rows shared
+// through LDS: every thread loads z, p_old and (SYM) its upper coefficients
+// at its own row, and a neighbour inside the work-group's kBlock rows (the
+// +-1 offsets, and half the rows' +-nx) is read from LDS; only neighbours
+// outside the tile (+-nx ny, the other half of +-nx, the tile-edge +-1) are
+// loaded from memory, all before the barrier.  Rows of a work-group are
+// contiguous (xcd_row).  Same arithmetic and order as the kernel above.
+template <int ND, bool SYM>
+__global__ __launch_bounds__(kBlock) void k_pcg_p_spmv_dia(
+    int n, DiaOffsets d, const double *__restrict__ ad, const double *__restrict__ z,
+    const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ q,
+    double *__restrict__ part, const double *__restrict__ scal)
+{
+    constexpr int MID = ND / 2;  // the zero offset of a symmetric offset set
+    __shared__ double sz[kBlock], sp[kBlock];
+    __shared__ double sa[SYM ? MID : 1][kBlock];
+    const int t = threadIdx.x;
+    const int i = xcd_row();
+    const int ic = i < n ? i : n - 1;
+    const double beta = scal[S_BETA];
+    const bool restart = beta == 0.0;
+    double av[ND], zk[ND], pk[ND];
+    bool in[ND], loc[ND];
+#pragma unroll
+    for (int o = 0; o < ND; ++o) {
+        const int k = i + d.off[o];
+        in[o] = k >= 0 && k < n;
+        const int kk = in[o] ? k : ic;
+        const int tl = t + d.off[o];
+        loc[o] = tl >= 0 && tl < kBlock;
+        if (!SYM || o >= MID)
+            av[o] = ad[static_cast<int64_t>(o) * n + ic];
+        if (!loc[o]) {
+            zk[o] = z[kk];
+            pk[o] = restart ? 0.0 : pold[kk];
+            if (SYM && o < MID) av[o] = ad[static_cast<int64_t>(ND - 1 - o) * n + kk];
+        }
+    }
+    sz[t] = z[ic];
+    sp[t] = restart ? 0.0 : pold[ic];
+    if constexpr (SYM) {
+#pragma unroll
+        for (int o = MID + 1; o < ND; ++o) sa[o - MID - 1][t] = av[o];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < ND; ++o) {
+        if (loc[o]) {
+            const int tl = t + d.off[o];
+            zk[o] = sz[tl];
+            pk[o] = sp[tl];
+            if (SYM && o < MID) av[o] = sa[ND - 1 - o - MID - 1][tl];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int o = 0; o < ND; ++o) {
+        const double pv = restart ? zk[o] : zk[o] + beta * pk[o];
+        zk[o] = pv;
+        s += av[o] * (in[o] ? pv : 0.0);
+    }
+    double v[1] = {0.0};
+    if (i < n) {
+        double pc = zk[0];
+#pragma unroll
+        for (int o = 1; o < ND; ++o)
+            if (d.off[o] == 0) pc = zk[o];
+        pnew[i] = pc;
+        q[i] = s;
+        v[0] = pc * s;
+    }
+    block_partials<1>(v, part);
+}
+
 // x += alpha p, r -= alpha q, and r.r
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict__ x,
                                                        double *__restrict__ r,
@@ -980,8 +1054,13 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
 {
     if (d.n > 0)
         with_ndiag(d, [&](auto nd, auto sym) {
-            k_pcg_p_spmv<MSRSB_DIA_ARGS(nd, sym)><<<grid_for(n), kBlock, 0, s>>>(
-                n, d, ad, rp, ci, a, z, pold, pnew, q, part, scal);
+            constexpr int ND = decltype(nd)::value;
+            if constexpr (ND > 0 && ND <= 9)
+                k_pcg_p_spmv_dia<MSRSB_DIA_ARGS(nd, sym)><<<grid_for(n), kBlock, 0, s>>>(
+                    n, d, ad, z, pold, pnew, q, part, scal);
+            else
+                k_pcg_p_spmv<MSRSB_DIA_ARGS(nd, sym)><<<grid_for(n), kBlock, 0, s>>>(
+                    n, d, ad, rp, ci, a, z, pold, pnew, q, part, scal);
         });
     else
         k_pcg_p_spmv<-1, false><<<grid_for(n), kBlock, 0, s>>>(n, d, ad, rp, ci, a, z, pold, pnew,
