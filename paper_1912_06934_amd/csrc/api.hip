@@ -178,6 +178,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rsrc);
     dfree(c->roff16);
     dfree(c->rbase);
+    dfree(c->rbox);
     dfree(c->r64);
     dfree(c->r32);
     dfree(c->ac);
@@ -723,6 +724,40 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         for (int jj = 0; jj < nc; ++jj)
             for (int t = pos[jj]; t < rrp[jj + 1]; ++t) rci[t] = rci[t - 1];
     }
+    // supports that are boxes of the assembled grid: the restriction then
+    // forms its columns instead of loading them.  Every entry is checked
+    // against the box formula, so the fast path is exact whenever it is taken.
+    std::vector<int> rbox;
+    if (c->tpfa && c->bs == 1) {
+        const int nx = c->tdims[0], ny = c->tdims[1];
+        const int64_t nxy = static_cast<int64_t>(nx) * ny;
+        rbox.resize(static_cast<size_t>(nc) * 4);
+        for (int jj = 0; jj < nc && !rbox.empty(); ++jj) {
+            const int len = rlen[jj], r0 = rrp[jj];
+            if (len == 0) {
+                rbox.clear();
+                break;
+            }
+            const int f = rci[r0], l = rci[r0 + len - 1];
+            const int x0 = f % nx, y0 = (f / nx) % ny, z0 = static_cast<int>(f / nxy);
+            const int bx = l % nx - x0 + 1, by = (l / nx) % ny - y0 + 1;
+            const int bz = static_cast<int>(l / nxy) - z0 + 1;
+            bool ok = len <= 65536 && bx > 0 && by > 0 && bz > 0 &&
+                      static_cast<int64_t>(bx) * by * bz == len;
+            for (int q = 0; q < len && ok; ++q) {
+                const int qx = q % bx, qy = (q / bx) % by, qz = q / (bx * by);
+                ok = rci[r0 + q] == f + qx + qy * nx + qz * nxy;
+            }
+            if (!ok) {
+                rbox.clear();
+                break;
+            }
+            rbox[4 * jj] = f;
+            rbox[4 * jj + 1] = bx;
+            rbox[4 * jj + 2] = bx * by;
+            rbox[4 * jj + 3] = len;
+        }
+    }
     // 16-bit column offsets when every 64-entry group spans fewer than 2^16 rows
     bool r16 = true;
     std::vector<int> rbase(rnnz / 64);
@@ -759,6 +794,12 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         hipMemcpyAsync(c->roff16, roff.data(), rnnz * sizeof(uint16_t), hipMemcpyHostToDevice,
                        c->stream);
         hipMemcpyAsync(c->rbase, rbase.data(), rnnz / 64 * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+    }
+    if (!rbox.empty()) {
+        if (!dalloc(c->rbox, rbox.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        hipMemcpyAsync(c->rbox, rbox.data(), rbox.size() * sizeof(int), hipMemcpyHostToDevice,
                        c->stream);
     }
     hipMemcpyAsync(c->pcol_ell, pcol.data(), pcol.size() * sizeof(int), hipMemcpyHostToDevice,

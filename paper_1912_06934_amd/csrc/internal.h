@@ -137,6 +137,9 @@ struct msrsb_ctx {
     int *rrp = nullptr, *rci = nullptr, *rsrc = nullptr;
     uint16_t *roff16 = nullptr;
     int *rbase = nullptr;
+    // supports that are boxes of the assembled grid: per coarse row the first
+    // fine row, bx, bx * by and the entry count (null when any is not)
+    int *rbox = nullptr;
     int64_t rnnz = 0;
     double *r64 = nullptr;
     float *r32 = nullptr;
@@ -319,10 +322,18 @@ void launch_residual(hipStream_t s, int n, const int *rp, const int *ci, const d
 void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const double *a,
                   const float *a32, const double *dinv, const float *dinv32, bool fp32,
                   const double *v, const double *zin, double *zout, bool zero_start);
-// xc = R x; columns from rci, or (roff16 non-null) rbase[e / 64] + roff16[e]
+// Coarse rows whose entries (fine rows ascending) are the cells of a box of
+// an nx x ny x nz grid: box[4 j ..] = first row, bx, bx * by, entry count.
+struct RestrictBoxes {
+    const int *box = nullptr;
+    int nx = 0, nxy = 0;
+};
+// xc = R x; columns from the boxes when given, else from rci, or (roff16
+// non-null) rbase[e / 64] + roff16[e]
 void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
                      const uint16_t *roff16, const int *rbase, bool fp32, const double *r64,
-                     const float *r32, const double *x, double *xc);
+                     const float *r32, const double *x, double *xc,
+                     const RestrictBoxes &boxes = RestrictBoxes{});
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
                 double *out);
 void launch_copy(hipStream_t s, int n, const double *x, double *y);
@@ -359,7 +370,8 @@ void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double 
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const uint16_t *roff16,
-                         const int *rbase, const float *r32, double *vc);
+                         const int *rbase, const float *r32, double *vc,
+                         const RestrictBoxes &boxes = RestrictBoxes{});
 void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,

@@ -152,6 +152,48 @@ __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__rest
     if (threadIdx.x == 0) xc[j] = s;
 }
 
+// v_c = R x when every support is a box of the grid: entry q of coarse row j
+// (fine rows ascending) is box cell (q mod bx, (q div bx) mod by, q div bx by),
+// so the columns follow from the box and a step's values and gathers are
+// loaded together (one memory round trip instead of two).  The entries per
+// lane and the summation order are those of k_restrict_b; its pads (value 0)
+// are not visited.  q < 2^16, so the float quotients below are exact.
+template <typename T, typename XT>
+__global__ __launch_bounds__(kBlock) void k_restrict_box(int nc, const int *__restrict__ rrp,
+                                                         const int *__restrict__ box, int nx,
+                                                         int nxy, const T *__restrict__ rv,
+                                                         const XT *__restrict__ x,
+                                                         double *__restrict__ xc)
+{
+    constexpr int U = 16;
+    const int j = xcd_group(blockIdx.x, gridDim.x);
+    if (j >= nc) return;
+    const int r0 = rrp[j];
+    const int org = box[4 * j], bx = box[4 * j + 1], bxy = box[4 * j + 2];
+    const int t1 = r0 + box[4 * j + 3];
+    const float ibx = 1.0f / static_cast<float>(bx), ibxy = 1.0f / static_cast<float>(bxy);
+    double s = 0.0;
+    for (int t = r0 + threadIdx.x; t < t1; t += U * kBlock) {
+        T v[U];
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(t + u * kBlock, t1 - 1);
+            const int q = e - r0;
+            const int qz = static_cast<int>((static_cast<float>(q) + 0.5f) * ibxy);
+            const int rem = q - qz * bxy;
+            const int qy = static_cast<int>((static_cast<float>(rem) + 0.5f) * ibx);
+            v[u] = rv[e];
+            xv[u] = x[org + (rem - qy * bx) + qy * nx + qz * nxy];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t + u * kBlock < t1) s += static_cast<double>(v[u]) * static_cast<double>(xv[u]);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) xc[j] = s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 double *__restrict__ part)
@@ -987,9 +1029,16 @@ void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const doub
 
 void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
                      const uint16_t *roff16, const int *rbase, bool fp32, const double *r64,
-                     const float *r32, const double *x, double *xc)
+                     const float *r32, const double *x, double *xc, const RestrictBoxes &boxes)
 {
-    if (fp32) {
+    if (boxes.box) {
+        if (fp32)
+            k_restrict_box<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx,
+                                                                boxes.nxy, r32, x, xc);
+        else
+            k_restrict_box<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx,
+                                                                 boxes.nxy, r64, x, xc);
+    } else if (fp32) {
         if (roff16)
             k_restrict_b<float, double, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
                                                                     r32, x, xc);
@@ -1159,7 +1208,8 @@ void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const uint16_t *roff16,
-                         const int *rbase, const float *r32, double *vc)
+                         const int *rbase, const float *r32, double *vc,
+                         const RestrictBoxes &boxes)
 {
     with_ndiag(d, [&](auto nd, auto sym) {
         k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
@@ -1167,7 +1217,10 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
-    if (roff16)
+    if (boxes.box)
+        k_restrict_box<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx, boxes.nxy,
+                                                           r32, tmp, vc);
+    else if (roff16)
         k_restrict_b<float, float, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, r32,
                                                                tmp, vc);
     else

@@ -273,6 +273,17 @@ static void coarse_apply(msrsb_ctx *c, bool trans)
         launch_gemv(c->stream, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
 }
 
+static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
+{
+    RestrictBoxes b;
+    if (c->rbox) {
+        b.box = c->rbox;
+        b.nx = c->tdims[0];
+        b.nxy = c->tdims[0] * c->tdims[1];
+    }
+    return b;
+}
+
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
                      bool trans, const PcgDots *dots)
 {
@@ -297,7 +308,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         const float *dinv = pre_k == MSRSB_SMOOTH_L1JACOBI ? op.dl132 : op.dj32;
         float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
         launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci,
-                            c->roff16, c->rbase, c->r32, c->vc);
+                            c->roff16, c->rbase, c->r32, c->vc, restrict_boxes(c));
         coarse_apply(c, trans);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
                              c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
@@ -324,7 +335,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
             res = tmp;
         }
         launch_restrict(s, c->nc, c->rrp, c->rci, c->roff16, c->rbase, c->p_is32, c->r64, c->r32,
-                        res, c->vc);
+                        res, c->vc, restrict_boxes(c));
         coarse_apply(c, trans);
         launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
                            c->wc, z, zero);
