@@ -179,6 +179,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->roff16);
     dfree(c->rbase);
     dfree(c->rbox);
+    dfree(c->paxes);
     dfree(c->r64);
     dfree(c->r32);
     dfree(c->ac);
@@ -758,6 +759,60 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
             rbox[4 * jj + 3] = len;
         }
     }
+    // P's columns as products of per-axis candidates (box supports on a grid):
+    // the coarse grid's extent from the boxes' origins, one table per axis,
+    // then every row of the pattern checked against the product it implies
+    std::vector<int> paxes;
+    int ncx = 0, ncxy = 0;
+    if (!rbox.empty() && (pw == 4 || pw == 8)) {
+        const int nx = c->tdims[0], ny = c->tdims[1], nz = c->tdims[2];
+        const int nxy = nx * ny;
+        auto ox = [&](int j) { return rbox[4 * j] % nx; };
+        auto oy = [&](int j) { return (rbox[4 * j] / nx) % ny; };
+        auto oz = [&](int j) { return rbox[4 * j] / nxy; };
+        int cx = 1, cy = 1;
+        while (cx < nc && oy(cx) == oy(0) && oz(cx) == oz(0)) ++cx;
+        while (cy * cx < nc && oz(cy * cx) == oz(0)) ++cy;
+        bool ok = nc % (cx * cy) == 0;
+        const int cz = ok ? nc / (cx * cy) : 0;
+        // tab entries: first candidate | count << 16, counts 1 or 2
+        auto axis = [&](int len, int nn, auto lo, auto ext) {
+            for (int x = 0; x < len && ok; ++x) {
+                int first = -1, cnt = 0;
+                for (int a = 0; a < nn; ++a)
+                    if (x >= lo(a) && x < lo(a) + ext(a)) {
+                        if (first < 0) first = a;
+                        ok = ok && a == first + cnt;
+                        ++cnt;
+                    }
+                ok = ok && cnt >= 1 && cnt <= 2 && first <= 0xFFFF;
+                if (ok) paxes.push_back(first | cnt << 16);
+            }
+        };
+        axis(nx, cx, [&](int a) { return ox(a); }, [&](int a) { return rbox[4 * a + 1]; });
+        axis(ny, cy, [&](int a) { return oy(a * cx); },
+             [&](int a) { return rbox[4 * a * cx + 2] / rbox[4 * a * cx + 1]; });
+        axis(nz, cz, [&](int a) { return oz(a * cx * cy); },
+             [&](int a) { return rbox[4 * a * cx * cy + 3] / rbox[4 * a * cx * cy + 2]; });
+        for (int i = 0; i < n && ok; ++i) {
+            const int x = i % nx, y = (i / nx) % ny, z = i / nxy;
+            const int tx = paxes[x], ty = paxes[nx + y], tz = paxes[nx + ny + z];
+            const int kx = tx >> 16, ky = ty >> 16, kz = tz >> 16;
+            ok = hprp[i + 1] - hprp[i] == kx * ky * kz;
+            int e = hprp[i];
+            for (int iz = 0; iz < kz && ok; ++iz)
+                for (int iy = 0; iy < ky && ok; ++iy)
+                    for (int ix = 0; ix < kx && ok; ++ix, ++e)
+                        ok = hpci[e] == (tx & 0xFFFF) + ix + cx * ((ty & 0xFFFF) + iy) +
+                                            cx * cy * ((tz & 0xFFFF) + iz);
+        }
+        if (ok) {
+            ncx = cx;
+            ncxy = cx * cy;
+        } else {
+            paxes.clear();
+        }
+    }
     // 16-bit column offsets when every 64-entry group spans fewer than 2^16 rows
     bool r16 = true;
     std::vector<int> rbase(rnnz / 64);
@@ -795,6 +850,14 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                        c->stream);
         hipMemcpyAsync(c->rbase, rbase.data(), rnnz / 64 * sizeof(int), hipMemcpyHostToDevice,
                        c->stream);
+    }
+    if (!paxes.empty()) {
+        if (!dalloc(c->paxes, paxes.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        hipMemcpyAsync(c->paxes, paxes.data(), paxes.size() * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+        c->pax_ncx = ncx;
+        c->pax_ncxy = ncxy;
     }
     if (!rbox.empty()) {
         if (!dalloc(c->rbox, rbox.size()))

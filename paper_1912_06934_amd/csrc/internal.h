@@ -140,6 +140,10 @@ struct msrsb_ctx {
     // supports that are boxes of the assembled grid: per coarse row the first
     // fine row, bx, bx * by and the entry count (null when any is not)
     int *rbox = nullptr;
+    // P's columns as products of per-axis coarse candidates (see ProlongAxes;
+    // null unless every row of the pattern was checked to be one)
+    int *paxes = nullptr;
+    int pax_ncx = 0, pax_ncxy = 0;
     int64_t rnnz = 0;
     double *r64 = nullptr;
     float *r32 = nullptr;
@@ -328,6 +332,14 @@ struct RestrictBoxes {
     const int *box = nullptr;
     int nx = 0, nxy = 0;
 };
+// P's pattern on an nx x ny x nz grid whose row (x, y, z) reaches the coarse
+// nodes (ax + ix) + ncx (ay + iy) + ncxy (az + iz) for ix < cx, iy < cy,
+// iz < cz in ascending order, with tab[x] = ax | cx << 16, tab[nx + y] =
+// ay | cy << 16, tab[nx + ny + z] = az | cz << 16 and cx, cy in {1, 2}.
+struct ProlongAxes {
+    const int *tab = nullptr;
+    int nx = 0, ny = 0, ncx = 0, ncxy = 0;
+};
 // xc = R x; columns from the boxes when given, else from rci, or (roff16
 // non-null) rbase[e / 64] + roff16[e]
 void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
@@ -376,10 +388,12 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,
                           double *zout, const double *zold, double *partials, double *scal,
-                          const double *part_rr, double *host_out, int tag);
+                          const double *part_rr, double *host_out, int tag,
+                          const ProlongAxes &axes = ProlongAxes{});
 void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
                         bool fp32, const double *p64, const float *p32, const double *wc,
-                        double *z, bool zero);
+                        double *z, bool zero,
+                        const ProlongAxes &axes = ProlongAxes{});
 void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,
                        const double *a, double *ad64, float *ad32);
 

@@ -944,6 +944,51 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *_
     z[i] = static_cast<ZT>(zero ? s : static_cast<double>(z[i]) + s);
 }
 
+// The same product with the columns formed from the row's grid position
+// (ProlongAxes) instead of loaded: the row's values are the only P data read.
+// Slot u of the row is (ix, iy, iz) with ix fastest, as the ascending column
+// order puts them; slots past cx cy cz are padding.
+template <typename T, int PW, typename ZT = double>
+__global__ __launch_bounds__(kBlock) void k_prolong_axes(int n, ProlongAxes ax,
+                                                         const T *__restrict__ pv,
+                                                         const double *__restrict__ wc,
+                                                         ZT *__restrict__ z, int zero)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const unsigned xy = static_cast<unsigned>(i) / static_cast<unsigned>(ax.nx);
+    const int x = i - static_cast<int>(xy) * ax.nx;
+    const unsigned zz = xy / static_cast<unsigned>(ax.ny);
+    const int y = static_cast<int>(xy - zz * static_cast<unsigned>(ax.ny));
+    const int tx = ax.tab[x], ty = ax.tab[ax.nx + y], tz = ax.tab[ax.nx + ax.ny + zz];
+    T val[PW];
+    {
+        constexpr int L = 16 / sizeof(T);
+        typedef T tvec __attribute__((ext_vector_type(L)));
+        const tvec *vs = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * PW);
+#pragma unroll
+        for (int q = 0; q < PW / L; ++q) {
+            const tvec v = vs[q];
+#pragma unroll
+            for (int u = 0; u < L; ++u) val[L * q + u] = v[u];
+        }
+    }
+    const int sx = (tx >> 16) - 1, sy = (ty >> 16) - 1;  // 0 or 1: shift of that axis
+    const int cnt = (tx >> 16) * (ty >> 16) * (tz >> 16);
+    const int base = (tx & 0xFFFF) + ax.ncx * (ty & 0xFFFF) + ax.ncxy * (tz & 0xFFFF);
+    double g[PW];
+#pragma unroll
+    for (int u = 0; u < PW; ++u) {
+        const int ix = u & sx, u1 = u >> sx;
+        const int iy = u1 & sy, iz = u1 >> sy;
+        g[u] = wc[u < cnt ? base + ix + ax.ncx * iy + ax.ncxy * iz : 0];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < PW; ++u) s += u < cnt ? static_cast<double>(val[u]) * g[u] : 0.0;
+    z[i] = static_cast<ZT>(zero ? s : static_cast<double>(z[i]) + s);
+}
+
 // generic width (rows wider than 8)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_ell_w(int n, int pw, const int *__restrict__ pcol,
@@ -1234,9 +1279,14 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,
                           double *zout, const double *zold, double *partials, double *scal,
-                          const double *part_rr, double *host_out, int tag)
+                          const double *part_rr, double *host_out, int tag,
+                          const ProlongAxes &axes)
 {
-    if (pw == 8)
+    if (axes.tab && pw == 8)
+        k_prolong_axes<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
+    else if (axes.tab)
+        k_prolong_axes<float, 4, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
+    else if (pw == 8)
         k_prolong_ell<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, p32, wc, z1, 0);
     else
         k_prolong_ell<float, 4, float><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, p32, wc, z1, 0);
@@ -1285,9 +1335,13 @@ void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double 
 
 template <typename T>
 void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16, const T *pv,
-               const double *wc, double *z, bool zero)
+               const double *wc, double *z, bool zero, const ProlongAxes &axes)
 {
-    if (pcol16 && pw == 4)
+    if (axes.tab && pw == 4)
+        k_prolong_axes<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);
+    else if (axes.tab && pw == 8)
+        k_prolong_axes<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);
+    else if (pcol16 && pw == 4)
         k_prolong_ell<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, pv, wc, z, zero ? 1 : 0);
     else if (pcol16 && pw == 8)
         k_prolong_ell<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, pcol16, pv, wc, z, zero ? 1 : 0);
@@ -1297,12 +1351,12 @@ void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pc
 
 void launch_prolong_ell(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16,
                         bool fp32, const double *p64, const float *p32, const double *wc,
-                        double *z, bool zero)
+                        double *z, bool zero, const ProlongAxes &axes)
 {
     if (fp32)
-        prolong_t<float>(s, n, pw, pcol, pcol16, p32, wc, z, zero);
+        prolong_t<float>(s, n, pw, pcol, pcol16, p32, wc, z, zero, axes);
     else
-        prolong_t<double>(s, n, pw, pcol, pcol16, p64, wc, z, zero);
+        prolong_t<double>(s, n, pw, pcol, pcol16, p64, wc, z, zero, axes);
 }
 
 void launch_csr_to_dia(hipStream_t s, int n, int noff, const int *rp, const int8_t *slot,

@@ -273,6 +273,19 @@ static void coarse_apply(msrsb_ctx *c, bool trans)
         launch_gemv(c->stream, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
 }
 
+static ProlongAxes prolong_axes(const msrsb_ctx *c)
+{
+    ProlongAxes a;
+    if (c->paxes) {
+        a.tab = c->paxes;
+        a.nx = c->tdims[0];
+        a.ny = c->tdims[1];
+        a.ncx = c->pax_ncx;
+        a.ncxy = c->pax_ncxy;
+    }
+    return a;
+}
+
 static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
 {
     RestrictBoxes b;
@@ -312,7 +325,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         coarse_apply(c, trans);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
                              c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
-                             dots->part_rr, dots->host_out, dots->tag);
+                             dots->part_rr, dots->host_out, dots->tag, prolong_axes(c));
         return;
     }
     bool zero = true;
@@ -338,7 +351,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
                         res, c->vc, restrict_boxes(c));
         coarse_apply(c, trans);
         launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
-                           c->wc, z, zero);
+                           c->wc, z, zero, prolong_axes(c));
         zero = false;
     }
     for (t = 0; t < post_n; ++t) {
