@@ -180,7 +180,7 @@ struct msrsb_ctx {
     bool ilu_valid = false;
 
     // Krylov workspace
-    double *w[12] = {};
+    double *w[13] = {};
     float *wf[3] = {};            // FP32 work vectors of the precision-form preconditioner
     double *vc = nullptr, *wc = nullptr;
     double *partials = nullptr, *scal = nullptr;
@@ -360,9 +360,23 @@ void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a,
                      double *y);
 void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double *a,
                          const float *a32, const double *f, const double *x, double *r);
+// The PCG update x += alpha p, rout = rin - alpha q with the r.r partials
+// (alpha = scal[S_ALPHA]).  Passed to the first kernel of the next
+// preconditioner application, which performs it where it can read the
+// residual at the stencil's rows (rout is that application's input and must
+// not alias rin).
+struct UpdArgs {
+    double *x = nullptr;
+    const double *rin = nullptr;
+    const double *p = nullptr, *q = nullptr;
+    double *rout = nullptr;
+    double *part = nullptr;
+    const double *scal = nullptr;
+};
 void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
                       const float *a32, const double *dinv64, const float *dinv32,
-                      const double *v, const double *zin, double *zout, bool zero2);
+                      const double *v, const double *zin, double *zout, bool zero2,
+                      const UpdArgs *upd = nullptr);
 void launch_dia_sweep_dots(hipStream_t s, int n, const DiaOffsets &d, bool fp32,
                            const double *a64, const float *a32, const double *dinv64,
                            const float *dinv32, const double *r, const double *zin, double *zout,
@@ -377,13 +391,13 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
                        const double *pold, double *pnew, double *q, double *part, double *scal);
 // x += alpha p, r -= alpha q; the r.r partials (one per block) go to
 // part_rr and are summed by the step's k_fin_beta
-void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part_rr, double *scal);
+void launch_pcg_update(hipStream_t s, int n, const UpdArgs &u);
 void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const uint16_t *roff16,
                          const int *rbase, const float *r32, double *vc,
-                         const RestrictBoxes &boxes = RestrictBoxes{});
+                         const RestrictBoxes &boxes = RestrictBoxes{},
+                         const UpdArgs *upd = nullptr);
 void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float *a32,
                           const float *dinv32, const double *v, float *z1, float *z2, int pw,
                           const uint16_t *pcol16, const float *p32, const double *wc,

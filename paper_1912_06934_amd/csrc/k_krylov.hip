@@ -454,6 +454,13 @@ __device__ __forceinline__ MT tile_dia_dot(int i, int n, const DiaOffsets &d,
 template <int ND, typename XT>
 constexpr bool kTiled = ND > 0 && ND <= kTileMaxDiag && sizeof(XT) == 8;
 
+// r - alpha q of the PCG update, one rounding, the same in every kernel that
+// forms it
+__device__ __forceinline__ double pcg_residual(double r, double q, double alpha)
+{
+    return fma(-alpha, q, r);
+}
+
 // Per-block partial sums of NV values, stored at part[q * gridDim.x + block];
 // a one-block finishing kernel then adds them in block order, so the total
 // does not depend on scheduling.
@@ -687,6 +694,64 @@ __global__ __launch_bounds__(kBlock) void k_dia_sweep2_zero(int n, DiaOffsets d,
     zout[i] = static_cast<ZT>(z1i + static_cast<double>(dinv[i] * (static_cast<MT>(v[i]) - s)));
 }
 
+// The PCG update x += alpha p, r_out = r_in - alpha q with the r.r partials,
+// fused with the two sweeps from zero above (tiled form) that read the
+// updated residual: a row's own r_out goes through LDS as z1 = dinv r_out,
+// and outside the tile r_in and q are read and the update formed on the spot.
+// r_out must not alias r_in (other work-groups still read r_in).
+template <int ND, bool SYM, typename MT, typename ZT>
+__global__ __launch_bounds__(kBlock) void k_pcg_update_sweep2(int n, DiaOffsets d,
+                                                              const MT *__restrict__ a,
+                                                              const MT *__restrict__ dinv,
+                                                              ZT *__restrict__ zout, UpdArgs u)
+{
+    __shared__ MT sz1[kBlock];
+    __shared__ MT sa[SYM ? ND / 2 : 1][kBlock];
+    const int i = xcd_row();
+    const int t = threadIdx.x;
+    const int ic = i < n ? i : n - 1;
+    const double alpha = u.scal[S_ALPHA];
+    const TileRows<ND> r(i, ic, t, n, d);
+    TileCoefs<ND, SYM, MT> c;
+    c.load(a, n, ic, t, r, sa);
+    MT dk[ND];
+    double vk[ND], qk[ND];
+#pragma unroll
+    for (int o = 0; o < ND; ++o)
+        if (!r.loc[o]) {
+            dk[o] = dinv[r.kk[o]];
+            vk[o] = u.rin[r.kk[o]];
+            qk[o] = u.q[r.kk[o]];
+        }
+    const double xi = u.x[ic], pi = u.p[ic];
+    const double vi = pcg_residual(u.rin[ic], u.q[ic], alpha);
+    const MT di = dinv[ic];
+    sz1[t] = static_cast<MT>(static_cast<double>(di * static_cast<MT>(vi)));
+    __syncthreads();
+    c.finish(t, d, r, sa);
+    MT s = MT(0);
+#pragma unroll
+    for (int o = 0; o < ND; ++o) {
+        MT z1;
+        if (r.loc[o]) {
+            z1 = sz1[t + d.off[o]];
+        } else {
+            const double vo = pcg_residual(vk[o], qk[o], alpha);
+            z1 = static_cast<MT>(static_cast<double>(dk[o] * static_cast<MT>(vo)));
+        }
+        s += c.av[o] * (r.in[o] ? z1 : MT(0));
+    }
+    double rr[1] = {0.0};
+    if (i < n) {
+        const double z1i = static_cast<double>(di * static_cast<MT>(vi));
+        zout[i] = static_cast<ZT>(z1i + static_cast<double>(di * (static_cast<MT>(vi) - s)));
+        u.x[i] = fma(alpha, pi, xi);
+        u.rout[i] = vi;
+        rr[0] = vi * vi;
+    }
+    block_partials<1>(rr, u.part);
+}
+
 // last smoothing sweep of the preconditioner inside PCG, fused with the dot
 // products r.z and r.(z - z_old) and the flexible beta
 template <int ND, bool SYM, typename MT, typename ZT = double>
@@ -886,9 +951,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_spmv_dia(
     block_partials<1>(v, part);
 }
 
-// x += alpha p, r -= alpha q, and r.r
+// x += alpha p, r_out = r_in - alpha q, and r.r (out of place, as the fused
+// form above)
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict__ x,
-                                                       double *__restrict__ r,
+                                                       const double *__restrict__ rin,
+                                                       double *__restrict__ rout,
                                                        const double *__restrict__ p,
                                                        const double *__restrict__ q,
                                                        double *__restrict__ part,
@@ -898,9 +965,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, double *__restrict
     const int i = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (i < n) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = pcg_residual(rin[i], q[i], alpha);
+        rout[i] = ri;
         v[0] = ri * ri;
     }
     block_partials<1>(v, part);
@@ -1208,9 +1275,25 @@ void launch_dia_residual(hipStream_t s, int n, const DiaOffsets &d, const double
 
 void launch_dia_sweep(hipStream_t s, int n, const DiaOffsets &d, bool fp32, const double *a64,
                       const float *a32, const double *dinv64, const float *dinv32,
-                      const double *v, const double *zin, double *zout, bool zero2)
+                      const double *v, const double *zin, double *zout, bool zero2,
+                      const UpdArgs *upd)
 {
     with_ndiag(d, [&](auto nd, auto sym) {
+        constexpr int ND = decltype(nd)::value;
+        if (zero2 && upd) {
+            // v is upd->rout; the tiled stencils fuse the update, others
+            // take it first on its own
+            if constexpr (kTiled<ND, double>) {
+                if (fp32)
+                    k_pcg_update_sweep2<MSRSB_DIA_ARGS(nd, sym), float, double>
+                        <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, zout, *upd);
+                else
+                    k_pcg_update_sweep2<MSRSB_DIA_ARGS(nd, sym), double, double>
+                        <<<grid_for(n), kBlock, 0, s>>>(n, d, a64, dinv64, zout, *upd);
+                return;
+            }
+            launch_pcg_update(s, n, *upd);
+        }
         if (zero2) {
             if (fp32)
                 k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float>
@@ -1254,11 +1337,23 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
                          const float *dinv32, const double *v, float *z1, float *tmp, int nc,
                          const int *rrp, const int *rci, const uint16_t *roff16,
                          const int *rbase, const float *r32, double *vc,
-                         const RestrictBoxes &boxes)
+                         const RestrictBoxes &boxes, const UpdArgs *upd)
 {
     with_ndiag(d, [&](auto nd, auto sym) {
-        k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float, float><<<grid_for(n), kBlock, 0, s>>>(
-            n, d, a32, dinv32, v, z1);
+        constexpr int ND = decltype(nd)::value;
+        bool fused = false;
+        if constexpr (kTiled<ND, double>) {
+            if (upd) {
+                k_pcg_update_sweep2<MSRSB_DIA_ARGS(nd, sym), float, float>
+                    <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, z1, *upd);
+                fused = true;
+            }
+        }
+        if (!fused) {
+            if (upd) launch_pcg_update(s, n, *upd);
+            k_dia_sweep2_zero<MSRSB_DIA_ARGS(nd, sym), float, float>
+                <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, dinv32, v, z1);
+        }
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
@@ -1327,10 +1422,9 @@ void launch_pcg_p_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *
     k_fin_alpha<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
 
-void launch_pcg_update(hipStream_t s, int n, double *x, double *r, const double *p,
-                       const double *q, double *part_rr, double *scal)
+void launch_pcg_update(hipStream_t s, int n, const UpdArgs &u)
 {
-    k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, x, r, p, q, part_rr, scal);
+    k_pcg_update<<<grid_for(n), kBlock, 0, s>>>(n, u.x, u.rin, u.rout, u.p, u.q, u.part, u.scal);
 }
 
 template <typename T>

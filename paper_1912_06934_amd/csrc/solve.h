@@ -18,8 +18,9 @@ struct PcgDots {
 
 msrsb_status ensure_workspace(msrsb_ctx *c);
 msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans);
+// With upd, v is first produced by the PCG update upd (upd->rout == v).
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
-                     bool trans, const PcgDots *dots);
+                     bool trans, const PcgDots *dots, const UpdArgs *upd = nullptr);
 msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
                  msrsb_solve_info *info, bool trans);
 msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,

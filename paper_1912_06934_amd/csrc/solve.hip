@@ -298,7 +298,7 @@ static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
 }
 
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
-                     bool trans, const PcgDots *dots)
+                     bool trans, const PcgDots *dots, const UpdArgs *upd)
 {
     hipStream_t s = c->stream;
     const int n = c->n;
@@ -315,13 +315,18 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     double *z = c->w[8], *spare = c->w[9], *tmp = c->w[10];
     // precision form inside PCG with two Jacobi-type sweeps on each side of a
     // stencil operator: FP32 intermediate vectors (launch_prec_f32_*)
-    if (fp32 && dots && o->use_multiscale && op.d.n > 0 && c->pcol16 && c->p_is32 &&
-        (c->pw == 4 || c->pw == 8) && is_diag(pre_k) && pre_n == 2 && pre_k == post_k &&
-        post_n == 2) {
+    const bool f32_path = fp32 && dots && o->use_multiscale && op.d.n > 0 && c->pcol16 &&
+                          c->p_is32 && (c->pw == 4 || c->pw == 8) && is_diag(pre_k) &&
+                          pre_n == 2 && pre_k == post_k && post_n == 2;
+    const bool sweep2 = pre_n >= 2 && is_diag(pre_k) && op.d.n > 0;
+    // the PCG update that produces v: inside the first two-sweep kernel, or
+    // on its own where the application starts otherwise
+    if (upd && !f32_path && !sweep2) launch_pcg_update(s, n, *upd);
+    if (f32_path) {
         const float *dinv = pre_k == MSRSB_SMOOTH_L1JACOBI ? op.dl132 : op.dj32;
         float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
         launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci,
-                            c->roff16, c->rbase, c->r32, c->vc, restrict_boxes(c));
+                            c->roff16, c->rbase, c->r32, c->vc, restrict_boxes(c), upd);
         coarse_apply(c, trans);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
                              c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
@@ -330,10 +335,10 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     }
     bool zero = true;
     int t = 0;
-    if (pre_n >= 2 && is_diag(pre_k) && op.d.n > 0) {
+    if (sweep2) {
         const bool l1 = pre_k == MSRSB_SMOOTH_L1JACOBI;
         launch_dia_sweep(s, n, op.d, fp32, op.ad, op.ad32, l1 ? op.dl1 : op.dj,
-                         l1 ? op.dl132 : op.dj32, v, nullptr, z, true);
+                         l1 ? op.dl132 : op.dj32, v, nullptr, z, true, upd);
         zero = false;
         t = 2;
     }
@@ -417,8 +422,10 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
     hipStream_t s = c->stream;
     const int n = c->n;
     const Op op = fine_op(c, trans);
+    // r and p each alternate between two buffers: the kernels that update
+    // them read the old values at neighbouring rows
     double *r = c->w[0], *z = c->w[1], *zold = c->w[2], *p = c->w[3], *q = c->w[4],
-           *p2 = c->w[7];
+           *p2 = c->w[7], *r2 = c->w[12];
     double *sc = c->scal;
     launch_fill(s, S_COUNT, sc, 0.0);
     launch_dot(s, n, f, f, c->partials, sc + S_FF);
@@ -457,15 +464,17 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             std::swap(p, p2);
         }
         ++it;
-        launch_pcg_update(s, n, x, r, p, q, c->partials_rr, sc);
-        // queue the next preconditioner application, and the next step's
-        // p = z + beta p, q = A p (neither touches x or r, so the work is
-        // merely dropped if this step turns out to be the last), while the
-        // host waits for r.r
+        // x += alpha p and r2 = r - alpha q (inside the preconditioner's first
+        // kernel where it can be), the next preconditioner application and
+        // the next step's p = z + beta p, q = A p, all queued while the host
+        // waits for r.r (the last two touch neither x nor r, so their work is
+        // merely dropped if this step turns out to be the last)
+        const UpdArgs upd{x, r, p, q, r2, c->partials_rr, sc};
+        std::swap(r, r2);
         std::swap(z, zold);
         dots.zold = zold;
         dots.tag = it;
-        apply_two_stage(c, o, r, z, trans, &dots);
+        apply_two_stage(c, o, r, z, trans, &dots, &upd);
         queued = it < o->max_iter;
         if (queued) {
             launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
