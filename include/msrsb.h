@@ -144,6 +144,10 @@ msrsb_status msrsb_assemble_tpfa(msrsb_ctx *ctx, int32_t dim, const int32_t dims
  * pattern and must contain part[i].  interior[i] != 0 marks rows that count
  * in the convergence measure e_it (rows not on a support edge, Alg. 1).
  * At most 32 entries per row.
+ * When the matrix came from msrsb_assemble_tpfa and every support is a box
+ * of grid cells whose pattern rows are products of per-axis coarse nodes,
+ * the restriction and prolongation form their column indices from the grid
+ * instead of loading them (checked for every row here; results unchanged).
  * Errors: E_ARG for nc < 1 or nc > 4096, empty rows, unsorted or
  * out-of-range columns, part[i] not in row i's pattern. */
 msrsb_status msrsb_set_coarse(msrsb_ctx *ctx, int32_t nc, const int32_t *part,
