@@ -469,6 +469,11 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
     st = o->krylov == MSRSB_KRYLOV_PCG ? pcg(c, df, dx, o, info, trans)
                                        : gmres(c, df, dx, o, info, trans);
     phase_end(c, ph);
+    // a device that stopped reporting (see wait_mailbox) is not waited for
+    if (st == MSRSB_E_HIP) {
+        const std::string why = c->err.empty() ? "solve failed on the device" : c->err;
+        return fail(c, st, why);
+    }
     if (where == MSRSB_HOST) hipMemcpyAsync(u, dx, bytes, hipMemcpyDeviceToHost, c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, MSRSB_E_HIP, "solve failed on the device");

@@ -386,11 +386,17 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
 // stream query puts a marker into the stream, and the barrier behind it
 // leaves the device idle for several microseconds.  After a second without
 // the tag the stream is queried, and if it has finished or failed without
-// the tag arriving the wait reports failure instead of spinning on.
+// the tag arriving the wait reports failure instead of spinning on.  One
+// Krylov step takes milliseconds at most, so a tag still missing after
+// kMailboxDeadline means the device is stuck: the wait gives up with an
+// error rather than holding the host forever.
+constexpr auto kMailboxDeadline = std::chrono::seconds(120);
+
 static bool wait_mailbox(hipStream_t s, volatile double *mb, int tag)
 {
     const double want = tag;
-    auto t0 = std::chrono::steady_clock::now();
+    const auto start = std::chrono::steady_clock::now();
+    auto t0 = start;
     for (unsigned spin = 1;; ++spin) {
         if (mb[2] == want) break;
         if ((spin & 0xFFFFu) == 0 &&
@@ -400,6 +406,7 @@ static bool wait_mailbox(hipStream_t s, volatile double *mb, int tag)
                 return false;
             }
             t0 = std::chrono::steady_clock::now();
+            if (t0 - start > kMailboxDeadline) return false;
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);
@@ -480,7 +487,10 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
             std::swap(p, p2);
         }
-        if (!wait_mailbox(s, hmon, it)) { rc = MSRSB_E_HIP; break; }
+        if (!wait_mailbox(s, hmon, it)) {
+            c->err = "the device did not report the residual of a Krylov step";
+            return MSRSB_E_HIP;
+        }
         const double rr = hmon[0], brk = hmon[1];
         if (hist && it < hcap) hist[it] = std::sqrt(rr) / fn;
         if (brk != 0.0 || !std::isfinite(rr)) { rc = MSRSB_E_BREAKDOWN; break; }

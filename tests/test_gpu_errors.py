@@ -117,7 +117,7 @@ def test_basis_divergence_is_reported(lib):
     # bound until it overflows; the filtered one stays a partition of unity
     from synth.mpfa import perturbed_nodes, mpfa_o
     import synth
-    X = perturbed_nodes((9, 9), np.random.default_rng(0), 0.4, lengths=(1.0, 10.0))
+    X = perturbed_nodes((9, 9), np.random.default_rng(0), 0.2, lengths=(1.0, 10.0))
     rp, ci, a = mpfa_o(X, np.eye(2)[None].repeat(81, 0))
     sup = synth.cell_supports((9, 9), 3)
     s = Msrsb()

@@ -310,6 +310,66 @@ def test_ilu0_exact_on_tridiagonal():
 
 
 # --------------------------------------------------------------------------
+# smoother sweeps of Alg. 4 against dense algebra: z += M^{-1} (v - A z)
+# --------------------------------------------------------------------------
+
+def _smoother_only(M):
+    """The oracle's preconditioner on M with one coarse block (its coarse
+    stage is switched off below, so only the sweeps act)."""
+    n = M.shape[0]
+    m = oracle.Msrsb(M.indptr, M.indices, M.data)
+    part = np.zeros(n, np.int32)
+    m.set_coarse(1, part, np.arange(n + 1, dtype=np.int32), part, np.ones(n, np.uint8))
+    m.setup_basis(kmax=1)
+    m.build_coarse()
+    return m
+
+
+def _dense_sweeps(A, v, solve_m, pre, post):
+    z = np.zeros_like(v)
+    for _ in range(pre + post):
+        z = z + solve_m(v - A @ z)
+    return z
+
+
+@pytest.mark.parametrize("pre,post", [(1, 0), (3, 0), (2, 1), (0, 2)])
+def test_l1_jacobi_sweeps_match_dense(pre, post):
+    # l1-Jacobi: M = diag(sum_j |A_ij|) (Sec. 4.2, two sweeps each side);
+    # a non-symmetric operator with negative off-diagonals, so sum_j A_ij,
+    # A_ii + sum_{j != i} |A_ij| / 2 and sum_j |A_ij| all differ
+    M = random_non_m(70, seed=21, density=0.15)
+    A = M.toarray()
+    assert np.abs(A - A.T).max() > 0.1
+    v = np.random.default_rng(5).standard_normal(70)
+    d = np.abs(A).sum(axis=1)
+    ref = _dense_sweeps(A, v, lambda r: r / d, pre, post)
+    z = _smoother_only(M).apply(v, pre=(2, pre), post=(2, post), use_ms=False)
+    np.testing.assert_allclose(z, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("pre,post", [(1, 0), (0, 1), (2, 2)])
+def test_ilu0_sweeps_match_dense(pre, post):
+    # ILU(0) as the second stage (Sec. 3.2): z += U^{-1} L^{-1} (v - A z) with
+    # the factors of the pinned natural-order ILU(0), applied as dense
+    # triangular solves (L first); the operator is non-symmetric and not an
+    # M-matrix, so U^{-1} L^{-1} and L^{-1} U^{-1} differ
+    M = random_non_m(60, seed=23, density=0.12)
+    A = M.toarray()
+    F = csr(M.indptr, M.indices, oracle.ilu0(M.indptr, M.indices, M.data)).toarray()
+    L = np.tril(F, -1) + np.eye(60)
+    U = np.triu(F)
+    v = np.random.default_rng(6).standard_normal(60)
+    ref = _dense_sweeps(A, v, lambda r: np.linalg.solve(U, np.linalg.solve(L, r)), pre, post)
+    # (one sweep in the wrong order differs visibly; more sweeps of either
+    # order approach A^{-1} v)
+    one = np.linalg.solve(U, np.linalg.solve(L, v))
+    swapped = np.linalg.solve(L, np.linalg.solve(U, v))
+    assert np.abs(swapped - one).max() > 1e-3 * np.abs(one).max()
+    z = _smoother_only(M).apply(v, pre=(3, pre), post=(3, post), use_ms=False)
+    np.testing.assert_allclose(z, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
 # solves: Alg. 4 inside PCG / GMRES against dense direct solves
 # --------------------------------------------------------------------------
 
