@@ -35,7 +35,9 @@
  *   setup_basis -> build_coarse -> apply / solve.  A call out of order
  *   returns MSRSB_E_STATE.  update_values keeps P and the coarse solver as a
  *   (stale) preconditioner until setup is run again.
- * - One context per host thread; there is no global mutable state.
+ * - One context per host thread.  The only state shared between contexts is
+ *   the static scratch array of msrsb_apply_preconditioner_noalloc (one per
+ *   device, its address looked up once under a lock).
  */
 #ifndef MSRSB_H
 #define MSRSB_H
@@ -233,6 +235,24 @@ typedef struct {
  * use_multiscale == 0). */
 msrsb_status msrsb_apply_preconditioner(msrsb_ctx *ctx, const msrsb_solve_opts *opts,
                                         const double *v, double *z, int where);
+
+/* msrsb_apply_preconditioner for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): z = B v exactly as
+ * msrsb_apply_preconditioner computes it (the same kernels), with v and z
+ * device pointers of n values on the context's device and every temporary in
+ * a static device array of the library (about 11 MB per device, held until
+ * the process ends) instead of the context's workspace.  Nothing is
+ * allocated or freed; the call only queues work on the context's stream and
+ * does not synchronise.
+ * Limits: n <= 262144 rows (E_ARG beyond), and the smoother's data must
+ * already exist (E_STATE otherwise): run msrsb_apply_preconditioner or
+ * msrsb_solve once with the same smoother options first.  All calls on one
+ * device share the array, so calls that overlap in time on one device (two
+ * streams, or two host threads) race; consecutive calls on one stream do
+ * not. */
+msrsb_status msrsb_apply_preconditioner_noalloc(msrsb_ctx *ctx, const msrsb_solve_opts *opts,
+                                                const double *v, double *z);
 
 /* Solve A u = f (n values) with the preconditioned Krylov method; u holds
  * the initial guess on entry and the solution on exit.  PCG uses the

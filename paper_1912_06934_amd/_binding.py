@@ -81,6 +81,7 @@ SIGNATURES = [
     ("msrsb_build_coarse", _ST, [_P, C.POINTER(CoarseOpts)]),
     ("msrsb_get_coarse_matrix", _ST, [_P, _P, C.c_int]),
     ("msrsb_apply_preconditioner", _ST, [_P, C.POINTER(SolveOpts), _P, _P, C.c_int]),
+    ("msrsb_apply_preconditioner_noalloc", _ST, [_P, C.POINTER(SolveOpts), _P, _P]),
     ("msrsb_solve", _ST, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_int]),
     ("msrsb_solve_transpose", _ST,
      [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_int]),
@@ -295,6 +296,18 @@ class Msrsb:
                                                          _where(w0, w1)), "apply")
         if isinstance(z, np.ndarray) and z is not k1:
             z[...] = k1
+        return z
+
+    def apply_noalloc(self, v, z, **kw):
+        """msrsb_apply_preconditioner_noalloc: v and z are device tensors; the
+        call only queues work on the context's stream."""
+        o = self.solve_opts(**kw)
+        pv, w0, k0 = _ptr(v, np.float64)
+        pz, w1, k1 = _ptr(z, np.float64)
+        if _where(w0, w1) != DEVICE:
+            raise ValueError("apply_noalloc takes device tensors")
+        self._check(self._lib.msrsb_apply_preconditioner_noalloc(self._h, C.byref(o), pv, pz),
+                    "apply_noalloc")
         return z
 
     def _solve(self, fn, what, f, u, history_cap=0, **kw):

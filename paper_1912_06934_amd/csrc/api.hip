@@ -508,6 +508,9 @@ msrsb_status msrsb_create(msrsb_ctx **out, int device, void *hip_stream)
         delete c;
         return MSRSB_E_NOMEM;
     }
+    // the device address of the allocation-free apply's scratch array (once
+    // per device; a failure only disables that entry point)
+    c->scratch = static_scratch_init(device);
     *out = c;
     return MSRSB_OK;
 }

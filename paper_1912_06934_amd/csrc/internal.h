@@ -18,6 +18,7 @@ constexpr int kReduceBlocks = 1024;   // partial-sum slots of two-stage reductio
 constexpr int kMaxCoarseNeighbours = 96;  // LDS slots per coarse row in R A P
 constexpr int kMaxDiag = 32;          // most diagonals of a DIA operator
 constexpr int kMapWidth = 8;          // P rows up to this width use slot maps
+constexpr int kNoAllocMaxN = 1 << 18; // most rows of msrsb_apply_preconditioner_noalloc
 
 // Offsets of a diagonal (DIA) operator, passed to kernels by value.
 struct DiaOffsets {
@@ -203,6 +204,9 @@ struct msrsb_ctx {
     double *qk0 = nullptr;       // element stiffness for E = 1, (dim 2^dim)^2
     double *qlogE = nullptr;     // log E per element
     uint8_t *qfixed = nullptr;   // Dirichlet flag per dof (null: none)
+
+    // device address of this device's static scratch array (noalloc.hip)
+    double *scratch = nullptr;
 
     // timings
     hipEvent_t ev_start[MSRSB_N_PHASES] = {}, ev_stop[MSRSB_N_PHASES] = {};
@@ -421,6 +425,9 @@ void launch_multi_axpy(hipStream_t s, int n, int k, const double *V, int64_t ldv
                        const double *h, double *w, double sign);
 void launch_norm_scale(hipStream_t s, int n, const double *w, double *vout, double *partials,
                        double *out_norm);
+
+// ---- static scratch of the allocation-free apply (noalloc.hip) ----
+double *static_scratch_init(int device);
 
 // ---- ILU(0) (k_ilu.hip) ----
 msrsb_status ilu0_setup(msrsb_ctx *c);

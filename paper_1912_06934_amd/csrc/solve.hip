@@ -265,12 +265,25 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
 // well, fused into the last sweep when possible.
 // wc = A_c^{-1} vc (A_c^{-T} for trans): the SPD path's symmetric inverse
 // from its packed lower tiles, otherwise the dense product
-static void coarse_apply(msrsb_ctx *c, bool trans)
+static void coarse_apply(msrsb_ctx *c, bool trans, const ApplyBufs &b)
 {
     if (c->acinv_sym)
-        launch_symv_packed(c->stream, c->nc, c->acinv_pk, c->vc, c->wc, c->symv_part);
+        launch_symv_packed(c->stream, c->nc, c->acinv_pk, b.vc, b.wc, c->symv_part);
     else
-        launch_gemv(c->stream, c->nc, c->acinv, c->vc, c->wc, trans, c->partials);
+        launch_gemv(c->stream, c->nc, c->acinv, b.vc, b.wc, trans, b.part);
+}
+
+ApplyBufs ctx_apply_bufs(msrsb_ctx *c)
+{
+    ApplyBufs b;
+    b.z = c->w[8];
+    b.spare = c->w[9];
+    b.tmp = c->w[10];
+    for (int k = 0; k < 3; ++k) b.f[k] = c->wf[k];
+    b.vc = c->vc;
+    b.wc = c->wc;
+    b.part = c->partials;
+    return b;
 }
 
 static ProlongAxes prolong_axes(const msrsb_ctx *c)
@@ -298,8 +311,9 @@ static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
 }
 
 void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, double *zout,
-                     bool trans, const PcgDots *dots, const UpdArgs *upd)
+                     bool trans, const PcgDots *dots, const UpdArgs *upd, const ApplyBufs *bufs)
 {
+    const ApplyBufs b = bufs ? *bufs : ctx_apply_bufs(c);
     hipStream_t s = c->stream;
     const int n = c->n;
     const Op op = fine_op(c, trans);
@@ -312,7 +326,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     }
     if (pre_k == MSRSB_SMOOTH_NONE) pre_n = 0;
     if (post_k == MSRSB_SMOOTH_NONE) post_n = 0;
-    double *z = c->w[8], *spare = c->w[9], *tmp = c->w[10];
+    double *z = b.z, *spare = b.spare, *tmp = b.tmp;
     // precision form inside PCG with two Jacobi-type sweeps on each side of a
     // stencil operator: FP32 intermediate vectors (launch_prec_f32_*)
     const bool f32_path = fp32 && dots && o->use_multiscale && op.d.n > 0 && c->pcol16 &&
@@ -324,12 +338,12 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
     if (upd && !f32_path && !sweep2) launch_pcg_update(s, n, *upd);
     if (f32_path) {
         const float *dinv = pre_k == MSRSB_SMOOTH_L1JACOBI ? op.dl132 : op.dj32;
-        float *z1 = c->wf[0], *z2 = c->wf[1], *tf = c->wf[2];
+        float *z1 = b.f[0], *z2 = b.f[1], *tf = b.f[2];
         launch_prec_f32_pre(s, n, op.d, op.ad32, dinv, v, z1, tf, c->nc, c->rrp, c->rci,
-                            c->roff16, c->rbase, c->r32, c->vc, restrict_boxes(c), upd);
-        coarse_apply(c, trans);
+                            c->roff16, c->rbase, c->r32, b.vc, restrict_boxes(c), upd);
+        coarse_apply(c, trans, b);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
-                             c->p32[c->pcur], c->wc, zout, dots->zold, dots->part, dots->scal,
+                             c->p32[c->pcur], b.wc, zout, dots->zold, dots->part, dots->scal,
                              dots->part_rr, dots->host_out, dots->tag, prolong_axes(c));
         return;
     }
@@ -353,10 +367,10 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
             res = tmp;
         }
         launch_restrict(s, c->nc, c->rrp, c->rci, c->roff16, c->rbase, c->p_is32, c->r64, c->r32,
-                        res, c->vc, restrict_boxes(c));
-        coarse_apply(c, trans);
+                        res, b.vc, restrict_boxes(c));
+        coarse_apply(c, trans, b);
         launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
-                           c->wc, z, zero, prolong_axes(c));
+                           b.wc, z, zero, prolong_axes(c));
         zero = false;
     }
     for (t = 0; t < post_n; ++t) {
