@@ -16,7 +16,9 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_ARG, E_SING, E_BREAK, E_NOCONV = 0, -1, -6, -7, -8
-SMOOTHERS = {"none": 0, "jacobi": 1, "l1jacobi": 2, "ilu0": 3}
+SMOOTHERS = {"none": 0, "jacobi": 1, "l1jacobi": 2, "ilu0": 3, "sgs": 4, "ic0": 5}
+ORDERINGS = {"natural": 0, "multicolor": 1}
+RESTRICTIONS = {"galerkin": 0, "msfv": 1}
 
 
 def build(force=True):
@@ -53,7 +55,8 @@ class Prec(C.Structure):
                 ("prp", _P), ("pci", _P), ("pv", _P), ("lu", _P), ("piv", _P),
                 ("lu_trans", _I), ("use_ms", _I), ("pre_kind", _I),
                 ("pre_sweeps", _I), ("post_kind", _I), ("post_sweeps", _I),
-                ("ilu", _P)]
+                ("order", _P), ("brp", _P), ("bci", _P), ("ba", _P), ("ilu", _P),
+                ("ic", _P), ("part", _P)]
 
 
 def _declare(L):
@@ -67,6 +70,14 @@ def _declare(L):
     L.orc_lu_solve.argtypes = [_I, _P, _P, _P, _I]
     L.orc_lu_solve.restype = None
     L.orc_ilu0.argtypes = [_I, _P, _P, _P, _P]
+    L.orc_ic0.argtypes = [_I, _P, _P, _P, _P]
+    L.orc_color.argtypes = [_I, _P, _P, _P]
+    L.orc_color_order.argtypes = [_I, _P, _I, _P]
+    L.orc_color_order.restype = None
+    L.orc_permute.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_richardson.argtypes = [C.POINTER(Prec), _P, _P, _D, _I, _P, _P, _P, _I]
+    L.orc_bicgstab.argtypes = [C.POINTER(Prec), _P, _P, _D, _I, _P, _P, _P, _I]
+    L.orc_rap_pg.argtypes = [_I, _P, _P, _P, _I, _P, _P, _P, _P, _P]
     L.orc_apply.argtypes = [C.POINTER(Prec), _P, _P]
     L.orc_pcg.argtypes = [C.POINTER(Prec), _P, _P, _D, _I, _P, _P, _P, _I]
     L.orc_gmres.argtypes = [C.POINTER(Prec), _P, _P, _I, _D, _I, _P, _P, _P, _I]
@@ -178,6 +189,58 @@ def ilu0(rp, ci, a):
     return out
 
 
+def ic0(rp, ci, a):
+    """IC(0) factor L of a symmetric matrix, on its pattern (zeros above the
+    diagonal)."""
+    rp, ci, a = _i32(rp), _i32(ci), _f64(a)
+    out = np.empty_like(a)
+    _check(lib().orc_ic0(rp.size - 1, _p(rp), _p(ci), _p(a), _p(out)), "ic0")
+    return out
+
+
+def color(rp, ci):
+    """First-fit colouring in ascending row order on the symmetrised
+    pattern: (colour per row, number of colours)."""
+    rp, ci = _i32(rp), _i32(ci)
+    col = np.empty(rp.size - 1, dtype=np.int32)
+    nc = lib().orc_color(rp.size - 1, _p(rp), _p(ci), _p(col))
+    if nc < 0:
+        raise OracleError(nc, "color")
+    return col, int(nc)
+
+
+def sweep_order(rp, ci, ordering):
+    """order[k] = k-th row visited by the triangular smoothers."""
+    n = rp.size - 1
+    if ORDERINGS.get(ordering, ordering) == 0:
+        return np.arange(n, dtype=np.int32)
+    col, ncol = color(rp, ci)
+    order = np.empty(n, dtype=np.int32)
+    lib().orc_color_order(n, _p(col), ncol, _p(order))
+    return order
+
+
+def permute(rp, ci, a, order):
+    """B = Q A Q^T for the given order (CSR, columns sorted)."""
+    rp, ci, a, order = _i32(rp), _i32(ci), _f64(a), _i32(order)
+    brp = np.empty_like(rp)
+    bci = np.empty_like(ci)
+    ba = np.empty_like(a)
+    _check(lib().orc_permute(rp.size - 1, _p(rp), _p(ci), _p(a), _p(order), _p(brp), _p(bci),
+                             _p(ba)), "permute")
+    return brp, bci, ba
+
+
+def rap_pg(rp, ci, a, nc, part, prp, pci, pv):
+    """Petrov-Galerkin (MsFV) coarse operator R A P with R the block indicator."""
+    rp, ci, a, part = _i32(rp), _i32(ci), _f64(a), _i32(part)
+    prp, pci, pv = _i32(prp), _i32(pci), _f64(pv)
+    ac = np.empty((nc, nc))
+    _check(lib().orc_rap_pg(rp.size - 1, _p(rp), _p(ci), _p(a), nc, _p(part), _p(prp),
+                            _p(pci), _p(pv), _p(ac)), "rap_pg")
+    return ac
+
+
 def tpfa(dims, h, logk, bc):
     """TPFA matrix (rp, ci, val) and right-hand side for a 2D or 3D grid."""
     dim = len(dims)
@@ -244,8 +307,10 @@ class Msrsb:
         self.n = self.rp.size - 1
         self.bs = block_size
         self.pv = None
-        self._ilu = None
+        self._fact = {}     # (ordering, kind) -> factors of B
+        self._perm = {}     # ordering -> (order, B)
         self._t = None
+        self.restriction = "galerkin"
 
     def set_coarse(self, nc, part, prp, pci, interior):
         self.nc = int(nc)
@@ -262,43 +327,76 @@ class Msrsb:
             kmax, tol, nit)
         return self.pv
 
-    def build_coarse(self):
-        self.ac = rap(self.rp, self.ci, self.a, self.nc, self.prp, self.pci, self.pv)
+    def build_coarse(self, restriction="galerkin"):
+        """Alg. 2: R = P^T (Galerkin) or the block indicator (Petrov-Galerkin,
+        MsFV), A_c = R A P, and its LU."""
+        self.restriction = restriction
+        if restriction == "galerkin":
+            self.ac = rap(self.rp, self.ci, self.a, self.nc, self.prp, self.pci, self.pv)
+        elif restriction == "msfv":
+            self.ac = rap_pg(self.rp, self.ci, self.a, self.nc, self.part, self.prp, self.pci,
+                             self.pv)
+        else:
+            raise ValueError(restriction)
         self.lu, self.piv = lu(self.ac)
         return self.ac
 
-    def _prec(self, pre, post, use_ms, transpose=False):
+    def _order(self, ordering):
+        if ordering not in self._perm:
+            order = sweep_order(self.rp, self.ci, ordering)
+            if ORDERINGS.get(ordering, ordering) == 0:
+                self._perm[ordering] = (None, (self.rp, self.ci, self.a))
+            else:
+                self._perm[ordering] = (order, permute(self.rp, self.ci, self.a, order))
+        return self._perm[ordering]
+
+    def _factor(self, ordering, kind):
+        key = (ordering, kind)
+        if key not in self._fact:
+            _, (brp, bci, ba) = self._order(ordering)
+            self._fact[key] = ilu0(brp, bci, ba) if kind == 3 else ic0(brp, bci, ba)
+        return self._fact[key]
+
+    def _prec(self, pre, post, use_ms, transpose=False, ordering="natural"):
         kinds = (pre[0], post[0])
         if transpose:
             if self._t is None:
                 self._t = transpose_csr(self.rp, self.ci, self.a)
             rp, ci, a = self._t
             pre, post = post, pre
+            if self.restriction != "galerkin" and use_ms:
+                raise OracleError(E_ARG, "transposed Petrov-Galerkin preconditioner")
         else:
             rp, ci, a = self.rp, self.ci, self.a
-        ilu = None
-        if 3 in kinds:
+        order, brp, bci, ba, ilu, ic = None, None, None, None, None, None
+        if any(k >= 3 for k in kinds):
             if transpose:
-                raise OracleError(E_ARG, "transposed ILU(0)")
-            if self._ilu is None:
-                self._ilu = ilu0(self.rp, self.ci, self.a)
-            ilu = self._ilu
-        keep = [rp, ci, a, ilu]
+                raise OracleError(E_ARG, "transposed triangular smoother")
+            order, (brp, bci, ba) = self._order(ordering)
+            if 3 in kinds:
+                ilu = self._factor(ordering, 3)
+            if 5 in kinds:
+                ic = self._factor(ordering, 5)
+        part = self.part if self.restriction == "msfv" else None
+        keep = [rp, ci, a, order, brp, bci, ba, ilu, ic, part]
         m = Prec(self.n, _p(rp), _p(ci), _p(a), self.nc, _p(self.prp), _p(self.pci),
                  _p(self.pv), _p(self.lu), _p(self.piv), int(transpose), int(use_ms),
-                 pre[0], pre[1], post[0], post[1], _p(ilu))
+                 pre[0], pre[1], post[0], post[1], _p(order), _p(brp), _p(bci), _p(ba),
+                 _p(ilu), _p(ic), _p(part))
         return m, keep
 
-    def apply(self, v, pre=(0, 0), post=(0, 0), use_ms=True, transpose=False):
-        m, keep = self._prec(pre, post, use_ms, transpose)
+    def apply(self, v, pre=(0, 0), post=(0, 0), use_ms=True, transpose=False,
+              ordering="natural"):
+        m, keep = self._prec(pre, post, use_ms, transpose, ordering)
         z = np.empty(self.n)
         v = _f64(v)
         _check(lib().orc_apply(C.byref(m), _p(v), _p(z)), "apply")
         return z
 
     def solve(self, f, x0=None, krylov="pcg", restart=30, rtol=1e-8, maxit=1000,
-              pre=(0, 0), post=(0, 0), use_ms=True, transpose=False, hist_cap=0):
-        m, keep = self._prec(pre, post, use_ms, transpose)
+              pre=(0, 0), post=(0, 0), use_ms=True, transpose=False, hist_cap=0,
+              ordering="natural"):
+        m, keep = self._prec(pre, post, use_ms, transpose, ordering)
         f = _f64(f)
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         it, tr = C.c_int(), C.c_double()
@@ -309,6 +407,12 @@ class Msrsb:
         elif krylov == "gmres":
             rc = lib().orc_gmres(C.byref(m), _p(f), _p(x), restart, rtol, maxit, C.byref(it),
                                  C.byref(tr), _p(hist), hist_cap)
+        elif krylov == "richardson":
+            rc = lib().orc_richardson(C.byref(m), _p(f), _p(x), rtol, maxit, C.byref(it),
+                                      C.byref(tr), _p(hist), hist_cap)
+        elif krylov == "bicgstab":
+            rc = lib().orc_bicgstab(C.byref(m), _p(f), _p(x), rtol, maxit, C.byref(it),
+                                    C.byref(tr), _p(hist), hist_cap)
         else:
             raise ValueError(krylov)
         return dict(x=x, iters=it.value, true_rel=tr.value, status=rc,

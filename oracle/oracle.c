@@ -388,6 +388,131 @@ int orc_ilu0(int n, const int *rp, const int *ci, const double *a, double *lu)
 }
 
 /* ------------------------------------------------------------------ */
+/* Sweep orders of the triangular smoothers (ILU(0), IC(0), symmetric
+ * Gauss-Seidel).  The paper names the smoothers but not the order in which
+ * they visit the unknowns.  Two orders are used: the natural one, and a
+ * multicolour order in which rows of one colour never couple, so that all
+ * rows of a colour can be processed at once.
+ *
+ * Colouring: first fit in ascending row order on the symmetrised pattern of
+ * A (j is a neighbour of i when A_ij or A_ji is stored, j != i): row i gets
+ * the smallest colour that none of its already coloured neighbours has.
+ * Returns the number of colours. */
+int orc_color(int n, const int *rp, const int *ci, int *color)
+{
+    int64_t nnz = rp[n];
+    /* pattern of A^T */
+    int *trp = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *tci = (int *)malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    int *pos = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *stamp = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    if (!trp || !tci || !pos || !stamp) { free(trp); free(tci); free(pos); free(stamp); return ORC_EARG; }
+    for (int64_t e = 0; e < nnz; ++e) trp[ci[e] + 1]++;
+    for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    for (int i = 0; i < n; ++i) pos[i] = trp[i];
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) tci[pos[ci[e]]++] = i;
+    for (int c = 0; c <= n; ++c) stamp[c] = -1;
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        /* colours taken by neighbours that come before i */
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] < i) stamp[color[ci[e]]] = i;
+        for (int e = trp[i]; e < trp[i + 1]; ++e)
+            if (tci[e] < i) stamp[color[tci[e]]] = i;
+        int c = 0;
+        while (stamp[c] == i) ++c;
+        color[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(trp); free(tci); free(pos); free(stamp);
+    return ncol;
+}
+
+/* The multicolour order: rows sorted by colour, ascending row index within a
+ * colour.  order[k] = the k-th row visited. */
+void orc_color_order(int n, const int *color, int ncol, int *order)
+{
+    int k = 0;
+    for (int c = 0; c < ncol; ++c)
+        for (int i = 0; i < n; ++i)
+            if (color[i] == c) order[k++] = i;
+}
+
+/* B = Q A Q^T for the order: row k of B is row order[k] of A, with every
+ * column j renumbered to its position in the order; columns sorted
+ * ascending.  brp (n+1), bci and ba (nnz) are the caller's. */
+int orc_permute(int n, const int *rp, const int *ci, const double *a, const int *order,
+                int *brp, int *bci, double *ba)
+{
+    int *rank = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!rank) return ORC_EARG;
+    for (int k = 0; k < n; ++k) rank[order[k]] = k;
+    brp[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        int i = order[k], b0 = brp[k];
+        int len = rp[i + 1] - rp[i];
+        for (int t = 0; t < len; ++t) {
+            /* insertion in ascending new column */
+            int col = rank[ci[rp[i] + t]];
+            double v = a[rp[i] + t];
+            int q = b0 + t;
+            while (q > b0 && bci[q - 1] > col) {
+                bci[q] = bci[q - 1];
+                ba[q] = ba[q - 1];
+                --q;
+            }
+            bci[q] = col;
+            ba[q] = v;
+        }
+        brp[k + 1] = b0 + len;
+    }
+    free(rank);
+    return ORC_OK;
+}
+
+/* IC(0): incomplete Cholesky on the lower part of a symmetric A's own
+ * pattern, natural order (the no-fill factorisation of Sec. 4.1 and
+ * Sec. 4.2).  For i ascending and each stored j < i, ascending,
+ *   L_ij = (A_ij - sum_{k < j} L_ik L_jk) / L_jj,
+ * the sum running over the k stored in both rows, then
+ *   L_ii = sqrt(A_ii - sum_{k < i} L_ik^2),
+ * so (L L^T)_ij = A_ij wherever the lower pattern has an entry.  l holds L
+ * on A's pattern (entries above the diagonal are set to zero).  A
+ * non-positive square-root argument is a breakdown (ORC_ESING). */
+int orc_ic0(int n, const int *rp, const int *ci, const double *a, double *l)
+{
+    int64_t nnz = rp[n];
+    for (int64_t e = 0; e < nnz; ++e) l[e] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        int dpos = -1;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (j > i) break;
+            if (j == i) { dpos = e; break; }
+            /* sum over k < j stored in rows i and j (both ascending) */
+            double s = a[e];
+            int p = rp[i], q = rp[j];
+            while (p < e && q < rp[j + 1] && ci[q] < j) {
+                if (ci[p] < ci[q]) ++p;
+                else if (ci[p] > ci[q]) ++q;
+                else { double prod = l[p] * l[q]; s = s - prod; ++p; ++q; }
+            }
+            int jd = -1;
+            for (int f = rp[j]; f < rp[j + 1]; ++f) if (ci[f] == j) jd = f;
+            if (jd < 0) return ORC_EARG;
+            l[e] = s / l[jd];
+        }
+        if (dpos < 0) return ORC_EARG;
+        double s = a[dpos];
+        for (int e = rp[i]; e < dpos; ++e) { double prod = l[e] * l[e]; s = s - prod; }
+        if (!(s > 0.0)) return ORC_ESING;
+        l[dpos] = sqrt(s);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Two-stage preconditioner (Alg. 3 and Alg. 4). */
 typedef struct {
     int n;
@@ -400,9 +525,19 @@ typedef struct {
     const int *piv;
     int lu_trans;             /* solve with A_c^T instead of A_c */
     int use_ms;               /* 0: smoother only (no coarse stage) */
-    int pre_kind, pre_sweeps; /* 0 none, 1 Jacobi, 2 l1-Jacobi, 3 ILU(0) */
+    int pre_kind, pre_sweeps; /* 0 none, 1 Jacobi, 2 l1-Jacobi, 3 ILU(0),
+                                 4 symmetric Gauss-Seidel, 5 IC(0) */
     int post_kind, post_sweeps;
-    const double *ilu;        /* ILU(0) factors on A's pattern when used */
+    /* kinds 3-5 work on B = Q A Q^T in natural order, i.e. on A in the
+     * order `order` (NULL: natural, and then B = A) */
+    const int *order;
+    const int *brp, *bci;
+    const double *ba;
+    const double *ilu;        /* ILU(0) factors of B (kind 3) */
+    const double *ic;         /* IC(0) factor L of B (kind 5) */
+    /* restriction: NULL = Galerkin R = P^T; otherwise the coarse block of
+     * every fine row, and R is the block indicator (Petrov-Galerkin, MsFV) */
+    const int *part;
 } orc_prec;
 
 static void spmv(int n, const int *rp, const int *ci, const double *a,
@@ -416,13 +551,89 @@ static void spmv(int n, const int *rp, const int *ci, const double *a,
     }
 }
 
-/* z += M^{-1} (v - A z) for one sweep of the given smoother */
+/* z += M^{-1} (v - A z) for one sweep of the given smoother.  tmp needs n
+ * doubles, perm 3n (kinds 3-5). */
 static void smooth_sweep(const orc_prec *m, int kind, const double *v,
-                         double *z, double *tmp)
+                         double *z, double *tmp, double *perm)
 {
     int n = m->n;
     const int *rp = m->rp, *ci = m->ci;
     const double *a = m->a;
+    if (kind >= 3) {
+        /* in B's numbering: vb = Q v, zb = Q z */
+        const int *brp = m->order ? m->brp : rp, *bci = m->order ? m->bci : ci;
+        const double *ba = m->order ? m->ba : a;
+        double *vb = perm, *zb = perm + n, *rb = perm + 2 * (size_t)n;
+        for (int k = 0; k < n; ++k) {
+            int i = m->order ? m->order[k] : k;
+            vb[k] = v[i];
+            zb[k] = z[i];
+        }
+        if (kind == 4) {
+            /* symmetric Gauss-Seidel: a forward sweep over the rows, each
+             * row corrected by its own residual with the values already
+             * updated, then the same backwards */
+            for (int pass = 0; pass < 2; ++pass)
+                for (int t = 0; t < n; ++t) {
+                    int k = pass == 0 ? t : n - 1 - t;
+                    double r = vb[k], d = 0.0;
+                    for (int e = brp[k]; e < brp[k + 1]; ++e) {
+                        r = r - ba[e] * zb[bci[e]];
+                        if (bci[e] == k) d = ba[e];
+                    }
+                    zb[k] = zb[k] + r / d;
+                }
+        } else {
+            /* rb = vb - B zb, then the two triangular solves */
+            for (int k = 0; k < n; ++k) {
+                double r = vb[k];
+                for (int e = brp[k]; e < brp[k + 1]; ++e) r = r - ba[e] * zb[bci[e]];
+                rb[k] = r;
+            }
+            if (kind == 3) {
+                /* L y = rb (unit lower), U w = y */
+                for (int k = 0; k < n; ++k) {
+                    double s = rb[k];
+                    for (int e = brp[k]; e < brp[k + 1] && bci[e] < k; ++e)
+                        s = s - m->ilu[e] * rb[bci[e]];
+                    rb[k] = s;
+                }
+                for (int k = n - 1; k >= 0; --k) {
+                    double s = rb[k], d = 0.0;
+                    for (int e = brp[k]; e < brp[k + 1]; ++e) {
+                        if (bci[e] == k) d = m->ilu[e];
+                        else if (bci[e] > k) s = s - m->ilu[e] * rb[bci[e]];
+                    }
+                    rb[k] = s / d;
+                }
+            } else {
+                /* L y = rb, then L^T w = y by columns: w_k = y_k / L_kk,
+                 * then y_j -= L_kj w_k for the stored j < k */
+                const double *L = m->ic;
+                for (int k = 0; k < n; ++k) {
+                    double s = rb[k], d = 0.0;
+                    for (int e = brp[k]; e < brp[k + 1] && bci[e] <= k; ++e) {
+                        if (bci[e] == k) d = L[e];
+                        else s = s - L[e] * rb[bci[e]];
+                    }
+                    rb[k] = s / d;
+                }
+                for (int k = n - 1; k >= 0; --k) {
+                    double d = 0.0;
+                    for (int e = brp[k]; e < brp[k + 1] && bci[e] <= k; ++e)
+                        if (bci[e] == k) d = L[e];
+                    rb[k] = rb[k] / d;
+                    for (int e = brp[k]; e < brp[k + 1] && bci[e] < k; ++e) {
+                        double prod = L[e] * rb[k];
+                        rb[bci[e]] = rb[bci[e]] - prod;
+                    }
+                }
+            }
+            for (int k = 0; k < n; ++k) zb[k] = zb[k] + rb[k];
+        }
+        for (int k = 0; k < n; ++k) z[m->order ? m->order[k] : k] = zb[k];
+        return;
+    }
     spmv(n, rp, ci, a, z, tmp);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) tmp[i] = v[i] - tmp[i];
@@ -436,40 +647,30 @@ static void smooth_sweep(const orc_prec *m, int kind, const double *v,
             }
             z[i] = z[i] + tmp[i] / d;
         }
-    } else if (kind == 3) {
-        /* forward: L y = res (unit lower), backward: U w = y */
-        for (int i = 0; i < n; ++i) {
-            double s = tmp[i];
-            for (int e = rp[i]; e < rp[i + 1] && ci[e] < i; ++e) s = s - m->ilu[e] * tmp[ci[e]];
-            tmp[i] = s;
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = tmp[i], d = 0.0;
-            for (int e = rp[i]; e < rp[i + 1]; ++e) {
-                if (ci[e] == i) d = m->ilu[e];
-                else if (ci[e] > i) s = s - m->ilu[e] * tmp[ci[e]];
-            }
-            tmp[i] = s / d;
-        }
-        for (int i = 0; i < n; ++i) z[i] = z[i] + tmp[i];
     }
 }
 
-/* z = B v, Alg. 4: z = 0; pre-smoothing; z += P A_c^{-1} P^T (v - A z);
- * post-smoothing.  work needs 2n + nc doubles. */
+/* z = B v, Alg. 4: z = 0; pre-smoothing; z += P A_c^{-1} R (v - A z);
+ * post-smoothing.  work needs PREC_WORK(n, nc) doubles. */
+#define PREC_WORK(n, nc) (5 * (size_t)(n) + (size_t)(nc) + 1)
 static void prec_apply(const orc_prec *m, const double *v, double *z, double *work)
 {
     int n = m->n;
-    double *tmp = work, *res = work + n, *vc = work + 2 * (size_t)n;
+    double *tmp = work, *res = work + n, *perm = work + 2 * (size_t)n,
+           *vc = work + 5 * (size_t)n;
     for (int i = 0; i < n; ++i) z[i] = 0.0;
-    for (int s = 0; s < m->pre_sweeps; ++s) smooth_sweep(m, m->pre_kind, v, z, tmp);
+    for (int s = 0; s < m->pre_sweeps; ++s) smooth_sweep(m, m->pre_kind, v, z, tmp, perm);
     if (m->use_ms) {
         spmv(n, m->rp, m->ci, m->a, z, res);
         for (int i = 0; i < n; ++i) res[i] = v[i] - res[i];
         for (int j = 0; j < m->nc; ++j) vc[j] = 0.0;
-        for (int i = 0; i < n; ++i)                       /* v_c = R r, R = P^T */
-            for (int e = m->prp[i]; e < m->prp[i + 1]; ++e)
-                vc[m->pci[e]] = vc[m->pci[e]] + m->pv[e] * res[i];
+        if (m->part) {                                     /* v_c = R r, R = block indicator */
+            for (int i = 0; i < n; ++i) vc[m->part[i]] = vc[m->part[i]] + res[i];
+        } else {                                           /* v_c = R r, R = P^T */
+            for (int i = 0; i < n; ++i)
+                for (int e = m->prp[i]; e < m->prp[i + 1]; ++e)
+                    vc[m->pci[e]] = vc[m->pci[e]] + m->pv[e] * res[i];
+        }
         orc_lu_solve(m->nc, m->lu, m->piv, vc, m->lu_trans); /* w_c = M_c^{-1} v_c */
         for (int i = 0; i < n; ++i) {                      /* z += P w_c */
             double s = 0.0;
@@ -477,12 +678,12 @@ static void prec_apply(const orc_prec *m, const double *v, double *z, double *wo
             z[i] = z[i] + s;
         }
     }
-    for (int s = 0; s < m->post_sweeps; ++s) smooth_sweep(m, m->post_kind, v, z, tmp);
+    for (int s = 0; s < m->post_sweeps; ++s) smooth_sweep(m, m->post_kind, v, z, tmp, perm);
 }
 
 int orc_apply(const orc_prec *m, const double *v, double *z)
 {
-    double *work = (double *)malloc(sizeof(double) * (2 * (size_t)m->n + (size_t)m->nc + 1));
+    double *work = (double *)malloc(sizeof(double) * PREC_WORK(m->n, m->nc));
     if (!work) return ORC_EARG;
     prec_apply(m, v, z, work);
     free(work);
@@ -514,7 +715,7 @@ int orc_pcg(const orc_prec *m, const double *f, double *x, double rtol,
     double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N),
            *zold = malloc(sizeof(double) * N), *p = malloc(sizeof(double) * N),
            *q = malloc(sizeof(double) * N),
-           *work = malloc(sizeof(double) * (2 * N + (size_t)m->nc + 1));
+           *work = malloc(sizeof(double) * PREC_WORK(n, m->nc));
     int rc = ORC_ENOCONV, it = 0;
     double fn = sqrt(dot(n, f, f));
     if (fn == 0.0) fn = 1.0;
@@ -580,7 +781,7 @@ int orc_gmres(const orc_prec *m, const double *f, double *x, int restart,
     double *cs = malloc(sizeof(double) * (size_t)mm), *sn = malloc(sizeof(double) * (size_t)mm);
     double *g = malloc(sizeof(double) * (size_t)(mm + 1)), *y = malloc(sizeof(double) * (size_t)mm);
     double *w = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
-    double *work = malloc(sizeof(double) * (2 * N + (size_t)m->nc + 1));
+    double *work = malloc(sizeof(double) * PREC_WORK(n, m->nc));
     double fn = sqrt(dot(n, f, f));
     if (fn == 0.0) fn = 1.0;
     int it = 0, rc = ORC_ENOCONV;
@@ -651,6 +852,168 @@ int orc_gmres(const orc_prec *m, const double *f, double *x, int restart,
     if (iters) *iters = it;
     free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(z); free(work);
     return rc;
+}
+
+/* Stand-alone (Richardson) iteration with the two-stage preconditioner, the
+ * "non-accelerated stand-alone solver" of Sec. 3.2:
+ *   x_{k+1} = x_k + B (f - A x_k).
+ * Stops when ||f - A x_k|| <= rtol ||f||; iterations count applications of
+ * B.  hist (may be NULL) receives ||f - A x_k|| / ||f|| for k = 0..iters. */
+int orc_richardson(const orc_prec *m, const double *f, double *x, double rtol, int maxit,
+                   int *iters, double *true_rel, double *hist, int hist_cap)
+{
+    int n = m->n;
+    size_t N = (size_t)n;
+    double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N),
+           *work = malloc(sizeof(double) * PREC_WORK(n, m->nc));
+    double fn = sqrt(dot(n, f, f));
+    if (fn == 0.0) fn = 1.0;
+    int it = 0, rc = ORC_ENOCONV;
+    double rr = 0.0;
+    for (;;) {
+        spmv(n, m->rp, m->ci, m->a, x, r);
+        for (int i = 0; i < n; ++i) r[i] = f[i] - r[i];
+        rr = sqrt(dot(n, r, r));
+        if (hist && it < hist_cap) hist[it] = rr / fn;
+        if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
+        if (rr <= rtol * fn) { rc = ORC_OK; break; }
+        if (it >= maxit) break;
+        prec_apply(m, r, z, work);
+        for (int i = 0; i < n; ++i) x[i] = x[i] + z[i];
+        ++it;
+    }
+    if (true_rel) *true_rel = rr / fn;
+    if (iters) *iters = it;
+    free(r); free(z); free(work);
+    return rc;
+}
+
+/* Right-preconditioned BiCGStab (Sec. 4.1: the preconditioner is applied
+ * twice per iteration).  With rhat = r_0, rho = rhat^T r:
+ *   p = r + beta (p - omega v),  beta = (rho_k / rho_{k-1}) (alpha / omega)
+ *   y = B p,  v = A y,  alpha = rho_k / rhat^T v,  s = r - alpha v
+ *   z = B s,  t = A z,  omega = t^T s / t^T t
+ *   x += alpha y + omega z,  r = s - omega t.
+ * An iteration that already meets the tolerance after its first half ends
+ * there (x += alpha y).  Convergence of the recursive residual is confirmed
+ * on the true one; if that is still above the tolerance the iteration starts
+ * again from x.  Iterations count passes of the loop (a half pass counts
+ * one).  hist receives the recursive relative residual per iteration. */
+int orc_bicgstab(const orc_prec *m, const double *f, double *x, double rtol, int maxit,
+                 int *iters, double *true_rel, double *hist, int hist_cap)
+{
+    int n = m->n;
+    size_t N = (size_t)n;
+    double *r = malloc(sizeof(double) * N), *rh = malloc(sizeof(double) * N),
+           *p = malloc(sizeof(double) * N), *v = malloc(sizeof(double) * N),
+           *y = malloc(sizeof(double) * N), *sv = malloc(sizeof(double) * N),
+           *z = malloc(sizeof(double) * N), *t = malloc(sizeof(double) * N),
+           *work = malloc(sizeof(double) * PREC_WORK(n, m->nc));
+    double fn = sqrt(dot(n, f, f));
+    if (fn == 0.0) fn = 1.0;
+    int it = 0, rc = ORC_ENOCONV, restart = 1;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    while (it <= maxit) {
+        if (restart) {
+            spmv(n, m->rp, m->ci, m->a, x, r);
+            for (int i = 0; i < n; ++i) r[i] = f[i] - r[i];
+            double rr = sqrt(dot(n, r, r));
+            if (hist && it < hist_cap) hist[it] = rr / fn;
+            if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
+            if (rr <= rtol * fn) { rc = ORC_OK; break; }
+            if (it >= maxit) break;
+            for (int i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = r[i]; v[i] = 0.0; }
+            rho = dot(n, rh, r);
+            restart = 0;
+        } else {
+            double rho_new = dot(n, rh, r);
+            if (rho_new == 0.0 || !is_finite(rho_new)) { rc = ORC_EBREAK; break; }
+            double beta = (rho_new / rho) * (alpha / omega);
+            for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            rho = rho_new;
+        }
+        prec_apply(m, p, y, work);
+        spmv(n, m->rp, m->ci, m->a, y, v);
+        double sig = dot(n, rh, v);
+        if (sig == 0.0 || !is_finite(sig)) { rc = ORC_EBREAK; break; }
+        alpha = rho / sig;
+        for (int i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
+        ++it;
+        double ss = sqrt(dot(n, sv, sv));
+        if (ss <= rtol * fn) {
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * y[i];
+            if (hist && it < hist_cap) hist[it] = ss / fn;
+            restart = 1;
+            continue;
+        }
+        prec_apply(m, sv, z, work);
+        spmv(n, m->rp, m->ci, m->a, z, t);
+        double tt = dot(n, t, t);
+        if (tt == 0.0 || !is_finite(tt)) { rc = ORC_EBREAK; break; }
+        omega = dot(n, t, sv) / tt;
+        for (int i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * y[i] + omega * z[i];
+            r[i] = sv[i] - omega * t[i];
+        }
+        double rr = sqrt(dot(n, r, r));
+        if (hist && it < hist_cap) hist[it] = rr / fn;
+        if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
+        if (rr <= rtol * fn) { restart = 1; continue; }
+        if (omega == 0.0) { rc = ORC_EBREAK; break; }
+        if (it >= maxit) break;
+    }
+    spmv(n, m->rp, m->ci, m->a, x, r);
+    for (int i = 0; i < n; ++i) r[i] = f[i] - r[i];
+    if (true_rel) *true_rel = sqrt(dot(n, r, r)) / fn;
+    if (iters) *iters = it;
+    free(r); free(rh); free(p); free(v); free(y); free(sv); free(z); free(t); free(work);
+    return rc;
+}
+
+/* Petrov-Galerkin coarse operator of the MsFV kind (Sec. 2: the rows of R
+ * make the coarse problem conserve mass over every coarse block; Alg. 2's
+ * Petrov-Galerkin branch): R_ji = 1 when fine row i lies in coarse block j
+ * (part[i] = j), else 0, so
+ *   Ac[j,l] = sum_{i : part(i) = j} sum_k A_ik P_kl,
+ * i ascending and k ascending, with the full, unfiltered A.  Dense,
+ * row-major, nc x nc. */
+int orc_rap_pg(int n, const int *rp, const int *ci, const double *a, int nc,
+               const int *part, const int *prp, const int *pci, const double *pv,
+               double *ac)
+{
+    for (int i = 0; i < n; ++i)
+        if (part[i] < 0 || part[i] >= nc) return ORC_EARG;
+    memset(ac, 0, sizeof(double) * (size_t)nc * (size_t)nc);
+#pragma omp parallel
+    {
+        double *ap = (double *)calloc((size_t)nc, sizeof(double));
+        int *touched = (int *)malloc(sizeof(int) * (size_t)nc);
+        char *mark = (char *)calloc((size_t)nc, 1);
+#pragma omp for schedule(dynamic, 4)
+        for (int j = 0; j < nc; ++j) {
+            double *row = ac + (size_t)j * nc;
+            for (int i = 0; i < n; ++i) {
+                if (part[i] != j) continue;
+                int nt = 0;
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    int k = ci[e];
+                    for (int q = prp[k]; q < prp[k + 1]; ++q) {
+                        int l = pci[q];
+                        double prod = a[e] * pv[q];
+                        if (!mark[l]) { mark[l] = 1; touched[nt++] = l; ap[l] = 0.0; }
+                        ap[l] = ap[l] + prod;
+                    }
+                }
+                for (int u = 0; u < nt; ++u) {
+                    int l = touched[u];
+                    row[l] = row[l] + ap[l];
+                    mark[l] = 0;
+                }
+            }
+        }
+        free(ap); free(touched); free(mark);
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */
