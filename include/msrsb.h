@@ -64,16 +64,47 @@ typedef enum {
 
 enum { MSRSB_HOST = 0, MSRSB_DEVICE = 1 };
 
-/* Smoothers of the two-stage preconditioner (Alg. 4). */
+/* Smoothers of the two-stage preconditioner (Alg. 4).  The paper uses
+ * Jacobi-type smoothers, ILU(0) and symmetric Gauss-Seidel as the second
+ * stage (Sec. 3.2), and IC(0) and l1-Jacobi in Sec. 4.  One sweep is
+ * z += M^{-1} (v - A z); for SGS, M = (D + L) D^{-1} (D + U), i.e. a forward
+ * and a backward Gauss-Seidel sweep.  ILU(0), IC(0) and SGS visit the rows
+ * in the order msrsb_solve_opts.ordering selects. */
 enum {
     MSRSB_SMOOTH_NONE = 0,
     MSRSB_SMOOTH_JACOBI = 1,     /* M = diag(A) */
     MSRSB_SMOOTH_L1JACOBI = 2,   /* M_ii = sum_j |A_ij| */
-    MSRSB_SMOOTH_ILU0 = 3        /* ILU(0) on A's pattern, natural order */
+    MSRSB_SMOOTH_ILU0 = 3,       /* M = L U, no-fill incomplete LU on A's pattern */
+    MSRSB_SMOOTH_SGS = 4,        /* symmetric Gauss-Seidel */
+    MSRSB_SMOOTH_IC0 = 5         /* M = L L^T, no-fill incomplete Cholesky (symmetric A) */
 };
 
-/* Krylov accelerators. */
-enum { MSRSB_KRYLOV_PCG = 0, MSRSB_KRYLOV_GMRES = 1 };
+/* Sweep orders of ILU(0), IC(0) and SGS (the paper does not fix one).
+ * NATURAL: ascending row index.  MULTICOLOR: first-fit colouring in
+ * ascending row order on the symmetrised pattern of A (row i takes the
+ * smallest colour none of its already coloured neighbours has; j is a
+ * neighbour when A_ij or A_ji is stored), rows visited colour by colour,
+ * ascending within a colour.  Rows of one colour never couple, so each
+ * colour is processed in parallel over the whole GPU; in the natural order
+ * a sweep is limited by the chain of dependencies between rows. */
+enum { MSRSB_ORDER_NATURAL = 0, MSRSB_ORDER_MULTICOLOR = 1 };
+
+/* Krylov accelerators and the stand-alone iteration (Sec. 3.2: Richardson
+ * x += B (f - A x) and right-preconditioned GMRES; Sec. 4: PCG and BiCGStab). */
+enum {
+    MSRSB_KRYLOV_PCG = 0,
+    MSRSB_KRYLOV_GMRES = 1,
+    MSRSB_KRYLOV_RICHARDSON = 2,
+    MSRSB_KRYLOV_BICGSTAB = 3
+};
+
+/* Restriction operators of Alg. 2. */
+enum {
+    MSRSB_RESTRICT_GALERKIN = 0, /* R = P^T (Sec. 2) */
+    MSRSB_RESTRICT_MSFV = 1      /* Petrov-Galerkin: R_ji = 1 when fine row i lies in
+                                    coarse block j (part[i] = j), else 0, so the coarse
+                                    problem conserves mass block by block (Sec. 2) */
+};
 
 /* Phases reported by msrsb_get_timings (milliseconds, last run of each). */
 enum {
@@ -192,37 +223,44 @@ msrsb_status msrsb_get_prolongation(msrsb_ctx *ctx, int32_t *rowptr, int32_t *co
                                     double *val, int where);
 
 typedef struct {
-    int32_t restriction; /* 0 = Galerkin R = P^T (Sec. 2); nothing else yet */
+    int32_t restriction; /* MSRSB_RESTRICT_GALERKIN or MSRSB_RESTRICT_MSFV */
 } msrsb_coarse_opts;
 
-/* Alg. 2: R = P^T, A_c = R A P with the unfiltered A (eq.
+/* Alg. 2: the restriction R (R = P^T, or the MsFV block indicator; opts may
+ * be NULL for Galerkin), A_c = R A P with the unfiltered A (eq.
  * lin_system_coarse), and the coarse solver M_c^{-1} = A_c^{-1} formed
- * explicitly in FP64 (applied as a dense product).  When A is symmetric
- * A_c is symmetric positive definite for the SPD problems of the paper and
- * the inverse comes from its Cholesky factor, A_c^{-1} = L^{-T} L^{-1} (a
- * band Cholesky, L^{-1} by forward substitution, the product on the FP64
- * matrix cores), kept as its lower 64 x 64 tiles; a non-positive pivot falls
- * back to Gauss-Jordan with partial pivoting, which is also used for
- * non-symmetric A.  Synchronises.
- * Errors: E_STATE before setup_basis; E_COARSE_SINGULAR on a zero pivot
- * (pivoting form). */
+ * explicitly in FP64 (applied as a dense product).  With the Galerkin
+ * restriction and symmetric A, A_c is symmetric positive definite for the
+ * SPD problems of the paper and the inverse comes from its Cholesky factor,
+ * A_c^{-1} = L^{-T} L^{-1} (a band Cholesky, L^{-1} by forward
+ * substitution, the product on the FP64 matrix cores), kept as its lower
+ * 64 x 64 tiles; a non-positive pivot falls back to Gauss-Jordan with
+ * partial pivoting, which is also used for non-symmetric A and for the MsFV
+ * restriction (whose A_c is not symmetric).  Synchronises.
+ * Errors: E_STATE before setup_basis; E_ARG for an unknown restriction;
+ * E_COARSE_SINGULAR on a zero pivot (pivoting form). */
 msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);
 /* Copy A_c out as a dense row-major nc x nc FP64 matrix. */
 msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *ctx, double *dense, int where);
 
 typedef struct {
-    int32_t krylov;          /* MSRSB_KRYLOV_PCG or MSRSB_KRYLOV_GMRES */
+    int32_t krylov;          /* MSRSB_KRYLOV_* */
     int32_t restart;         /* GMRES restart length */
     double rtol;             /* stop at ||f - A u|| <= rtol ||f|| */
     int32_t max_iter;
     int32_t pre_smoother, pre_sweeps;
     int32_t post_smoother, post_sweeps;
-    int32_t fp32_smoother;   /* 1 = smoother matrix values and arithmetic in FP32 */
+    int32_t fp32_smoother;   /* 1 = Jacobi-type smoother values and arithmetic in FP32
+                                (ILU(0), IC(0) and SGS always run in FP64) */
     int32_t use_multiscale;  /* 0 = smoother-only preconditioner */
+    int32_t ordering;        /* MSRSB_ORDER_*: sweep order of ILU(0), IC(0), SGS */
 } msrsb_solve_opts;
 
 typedef struct {
-    int32_t iters;           /* Krylov iterations (products A p / Arnoldi steps) */
+    int32_t iters;           /* iterations: products A p (PCG), Arnoldi steps (GMRES),
+                                applications of B (Richardson), passes of the loop
+                                with two applications of B each (BiCGStab; a pass
+                                that converges after its first half counts one) */
     double true_rel_res;     /* ||f - A u|| / ||f||, recomputed at exit */
     double *history;         /* optional host buffer: relative residual per
                                 iteration (recursive estimate) */
@@ -230,9 +268,10 @@ typedef struct {
 } msrsb_solve_info;
 
 /* z = B v with B the two-stage preconditioner of Alg. 4: z = 0; pre-sweeps
- * z += M_pre^{-1}(v - A z); z += P A_c^{-1} P^T (v - A z) (Alg. 3);
+ * z += M_pre^{-1}(v - A z); z += P A_c^{-1} R (v - A z) (Alg. 3);
  * post-sweeps.  n values each.  Errors: E_STATE before build_coarse (unless
- * use_multiscale == 0). */
+ * use_multiscale == 0); E_ARG for IC(0) on a non-symmetric A;
+ * E_BREAKDOWN when ILU(0) meets a zero pivot or IC(0) a non-positive one. */
 msrsb_status msrsb_apply_preconditioner(msrsb_ctx *ctx, const msrsb_solve_opts *opts,
                                         const double *v, double *z, int where);
 
@@ -254,12 +293,15 @@ msrsb_status msrsb_apply_preconditioner(msrsb_ctx *ctx, const msrsb_solve_opts *
 msrsb_status msrsb_apply_preconditioner_noalloc(msrsb_ctx *ctx, const msrsb_solve_opts *opts,
                                                 const double *v, double *z);
 
-/* Solve A u = f (n values) with the preconditioned Krylov method; u holds
- * the initial guess on entry and the solution on exit.  PCG uses the
- * flexible Polak-Ribiere beta.  Convergence is tested on the recursive
- * residual and confirmed on the true residual.  Synchronises; info may be
- * NULL.  Errors: E_BREAKDOWN, E_NOT_CONVERGED (u still holds the last
- * iterate and info the achieved residual). */
+/* Solve A u = f (n values) with the preconditioned Krylov method or the
+ * stand-alone iteration; u holds the initial guess on entry and the
+ * solution on exit.  PCG uses the flexible Polak-Ribiere beta; GMRES and
+ * BiCGStab are right-preconditioned; Richardson is x += B (f - A x)
+ * (Sec. 3.2), stopped on its true residual.  Convergence of the Krylov
+ * methods is tested on the recursive residual and confirmed on the true
+ * residual.  Synchronises; info may be NULL.  Errors: E_BREAKDOWN,
+ * E_NOT_CONVERGED (u still holds the last iterate and info the achieved
+ * residual). */
 msrsb_status msrsb_solve(msrsb_ctx *ctx, const double *f, double *u,
                          const msrsb_solve_opts *opts, msrsb_solve_info *info,
                          int where);
@@ -269,8 +311,8 @@ msrsb_status msrsb_solve(msrsb_ctx *ctx, const double *f, double *u,
  * residuals, the smoothers built from A^T with the pre and post sweeps
  * exchanged, and the coarse correction P A_c^{-T} P^T (P, R and the coarse
  * inverse are reused).  For symmetric A, and for point Jacobi on any A, this
- * is exactly B^T.  ILU(0) is not available here (E_ARG).  Other arguments and
- * errors as msrsb_solve. */
+ * is exactly B^T.  ILU(0), IC(0), SGS and the MsFV restriction are not
+ * available here (E_ARG).  Other arguments and errors as msrsb_solve. */
 msrsb_status msrsb_solve_transpose(msrsb_ctx *ctx, const double *g, double *lambda,
                                    const msrsb_solve_opts *opts, msrsb_solve_info *info,
                                    int where);

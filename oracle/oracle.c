@@ -898,7 +898,10 @@ int orc_richardson(const orc_prec *m, const double *f, double *x, double rtol, i
  * there (x += alpha y).  Convergence of the recursive residual is confirmed
  * on the true one; if that is still above the tolerance the iteration starts
  * again from x.  Iterations count passes of the loop (a half pass counts
- * one).  hist receives the recursive relative residual per iteration. */
+ * one).  hist receives the recursive relative residual per iteration.
+ * Breakdown: rhat^T r is negligible, |rho_k| <= 1e-14 ||rhat|| ||r||
+ * (rounding keeps an exact zero from showing), or rhat^T v or t^T t is
+ * zero. */
 int orc_bicgstab(const orc_prec *m, const double *f, double *x, double rtol, int maxit,
                  int *iters, double *true_rel, double *hist, int hist_cap)
 {
@@ -912,7 +915,7 @@ int orc_bicgstab(const orc_prec *m, const double *f, double *x, double rtol, int
     double fn = sqrt(dot(n, f, f));
     if (fn == 0.0) fn = 1.0;
     int it = 0, rc = ORC_ENOCONV, restart = 1;
-    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    double rho = 1.0, alpha = 1.0, omega = 1.0, rhn = 0.0, rn = 0.0;
     while (it <= maxit) {
         if (restart) {
             spmv(n, m->rp, m->ci, m->a, x, r);
@@ -924,10 +927,11 @@ int orc_bicgstab(const orc_prec *m, const double *f, double *x, double rtol, int
             if (it >= maxit) break;
             for (int i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = r[i]; v[i] = 0.0; }
             rho = dot(n, rh, r);
+            rhn = rr;
             restart = 0;
         } else {
             double rho_new = dot(n, rh, r);
-            if (rho_new == 0.0 || !is_finite(rho_new)) { rc = ORC_EBREAK; break; }
+            if (!(fabs(rho_new) > 1e-14 * rhn * rn)) { rc = ORC_EBREAK; break; }
             double beta = (rho_new / rho) * (alpha / omega);
             for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
             rho = rho_new;
@@ -956,6 +960,7 @@ int orc_bicgstab(const orc_prec *m, const double *f, double *x, double rtol, int
             r[i] = sv[i] - omega * t[i];
         }
         double rr = sqrt(dot(n, r, r));
+        rn = rr;
         if (hist && it < hist_cap) hist[it] = rr / fn;
         if (!is_finite(rr)) { rc = ORC_EBREAK; break; }
         if (rr <= rtol * fn) { restart = 1; continue; }

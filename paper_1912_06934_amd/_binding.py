@@ -15,8 +15,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsrsb.so")
 
 HOST, DEVICE = 0, 1
-SMOOTH_NONE, SMOOTH_JACOBI, SMOOTH_L1JACOBI, SMOOTH_ILU0 = 0, 1, 2, 3
-KRYLOV_PCG, KRYLOV_GMRES = 0, 1
+SMOOTH_NONE, SMOOTH_JACOBI, SMOOTH_L1JACOBI, SMOOTH_ILU0, SMOOTH_SGS, SMOOTH_IC0 = 0, 1, 2, 3, 4, 5
+KRYLOV_PCG, KRYLOV_GMRES, KRYLOV_RICHARDSON, KRYLOV_BICGSTAB = 0, 1, 2, 3
+KRYLOV = {"pcg": KRYLOV_PCG, "gmres": KRYLOV_GMRES, "richardson": KRYLOV_RICHARDSON,
+          "bicgstab": KRYLOV_BICGSTAB}
+ORDER_NATURAL, ORDER_MULTICOLOR = 0, 1
+ORDERING = {"natural": ORDER_NATURAL, "multicolor": ORDER_MULTICOLOR}
+RESTRICT_GALERKIN, RESTRICT_MSFV = 0, 1
+RESTRICTION = {"galerkin": RESTRICT_GALERKIN, "msfv": RESTRICT_MSFV}
 PHASES = ["filter", "init", "smooth", "rap", "factor", "solve", "solve_t", "grad", "assemble",
           "smoother_setup"]
 
@@ -52,7 +58,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("krylov", C.c_int32), ("restart", C.c_int32), ("rtol", C.c_double),
                 ("max_iter", C.c_int32), ("pre_smoother", C.c_int32), ("pre_sweeps", C.c_int32),
                 ("post_smoother", C.c_int32), ("post_sweeps", C.c_int32),
-                ("fp32_smoother", C.c_int32), ("use_multiscale", C.c_int32)]
+                ("fp32_smoother", C.c_int32), ("use_multiscale", C.c_int32),
+                ("ordering", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -270,8 +277,8 @@ class Msrsb:
             va.ctypes.data_as(C.c_void_p), HOST), "get_prolongation")
         return rp, ci, va
 
-    def build_coarse(self, restriction=0):
-        o = CoarseOpts(restriction)
+    def build_coarse(self, restriction="galerkin"):
+        o = CoarseOpts(RESTRICTION.get(restriction, restriction))
         self._check(self._lib.msrsb_build_coarse(self._h, C.byref(o)), "build_coarse")
 
     def get_coarse_matrix(self):
@@ -283,10 +290,11 @@ class Msrsb:
     # -- apply / solve --
     @staticmethod
     def solve_opts(krylov="pcg", restart=30, rtol=1e-8, max_iter=1000, pre=(0, 0), post=(0, 0),
-                   fp32_smoother=False, use_multiscale=True):
-        k = {"pcg": KRYLOV_PCG, "gmres": KRYLOV_GMRES}[krylov] if isinstance(krylov, str) else krylov
+                   fp32_smoother=False, use_multiscale=True, ordering="natural"):
+        k = KRYLOV[krylov] if isinstance(krylov, str) else krylov
+        od = ORDERING[ordering] if isinstance(ordering, str) else ordering
         return SolveOpts(k, restart, rtol, max_iter, pre[0], pre[1], post[0], post[1],
-                         int(fp32_smoother), int(use_multiscale))
+                         int(fp32_smoother), int(use_multiscale), od)
 
     def apply(self, v, z, **kw):
         o = self.solve_opts(**kw)

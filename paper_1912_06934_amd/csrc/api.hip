@@ -118,11 +118,12 @@ void free_matrix(msrsb_ctx *c)
     c->j_own_pattern = false;
     dfree(c->jv);
     dfree(c->jv32);
-    dfree(c->ilu);
-    dfree(c->ilu_lev_ptr);
-    dfree(c->ilu_lev_rows);
-    dfree(c->ilu_lev_ptr_u);
-    dfree(c->ilu_lev_rows_u);
+    for (int o = 0; o < 2; ++o) {
+        free_tri_order(c->tri[o]);
+        dfree(c->ilu_f[o]);
+        dfree(c->ic_f[o]);
+        c->ilu_ok[o] = c->ic_ok[o] = false;
+    }
     dfree(c->dinv_jac);
     dfree(c->dinv_l1);
     dfree(c->dinv_jac32);
@@ -159,7 +160,6 @@ void free_matrix(msrsb_ctx *c)
     c->at_pattern = false;
     c->smoother_valid = c->smoother32_valid = false;
     c->smoother_t_valid = c->smoother32_t_valid = false;
-    c->ilu_valid = false;
     c->tpfa = false;
 }
 
@@ -289,7 +289,7 @@ msrsb_status refresh_values(msrsb_ctx *c)
     }
     c->smoother_valid = c->smoother32_valid = false;
     c->smoother_t_valid = c->smoother32_t_valid = false;
-    c->ilu_valid = false;
+    c->ilu_ok[0] = c->ilu_ok[1] = c->ic_ok[0] = c->ic_ok[1] = false;
     return MSRSB_OK;
 }
 
@@ -426,11 +426,13 @@ msrsb_status ensure_transpose(msrsb_ctx *c)
 msrsb_status solve_opts_check(msrsb_ctx *c, const msrsb_solve_opts *o)
 {
     if (!o) return fail(c, MSRSB_E_ARG, "solve options are NULL");
-    auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_ILU0; };
+    auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_IC0; };
     if (!sm_ok(o->pre_smoother) || !sm_ok(o->post_smoother) || o->pre_sweeps < 0 ||
         o->post_sweeps < 0 || o->pre_sweeps > 64 || o->post_sweeps > 64)
         return fail(c, MSRSB_E_ARG, "invalid smoother options");
-    if (o->krylov != MSRSB_KRYLOV_PCG && o->krylov != MSRSB_KRYLOV_GMRES)
+    if (o->ordering != MSRSB_ORDER_NATURAL && o->ordering != MSRSB_ORDER_MULTICOLOR)
+        return fail(c, MSRSB_E_ARG, "invalid sweep order");
+    if (o->krylov < MSRSB_KRYLOV_PCG || o->krylov > MSRSB_KRYLOV_BICGSTAB)
         return fail(c, MSRSB_E_ARG, "invalid Krylov method");
     if (!(o->rtol > 0.0) || o->max_iter < 0)
         return fail(c, MSRSB_E_ARG, "rtol must be > 0 and max_iter >= 0");
@@ -452,6 +454,8 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
     if (st) return st;
     st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
+    if (trans && o->use_multiscale && c->restriction != MSRSB_RESTRICT_GALERKIN)
+        return fail(c, MSRSB_E_ARG, "the transposed solve needs the Galerkin restriction");
     if (trans && !c->a_symmetric && (st = ensure_transpose(c))) return st;
     if ((st = ensure_smoother(c, o, trans))) return fail(c, st, c->err.empty() ? "smoother set-up failed" : c->err);
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
@@ -466,8 +470,12 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
     }
     const int ph = trans ? MSRSB_PHASE_SOLVE_T : MSRSB_PHASE_SOLVE;
     phase_begin(c, ph);
-    st = o->krylov == MSRSB_KRYLOV_PCG ? pcg(c, df, dx, o, info, trans)
-                                       : gmres(c, df, dx, o, info, trans);
+    switch (o->krylov) {
+    case MSRSB_KRYLOV_PCG: st = pcg(c, df, dx, o, info, trans); break;
+    case MSRSB_KRYLOV_GMRES: st = gmres(c, df, dx, o, info, trans); break;
+    case MSRSB_KRYLOV_RICHARDSON: st = richardson(c, df, dx, o, info, trans); break;
+    default: st = bicgstab(c, df, dx, o, info, trans); break;
+    }
     phase_end(c, ph);
     // a device that stopped reporting (see wait_mailbox) is not waited for
     if (st == MSRSB_E_HIP) {
@@ -1122,8 +1130,11 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     DeviceGuard g(c->device);
     c->err.clear();
     if (!c->has_basis) return fail(c, MSRSB_E_STATE, "setup_basis must come first");
-    if (o && o->restriction != 0)
-        return fail(c, MSRSB_E_ARG, "only the Galerkin restriction R = P^T is available");
+    const int restriction = o ? o->restriction : MSRSB_RESTRICT_GALERKIN;
+    if (restriction != MSRSB_RESTRICT_GALERKIN && restriction != MSRSB_RESTRICT_MSFV)
+        return fail(c, MSRSB_E_ARG, "unknown restriction");
+    c->has_coarse_op = false;
+    c->restriction = restriction;
     hipStream_t s = c->stream;
     msrsb_status st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
@@ -1134,7 +1145,12 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     const int64_t nn = static_cast<int64_t>(nc) * nc;
     if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
     phase_begin(c, MSRSB_PHASE_RAP);
-    launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64, c->r32);
+    if (restriction == MSRSB_RESTRICT_GALERKIN)
+        launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64,
+                        c->r32);
+    else  // the block indicator, on the pattern of P^T (which contains it)
+        launch_r_indicator(s, nc, c->rnnz, c->rrp, c->rci, c->rsrc, c->part, fp32, c->r64,
+                           c->r32);
     bool have_csr = false;  // the CSR copy of P, for the general RAP only
     bool lists_rebuilt = false;
     for (;;) {
@@ -1178,7 +1194,7 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     st = MSRSB_E_COARSE_SINGULAR;
     c->acinv_sym = false;
     double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
-    if (c->a_symmetric) {
+    if (c->a_symmetric && restriction == MSRSB_RESTRICT_GALERKIN) {
         // symmetric positive definite A_c: band Cholesky, W = L^{-1} and
         // W^T W; a non-positive pivot falls back to partial pivoting
         hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);

@@ -52,6 +52,31 @@ struct Status {
     std::string msg;
 };
 
+// Launch segment of a level-scheduled triangular sweep: one wide level (a
+// launch across the GPU) or a run of narrow levels (one work-group).
+struct TriSegment {
+    int lev0, lev1;
+    bool wide;
+};
+
+// Symbolic data of the triangular smoothers for one sweep order (k_tri.hip):
+// formed from A's pattern only.
+struct TriOrder {
+    bool built = false;
+    bool sym_pattern = false;  // A_ij stored <=> A_ji stored
+    int ncolours = 0;          // multicolour order: number of colours
+    const int *rp = nullptr, *ci = nullptr, *dpos = nullptr;  // A's pattern (not owned)
+    int *rank = nullptr;       // position of each row in the order
+    int8_t *side = nullptr;    // per entry: -1 earlier column, 0 diagonal, +1 later
+    int *lord = nullptr;       // earlier entries of each row sorted by the column's rank
+    int *nlow = nullptr;       // their count per row
+    int *tpos = nullptr;       // index of the transposed entry, -1 if not stored
+    int *rows_l = nullptr, *rows_u = nullptr;  // rows by level (lower / upper)
+    int *ptr_l = nullptr, *ptr_u = nullptr;    // level pointers (device copies)
+    std::vector<int> h_lev_l, h_lev_u;
+    std::vector<TriSegment> seg_l, seg_u;
+};
+
 }  // namespace msrsb
 
 struct msrsb_ctx {
@@ -173,15 +198,18 @@ struct msrsb_ctx {
     float *dinv_jac32_t = nullptr, *dinv_l1_32_t = nullptr;
     float *at32 = nullptr;
     bool smoother32_valid = false, smoother_t_valid = false, smoother32_t_valid = false;
-    double *ilu = nullptr;
-    int *ilu_lev_ptr = nullptr, *ilu_lev_rows = nullptr;
-    int ilu_nlev_l = 0, ilu_nlev_u = 0;
-    int *ilu_lev_ptr_u = nullptr, *ilu_lev_rows_u = nullptr;
-    std::vector<int> h_lev_ptr_l, h_lev_ptr_u;
-    bool ilu_valid = false;
+    // triangular smoothers by sweep order (MSRSB_ORDER_*): symbolic data, and
+    // the ILU(0) and IC(0) factors on A's pattern (IC(0): L below and on the
+    // diagonal, its transpose mirrored above)
+    msrsb::TriOrder tri[2];
+    double *ilu_f[2] = {nullptr, nullptr}, *ic_f[2] = {nullptr, nullptr};
+    bool ilu_ok[2] = {false, false}, ic_ok[2] = {false, false};
+
+    // restriction of the coarse operator (MSRSB_RESTRICT_*)
+    int restriction = MSRSB_RESTRICT_GALERKIN;
 
     // Krylov workspace
-    double *w[13] = {};
+    double *w[15] = {};
     float *wf[3] = {};            // FP32 work vectors of the precision-form preconditioner
     double *vc = nullptr, *wc = nullptr;
     double *partials = nullptr, *scal = nullptr;
@@ -429,9 +457,20 @@ void launch_norm_scale(hipStream_t s, int n, const double *w, double *vout, doub
 // ---- static scratch of the allocation-free apply (noalloc.hip) ----
 double *static_scratch_init(int device);
 
-// ---- ILU(0) (k_ilu.hip) ----
-msrsb_status ilu0_setup(msrsb_ctx *c);
-void launch_ilu0_apply(msrsb_ctx *c, const double *res, double *zinout, double *tmp);
+// ---- triangular smoothers (k_tri.hip) ----
+msrsb_status tri_order_setup(msrsb_ctx *c, int ordering);
+void free_tri_order(TriOrder &t);
+// ILU(0) or IC(0) factors in the order; E_BREAKDOWN on a zero (ILU) or
+// non-positive (IC) pivot
+msrsb_status tri_factor(msrsb_ctx *c, int ordering, int kind);
+// z += M^{-1} res for ILU(0) / IC(0); res is overwritten
+void tri_apply(msrsb_ctx *c, int ordering, int kind, double *res, double *z);
+// z += (D + L)^{-1} res (lower) or (D + U)^{-1} res, A's values; res overwritten
+void tri_gs_half(msrsb_ctx *c, int ordering, bool lower, double *res, double *z);
+// R's values of the MsFV restriction: 1 where the entry's fine row lies in
+// the coarse row's block, else 0
+void launch_r_indicator(hipStream_t s, int nc, int64_t rnnz, const int *rrp, const int *rci,
+                        const int *rsrc, const int *part, bool fp32, double *r64, float *r32);
 
 // ---- TPFA (k_tpfa.hip) ----
 void launch_tpfa_values(hipStream_t s, int dim, const int *dims, const double *h,

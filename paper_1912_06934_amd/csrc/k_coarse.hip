@@ -1404,6 +1404,38 @@ void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const
         k_gather<double><<<grid_for(m), kBlock, 0, s>>>(m, rsrc, p64, r64);
 }
 
+// R's values of the MsFV restriction on P^T's pattern: entry t of coarse
+// row j (found by bisection of the row pointers) is 1 when its fine row lies
+// in block j, else 0; pads (rsrc < 0) stay 0
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_r_indicator(int nc, int64_t m,
+                                                        const int *__restrict__ rrp,
+                                                        const int *__restrict__ rci,
+                                                        const int *__restrict__ rsrc,
+                                                        const int *__restrict__ part,
+                                                        T *__restrict__ rv)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t >= m) return;
+    int lo = 0, hi = nc - 1;  // the last row j with rrp[j] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rrp[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    rv[t] = (rsrc[t] >= 0 && part[rci[t]] == lo) ? T(1) : T(0);
+}
+
+void launch_r_indicator(hipStream_t s, int nc, int64_t m, const int *rrp, const int *rci,
+                        const int *rsrc, const int *part, bool fp32, double *r64, float *r32)
+{
+    if (m <= 0) return;
+    if (fp32)
+        k_r_indicator<float><<<grid_for(m), kBlock, 0, s>>>(nc, m, rrp, rci, rsrc, part, r32);
+    else
+        k_r_indicator<double><<<grid_for(m), kBlock, 0, s>>>(nc, m, rrp, rci, rsrc, part, r64);
+}
+
 template <typename T, int NT>
 void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp, const int *rci,
            const T *rv, const int *rp, const int *ci, const double *a, const DiaOffsets &d,

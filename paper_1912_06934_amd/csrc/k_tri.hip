@@ -1,0 +1,412 @@
+// Triangular smoothers of the two-stage preconditioner: ILU(0) (Sec. 3.2,
+// Sec. 4.1), IC(0) (Sec. 4.1, Sec. 4.2) and symmetric Gauss-Seidel (Sec. 3.2,
+// Sec. 4.2), each in a sweep order: the natural order, or a multicolour
+// order (first-fit colouring in ascending row order on the symmetrised
+// pattern, rows sorted by colour, ascending within a colour).
+//
+// Everything runs on A's own CSR pattern in its original numbering; the
+// order only decides which stored entries count as "earlier" (lower) or
+// "later" (upper).  Rows are grouped into dependency levels of the lower and
+// of the upper triangle in that order.  A level with many rows is one launch
+// across the whole GPU (thread per row); consecutive levels with few rows are
+// walked by a single work-group with a barrier between levels.  In the
+// multicolour order every colour is one level, so a sweep is a handful of
+// wide launches; in the natural order a 2D grid has a few hundred narrow
+// levels.  Either way every row sees its predecessors final, so the factors
+// and solves equal the sequential algorithm in that order (up to the
+// rounding of the sums).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+namespace msrsb {
+namespace {
+
+constexpr int kNarrowThreads = 1024;
+constexpr int kWideRows = 2048;  // a level with at least this many rows gets its own launch
+
+// --- per-row device work ---
+
+// position of column col in row i (columns ascending), or -1
+__device__ __forceinline__ int find_col(const int *__restrict__ ci, int e0, int e1, int col)
+{
+    int lo = e0, hi = e1 - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = ci[mid];
+        if (c == col) return mid;
+        if (c < col) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+struct TriArgs {
+    const int *rp, *ci, *dpos;
+    const int8_t *side;  // -1 earlier column, 0 diagonal, +1 later
+    const int *lord;     // earlier entries of each row, sorted by the column's rank
+    const int *nlow;     // their count per row
+};
+
+// IKJ elimination of row i in the order (earlier neighbours k by rank)
+__device__ void ilu_row(const TriArgs &t, int i, double *__restrict__ lu, int *__restrict__ flag)
+{
+    const int e0 = t.rp[i], e1 = t.rp[i + 1], nl = t.nlow[i];
+    for (int u = 0; u < nl; ++u) {
+        const int e = t.lord[e0 + u];
+        const int k = t.ci[e];
+        const double piv = lu[t.dpos[k]];
+        if (piv == 0.0) flag[0] = 1;
+        const double lik = lu[e] / piv;
+        lu[e] = lik;
+        for (int q = t.rp[k]; q < t.rp[k + 1]; ++q) {
+            if (t.side[q] <= 0) continue;  // only entries later than k
+            const int f = find_col(t.ci, e0, e1, t.ci[q]);
+            if (f >= 0) lu[f] -= lik * lu[q];
+        }
+    }
+}
+
+// IC(0) row i: L_ij = (A_ij - sum_k L_ik L_jk) / L_jj over earlier j by rank,
+// then L_ii = sqrt(A_ii - sum_k L_ik^2)
+__device__ void ic_row(const TriArgs &t, int i, const double *__restrict__ a,
+                       double *__restrict__ l, int *__restrict__ flag)
+{
+    const int e0 = t.rp[i], nl = t.nlow[i];
+    for (int u = 0; u < nl; ++u) {
+        const int e = t.lord[e0 + u];
+        const int j = t.ci[e];
+        double s = a[e];
+        const int j0 = t.rp[j], j1 = t.rp[j + 1];
+        for (int w = 0; w < u; ++w) {  // k earlier than j, stored in row i
+            const int p = t.lord[e0 + w];
+            const int f = find_col(t.ci, j0, j1, t.ci[p]);
+            if (f >= 0) s -= l[p] * l[f];
+        }
+        l[e] = s / l[t.dpos[j]];
+    }
+    double s = a[t.dpos[i]];
+    for (int u = 0; u < nl; ++u) {
+        const double v = l[t.lord[e0 + u]];
+        s -= v * v;
+    }
+    if (!(s > 0.0)) {
+        flag[0] = 1;
+        s = 1.0;
+    }
+    l[t.dpos[i]] = sqrt(s);
+}
+
+// x_i <- (x_i - sum over the stored entries on one side of vals x) / d_i
+__device__ __forceinline__ void solve_row(const TriArgs &t, int i, int side, bool unit,
+                                          const double *__restrict__ vals,
+                                          double *__restrict__ x)
+{
+    double s = x[i];
+    for (int e = t.rp[i]; e < t.rp[i + 1]; ++e)
+        if (t.side[e] == side) s -= vals[e] * x[t.ci[e]];
+    x[i] = unit ? s : s / vals[t.dpos[i]];
+}
+
+// --- kernels: wide (one level, thread per row) and narrow (levels walked by
+// one work-group) ---
+
+enum { OP_ILU = 0, OP_IC = 1, OP_LOWER = 2, OP_UPPER = 3 };
+
+struct RowOp {
+    int op = OP_LOWER;
+    bool unit = false;
+    const double *a = nullptr;  // IC(0): A's values
+    double *f = nullptr;        // factor values (ILU, IC) or solve values
+    double *x = nullptr;        // solve vector
+    int *flag = nullptr;
+};
+
+__device__ __forceinline__ void do_row(const TriArgs &t, const RowOp &r, int i)
+{
+    switch (r.op) {
+    case OP_ILU: ilu_row(t, i, r.f, r.flag); break;
+    case OP_IC: ic_row(t, i, r.a, r.f, r.flag); break;
+    case OP_LOWER: solve_row(t, i, -1, r.unit, r.f, r.x); break;
+    default: solve_row(t, i, 1, r.unit, r.f, r.x); break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tri_wide(TriArgs t, RowOp r,
+                                                  const int *__restrict__ rows, int count)
+{
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u < count) do_row(t, r, rows[u]);
+}
+
+__global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow(TriArgs t, RowOp r,
+                                                               const int *__restrict__ lev_ptr,
+                                                               const int *__restrict__ rows,
+                                                               int lev0, int lev1)
+{
+    for (int l = lev0; l < lev1; ++l) {
+        for (int u = lev_ptr[l] + threadIdx.x; u < lev_ptr[l + 1]; u += kNarrowThreads)
+            do_row(t, r, rows[u]);
+        __syncthreads();
+    }
+}
+
+// upper entries of the IC(0) array take the factor value of their transpose
+__global__ __launch_bounds__(256) void k_ic_mirror(int64_t nnz, const int8_t *__restrict__ side,
+                                                   const int *__restrict__ tpos,
+                                                   double *__restrict__ l)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e < nnz && side[e] > 0) l[e] = l[tpos[e]];
+}
+
+__global__ __launch_bounds__(256) void k_copy_vals(int64_t m, const double *__restrict__ a,
+                                                   double *__restrict__ b)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t < m) b[t] = a[t];
+}
+
+__global__ __launch_bounds__(256) void k_add(int n, const double *__restrict__ x,
+                                             double *__restrict__ z)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) z[i] += x[i];
+}
+
+// --- host: colouring, levels, launch segments ---
+
+// first fit in ascending row order on the symmetrised pattern
+int first_fit_colours(int n, const std::vector<int> &rp, const std::vector<int> &ci,
+                      std::vector<int> &colour)
+{
+    std::vector<int> trp(n + 1, 0), tci(ci.size());
+    for (int c : ci) trp[c + 1]++;
+    for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    {
+        std::vector<int> pos(trp.begin(), trp.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int e = rp[i]; e < rp[i + 1]; ++e) tci[pos[ci[e]]++] = i;
+    }
+    colour.assign(n, 0);
+    std::vector<int> seen(n + 1, -1);
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] < i) seen[colour[ci[e]]] = i;
+        for (int e = trp[i]; e < trp[i + 1]; ++e)
+            if (tci[e] < i) seen[colour[tci[e]]] = i;
+        int c = 0;
+        while (seen[c] == i) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+// rows grouped by dependency level (lower: on earlier entries, visited in
+// order; upper: on later entries, visited backwards); rows ascending within
+// a level
+void level_sets(int n, const std::vector<int> &rp, const std::vector<int> &ci,
+                const std::vector<int> &order, const std::vector<int> &rank, bool lower,
+                std::vector<int> &ptr, std::vector<int> &rows)
+{
+    std::vector<int> lev(n, 0);
+    int maxl = 0;
+    for (int t = 0; t < n; ++t) {
+        const int i = order[lower ? t : n - 1 - t];
+        int l = 0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            if (lower ? rank[j] < rank[i] : rank[j] > rank[i]) l = std::max(l, lev[j] + 1);
+        }
+        lev[i] = l;
+        maxl = std::max(maxl, l);
+    }
+    ptr.assign(maxl + 2, 0);
+    for (int i = 0; i < n; ++i) ptr[lev[i] + 1]++;
+    for (int l = 0; l <= maxl; ++l) ptr[l + 1] += ptr[l];
+    rows.resize(n);
+    std::vector<int> pos(ptr.begin(), ptr.end() - 1);
+    for (int i = 0; i < n; ++i) rows[pos[lev[i]]++] = i;
+}
+
+void segments(const std::vector<int> &ptr, std::vector<TriSegment> &seg)
+{
+    seg.clear();
+    const int nlev = static_cast<int>(ptr.size()) - 1;
+    for (int l = 0; l < nlev; ++l) {
+        const bool wide = ptr[l + 1] - ptr[l] >= kWideRows;
+        if (!wide && !seg.empty() && !seg.back().wide && seg.back().lev1 == l) {
+            seg.back().lev1 = l + 1;
+            continue;
+        }
+        seg.push_back(TriSegment{l, l + 1, wide});
+    }
+}
+
+template <typename T>
+bool upload(T *&d, const std::vector<T> &h)
+{
+    if (hipMalloc(&d, std::max<size_t>(h.size(), 1) * sizeof(T)) != hipSuccess) return false;
+    return hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
+{
+    const TriArgs a{t.rp, t.ci, t.dpos, t.side, t.lord, t.nlow};
+    const std::vector<int> &ptr = lower ? t.h_lev_l : t.h_lev_u;
+    const std::vector<TriSegment> &seg = lower ? t.seg_l : t.seg_u;
+    const int *rows = lower ? t.rows_l : t.rows_u;
+    const int *dptr = lower ? t.ptr_l : t.ptr_u;
+    for (const TriSegment &g : seg) {
+        if (g.wide) {
+            const int cnt = ptr[g.lev0 + 1] - ptr[g.lev0];
+            k_tri_wide<<<(cnt + 255) / 256, 256, 0, s>>>(a, r, rows + ptr[g.lev0], cnt);
+        } else {
+            k_tri_narrow<<<1, kNarrowThreads, 0, s>>>(a, r, dptr, rows, g.lev0, g.lev1);
+        }
+    }
+}
+
+}  // namespace
+
+void free_tri_order(TriOrder &t)
+{
+    for (void *p : {static_cast<void *>(t.rank), static_cast<void *>(t.side),
+                    static_cast<void *>(t.lord), static_cast<void *>(t.nlow),
+                    static_cast<void *>(t.tpos), static_cast<void *>(t.rows_l),
+                    static_cast<void *>(t.rows_u), static_cast<void *>(t.ptr_l),
+                    static_cast<void *>(t.ptr_u)})
+        if (p) hipFree(p);
+    t = TriOrder();
+}
+
+msrsb_status tri_order_setup(msrsb_ctx *c, int ordering)
+{
+    TriOrder &t = c->tri[ordering];
+    if (t.built) return MSRSB_OK;
+    const int n = c->n;
+    const std::vector<int> &rp = c->h_rp, &ci = c->h_ci;
+    std::vector<int> order(n), rank(n);
+    if (ordering == MSRSB_ORDER_MULTICOLOR) {
+        std::vector<int> colour;
+        const int ncol = first_fit_colours(n, rp, ci, colour);
+        std::vector<int> start(ncol + 1, 0);
+        for (int i = 0; i < n; ++i) start[colour[i] + 1]++;
+        for (int k = 0; k < ncol; ++k) start[k + 1] += start[k];
+        for (int i = 0; i < n; ++i) order[start[colour[i]]++] = i;
+        t.ncolours = ncol;
+    } else {
+        std::iota(order.begin(), order.end(), 0);
+        t.ncolours = 0;
+    }
+    for (int k = 0; k < n; ++k) rank[order[k]] = k;
+    const int64_t nnz = c->nnz;
+    std::vector<int8_t> side(nnz);
+    std::vector<int> lord(nnz, 0), nlow(n, 0), tpos(nnz, -1);
+    for (int i = 0; i < n; ++i) {
+        std::vector<std::pair<int, int>> low;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            side[e] = j == i ? 0 : (rank[j] < rank[i] ? -1 : 1);
+            if (side[e] < 0) low.emplace_back(rank[j], e);
+            // the transposed entry (j, i), when stored
+            const auto b = ci.begin() + rp[j], en = ci.begin() + rp[j + 1];
+            const auto it = std::lower_bound(b, en, i);
+            if (it != en && *it == i) tpos[e] = static_cast<int>(it - ci.begin());
+        }
+        std::sort(low.begin(), low.end());
+        nlow[i] = static_cast<int>(low.size());
+        for (size_t u = 0; u < low.size(); ++u) lord[rp[i] + u] = low[u].second;
+    }
+    t.sym_pattern = std::all_of(tpos.begin(), tpos.end(), [](int p) { return p >= 0; });
+    std::vector<int> pl, rl, pu, ru;
+    level_sets(n, rp, ci, order, rank, true, pl, rl);
+    level_sets(n, rp, ci, order, rank, false, pu, ru);
+    segments(pl, t.seg_l);
+    segments(pu, t.seg_u);
+    t.h_lev_l = pl;
+    t.h_lev_u = pu;
+    if (!upload(t.rank, rank) || !upload(t.side, side) || !upload(t.lord, lord) ||
+        !upload(t.nlow, nlow) || !upload(t.tpos, tpos) || !upload(t.rows_l, rl) ||
+        !upload(t.rows_u, ru) || !upload(t.ptr_l, pl) || !upload(t.ptr_u, pu)) {
+        free_tri_order(t);
+        return MSRSB_E_NOMEM;
+    }
+    t.rp = c->rp;
+    t.ci = c->ci;
+    t.dpos = c->diag_pos;
+    t.built = true;
+    return MSRSB_OK;
+}
+
+msrsb_status tri_factor(msrsb_ctx *c, int ordering, int kind)
+{
+    hipStream_t s = c->stream;
+    TriOrder &t = c->tri[ordering];
+    double *&f = kind == MSRSB_SMOOTH_ILU0 ? c->ilu_f[ordering] : c->ic_f[ordering];
+    if (!f && hipMalloc(&f, c->nnz * sizeof(double)) != hipSuccess) return MSRSB_E_NOMEM;
+    int *flag = c->dev_flag;
+    hipMemsetAsync(flag, 0, sizeof(int), s);
+    RowOp r;
+    r.f = f;
+    r.flag = flag;
+    const int nb = static_cast<int>((c->nnz + 255) / 256);
+    if (kind == MSRSB_SMOOTH_ILU0) {
+        k_copy_vals<<<nb, 256, 0, s>>>(c->nnz, c->a, f);
+        r.op = OP_ILU;
+        run_levels(s, t, true, r);
+    } else {
+        r.op = OP_IC;
+        r.a = c->a;
+        run_levels(s, t, true, r);
+        k_ic_mirror<<<nb, 256, 0, s>>>(c->nnz, t.side, t.tpos, f);
+    }
+    int hflag = 0;
+    hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
+    return hflag ? MSRSB_E_BREAKDOWN : MSRSB_OK;
+}
+
+// z += M^{-1} res for ILU(0) / IC(0) (res is overwritten); one half of a
+// Gauss-Seidel sweep: (D + L)^{-1} (lower) or (D + U)^{-1} (upper) with A's
+// own values
+void tri_apply(msrsb_ctx *c, int ordering, int kind, double *res, double *z)
+{
+    hipStream_t s = c->stream;
+    const TriOrder &t = c->tri[ordering];
+    RowOp r;
+    r.x = res;
+    if (kind == MSRSB_SMOOTH_ILU0) {
+        r.f = c->ilu_f[ordering];
+        r.op = OP_LOWER;
+        r.unit = true;
+        run_levels(s, t, true, r);
+        r.op = OP_UPPER;
+        r.unit = false;
+        run_levels(s, t, false, r);
+    } else if (kind == MSRSB_SMOOTH_IC0) {
+        r.f = c->ic_f[ordering];
+        r.op = OP_LOWER;
+        run_levels(s, t, true, r);
+        r.op = OP_UPPER;
+        run_levels(s, t, false, r);
+    }
+    k_add<<<(c->n + 255) / 256, 256, 0, s>>>(c->n, res, z);
+}
+
+void tri_gs_half(msrsb_ctx *c, int ordering, bool lower, double *res, double *z)
+{
+    hipStream_t s = c->stream;
+    RowOp r;
+    r.x = res;
+    r.f = c->a;
+    r.op = lower ? OP_LOWER : OP_UPPER;
+    run_levels(s, c->tri[ordering], lower, r);
+    k_add<<<(c->n + 255) / 256, 256, 0, s>>>(c->n, res, z);
+}
+
+}  // namespace msrsb

@@ -75,9 +75,10 @@ extern "C" msrsb_status msrsb_apply_preconditioner_noalloc(msrsb_ctx *c,
     if (c->n > kNoAllocMaxN)
         return done(MSRSB_E_ARG, "n exceeds the static scratch limit of 262144 rows");
     if (!o || !v || !z) return done(MSRSB_E_ARG, "invalid arguments");
-    auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_ILU0; };
+    auto sm_ok = [](int k) { return k >= MSRSB_SMOOTH_NONE && k <= MSRSB_SMOOTH_IC0; };
     if (!sm_ok(o->pre_smoother) || !sm_ok(o->post_smoother) || o->pre_sweeps < 0 ||
-        o->post_sweeps < 0 || o->pre_sweeps > 64 || o->post_sweeps > 64)
+        o->post_sweeps < 0 || o->pre_sweeps > 64 || o->post_sweeps > 64 ||
+        (o->ordering != MSRSB_ORDER_NATURAL && o->ordering != MSRSB_ORDER_MULTICOLOR))
         return done(MSRSB_E_ARG, "invalid smoother options");
     if (o->use_multiscale && !c->has_coarse_op)
         return done(MSRSB_E_STATE, "build_coarse must run before a multiscale apply");
@@ -89,9 +90,12 @@ extern "C" msrsb_status msrsb_apply_preconditioner_noalloc(msrsb_ctx *c,
             (!c->smoother_valid || (fp32 && !c->smoother32_valid)))
             return done(MSRSB_E_STATE,
                         "the smoother is not set up: apply or solve with these options first");
-        if (k == MSRSB_SMOOTH_ILU0 && !c->ilu_valid)
+        const int ord = o->ordering;
+        if ((k == MSRSB_SMOOTH_ILU0 && !c->ilu_ok[ord]) ||
+            (k == MSRSB_SMOOTH_IC0 && !c->ic_ok[ord]) ||
+            (k == MSRSB_SMOOTH_SGS && !c->tri[ord].built))
             return done(MSRSB_E_STATE,
-                        "ILU(0) is not set up: apply or solve with these options first");
+                        "the smoother is not set up: apply or solve with these options first");
     }
     if (!c->scratch) return done(MSRSB_E_HIP, "the static scratch array is not available");
     double *base = c->scratch;

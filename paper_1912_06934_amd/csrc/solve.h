@@ -38,5 +38,9 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
                  msrsb_solve_info *info, bool trans);
 msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
                    msrsb_solve_info *info, bool trans);
+msrsb_status richardson(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                        msrsb_solve_info *info, bool trans);
+msrsb_status bicgstab(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                      msrsb_solve_info *info, bool trans);
 
 }  // namespace msrsb

@@ -75,6 +75,24 @@ __global__ void k_vec_add(int k, double *__restrict__ a, const double *__restric
     if (t < k) a[t] += b[t];
 }
 
+// out = a x + b y + c w (w may be null); out may alias x, y or w
+__global__ __launch_bounds__(kBlock) void k_lincomb(int n, double a, const double *x, double b,
+                                                    const double *y, double c, const double *w,
+                                                    double *out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double v = a * x[i] + b * y[i];
+    if (w) v += c * w[i];
+    out[i] = v;
+}
+
+void lincomb(hipStream_t s, int n, double a, const double *x, double b, const double *y,
+             double c, const double *w, double *out)
+{
+    k_lincomb<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, a, x, b, y, c, w, out);
+}
+
 // The fine operator (A, or A^T for the transposed solve) in its CSR and,
 // when available, DIA forms, with the diagonal inverses of its smoothers.
 struct Op {
@@ -150,11 +168,16 @@ msrsb_status dev_alloc(T **p, size_t count)
 
 bool is_diag(int kind) { return kind == MSRSB_SMOOTH_JACOBI || kind == MSRSB_SMOOTH_L1JACOBI; }
 
+bool is_tri(int kind)
+{
+    return kind == MSRSB_SMOOTH_ILU0 || kind == MSRSB_SMOOTH_IC0 || kind == MSRSB_SMOOTH_SGS;
+}
+
 // one smoothing sweep z += M^{-1} (v - A z); with zero, z is known to be zero
 // and is not read.  The result may land in *spare, in which case the two
-// pointers are exchanged.
+// pointers are exchanged.  ord: sweep order of the triangular smoothers.
 void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, double **z,
-           double **spare, bool zero, double *tmp)
+           double **spare, bool zero, double *tmp, int ord)
 {
     hipStream_t s = c->stream;
     const int n = c->n;
@@ -167,14 +190,23 @@ void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, doub
         else
             launch_sweep(s, n, o.rp, o.ci, o.a, o.a32, d64, d32, fp32, v, *z, *spare, zero);
         std::swap(*z, *spare);
-    } else if (kind == MSRSB_SMOOTH_ILU0) {
+    } else if (is_tri(kind)) {
+        // residual, then the triangular solves in the order; SGS is a forward
+        // sweep (D + L)^{-1} and a backward one (D + U)^{-1}, each on the
+        // residual of the current iterate
         if (zero) {
             launch_copy(s, n, v, tmp);
             launch_fill(s, n, *z, 0.0);
         } else {
             op_residual(s, n, o, v, *z, tmp);
         }
-        launch_ilu0_apply(c, tmp, *z, nullptr);
+        if (kind == MSRSB_SMOOTH_SGS) {
+            tri_gs_half(c, ord, true, tmp, *z);
+            op_residual(s, n, o, v, *z, tmp);
+            tri_gs_half(c, ord, false, tmp, *z);
+        } else {
+            tri_apply(c, ord, kind, tmp, *z);
+        }
     }
 }
 
@@ -204,10 +236,11 @@ msrsb_status ensure_workspace(msrsb_ctx *c)
 
 msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans)
 {
-    const bool need_ilu =
-        o->pre_smoother == MSRSB_SMOOTH_ILU0 || o->post_smoother == MSRSB_SMOOTH_ILU0;
-    if (need_ilu && trans) {
-        c->err = "ILU(0) is not available for the transposed solve";
+    const int kinds[2] = {o->pre_sweeps > 0 ? o->pre_smoother : MSRSB_SMOOTH_NONE,
+                          o->post_sweeps > 0 ? o->post_smoother : MSRSB_SMOOTH_NONE};
+    const bool need_tri = is_tri(kinds[0]) || is_tri(kinds[1]);
+    if (need_tri && trans) {
+        c->err = "ILU(0), IC(0) and SGS are not available for the transposed solve";
         return MSRSB_E_ARG;
     }
     const bool fp32 = o->fp32_smoother != 0;
@@ -248,11 +281,29 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
             c->smoother32_t_valid = fp32;
         }
     }
-    if (need_ilu && !c->ilu_valid) {
-        const msrsb_status st = ilu0_setup(c);
-        if (st != MSRSB_OK) {
-            c->err = st == MSRSB_E_COARSE_SINGULAR ? "zero pivot in ILU(0)" : "ILU(0) setup failed";
-            return st == MSRSB_E_COARSE_SINGULAR ? MSRSB_E_BREAKDOWN : st;
+    if (need_tri) {
+        const int ord = o->ordering;
+        msrsb_status st = tri_order_setup(c, ord);
+        if (st) {
+            c->err = "sweep order set-up failed";
+            return st;
+        }
+        for (int k : kinds) {
+            if (k == MSRSB_SMOOTH_IC0 && (!c->a_symmetric || !c->tri[ord].sym_pattern)) {
+                c->err = "IC(0) needs a symmetric matrix";
+                return MSRSB_E_ARG;
+            }
+            bool &ok = k == MSRSB_SMOOTH_ILU0 ? c->ilu_ok[ord] : c->ic_ok[ord];
+            if ((k != MSRSB_SMOOTH_ILU0 && k != MSRSB_SMOOTH_IC0) || ok) continue;
+            st = tri_factor(c, ord, k);
+            if (st) {
+                c->err = st == MSRSB_E_BREAKDOWN
+                             ? (k == MSRSB_SMOOTH_ILU0 ? "zero pivot in ILU(0)"
+                                                       : "non-positive pivot in IC(0)")
+                             : "smoother factorisation failed";
+                return st;
+            }
+            ok = true;
         }
     }
     return MSRSB_OK;
@@ -357,7 +408,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         t = 2;
     }
     for (; t < pre_n; ++t) {
-        sweep(c, op, pre_k, fp32, v, &z, &spare, zero, tmp);
+        sweep(c, op, pre_k, fp32, v, &z, &spare, zero, tmp, o->ordering);
         zero = false;
     }
     if (o->use_multiscale) {
@@ -383,7 +434,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
                                   dots->tag);
             return;
         }
-        sweep(c, op, post_k, fp32, v, &z, &spare, zero, tmp);
+        sweep(c, op, post_k, fp32, v, &z, &spare, zero, tmp, o->ordering);
         zero = false;
     }
     if (zero)
@@ -608,5 +659,143 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
     return rc;
 }
 
+// The stand-alone iteration of Sec. 3.2 (Richardson): x += B (f - A x) until
+// the true residual meets the tolerance; iterations count applications of B.
+msrsb_status richardson(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                        msrsb_solve_info *info, bool trans)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const Op op = fine_op(c, trans);
+    double *r = c->w[0], *z = c->w[1];
+    double *sc = c->scal;
+    launch_dot(s, n, f, f, c->partials, sc + S_FF);
+    if (read_scalars(c, S_FF, 1)) return MSRSB_E_HIP;
+    double fn = std::sqrt(c->h_pinned[0]);
+    if (fn == 0.0) fn = 1.0;
+    double *hist = info ? info->history : nullptr;
+    const int hcap = info ? info->history_cap : 0;
+    int it = 0;
+    double rel = 0.0;
+    msrsb_status rc = MSRSB_E_NOT_CONVERGED;
+    for (;;) {
+        op_residual(s, n, op, f, x, r);
+        launch_dot(s, n, r, r, c->partials, sc + S_RR);
+        if (read_scalars(c, S_RR, 1)) return MSRSB_E_HIP;
+        rel = std::sqrt(c->h_pinned[0]) / fn;
+        if (hist && it < hcap) hist[it] = rel;
+        if (!std::isfinite(rel)) { rc = MSRSB_E_BREAKDOWN; break; }
+        if (rel <= o->rtol) { rc = MSRSB_OK; break; }
+        if (it >= o->max_iter) break;
+        apply_two_stage(c, o, r, z, trans, nullptr);
+        launch_axpy(s, n, 1.0, z, x);
+        ++it;
+    }
+    if (info) {
+        info->iters = it;
+        info->true_rel_res = rel;
+    }
+    return rc;
+}
+
+// Right-preconditioned BiCGStab (two applications of B per iteration,
+// Sec. 4.1).  Scalars are read back on the host after each product; a pass
+// that meets the tolerance after its first half ends there.  Convergence of
+// the recursive residual is confirmed on the true residual, and the method
+// starts again from x if that is still above the tolerance.  Breakdown:
+// |rhat^T r| <= 1e-14 ||rhat|| ||r|| (an exact zero is hidden by rounding),
+// or rhat^T v or t^T t zero.
+msrsb_status bicgstab(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opts *o,
+                      msrsb_solve_info *info, bool trans)
+{
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const Op op = fine_op(c, trans);
+    // (w[5] and w[6] hold f and x of a host-staged solve)
+    double *r = c->w[0], *rh = c->w[1], *p = c->w[2], *v = c->w[3], *y = c->w[4],
+           *sv = c->w[7], *z = c->w[12], *t = c->w[13];
+    double *sc = c->scal;
+    auto dot = [&](const double *a, const double *b, double &out) {
+        launch_dot(s, n, a, b, c->partials, sc + S_TMP0);
+        if (read_scalars(c, S_TMP0, 1)) return false;
+        out = c->h_pinned[0];
+        return true;
+    };
+    double ff = 0.0;
+    if (!dot(f, f, ff)) return MSRSB_E_HIP;
+    double fn = std::sqrt(ff);
+    if (fn == 0.0) fn = 1.0;
+    double *hist = info ? info->history : nullptr;
+    const int hcap = info ? info->history_cap : 0;
+    int it = 0;
+    msrsb_status rc = MSRSB_E_NOT_CONVERGED;
+    bool restart = true;
+    double rho = 1.0, alpha = 1.0, omega = 1.0, rhn = 0.0, rn = 0.0;
+    while (it <= o->max_iter) {
+        if (restart) {
+            op_residual(s, n, op, f, x, r);
+            double rr = 0.0;
+            if (!dot(r, r, rr)) return MSRSB_E_HIP;
+            const double rel = std::sqrt(rr) / fn;
+            if (hist && it < hcap) hist[it] = rel;
+            if (!std::isfinite(rel)) { rc = MSRSB_E_BREAKDOWN; break; }
+            if (rel <= o->rtol) { rc = MSRSB_OK; break; }
+            if (it >= o->max_iter) break;
+            launch_copy(s, n, r, rh);
+            launch_copy(s, n, r, p);
+            rho = rr;
+            rhn = std::sqrt(rr);
+            restart = false;
+        } else {
+            double rho_new = 0.0;
+            if (!dot(rh, r, rho_new)) return MSRSB_E_HIP;
+            if (!(std::fabs(rho_new) > 1e-14 * rhn * rn)) { rc = MSRSB_E_BREAKDOWN; break; }
+            const double beta = (rho_new / rho) * (alpha / omega);
+            lincomb(s, n, 1.0, r, beta, p, -beta * omega, v, p);  // p = r + beta (p - omega v)
+            rho = rho_new;
+        }
+        apply_two_stage(c, o, p, y, trans, nullptr);
+        op_spmv(s, n, op, y, v);
+        double sig = 0.0;
+        if (!dot(rh, v, sig)) return MSRSB_E_HIP;
+        if (sig == 0.0 || !std::isfinite(sig)) { rc = MSRSB_E_BREAKDOWN; break; }
+        alpha = rho / sig;
+        lincomb(s, n, 1.0, r, -alpha, v, 0.0, nullptr, sv);  // s = r - alpha v
+        ++it;
+        double ss = 0.0;
+        if (!dot(sv, sv, ss)) return MSRSB_E_HIP;
+        if (std::sqrt(ss) <= o->rtol * fn) {
+            lincomb(s, n, 1.0, x, alpha, y, 0.0, nullptr, x);
+            if (hist && it < hcap) hist[it] = std::sqrt(ss) / fn;
+            restart = true;
+            continue;
+        }
+        apply_two_stage(c, o, sv, z, trans, nullptr);
+        op_spmv(s, n, op, z, t);
+        double tt = 0.0, ts = 0.0;
+        if (!dot(t, t, tt) || !dot(t, sv, ts)) return MSRSB_E_HIP;
+        if (tt == 0.0 || !std::isfinite(tt)) { rc = MSRSB_E_BREAKDOWN; break; }
+        omega = ts / tt;
+        lincomb(s, n, 1.0, x, alpha, y, omega, z, x);        // x += alpha y + omega z
+        lincomb(s, n, 1.0, sv, -omega, t, 0.0, nullptr, r);  // r = s - omega t
+        double rr = 0.0;
+        if (!dot(r, r, rr)) return MSRSB_E_HIP;
+        rn = std::sqrt(rr);
+        const double rel = rn / fn;
+        if (hist && it < hcap) hist[it] = rel;
+        if (!std::isfinite(rel)) { rc = MSRSB_E_BREAKDOWN; break; }
+        if (rel <= o->rtol) { restart = true; continue; }
+        if (omega == 0.0) { rc = MSRSB_E_BREAKDOWN; break; }
+        if (it >= o->max_iter) break;
+    }
+    op_residual(s, n, op, f, x, r);
+    double rr = 0.0;
+    if (!dot(r, r, rr)) return MSRSB_E_HIP;
+    if (info) {
+        info->iters = it;
+        info->true_rel_res = std::sqrt(rr) / fn;
+    }
+    return rc;
+}
 
 }  // namespace msrsb

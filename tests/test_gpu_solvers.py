@@ -1,0 +1,245 @@
+"""GPU parity of the solver options against the oracle: ILU(0), IC(0) and
+symmetric Gauss-Seidel in natural and multicolour order, the stand-alone
+(Richardson) iteration, BiCGStab, and the Petrov-Galerkin (MsFV) restriction;
+plus PCG on a stencil operator with more diagonals than the tiled sweep
+kernels take (the untiled fallback).
+
+Tolerances: one preconditioner application 1e-11 relative (the coarse solve
+amplifies A_c's rounding by its condition number); A_c 1e-12; solutions of
+both sides solved to 1e-11 or tighter agree to 1e-8; iteration counts agree
+to within a few (the stopping test sees residuals that differ by rounding)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from _cases import (gpu_setup_matrix, gpu_setup_tpfa, matrix_inputs, oracle_setup, rel_max,
+                    tpfa_inputs)
+
+pytestmark = pytest.mark.gpu
+
+ILU0, SGS, IC0 = 3, 4, 5
+
+
+def _gpu_apply(s, v, **kw):
+    import torch
+    dev = torch.device("cuda", 0)
+    z = torch.empty(v.size, dtype=torch.float64, device=dev)
+    s.apply(torch.from_numpy(v).to(dev), z, **kw)
+    return z.cpu().numpy()
+
+
+def _gpu_solve(s, f, **kw):
+    import torch
+    dev = torch.device("cuda", 0)
+    u = torch.zeros(f.size, dtype=torch.float64, device=dev)
+    info = s.solve(torch.from_numpy(np.ascontiguousarray(f)).to(dev), u, **kw)
+    return u.cpu().numpy(), info
+
+
+@pytest.fixture(scope="module")
+def tpfa3d():
+    cfg = tpfa_inputs("c5", dims=(24, 20, 18), block=6)
+    m = oracle_setup(cfg, kmax=60)
+    s, rhs, _ = gpu_setup_tpfa(cfg, kmax=60)
+    return cfg, m, s
+
+
+@pytest.fixture(scope="module")
+def mpfa2d():
+    cfg = matrix_inputs("c2", dims=(48, 40), block=8)
+    m = oracle_setup(cfg, kmax=100)
+    s, _ = gpu_setup_matrix(cfg, kmax=100)
+    return cfg, m, s
+
+
+@pytest.mark.parametrize("ordering", ["natural", "multicolor"])
+@pytest.mark.parametrize("kind", [ILU0, SGS, IC0])
+def test_triangular_smoother_apply_symmetric(tpfa3d, kind, ordering):
+    cfg, m, s = tpfa3d
+    n = cfg["f"].size
+    v = np.random.default_rng(kind).standard_normal(n)
+    for pre, post in (((kind, 1), (kind, 1)), ((0, 0), (kind, 2))):
+        ref = m.apply(v, pre=pre, post=post, ordering=ordering)
+        z = _gpu_apply(s, v, pre=pre, post=post, ordering=ordering)
+        assert rel_max(z, ref) <= 1e-11, (kind, ordering, pre, post)
+        ref0 = m.apply(v, pre=pre, post=post, ordering=ordering, use_ms=False)
+        z0 = _gpu_apply(s, v, pre=pre, post=post, ordering=ordering, use_multiscale=False)
+        assert rel_max(z0, ref0) <= 1e-12
+
+
+@pytest.mark.parametrize("ordering", ["natural", "multicolor"])
+@pytest.mark.parametrize("kind", [ILU0, SGS])
+def test_triangular_smoother_apply_nonsymmetric(mpfa2d, kind, ordering):
+    cfg, m, s = mpfa2d
+    v = np.random.default_rng(7).standard_normal(cfg["f"].size)
+    ref = m.apply(v, post=(kind, 1), ordering=ordering)
+    z = _gpu_apply(s, v, post=(kind, 1), ordering=ordering)
+    assert rel_max(z, ref) <= 1e-11
+
+
+def test_q1_multicolour_sgs_apply():
+    # 24 colours: 8 node parities times 3 interleaved components
+    cfg = matrix_inputs("c3", dims=(10, 8, 6), block=4)
+    m = oracle_setup(cfg, kmax=40)
+    s, _ = gpu_setup_matrix(cfg, kmax=40)
+    v = np.random.default_rng(3).standard_normal(cfg["f"].size)
+    for kind in (SGS, IC0):
+        ref = m.apply(v, pre=(kind, 1), post=(kind, 1), ordering="multicolor")
+        z = _gpu_apply(s, v, pre=(kind, 1), post=(kind, 1), ordering="multicolor")
+        assert rel_max(z, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("krylov,pre,post,ordering", [
+    ("pcg", (IC0, 1), (IC0, 1), "natural"),
+    ("pcg", (IC0, 1), (IC0, 1), "multicolor"),
+    ("pcg", (SGS, 1), (SGS, 1), "multicolor"),
+    ("bicgstab", (0, 0), (ILU0, 1), "natural"),
+    ("richardson", (0, 0), (SGS, 1), "multicolor"),
+    ("richardson", (0, 0), (ILU0, 1), "natural"),
+    ("gmres", (0, 0), (SGS, 1), "natural"),
+])
+def test_solves_symmetric(tpfa3d, krylov, pre, post, ordering):
+    cfg, m, s = tpfa3d
+    f = cfg["f"]
+    kw = dict(pre=pre, post=post, ordering=ordering)
+    ref = m.solve(f, krylov=krylov, rtol=1e-11, maxit=2000, **kw)
+    u, info = _gpu_solve(s, f, krylov=krylov, rtol=1e-11, max_iter=2000, **kw)
+    assert ref["status"] == 0 and info["true_rel_res"] <= 1e-11
+    assert rel_max(u, ref["x"]) <= 1e-8
+    assert abs(info["iters"] - ref["iters"]) <= 2, (info["iters"], ref["iters"])
+
+
+@pytest.mark.parametrize("krylov,ordering", [("gmres", "multicolor"), ("bicgstab", "multicolor"),
+                                             ("bicgstab", "natural")])
+def test_solves_nonsymmetric_ilu0(mpfa2d, krylov, ordering):
+    # a seeded random right-hand side (with the workload's single point
+    # source the shadow residual of BiCGStab is e_0, and every ILU(0) sweep
+    # leaves the residual exactly zero in row 0, the first row of either
+    # order: rho = 0 at the second step, a breakdown; tested below)
+    cfg, m, s = mpfa2d
+    f = np.random.default_rng(11).standard_normal(cfg["f"].size)
+    kw = dict(post=(ILU0, 1), ordering=ordering)
+    ref = m.solve(f, krylov=krylov, rtol=1e-10, maxit=3000, **kw)
+    u, info = _gpu_solve(s, f, krylov=krylov, rtol=1e-10, max_iter=3000, **kw)
+    assert ref["status"] == 0 and info["true_rel_res"] <= 1e-10
+    assert rel_max(u, ref["x"]) <= 1e-7
+    # BiCGStab's residual is not monotone: on this rough non-M operator,
+    # rounding-level differences in alpha and omega move its path by several
+    # iterations (GMRES minimises the residual and keeps to a few)
+    slack = ref["iters"] // 5 if krylov == "bicgstab" else ref["iters"] // 20
+    assert abs(info["iters"] - ref["iters"]) <= max(3, slack)
+
+
+def test_bicgstab_breakdown_is_reported(mpfa2d):
+    from paper_1912_06934_amd import MsrsbError
+    cfg, m, s = mpfa2d
+    ref = m.solve(cfg["f"], krylov="bicgstab", post=(ILU0, 1), ordering="multicolor", rtol=1e-10)
+    assert ref["status"] == -7
+    with pytest.raises(MsrsbError) as e:
+        _gpu_solve(s, cfg["f"], krylov="bicgstab", post=(ILU0, 1), ordering="multicolor",
+                   rtol=1e-10)
+    assert e.value.code == -7
+
+
+def test_msfv_restriction(tpfa3d):
+    import torch
+    cfg, m, s = tpfa3d
+    f = cfg["f"]
+    ac = m.build_coarse(restriction="msfv")
+    s.build_coarse(restriction="msfv")
+    try:
+        assert rel_max(s.get_coarse_matrix(), ac) <= 1e-12
+        v = np.random.default_rng(9).standard_normal(f.size)
+        ref = m.apply(v, post=(1, 1))
+        assert rel_max(_gpu_apply(s, v, post=(1, 1)), ref) <= 1e-11
+        # the coarse stage alone conserves mass block by block (Sec. 2)
+        u = _gpu_apply(s, f)
+        A = sp.csr_matrix((cfg["a"], cfg["ci"], cfg["rp"]), shape=(f.size, f.size))
+        blk = np.bincount(cfg["supports"]["part"], weights=f - A @ u)
+        assert np.abs(blk).max() <= 1e-11 * np.abs(f).sum()
+        for krylov in ("gmres", "richardson"):
+            r = m.solve(f, krylov=krylov, post=(SGS, 1), rtol=1e-11, maxit=500)
+            uu, info = _gpu_solve(s, f, krylov=krylov, post=(SGS, 1), rtol=1e-11, max_iter=500)
+            assert r["status"] == 0 and info["true_rel_res"] <= 1e-11
+            assert rel_max(uu, r["x"]) <= 1e-8
+        from paper_1912_06934_amd import MsrsbError
+        lam = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(MsrsbError) as e:
+            s.solve_transpose(torch.from_numpy(f).to("cuda:0"), lam, pre=(1, 1), post=(1, 1))
+        assert e.value.code == -1
+    finally:
+        m.build_coarse()
+        s.build_coarse()
+
+
+def test_option_errors(mpfa2d, tpfa3d):
+    import torch
+    from paper_1912_06934_amd import MsrsbError
+    cfg, m, s = mpfa2d
+    v = np.ones(cfg["f"].size)
+    with pytest.raises(MsrsbError) as e:              # IC(0) needs a symmetric A
+        _gpu_apply(s, v, post=(IC0, 1))
+    assert e.value.code == -1
+    with pytest.raises(MsrsbError) as e:
+        _gpu_apply(s, v, post=(6, 1))
+    assert e.value.code == -1
+    with pytest.raises(MsrsbError) as e:
+        _gpu_apply(s, v, post=(SGS, 1), ordering=2)
+    assert e.value.code == -1
+    cfg, m, s = tpfa3d
+    f = torch.from_numpy(cfg["f"]).to("cuda:0")
+    lam = torch.zeros_like(f)
+    with pytest.raises(MsrsbError) as e:              # no transposed triangular smoothers
+        s.solve_transpose(f, lam, post=(SGS, 1))
+    assert e.value.code == -1
+
+
+def _stencil27(dims, seed):
+    """A symmetric positive definite 27-point stencil matrix (weighted graph
+    Laplacian of the 26-neighbourhood plus a positive diagonal shift)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    idx = np.arange(n).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dz, dy, dx) <= (0, 0, 0):
+                    continue
+                sl_a = idx[max(0, -dz):nz - max(0, dz), max(0, -dy):ny - max(0, dy),
+                           max(0, -dx):nx - max(0, dx)]
+                sl_b = idx[max(0, dz):nz - max(0, -dz), max(0, dy):ny - max(0, -dy),
+                           max(0, dx):nx - max(0, -dx)]
+                w = rng.uniform(0.2, 1.0, sl_a.size)
+                rows += [sl_a.ravel(), sl_b.ravel()]
+                cols += [sl_b.ravel(), sl_a.ravel()]
+                vals += [-w, -w]
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n)).tocsr()
+    A = (A + sp.diags(-A.sum(axis=1).A1 + rng.uniform(0.01, 0.1, n))).tocsr()
+    A.sort_indices()
+    return A
+
+
+def test_pcg_on_27_diagonal_stencil():
+    # 27 diagonals: stored as DIA, but wider than the tiled two-sweep kernels
+    # take, so the PCG update and the sweeps run untiled
+    import synth
+    dims = (20, 18, 16)
+    A = _stencil27(dims, 5)
+    n = A.shape[0]
+    sup = synth.cell_supports(dims, 5)
+    f = np.random.default_rng(6).standard_normal(n)
+    cfg = dict(rp=A.indptr.astype(np.int32), ci=A.indices.astype(np.int32), a=A.data, f=f,
+               supports=sup)
+    m = oracle_setup(cfg, kmax=50)
+    s, _ = gpu_setup_matrix(cfg, kmax=50)
+    for fp32 in (False, True):
+        ref = m.solve(f, pre=(2, 2), post=(2, 2), rtol=1e-11, maxit=1000)
+        u, info = _gpu_solve(s, f, pre=(2, 2), post=(2, 2), rtol=1e-11, max_iter=1000,
+                             fp32_smoother=fp32)
+        assert info["true_rel_res"] <= 1e-11
+        assert rel_max(u, ref["x"]) <= 1e-8
+        if not fp32:
+            assert abs(info["iters"] - ref["iters"]) <= 1

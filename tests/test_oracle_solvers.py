@@ -324,3 +324,20 @@ def test_msfv_solves_with_gmres_and_richardson():
         np.testing.assert_allclose(r["x"], ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
     with pytest.raises(oracle.OracleError):
         m.solve(f, transpose=True, post=(1, 1))
+
+
+def test_bicgstab_breakdown_with_point_source():
+    # with f = e_0 the shadow residual is e_0; row 0 comes first in either
+    # order, row 0 of L U is row 0 of A, so every ILU(0) sweep leaves the
+    # residual zero there: rhat^T r vanishes at the second step
+    A = stencil((12, 10), NINE, seed=12, spd=False)
+    n = 120
+    f = np.zeros(n)
+    f[0] = 1.0
+    m = _smoother_only(A)
+    for ordering in ("natural", "multicolor"):
+        z = m.apply(f, post=(ILU0, 1), use_ms=False, ordering=ordering)
+        assert abs((f - A @ z)[0]) <= 1e-15
+        r = m.solve(f, krylov="bicgstab", post=(ILU0, 1), use_ms=False, ordering=ordering,
+                    rtol=1e-10, maxit=50)
+        assert r["status"] == oracle.E_BREAK and r["iters"] == 1
