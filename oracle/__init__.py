@@ -56,7 +56,7 @@ class Prec(C.Structure):
                 ("lu_trans", _I), ("use_ms", _I), ("pre_kind", _I),
                 ("pre_sweeps", _I), ("post_kind", _I), ("post_sweeps", _I),
                 ("order", _P), ("brp", _P), ("bci", _P), ("ba", _P), ("ilu", _P),
-                ("ic", _P), ("part", _P)]
+                ("ic", _P), ("part", _P), ("next", _P)]
 
 
 def _declare(L):
@@ -311,14 +311,27 @@ class Msrsb:
         self._perm = {}     # ordering -> (order, B)
         self._t = None
         self.restriction = "galerkin"
+        self.levels = {}    # level >= 1 -> coarse space of that level's unknowns
+        self.child = None   # the next level (multilevel), built on A_c
 
     def set_coarse(self, nc, part, prp, pci, interior):
         self.nc = int(nc)
         self.part, self.prp, self.pci = _i32(part), _i32(prp), _i32(pci)
         self.interior = np.ascontiguousarray(interior, dtype=np.uint8)
 
+    def set_coarse_level(self, level, nc, part, prp, pci, interior):
+        """Coarse space of level `level` >= 1 (a partition of the level's
+        unknowns, the coarse nodes of the level above, with its supports):
+        A_c of the level above is then not factored but gets its own
+        enhanced MsRSB preconditioner (multilevel)."""
+        if level < 1:
+            raise ValueError("level must be >= 1")
+        self.levels[level] = (int(nc), _i32(part), _i32(prp), _i32(pci),
+                              np.ascontiguousarray(interior, dtype=np.uint8))
+
     def setup_basis(self, omega=2.0 / 3.0, kmax=100, tol=-1.0, nit=1, filt=True,
                     warm_start=False):
+        self._basis_opts = dict(omega=omega, kmax=kmax, tol=tol, nit=nit, filt=filt)
         self.jv, self.dhat = filter_jacobi(self.rp, self.ci, self.a, self.bs, filt, omega)
         if not warm_start or self.pv is None:
             self.pv = init_basis(self.prp, self.pci, self.part)
@@ -338,7 +351,25 @@ class Msrsb:
                              self.pv)
         else:
             raise ValueError(restriction)
-        self.lu, self.piv = lu(self.ac)
+        self.child = None
+        if 1 in self.levels:
+            # the next level: A_c as a sparse matrix (its nonzeros and the
+            # diagonal), its own coarse space, basis and coarse operator
+            nc = self.nc
+            mask = (self.ac != 0.0) | np.eye(nc, dtype=bool)
+            rows, cols = np.nonzero(mask)
+            crp = np.zeros(nc + 1, dtype=np.int32)
+            np.add.at(crp, rows + 1, 1)
+            crp = np.cumsum(crp).astype(np.int32)
+            child = Msrsb(crp, cols.astype(np.int32), self.ac[rows, cols])
+            child.set_coarse(*self.levels[1])
+            child.levels = {lv - 1: spec for lv, spec in self.levels.items() if lv > 1}
+            child.setup_basis(**self._basis_opts)
+            child.build_coarse()
+            self.child = child
+            self.lu, self.piv = None, None
+        else:
+            self.lu, self.piv = lu(self.ac)
         return self.ac
 
     def _order(self, ordering):
@@ -378,11 +409,19 @@ class Msrsb:
             if 5 in kinds:
                 ic = self._factor(ordering, 5)
         part = self.part if self.restriction == "msfv" else None
+        nxt = None
         keep = [rp, ci, a, order, brp, bci, ba, ilu, ic, part]
+        if self.child is not None and use_ms:
+            # the next level's two-stage preconditioner with the same smoothers
+            cm, ckeep = self.child._prec(pre if not transpose else post,
+                                         post if not transpose else pre, True, transpose,
+                                         ordering)
+            keep += [cm, ckeep]
+            nxt = C.cast(C.pointer(cm), C.c_void_p)
         m = Prec(self.n, _p(rp), _p(ci), _p(a), self.nc, _p(self.prp), _p(self.pci),
                  _p(self.pv), _p(self.lu), _p(self.piv), int(transpose), int(use_ms),
                  pre[0], pre[1], post[0], post[1], _p(order), _p(brp), _p(bci), _p(ba),
-                 _p(ilu), _p(ic), _p(part))
+                 _p(ilu), _p(ic), _p(part), nxt)
         return m, keep
 
     def apply(self, v, pre=(0, 0), post=(0, 0), use_ms=True, transpose=False,

@@ -514,7 +514,7 @@ int orc_ic0(int n, const int *rp, const int *ci, const double *a, double *l)
 
 /* ------------------------------------------------------------------ */
 /* Two-stage preconditioner (Alg. 3 and Alg. 4). */
-typedef struct {
+typedef struct orc_prec_s {
     int n;
     const int *rp, *ci;
     const double *a;          /* fine operator (A, or A^T for the adjoint) */
@@ -538,6 +538,10 @@ typedef struct {
     /* restriction: NULL = Galerkin R = P^T; otherwise the coarse block of
      * every fine row, and R is the block indicator (Petrov-Galerkin, MsFV) */
     const int *part;
+    /* multilevel MsRSB (the conclusion's multilevel use of the enhanced
+     * method): when not NULL, the coarse solve M_c^{-1} is the two-stage
+     * preconditioner of the next level, built on A_c, instead of the LU */
+    const struct orc_prec_s *next;
 } orc_prec;
 
 static void spmv(int n, const int *rp, const int *ci, const double *a,
@@ -671,7 +675,16 @@ static void prec_apply(const orc_prec *m, const double *v, double *z, double *wo
                 for (int e = m->prp[i]; e < m->prp[i + 1]; ++e)
                     vc[m->pci[e]] = vc[m->pci[e]] + m->pv[e] * res[i];
         }
-        orc_lu_solve(m->nc, m->lu, m->piv, vc, m->lu_trans); /* w_c = M_c^{-1} v_c */
+        if (m->next) {                                      /* w_c = B_next v_c */
+            double *wc = (double *)malloc(sizeof(double) * (size_t)(m->nc > 0 ? m->nc : 1));
+            double *w2 = (double *)malloc(sizeof(double) * PREC_WORK(m->nc, m->next->nc));
+            prec_apply(m->next, vc, wc, w2);
+            for (int j = 0; j < m->nc; ++j) vc[j] = wc[j];
+            free(wc);
+            free(w2);
+        } else {
+            orc_lu_solve(m->nc, m->lu, m->piv, vc, m->lu_trans); /* w_c = M_c^{-1} v_c */
+        }
         for (int i = 0; i < n; ++i) {                      /* z += P w_c */
             double s = 0.0;
             for (int e = m->prp[i]; e < m->prp[i + 1]; ++e) s = s + m->pv[e] * vc[m->pci[e]];
