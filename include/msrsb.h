@@ -181,11 +181,40 @@ msrsb_status msrsb_assemble_tpfa(msrsb_ctx *ctx, int32_t dim, const int32_t dims
  * of grid cells whose pattern rows are products of per-axis coarse nodes,
  * the restriction and prolongation form their column indices from the grid
  * instead of loading them (checked for every row here; results unchanged).
- * Errors: E_ARG for nc < 1 or nc > 4096, empty rows, unsorted or
- * out-of-range columns, part[i] not in row i's pattern. */
+ * Errors: E_ARG for nc < 1 or nc > 32768 (more than 4096 needs a further
+ * level, see msrsb_set_coarse_level), empty rows, unsorted or out-of-range
+ * columns, part[i] not in row i's pattern. */
 msrsb_status msrsb_set_coarse(msrsb_ctx *ctx, int32_t nc, const int32_t *part,
                               const int32_t *sup_rowptr, const int32_t *sup_col,
                               const uint8_t *interior, int where);
+
+/* Multilevel MsRSB (Conclusion: the filter makes the multipoint coarse
+ * operator a valid input of the enhanced method, so it can be applied again
+ * to A_c).  Level 0 is the fine level of msrsb_set_coarse; level L >= 1 gives
+ * the coarse space of level L's unknowns, the nc_L coarse nodes of the level
+ * above: part (nc_L values), the support pattern and the interior flags as
+ * in msrsb_set_coarse.  Level L - 1 must be set first.  build_coarse then
+ * writes A_c straight into level 1's sparse matrix (CSR on the column
+ * pattern of R A P) instead of a dense matrix, and the coarse solver of
+ * Alg. 2 becomes level 1's own set-up: the filter and basis (with the
+ * options of the last msrsb_setup_basis) and its coarse operator, down to
+ * the last level, whose A_c is inverted exactly.  Every apply then replaces
+ * A_c^{-1} by one two-stage application (Alg. 4) of the next level, with the
+ * same smoothers in FP64.  A level that has a further level may have up to
+ * 32768 coarse unknowns (the last level up to 4096).
+ * Limits: the operator of a level that gets a further level must be a
+ * stencil with 3, 5, 7 or 9 diagonals and supports of at most 8 coarse nodes
+ * per row (E_ARG otherwise); coarse levels take Jacobi-type smoothers only
+ * (E_ARG at solve time).  Errors: E_STATE before msrsb_set_coarse or with
+ * level L - 1 missing; as msrsb_set_coarse for the partition. */
+msrsb_status msrsb_set_coarse_level(msrsb_ctx *ctx, int32_t level, int32_t nc,
+                                    const int32_t *part, const int32_t *sup_rowptr,
+                                    const int32_t *sup_col, const uint8_t *interior, int where);
+/* The context of level `level` (0 = ctx itself): borrowed, owned by ctx and
+ * valid until ctx or its coarse space changes; it answers msrsb_get_matrix
+ * (level L's matrix is A_c of level L - 1), msrsb_get_prolongation and
+ * msrsb_get_coarse_matrix.  Errors: E_ARG for a level that does not exist. */
+msrsb_status msrsb_get_level(msrsb_ctx *ctx, int32_t level, msrsb_ctx **out);
 
 typedef struct {
     double omega;        /* relaxation factor, the paper uses 2/3 (Sec. 2.1) */

@@ -82,6 +82,8 @@ SIGNATURES = [
     ("msrsb_get_matrix", _ST, [_P, _P, _P, _P, C.c_int]),
     ("msrsb_assemble_tpfa", _ST, [_P, _I32, _P, _P, _P, _P, _P, C.c_int]),
     ("msrsb_set_coarse", _ST, [_P, _I32, _P, _P, _P, _P, C.c_int]),
+    ("msrsb_set_coarse_level", _ST, [_P, _I32, _I32, _P, _P, _P, _P, C.c_int]),
+    ("msrsb_get_level", _ST, [_P, _I32, C.POINTER(_P)]),
     ("msrsb_setup_basis", _ST, [_P, C.POINTER(BasisOpts), C.POINTER(BasisInfo)]),
     ("msrsb_set_prolongation", _ST, [_P, _P, C.c_int]),
     ("msrsb_get_prolongation", _ST, [_P, _P, _P, _P, C.c_int]),
@@ -162,12 +164,15 @@ class Msrsb:
         if rc != 0:
             raise MsrsbError(rc, f"msrsb_create(device={device}) failed")
         self._h = h
+        self._owned = True
         self.n = None
         self.nc = None
+        self._levels = {}
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.msrsb_destroy(self._h)
+            if self._owned:
+                self._lib.msrsb_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -252,6 +257,29 @@ class Msrsb:
                                                a[3][0], _where(*[x[1] for x in a])), "set_coarse")
         self.nc = int(nc)
         self.pnnz = len(sup_col)
+
+    def set_coarse_level(self, level, nc, part, sup_rowptr, sup_col, interior):
+        """Coarse space of level `level` >= 1 (multilevel MsRSB)."""
+        a = [_ptr(part, np.int32), _ptr(sup_rowptr, np.int32), _ptr(sup_col, np.int32),
+             _ptr(interior, np.uint8)]
+        self._check(self._lib.msrsb_set_coarse_level(self._h, int(level), int(nc), a[0][0],
+                                                     a[1][0], a[2][0], a[3][0],
+                                                     _where(*[x[1] for x in a])),
+                    "set_coarse_level")
+        self._levels[int(level)] = (int(nc), len(sup_col))
+
+    def level(self, level):
+        """The context of level `level` (borrowed: owned by this one)."""
+        h = C.c_void_p()
+        self._check(self._lib.msrsb_get_level(self._h, int(level), C.byref(h)), "get_level")
+        if level == 0:
+            return self
+        lv = Msrsb.__new__(Msrsb)
+        lv._lib, lv._h, lv._owned, lv._levels = self._lib, h, False, {}
+        lv.n = self.nc if level == 1 else self._levels[level - 1][0]
+        lv.nc, lv.pnnz = self._levels[level]
+        lv._parent = self                     # keeps the owner alive
+        return lv
 
     def setup_basis(self, omega=2.0 / 3.0, max_iter=100, tol=-1.0, check_every=1, filter=True,
                     fp32_basis=False, warm_start=False):

@@ -443,6 +443,28 @@ msrsb_status solve_opts_check(msrsb_ctx *c, const msrsb_solve_opts *o)
     return MSRSB_OK;
 }
 
+// The levels below this one (multilevel): their apply options (the same
+// smoothers, in FP64, with their own coarse stage), workspaces, smoother data
+// and, for a transposed solve of a non-symmetric level, A_c^T.
+msrsb_status ensure_levels(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans)
+{
+    for (msrsb_ctx *l = c; l->child; l = l->child) {
+        if (is_tri(o->pre_smoother) || is_tri(o->post_smoother))
+            return fail(c, MSRSB_E_ARG, "the coarse levels take Jacobi-type smoothers only");
+        msrsb_ctx *ch = l->child;
+        l->child_opts = *o;
+        l->child_opts.fp32_smoother = 0;
+        l->child_opts.use_multiscale = 1;
+        msrsb_status st = ensure_workspace(ch);
+        if (st) return fail(c, st, "workspace allocation of a coarse level failed");
+        if (trans && !ch->a_symmetric && (st = ensure_transpose(ch)))
+            return fail(c, st, "next level: " + ch->err);
+        if ((st = ensure_smoother(ch, &l->child_opts, trans)))
+            return fail(c, st, "next level: " + ch->err);
+    }
+    return MSRSB_OK;
+}
+
 msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solve_opts *o,
                       msrsb_solve_info *info, int where, bool trans)
 {
@@ -458,6 +480,7 @@ msrsb_status do_solve(msrsb_ctx *c, const double *f, double *u, const msrsb_solv
         return fail(c, MSRSB_E_ARG, "the transposed solve needs the Galerkin restriction");
     if (trans && !c->a_symmetric && (st = ensure_transpose(c))) return st;
     if ((st = ensure_smoother(c, o, trans))) return fail(c, st, c->err.empty() ? "smoother set-up failed" : c->err);
+    if (o->use_multiscale && (st = ensure_levels(c, o, trans))) return st;
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
     // device buffers are used in place; host buffers are staged
     const double *df = f;
@@ -528,6 +551,7 @@ void msrsb_destroy(msrsb_ctx *c)
     if (!c) return;
     DeviceGuard g(c->device);
     hipStreamSynchronize(c->stream);
+    if (c->child) msrsb_destroy(c->child);
     free_coarse(c);
     free_matrix(c);
     dfree(c->dev_flag);
@@ -549,6 +573,7 @@ msrsb_status msrsb_set_stream(msrsb_ctx *c, void *hip_stream)
     if (!c) return MSRSB_E_ARG;
     DeviceGuard g(c->device);
     hipStreamSynchronize(c->stream);
+    if (c->child) msrsb_set_stream(c->child, hip_stream);
     c->stream = static_cast<hipStream_t>(hip_stream);
     return MSRSB_OK;
 }
@@ -671,8 +696,8 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     DeviceGuard g(c->device);
     c->err.clear();
     if (!c->has_matrix) return fail(c, MSRSB_E_STATE, "set_matrix must come first");
-    if (nc < 1 || nc > kMaxCoarse)
-        return fail(c, MSRSB_E_ARG, "nc must be in [1, " + std::to_string(kMaxCoarse) + "]");
+    if (nc < 1 || nc > kMaxCoarseLevel)
+        return fail(c, MSRSB_E_ARG, "nc must be in [1, " + std::to_string(kMaxCoarseLevel) + "]");
     if (!part || !sup_rowptr || !sup_col || !interior || !valid_where(where))
         return fail(c, MSRSB_E_ARG, "invalid coarse arguments");
     const int n = c->n;
@@ -706,6 +731,10 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
             return fail(c, MSRSB_E_ARG, "part[" + std::to_string(i) + "] not in its support row");
     }
     free_coarse(c);
+    if (c->child) {  // a new coarse space replaces every level below it
+        msrsb_destroy(c->child);
+        c->child = nullptr;
+    }
     c->nc = nc;
     c->pnnz = pnnz;
     c->pmaxw = maxw;
@@ -842,18 +871,27 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         }
     }
     c->rnnz = rnnz;
-    const size_t nn = static_cast<size_t>(nc) * nc;
-    const int ntc = (nc + 63) / 64, ntri = ntc * (ntc + 1) / 2;
     if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
         !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, rnnz) ||
-        !dalloc(c->rsrc, rnnz) || !dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
-        !dalloc(c->acinv_pk, static_cast<size_t>(ntri) * 64 * 64) ||
-        !dalloc(c->symv_part, static_cast<size_t>(ntri) * 128) ||
+        !dalloc(c->rsrc, rnnz) ||
         (r16 && (!dalloc(c->roff16, rnnz) || !dalloc(c->rbase, rnnz / 64))) ||
-        !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) || !dalloc(c->piv, nc) ||
-        !dalloc(c->colsrc, nc) || !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2) ||
-        !dalloc(c->spd_buf, static_cast<size_t>((nc + 63) / 64) * 64 * 64))
+        !dalloc(c->pcol_ell, pcol.size()) || !dalloc(c->band, 2))
         return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+    // the dense coarse operator and its inverse: only for a coarse space small
+    // enough to be the last level (a larger one needs a further level, whose
+    // matrix is the sparse A_c)
+    c->dense_coarse = nc <= kMaxCoarse;
+    if (c->dense_coarse) {
+        const size_t nn = static_cast<size_t>(nc) * nc;
+        const int ntc = (nc + 63) / 64, ntri = ntc * (ntc + 1) / 2;
+        if (!dalloc(c->ac, nn) || !dalloc(c->acinv, nn) ||
+            !dalloc(c->acinv_pk, static_cast<size_t>(ntri) * 64 * 64) ||
+            !dalloc(c->symv_part, static_cast<size_t>(ntri) * 128) ||
+            !dalloc(c->gj_b, 8 * 64 + 64 * static_cast<size_t>(nc) + nn) ||
+            !dalloc(c->piv, nc) || !dalloc(c->colsrc, nc) ||
+            !dalloc(c->spd_buf, static_cast<size_t>((nc + 63) / 64) * 64 * 64))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+    }
     hipMemcpyAsync(c->part, hpart.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->prp, hprp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(c->pci, hpci.data(), pnnz * sizeof(int), hipMemcpyHostToDevice, c->stream);
@@ -962,7 +1000,8 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
             return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
         launch_rap_cols(c->stream, c->n, nc, c->rrp, c->rci, c->a_off, c->a_dia, c->pcol16,
                         c->rap_cols, c->rap_ncol);
-        if (hipStreamSynchronize(c->stream) != hipSuccess)
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
             return fail(c, MSRSB_E_HIP, "coarse pattern failed on the device");
         c->rap_cols_valid = true;
     }
@@ -971,9 +1010,74 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     return MSRSB_OK;
 }
 
+msrsb_status msrsb_set_coarse_level(msrsb_ctx *c, int32_t level, int32_t nc, const int32_t *part,
+                                    const int32_t *sup_rowptr, const int32_t *sup_col,
+                                    const uint8_t *interior, int where)
+{
+    if (!c) return MSRSB_E_ARG;
+    DeviceGuard g(c->device);
+    c->err.clear();
+    if (level < 1) return fail(c, MSRSB_E_ARG, "level must be >= 1");
+    if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
+    if (level > 1) {
+        if (!c->child) return fail(c, MSRSB_E_STATE, "set level " + std::to_string(level - 1) +
+                                                         " first");
+        const msrsb_status st = msrsb_set_coarse_level(c->child, level - 1, nc, part, sup_rowptr,
+                                                       sup_col, interior, where);
+        if (st) return fail(c, st, c->child->err);
+        return MSRSB_OK;
+    }
+    // A_c's CSR pattern: the column lists of R A P (formed with the coarse
+    // space, ascending), which the product writes into directly
+    if (!c->rap_cols_valid || c->rmaxnb > 32)
+        return fail(c, MSRSB_E_ARG, "a further level needs a stencil operator (3, 5, 7 or 9 "
+                                    "diagonals) and supports of at most 8 coarse nodes per row");
+    const int n1 = c->nc;
+    std::vector<int> ncol(n1), cols(static_cast<size_t>(n1) * kMaxCoarseNeighbours);
+    hipMemcpyAsync(ncol.data(), c->rap_ncol, n1 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(cols.data(), c->rap_cols, cols.size() * sizeof(int), hipMemcpyDeviceToHost,
+                   c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, MSRSB_E_HIP, "reading the coarse pattern failed");
+    std::vector<int> rp(n1 + 1, 0), ci;
+    for (int j = 0; j < n1; ++j) {
+        if (ncol[j] > 32)
+            return fail(c, MSRSB_E_ARG, "a coarse row has more than 32 coarse neighbours");
+        rp[j + 1] = rp[j] + ncol[j];
+    }
+    ci.reserve(rp[n1]);
+    for (int j = 0; j < n1; ++j)
+        for (int t = 0; t < ncol[j]; ++t) ci.push_back(cols[static_cast<size_t>(j) * kMaxCoarseNeighbours + t]);
+    if (!c->child) {
+        msrsb_status st = msrsb_create(&c->child, c->device, c->stream);
+        if (st) return fail(c, st, "creating the next level failed");
+    }
+    // zero values until the first build_coarse writes A_c (a missing
+    // diagonal in the pattern is refused here)
+    std::vector<double> zeros(ci.size(), 0.0);
+    msrsb_status st = msrsb_set_matrix(c->child, n1, static_cast<int64_t>(ci.size()), rp.data(),
+                                       ci.data(), zeros.data(), 1, MSRSB_HOST);
+    if (!st) st = msrsb_set_coarse(c->child, nc, part, sup_rowptr, sup_col, interior, where);
+    if (st) return fail(c, st, "next level: " + c->child->err);
+    c->has_coarse_op = false;
+    return MSRSB_OK;
+}
+
+msrsb_status msrsb_get_level(msrsb_ctx *c, int32_t level, msrsb_ctx **out)
+{
+    if (!c || !out) return MSRSB_E_ARG;
+    *out = nullptr;
+    msrsb_ctx *l = c;
+    for (int k = 0; k < level && l; ++k) l = l->child;
+    if (level < 0 || !l) return fail(c, MSRSB_E_ARG, "no such level");
+    *out = l;
+    return MSRSB_OK;
+}
+
 msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_basis_info *info)
 {
     if (!c) return MSRSB_E_ARG;
+    if (o) c->basis_opts = *o;
     DeviceGuard g(c->device);
     c->err.clear();
     if (!c->has_coarse) return fail(c, MSRSB_E_STATE, "set_coarse must come first");
@@ -1143,7 +1247,14 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     const int nc = c->nc;
     const int64_t nn = static_cast<int64_t>(nc) * nc;
+    if (!c->child && !c->dense_coarse)
+        return fail(c, MSRSB_E_ARG, "a coarse space of more than " + std::to_string(kMaxCoarse) +
+                                        " unknowns needs a further level "
+                                        "(msrsb_set_coarse_level)");
     if (!dalloc_keep(c->p_csr_tmp, c->pnnz)) return fail(c, MSRSB_E_NOMEM, "allocation failed");
+    // with a further level the product is written as that level's CSR matrix
+    double *acout = c->child ? c->child->a : c->ac;
+    const int *csr_rp = c->child ? c->child->rp : nullptr;
     phase_begin(c, MSRSB_PHASE_RAP);
     if (restriction == MSRSB_RESTRICT_GALERKIN)
         launch_gather_r(s, c->rnnz, c->rsrc, fp32, c->p64[c->pcur], c->p32[c->pcur], c->r64,
@@ -1161,16 +1272,25 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         }
         hipMemsetAsync(c->dev_flag, 0, 2 * sizeof(int), s);
         hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
-        launch_fill(s, nn, c->ac, 0.0);
+        if (!c->child) launch_fill(s, nn, c->ac, 0.0);
         launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
-                   c->p64[c->pcur], c->p32[c->pcur], c->ac, c->dev_flag, c->band,
-                   c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol);
+                   c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
+                   c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp);
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess)
+            return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +
+                                            hipGetErrorString(le));
         int hflag[2] = {0, 0};
         hipMemcpyAsync(hflag, c->dev_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(c->h_band, c->band, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (hipStreamSynchronize(s) != hipSuccess)
             return fail(c, MSRSB_E_HIP, "coarse operator failed on the device");
+        if (hflag[1] && c->child)
+            return fail(c, MSRSB_E_ARG, "A's values opened a coarse coupling outside the next "
+                                        "level's pattern: set the coarse levels again");
+        if (hflag[0] && c->child)
+            return fail(c, MSRSB_E_ARG, "a coarse row has more columns than the next level holds");
         if (hflag[1]) {
             // A gained a nonzero outside the column lists: form them again
             // from A's current values and repeat the product
@@ -1190,6 +1310,20 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     }
     phase_end(c, MSRSB_PHASE_RAP);
     phase_begin(c, MSRSB_PHASE_FACTOR);
+    if (c->child) {
+        // the coarse solver of this level is the next level's preconditioner
+        // (Alg. 2 "set up coarse system solver"): its matrix A_c was written
+        // above; filter, basis and coarse operator of that level follow
+        msrsb_ctx *ch = c->child;
+        st = refresh_values(ch);
+        if (!st) st = msrsb_setup_basis(ch, &c->basis_opts, nullptr);
+        msrsb_coarse_opts co{MSRSB_RESTRICT_GALERKIN};
+        if (!st) st = msrsb_build_coarse(ch, &co);
+        phase_end(c, MSRSB_PHASE_FACTOR);
+        if (st) return fail(c, st, "next level: " + ch->err);
+        c->has_coarse_op = true;
+        return MSRSB_OK;
+    }
     int hflag = 0;
     st = MSRSB_E_COARSE_SINGULAR;
     c->acinv_sym = false;
@@ -1220,6 +1354,9 @@ msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *c, double *dense, int where)
     if (!c) return MSRSB_E_ARG;
     DeviceGuard g(c->device);
     if (!c->has_coarse_op) return fail(c, MSRSB_E_STATE, "build_coarse must come first");
+    if (c->child)
+        return fail(c, MSRSB_E_STATE, "with a further level A_c is that level's (sparse) matrix: "
+                                      "read it with msrsb_get_matrix on msrsb_get_level");
     if (!dense || !valid_where(where)) return fail(c, MSRSB_E_ARG, "invalid buffer");
     hipMemcpyAsync(dense, c->ac, static_cast<size_t>(c->nc) * c->nc * sizeof(double),
                    kind_out(where), c->stream);
@@ -1240,6 +1377,7 @@ msrsb_status msrsb_apply_preconditioner(msrsb_ctx *c, const msrsb_solve_opts *o,
     st = ensure_workspace(c);
     if (st) return fail(c, st, "workspace allocation failed");
     if ((st = ensure_smoother(c, o, false))) return st;
+    if (o->use_multiscale && (st = ensure_levels(c, o, false))) return st;
     const size_t bytes = static_cast<size_t>(c->n) * sizeof(double);
     hipMemcpyAsync(c->w[5], v, bytes, kind_in(where), c->stream);
     apply_two_stage(c, o, c->w[5], c->w[6], false, nullptr);

@@ -13,7 +13,8 @@ namespace msrsb {
 
 constexpr int kBlock = 256;           // default work-group size
 constexpr int kMaxPatternWidth = 32;  // max support entries per fine row
-constexpr int kMaxCoarse = 4096;      // dense coarse inverse limit
+constexpr int kMaxCoarse = 4096;      // dense coarse inverse limit (the last level)
+constexpr int kMaxCoarseLevel = 32768;  // coarse size of a level that has a further level
 constexpr int kReduceBlocks = 1024;   // partial-sum slots of two-stage reductions
 constexpr int kMaxCoarseNeighbours = 96;  // LDS slots per coarse row in R A P
 constexpr int kMaxDiag = 32;          // most diagonals of a DIA operator
@@ -208,6 +209,14 @@ struct msrsb_ctx {
     // restriction of the coarse operator (MSRSB_RESTRICT_*)
     int restriction = MSRSB_RESTRICT_GALERKIN;
 
+    // multilevel: the next level is a context of its own whose matrix is A_c
+    // (CSR on R A P's column lists, written there by the product) and whose
+    // two-stage preconditioner replaces the coarse inverse of this level
+    msrsb_ctx *child = nullptr;
+    bool dense_coarse = false;       // ac / acinv are allocated (last level)
+    msrsb_basis_opts basis_opts = {};  // of the last setup_basis (used by the levels below)
+    msrsb_solve_opts child_opts = {};  // the next level's apply options (set per solve)
+
     // Krylov workspace
     double *w[15] = {};
     float *wf[3] = {};            // FP32 work vectors of the precision-form preconditioner
@@ -333,7 +342,8 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
-                const int *cols = nullptr, const int *ncol = nullptr);
+                const int *cols = nullptr, const int *ncol = nullptr,
+                const int *csr_rp = nullptr);
 // the column lists of R A P by coarse row (ELL form only; see k_rap_cols):
 // cols [nc][kMaxCoarseNeighbours], ncol [nc]
 void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,

@@ -283,7 +283,8 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                                                 const T *__restrict__ pv, double *__restrict__ ac,
                                                 int *__restrict__ flag, int *__restrict__ band,
                                                 const int *__restrict__ cols,
-                                                const int *__restrict__ ncol)
+                                                const int *__restrict__ ncol,
+                                                const int *__restrict__ csr_rp)
 {
     extern __shared__ double smem[];
     double *acc = smem;                                         // maxnb * NT
@@ -367,7 +368,12 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
         double sum = 0.0;
         for (int l = 0; l < NT; ++l) sum += acc[s * NT + l];
         const int col = inv[s];
-        ac[static_cast<int64_t>(j) * nc + col] = sum;
+        // dense row-major, or (csr_rp) the CSR whose row j lists the columns
+        // of cols[j] in order
+        if (csr_rp)
+            ac[csr_rp[j] + s] = sum;
+        else
+            ac[static_cast<int64_t>(j) * nc + col] = sum;
         if (sum != 0.0) {
             bl = max(bl, j - col);
             bu = max(bu, col - j);
@@ -1450,34 +1456,45 @@ void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp
                                                   pci, pv, ac, flag, band);
 }
 
+// a kernel's dynamic LDS above the 64 KB default needs the function's limit
+// raised first (the column map of the coarse grid grows with nc)
+template <typename F>
+void allow_lds(F *f, size_t shmem)
+{
+    if (shmem > 65536)
+        hipFuncSetAttribute(reinterpret_cast<const void *>(f),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+}
+
 template <typename T, int ND>
 void rap_ell_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
                const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
                const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
-               const int *cols, const int *ncol)
+               const int *cols, const int *ncol, const int *csr_rp)
 {
+    allow_lds(k_rap_ell<T, 128, ND>, shmem);
     k_rap_ell<T, 128, ND><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac,
-                                                 flag, band, cols, ncol);
+                                                 flag, band, cols, ncol, csr_rp);
 }
 
 template <typename T>
 bool rap_ell(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
              const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
              const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
-             const int *cols, const int *ncol)
+             const int *cols, const int *ncol, const int *csr_rp)
 {
     switch (d.n) {
     case 3: rap_ell_t<T, 3>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol);
+                            cols, ncol, csr_rp);
         return true;
     case 5: rap_ell_t<T, 5>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol);
+                            cols, ncol, csr_rp);
         return true;
     case 7: rap_ell_t<T, 7>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol);
+                            cols, ncol, csr_rp);
         return true;
     case 9: rap_ell_t<T, 9>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol);
+                            cols, ncol, csr_rp);
         return true;
     default: return false;
     }
@@ -1495,10 +1512,22 @@ void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rc
 {
     const size_t shmem = sizeof(int) * kMaxCoarseNeighbours + sizeof(short) * nc + 16;
     switch (d.n) {
-    case 3: k_rap_cols<3><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
-    case 5: k_rap_cols<5><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
-    case 7: k_rap_cols<7><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
-    case 9: k_rap_cols<9><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol); break;
+    case 3:
+        allow_lds(k_rap_cols<3>, shmem);
+        k_rap_cols<3><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol);
+        break;
+    case 5:
+        allow_lds(k_rap_cols<5>, shmem);
+        k_rap_cols<5><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol);
+        break;
+    case 7:
+        allow_lds(k_rap_cols<7>, shmem);
+        k_rap_cols<7><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol);
+        break;
+    case 9:
+        allow_lds(k_rap_cols<9>, shmem);
+        k_rap_cols<9><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, d, ad, pcol16, cols, ncol);
+        break;
     default: break;
     }
 }
@@ -1508,7 +1537,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
-                const int *cols, const int *ncol)
+                const int *cols, const int *ncol, const int *csr_rp)
 {
     // 128 threads while the per-thread partial sums fit in 32 KB of LDS
     const int nt = maxnb <= 32 ? 128 : 64;
@@ -1516,10 +1545,11 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                          sizeof(short) * static_cast<size_t>(nc) + 16;
     // stencil A and 8-wide ELL P: the batched form
     if (nt == 128 && d.n > 0 && pw == 8 && pcol16) {
-        const bool done = fp32 ? rap_ell<float>(s, shmem, n, nc, maxnb, rrp, rci, r32, d, ad,
-                                                pcol16, pe32, ac, flag, band, cols, ncol)
-                               : rap_ell<double>(s, shmem, n, nc, maxnb, rrp, rci, r64, d, ad,
-                                                 pcol16, pe64, ac, flag, band, cols, ncol);
+        const bool done =
+            fp32 ? rap_ell<float>(s, shmem, n, nc, maxnb, rrp, rci, r32, d, ad, pcol16, pe32, ac,
+                                  flag, band, cols, ncol, csr_rp)
+                 : rap_ell<double>(s, shmem, n, nc, maxnb, rrp, rci, r64, d, ad, pcol16, pe64, ac,
+                                   flag, band, cols, ncol, csr_rp);
         if (done) return;
     }
     if (nt == 128) {

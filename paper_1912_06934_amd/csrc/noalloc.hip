@@ -82,6 +82,8 @@ extern "C" msrsb_status msrsb_apply_preconditioner_noalloc(msrsb_ctx *c,
         return done(MSRSB_E_ARG, "invalid smoother options");
     if (o->use_multiscale && !c->has_coarse_op)
         return done(MSRSB_E_STATE, "build_coarse must run before a multiscale apply");
+    if (o->use_multiscale && c->child)
+        return done(MSRSB_E_ARG, "the allocation-free apply takes two-level preconditioners only");
     // the smoother's data must already exist: forming it allocates
     const bool fp32 = o->fp32_smoother != 0;
     for (int k : {o->pre_sweeps > 0 ? o->pre_smoother : 0,

@@ -28,6 +28,7 @@ struct ApplyBufs {
 ApplyBufs ctx_apply_bufs(msrsb_ctx *c);
 
 msrsb_status ensure_workspace(msrsb_ctx *c);
+bool is_tri(int kind);
 msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans);
 // With upd, v is first produced by the PCG update upd (upd->rout == v).
 // bufs: the temporaries (null: the context's workspace).

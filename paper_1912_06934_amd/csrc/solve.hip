@@ -168,11 +168,6 @@ msrsb_status dev_alloc(T **p, size_t count)
 
 bool is_diag(int kind) { return kind == MSRSB_SMOOTH_JACOBI || kind == MSRSB_SMOOTH_L1JACOBI; }
 
-bool is_tri(int kind)
-{
-    return kind == MSRSB_SMOOTH_ILU0 || kind == MSRSB_SMOOTH_IC0 || kind == MSRSB_SMOOTH_SGS;
-}
-
 // one smoothing sweep z += M^{-1} (v - A z); with zero, z is known to be zero
 // and is not read.  The result may land in *spare, in which case the two
 // pointers are exchanged.  ord: sweep order of the triangular smoothers.
@@ -211,6 +206,11 @@ void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, doub
 }
 
 }  // namespace
+
+bool is_tri(int kind)
+{
+    return kind == MSRSB_SMOOTH_ILU0 || kind == MSRSB_SMOOTH_IC0 || kind == MSRSB_SMOOTH_SGS;
+}
 
 msrsb_status ensure_workspace(msrsb_ctx *c)
 {
@@ -318,6 +318,10 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
 // from its packed lower tiles, otherwise the dense product
 static void coarse_apply(msrsb_ctx *c, bool trans, const ApplyBufs &b)
 {
+    if (c->child) {  // multilevel: w_c = B_next v_c (the next level's workspace)
+        apply_two_stage(c->child, &c->child_opts, b.vc, b.wc, trans, nullptr);
+        return;
+    }
     if (c->acinv_sym)
         launch_symv_packed(c->stream, c->nc, c->acinv_pk, b.vc, b.wc, c->symv_part);
     else
