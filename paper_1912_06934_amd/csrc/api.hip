@@ -151,6 +151,10 @@ void free_matrix(msrsb_ctx *c)
     dfree(c->at_dia);
     dfree(c->at_dia32);
     dfree(c->jcol_ell);
+    dfree(c->ns_slot);
+    dfree(c->a_ns_val);
+    dfree(c->a_ns_val32);
+    c->a_ns = NodeStencil();
     c->a_off = DiaOffsets();
     c->at_off = DiaOffsets();
     c->j_off = DiaOffsets();
@@ -269,6 +273,9 @@ msrsb_status refresh_values(msrsb_ctx *c)
 {
     hipStream_t s = c->stream;
     if (c->a_off.n > 0) launch_csr_to_dia(s, c->n, c->a_off.n, c->rp, c->a_slot, c->a, c->a_dia, nullptr);
+    if (c->a_ns.n > 0)
+        launch_csr_to_nbs(s, c->n, c->a_ns.n * c->a_ns.bs, c->rp, c->ns_slot, c->a, c->a_ns_val,
+                          nullptr);
     hipMemsetAsync(c->dev_flag, 0, sizeof(int), s);
     launch_check_symmetric(s, c->n, c->rp, c->ci, c->a, c->dev_flag);
     int flag = 1;
@@ -322,6 +329,39 @@ msrsb_status install_pattern(msrsb_ctx *c, int n, int64_t nnz, std::vector<int> 
             if (!dalloc(c->a_slot, nnz) || !dalloc(c->a_dia, static_cast<size_t>(n) * offs.size()))
                 return fail(c, MSRSB_E_NOMEM, "device allocation of A (DIA) failed");
             hipMemcpy(c->a_slot, slot.data(), nnz, hipMemcpyHostToDevice);
+        }
+    }
+    // NBS form of a vector operator that is no DIA stencil: every entry's node
+    // offset from one set of at most 27, and each row's columns distinct slots
+    if (bs > 1 && c->a_off.n == 0 && n % bs == 0) {
+        std::vector<int> offs;
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i)
+            for (int e = c->h_rp[i]; e < c->h_rp[i + 1] && ok; ++e) {
+                const int d = c->h_ci[e] / bs - i / bs;
+                if (std::find(offs.begin(), offs.end(), d) == offs.end()) {
+                    offs.push_back(d);
+                    ok = static_cast<int>(offs.size()) <= kMaxNodeOffsets;
+                }
+            }
+        if (ok && !offs.empty()) {
+            std::sort(offs.begin(), offs.end());
+            std::vector<int8_t> slot(nnz);
+            for (int i = 0; i < n; ++i)
+                for (int e = c->h_rp[i]; e < c->h_rp[i + 1]; ++e) {
+                    const int o = static_cast<int>(
+                        std::lower_bound(offs.begin(), offs.end(), c->h_ci[e] / bs - i / bs) -
+                        offs.begin());
+                    slot[e] = static_cast<int8_t>(o * bs + c->h_ci[e] % bs);
+                }
+            c->a_ns.n = static_cast<int>(offs.size());
+            c->a_ns.bs = bs;
+            c->a_ns.nn = n / bs;
+            for (size_t t = 0; t < offs.size(); ++t) c->a_ns.off[t] = offs[t];
+            if (!dalloc(c->ns_slot, nnz) ||
+                !dalloc(c->a_ns_val, static_cast<size_t>(n) * offs.size() * bs))
+                return fail(c, MSRSB_E_NOMEM, "device allocation of A (node stencil) failed");
+            hipMemcpy(c->ns_slot, slot.data(), nnz, hipMemcpyHostToDevice);
         }
     }
     // J's pattern: A's own for scalar problems, same-component entries otherwise

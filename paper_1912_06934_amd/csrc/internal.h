@@ -53,6 +53,20 @@ struct Status {
     std::string msg;
 };
 
+// Node-block stencil (NBS) form of a vector operator with interleaved dofs
+// (dof = bs * node + l): every row reaches, for each of at most 27 node
+// offsets, the bs dofs of that neighbour node.  Values are stored as
+// [n_off * bs][n] "diagonals" (slot o * bs + l' of row r holds the entry in
+// column bs * (r / bs + off[o]) + l'), zero where a row has no such entry, so
+// the kernels read no indices and every slot is one coalesced stream.
+constexpr int kMaxNodeOffsets = 27;
+struct NodeStencil {
+    int n = 0;      // node offsets (0: no NBS form)
+    int bs = 1;
+    int nn = 0;     // nodes
+    int off[kMaxNodeOffsets] = {};
+};
+
 // Launch segment of a level-scheduled triangular sweep: one wide level (a
 // launch across the GPU) or a run of narrow levels (one work-group).
 struct TriSegment {
@@ -105,6 +119,11 @@ struct msrsb_ctx {
     bool at_pattern = false;
     bool a_symmetric_pattern_checked = false;
 
+    // NBS form of A (vector operators whose node pattern is a stencil)
+    msrsb::NodeStencil a_ns;
+    int8_t *ns_slot = nullptr;          // NBS slot of every CSR entry
+    double *a_ns_val = nullptr;         // [a_ns.n * bs][n]
+    float *a_ns_val32 = nullptr;
     // DIA form of A (when its rows use few distinct column offsets)
     msrsb::DiaOffsets a_off;
     int8_t *a_slot = nullptr;           // DIA slot of every CSR entry
@@ -396,6 +415,21 @@ void launch_diag_inverses(hipStream_t s, int n, const int *rp, const int *ci, co
                           double *dj, double *dl1, float *dj32, float *dl1_32, float *a32,
                           int64_t nnz, int *flag);
 void launch_gather_values(hipStream_t s, int64_t m, const int *src, const double *a, double *out);
+
+// ---- node-block stencil kernels (k_krylov.hip) ----
+void launch_csr_to_nbs(hipStream_t s, int n, int nslot, const int *rp, const int8_t *slot,
+                       const double *a, double *v64, float *v32);
+void launch_nbs_spmv(hipStream_t s, int n, const NodeStencil &ns, const double *v, const double *x,
+                     double *y);
+// r = f - A x; with v32 (non-null) the FP32 values and arithmetic
+void launch_nbs_residual(hipStream_t s, int n, const NodeStencil &ns, const double *v,
+                         const float *v32, const double *f, const double *x, double *r);
+void launch_nbs_sweep(hipStream_t s, int n, const NodeStencil &ns, bool fp32, const double *v,
+                      const float *v32, const double *dinv, const float *dinv32,
+                      const double *vin, const double *zin, double *zout, bool zero_start);
+void launch_nbs_pcg_p_spmv(hipStream_t s, int n, const NodeStencil &ns, const double *v,
+                           const double *z, const double *pold, double *pnew, double *q,
+                           double *part, double *scal);
 
 // ---- DIA / fused PCG kernels (k_krylov.hip) ----
 void launch_dia_spmv(hipStream_t s, int n, const DiaOffsets &d, const double *a, const double *x,

@@ -567,6 +567,127 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(int nb, const double *
     host_out[2] = tag;
 }
 
+// ---------------------------------------------------------------------------
+// Node-block stencil (NBS) kernels: thread per row r = bs * node + l, the
+// row's entries visited by node offset, then component (ascending columns,
+// the CSR order); an offset that leaves the node range, or reaches a node that
+// is no neighbour (a wrap at a grid line), has zero values.
+// ---------------------------------------------------------------------------
+template <int BS, typename MT>
+__device__ __forceinline__ MT nbs_dot(int r, int n, const NodeStencil &ns,
+                                      const MT *__restrict__ v, const double *__restrict__ x)
+{
+    const int node = r / BS;
+    MT s = MT(0);
+#pragma unroll 3
+    for (int o = 0; o < ns.n; ++o) {
+        const int nb = node + ns.off[o];
+        const bool in = nb >= 0 && nb < ns.nn;
+        const int base = (in ? nb : node) * BS;
+        MT a[BS];
+        double xv[BS];
+#pragma unroll
+        for (int l = 0; l < BS; ++l) {
+            a[l] = v[static_cast<int64_t>(o * BS + l) * n + r];
+            xv[l] = x[base + l];
+        }
+#pragma unroll
+        for (int l = 0; l < BS; ++l) s += in ? a[l] * static_cast<MT>(xv[l]) : MT(0);
+    }
+    return s;
+}
+
+template <int BS>
+__global__ __launch_bounds__(kBlock) void k_nbs_spmv(int n, NodeStencil ns,
+                                                     const double *__restrict__ v,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r < n) y[r] = nbs_dot<BS, double>(r, n, ns, v, x);
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kBlock) void k_nbs_residual(int n, NodeStencil ns,
+                                                         const MT *__restrict__ v,
+                                                         const double *__restrict__ f,
+                                                         const double *__restrict__ x,
+                                                         double *__restrict__ res)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r < n)
+        res[r] = static_cast<double>(static_cast<MT>(f[r]) - nbs_dot<BS, MT>(r, n, ns, v, x));
+}
+
+// z_out = z_in + D^{-1} (v - A z_in) (Jacobi-type sweep), or D^{-1} v from zero
+template <int BS, typename MT>
+__global__ __launch_bounds__(kBlock) void k_nbs_sweep(int n, NodeStencil ns,
+                                                      const MT *__restrict__ a,
+                                                      const MT *__restrict__ dinv,
+                                                      const double *__restrict__ vin,
+                                                      const double *__restrict__ zin,
+                                                      double *__restrict__ zout, int zero_start)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    if (zero_start) {
+        zout[r] = static_cast<double>(dinv[r] * static_cast<MT>(vin[r]));
+        return;
+    }
+    const MT s = nbs_dot<BS, MT>(r, n, ns, a, zin);
+    zout[r] = zin[r] + static_cast<double>(dinv[r] * (static_cast<MT>(vin[r]) - s));
+}
+
+// p = z + beta p_old (p = z when beta = 0), q = A p, and the p.q partials
+template <int BS>
+__global__ __launch_bounds__(kBlock) void k_nbs_pcg_p_spmv(
+    int n, NodeStencil ns, const double *__restrict__ v, const double *__restrict__ z,
+    const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ q,
+    double *__restrict__ part, const double *__restrict__ scal)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    const double beta = scal[S_BETA];
+    const bool restart = beta == 0.0;
+    double pq[1] = {0.0};
+    if (r < n) {
+        const int node = r / BS;
+        double s = 0.0;
+#pragma unroll 3
+        for (int o = 0; o < ns.n; ++o) {
+            const int nb = node + ns.off[o];
+            const bool in = nb >= 0 && nb < ns.nn;
+            const int base = (in ? nb : node) * BS;
+            double a[BS], pk[BS];
+#pragma unroll
+            for (int l = 0; l < BS; ++l) {
+                a[l] = v[static_cast<int64_t>(o * BS + l) * n + r];
+                pk[l] = restart ? z[base + l] : z[base + l] + beta * pold[base + l];
+            }
+#pragma unroll
+            for (int l = 0; l < BS; ++l) s += in ? a[l] * pk[l] : 0.0;
+        }
+        const double pr = restart ? z[r] : z[r] + beta * pold[r];
+        pnew[r] = pr;
+        q[r] = s;
+        pq[0] = pr * s;
+    }
+    block_partials<1>(pq, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_csr_to_nbs(int n, int nslot,
+                                                       const int *__restrict__ rp,
+                                                       const int8_t *__restrict__ slot,
+                                                       const double *__restrict__ a,
+                                                       T *__restrict__ v)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    for (int t = 0; t < nslot; ++t) v[static_cast<int64_t>(t) * n + r] = T(0);
+    for (int e = rp[r]; e < rp[r + 1]; ++e)
+        v[static_cast<int64_t>(slot[e]) * n + r] = static_cast<T>(a[e]);
+}
+
 template <int ND, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_dia_spmv(int n, DiaOffsets d,
                                                      const double *__restrict__ a,
@@ -1466,6 +1587,68 @@ void launch_check_symmetric(hipStream_t s, int n, const int *rp, const int *ci, 
                             int *flag)
 {
     k_check_symmetric<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, a, flag);
+}
+
+
+// ---- node-block stencil launchers ----
+template <typename F>
+void with_bs(int bs, F &&f)
+{
+    if (bs == 2) f(std::integral_constant<int, 2>{});
+    else f(std::integral_constant<int, 3>{});
+}
+
+void launch_csr_to_nbs(hipStream_t s, int n, int nslot, const int *rp, const int8_t *slot,
+                       const double *a, double *v64, float *v32)
+{
+    if (v64) k_csr_to_nbs<double><<<grid_for(n), kBlock, 0, s>>>(n, nslot, rp, slot, a, v64);
+    if (v32) k_csr_to_nbs<float><<<grid_for(n), kBlock, 0, s>>>(n, nslot, rp, slot, a, v32);
+}
+
+void launch_nbs_spmv(hipStream_t s, int n, const NodeStencil &ns, const double *v, const double *x,
+                     double *y)
+{
+    with_bs(ns.bs, [&](auto b) {
+        k_nbs_spmv<decltype(b)::value><<<grid_for(n), kBlock, 0, s>>>(n, ns, v, x, y);
+    });
+}
+
+void launch_nbs_residual(hipStream_t s, int n, const NodeStencil &ns, const double *v,
+                         const float *v32, const double *f, const double *x, double *r)
+{
+    with_bs(ns.bs, [&](auto b) {
+        constexpr int BS = decltype(b)::value;
+        if (v32)
+            k_nbs_residual<BS, float><<<grid_for(n), kBlock, 0, s>>>(n, ns, v32, f, x, r);
+        else
+            k_nbs_residual<BS, double><<<grid_for(n), kBlock, 0, s>>>(n, ns, v, f, x, r);
+    });
+}
+
+void launch_nbs_sweep(hipStream_t s, int n, const NodeStencil &ns, bool fp32, const double *v,
+                      const float *v32, const double *dinv, const float *dinv32,
+                      const double *vin, const double *zin, double *zout, bool zero_start)
+{
+    with_bs(ns.bs, [&](auto b) {
+        constexpr int BS = decltype(b)::value;
+        if (fp32)
+            k_nbs_sweep<BS, float><<<grid_for(n), kBlock, 0, s>>>(n, ns, v32, dinv32, vin, zin,
+                                                                  zout, zero_start ? 1 : 0);
+        else
+            k_nbs_sweep<BS, double><<<grid_for(n), kBlock, 0, s>>>(n, ns, v, dinv, vin, zin, zout,
+                                                                   zero_start ? 1 : 0);
+    });
+}
+
+void launch_nbs_pcg_p_spmv(hipStream_t s, int n, const NodeStencil &ns, const double *v,
+                           const double *z, const double *pold, double *pnew, double *q,
+                           double *part, double *scal)
+{
+    with_bs(ns.bs, [&](auto b) {
+        k_nbs_pcg_p_spmv<decltype(b)::value><<<grid_for(n), kBlock, 0, s>>>(n, ns, v, z, pold,
+                                                                            pnew, q, part, scal);
+    });
+    k_fin_alpha<<<1, kFinThreads, 0, s>>>(grid_for(n), part, scal);
 }
 
 }  // namespace msrsb

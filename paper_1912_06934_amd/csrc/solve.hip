@@ -104,6 +104,9 @@ struct Op {
     const float *ad32;
     const double *dj, *dl1;
     const float *dj32, *dl132;
+    NodeStencil ns;            // NBS form (ns.n == 0: none)
+    const double *nv;
+    const float *nv32;
 };
 
 Op fine_op(msrsb_ctx *c, bool trans)
@@ -121,6 +124,9 @@ Op fine_op(msrsb_ctx *c, bool trans)
         o.dl1 = c->dinv_l1;
         o.dj32 = c->dinv_jac32;
         o.dl132 = c->dinv_l1_32;
+        o.ns = c->a_ns;
+        o.nv = c->a_ns_val;
+        o.nv32 = c->a_ns_val32;
     } else {
         o.rp = c->at_rp;
         o.ci = c->at_ci;
@@ -133,6 +139,9 @@ Op fine_op(msrsb_ctx *c, bool trans)
         o.dl1 = c->dinv_l1_t;
         o.dj32 = c->dinv_jac32_t;
         o.dl132 = c->dinv_l1_32_t;
+        o.ns = NodeStencil();
+        o.nv = nullptr;
+        o.nv32 = nullptr;
     }
     return o;
 }
@@ -144,6 +153,8 @@ void op_residual(hipStream_t s, int n, const Op &o, const double *f, const doubl
 {
     if (o.d.n > 0)
         launch_dia_residual(s, n, o.d, o.ad, fp32 ? o.ad32 : nullptr, f, x, r);
+    else if (o.ns.n > 0)
+        launch_nbs_residual(s, n, o.ns, o.nv, fp32 ? o.nv32 : nullptr, f, x, r);
     else
         launch_residual(s, n, o.rp, o.ci, o.a, f, x, r);
 }
@@ -152,8 +163,20 @@ void op_spmv(hipStream_t s, int n, const Op &o, const double *x, double *y)
 {
     if (o.d.n > 0)
         launch_dia_spmv(s, n, o.d, o.ad, x, y);
+    else if (o.ns.n > 0)
+        launch_nbs_spmv(s, n, o.ns, o.nv, x, y);
     else
         launch_spmv(s, n, o.rp, o.ci, o.a, x, y);
+}
+
+// p = z + beta p_old, q = A p, p.q and alpha (PCG)
+void p_spmv(hipStream_t s, int n, const Op &o, const double *z, const double *pold, double *pnew,
+            double *q, double *part, double *sc)
+{
+    if (o.d.n == 0 && o.ns.n > 0)
+        launch_nbs_pcg_p_spmv(s, n, o.ns, o.nv, z, pold, pnew, q, part, sc);
+    else
+        launch_pcg_p_spmv(s, n, o.d, o.ad, o.rp, o.ci, o.a, z, pold, pnew, q, part, sc);
 }
 
 template <typename T>
@@ -182,6 +205,8 @@ void sweep(msrsb_ctx *c, const Op &o, int kind, bool fp32, const double *v, doub
         const float *d32 = l1 ? o.dl132 : o.dj32;
         if (o.d.n > 0 && !zero)
             launch_dia_sweep(s, n, o.d, fp32, o.ad, o.ad32, d64, d32, v, *z, *spare, false);
+        else if (o.ns.n > 0)
+            launch_nbs_sweep(s, n, o.ns, fp32, o.nv, o.nv32, d64, d32, v, *z, *spare, zero);
         else
             launch_sweep(s, n, o.rp, o.ci, o.a, o.a32, d64, d32, fp32, v, *z, *spare, zero);
         std::swap(*z, *spare);
@@ -255,11 +280,16 @@ msrsb_status ensure_smoother(msrsb_ctx *c, const msrsb_solve_opts *o, bool trans
                          dev_alloc(&c->a32, static_cast<size_t>(c->nnz))))
                 return MSRSB_E_NOMEM;
             if (fp32 && noff > 0 && dev_alloc(&c->a_dia32, n * noff)) return MSRSB_E_NOMEM;
+            const size_t nslot = static_cast<size_t>(c->a_ns.n) * c->a_ns.bs;
+            if (fp32 && nslot > 0 && dev_alloc(&c->a_ns_val32, n * nslot)) return MSRSB_E_NOMEM;
             launch_diag_inverses(s, c->n, c->rp, c->ci, c->a, c->dinv_jac, c->dinv_l1,
                                  fp32 ? c->dinv_jac32 : nullptr, fp32 ? c->dinv_l1_32 : nullptr,
                                  fp32 ? c->a32 : nullptr, c->nnz, c->dev_flag);
             if (fp32 && noff > 0)
                 launch_csr_to_dia(s, c->n, noff, c->rp, c->a_slot, c->a, nullptr, c->a_dia32);
+            if (fp32 && nslot > 0)
+                launch_csr_to_nbs(s, c->n, static_cast<int>(nslot), c->rp, c->ns_slot, c->a,
+                                  nullptr, c->a_ns_val32);
             c->smoother_valid = true;
             c->smoother32_valid = fp32;
         }
@@ -536,7 +566,7 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
             queued = false;
         }
         if (!queued) {
-            launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
+            p_spmv(s, n, op, z, p, p2, q, c->partials, sc);
             std::swap(p, p2);
         }
         ++it;
@@ -553,7 +583,7 @@ msrsb_status pcg(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_opt
         apply_two_stage(c, o, r, z, trans, &dots, &upd);
         queued = it < o->max_iter;
         if (queued) {
-            launch_pcg_p_spmv(s, n, op.d, op.ad, op.rp, op.ci, op.a, z, p, p2, q, c->partials, sc);
+            p_spmv(s, n, op, z, p, p2, q, c->partials, sc);
             std::swap(p, p2);
         }
         if (!wait_mailbox(s, hmon, it)) {
