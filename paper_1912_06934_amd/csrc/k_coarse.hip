@@ -273,7 +273,7 @@ __global__ __launch_bounds__(128) void k_rap_cols(int n, int nc, const int *__re
 // values gained a nonzero since the lists were formed) sets flag[1], and
 // the caller rebuilds the lists and repeats; more columns than maxnb set
 // flag[0].
-template <typename T, int NT, int ND>
+template <typename T, int NT, int ND, bool CSR>
 __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                                                 const int *__restrict__ rrp,
                                                 const int *__restrict__ rci,
@@ -368,9 +368,9 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
         double sum = 0.0;
         for (int l = 0; l < NT; ++l) sum += acc[s * NT + l];
         const int col = inv[s];
-        // dense row-major, or (csr_rp) the CSR whose row j lists the columns
-        // of cols[j] in order
-        if (csr_rp)
+        // dense row-major, or (CSR) the CSR whose row j lists the columns of
+        // cols[j] in order
+        if constexpr (CSR)
             ac[csr_rp[j] + s] = sum;
         else
             ac[static_cast<int64_t>(j) * nc + col] = sum;
@@ -1472,9 +1472,17 @@ void rap_ell_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int 
                const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
                const int *cols, const int *ncol, const int *csr_rp)
 {
-    allow_lds(k_rap_ell<T, 128, ND>, shmem);
-    k_rap_ell<T, 128, ND><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac,
-                                                 flag, band, cols, ncol, csr_rp);
+    if (csr_rp) {
+        allow_lds(k_rap_ell<T, 128, ND, true>, shmem);
+        k_rap_ell<T, 128, ND, true><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad,
+                                                           pcol16, pv, ac, flag, band, cols,
+                                                           ncol, csr_rp);
+    } else {
+        allow_lds(k_rap_ell<T, 128, ND, false>, shmem);
+        k_rap_ell<T, 128, ND, false><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad,
+                                                            pcol16, pv, ac, flag, band, cols,
+                                                            ncol, nullptr);
+    }
 }
 
 template <typename T>
