@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--forms", default="fp32,fp64",
+                    help="forms of the 128^3 step to run (profiling runs take one)")
     ap.add_argument("--dims", type=int, nargs=3, default=None, help="override the grid (debug)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
@@ -369,7 +371,8 @@ def main():
         return b, info
 
     results = {}
-    for form, fp32 in (("fp32", True), ("fp64", False)):
+    forms = [f for f in ("fp32", "fp64") if f in args.forms.split(",")]
+    for form, fp32 in [(f, f == "fp32") for f in forms]:
         for _ in range(args.warmup):
             step(fp32)
         torch.cuda.synchronize()
@@ -422,6 +425,10 @@ def main():
 
     # ---------------- the other workloads ----------------
     extra = None if args.no_extra else run_extra(dev, max(1, min(args.steps, 3)))
+
+    if "fp32" not in results or "fp64" not in results:
+        log("profiling run: one form only, no JSON line")
+        return
 
     # ---------------- rooflines ----------------
     fp32 = results["fp32"]

@@ -183,7 +183,7 @@ msrsb_status msrsb_assemble_tpfa(msrsb_ctx *ctx, int32_t dim, const int32_t dims
  * instead of loading them (checked for every row here; results unchanged).
  * Errors: E_ARG for nc < 1 or nc > 32768 (more than 4096 needs a further
  * level, see msrsb_set_coarse_level), empty rows, unsorted or out-of-range
- * columns, part[i] not in row i's pattern. */
+ * columns, part[i] not in row i's pattern, a coarse block without rows. */
 msrsb_status msrsb_set_coarse(msrsb_ctx *ctx, int32_t nc, const int32_t *part,
                               const int32_t *sup_rowptr, const int32_t *sup_col,
                               const uint8_t *interior, int where);

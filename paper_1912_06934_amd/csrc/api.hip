@@ -770,6 +770,14 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         if (!found)
             return fail(c, MSRSB_E_ARG, "part[" + std::to_string(i) + "] not in its support row");
     }
+    {
+        // every coarse block holds a row (its basis function starts there)
+        std::vector<uint8_t> owned(nc, 0);
+        for (int i = 0; i < n; ++i) owned[hpart[i]] = 1;
+        for (int j = 0; j < nc; ++j)
+            if (!owned[j])
+                return fail(c, MSRSB_E_ARG, "coarse block " + std::to_string(j) + " has no row");
+    }
     free_coarse(c);
     if (c->child) {  // a new coarse space replaces every level below it
         msrsb_destroy(c->child);

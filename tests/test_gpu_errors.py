@@ -97,6 +97,9 @@ def test_invalid_inputs(lib):
         s.set_coarse(2, part, prp, np.array([0, 0, 1, 1, 1, 1], np.int32), np.ones(6, np.uint8))
     assert _code(e) == E_ARG
     with pytest.raises(MsrsbError) as e:                 # too many coarse unknowns
+        s.set_coarse(32769, part, prp, part, np.ones(6, np.uint8))
+    assert _code(e) == E_ARG
+    with pytest.raises(MsrsbError) as e:                 # coarse blocks without rows
         s.set_coarse(5000, part, prp, part, np.ones(6, np.uint8))
     assert _code(e) == E_ARG
 
