@@ -145,8 +145,12 @@ msrsb_status msrsb_set_matrix(msrsb_ctx *ctx, int32_t n, int64_t nnz,
                               const int32_t *rowptr, const int32_t *col,
                               const double *val, int32_t block_size, int where);
 
-/* New values on the same pattern (nnz values).  P, A_c and the smoother
- * keep their old values until the next setup_basis / build_coarse. */
+/* New values on the same pattern (nnz values): the next time step of
+ * Alg. 2, whose set-up runs again on the changed operator while the
+ * partition, the supports and P's frozen pattern (Sec. 2.1) stay.  P, A_c
+ * and the smoother keep their old values until the next setup_basis /
+ * build_coarse, so the smoothing may warm-start from the previous P.
+ * Errors: E_STATE before set_matrix. */
 msrsb_status msrsb_update_values(msrsb_ctx *ctx, const double *val, int where);
 
 /* Copy the current A out: rowptr (n+1), col (nnz) and val (nnz) buffers,
@@ -245,9 +249,15 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *ctx, const msrsb_basis_opts *opts,
                                msrsb_basis_info *info);
 
 /* Overwrite P's values (nnz_P values on the support pattern, FP64), e.g. to
- * resume from a saved basis.  Marks the basis as set up. */
+ * resume from a saved basis: Alg. 2 initialises the basis only when none
+ * exists, so a P put back here is the start of the next warm-started
+ * smoothing (Alg. 1).  Marks the basis as set up; the caller owns val.
+ * Errors: E_STATE before set_coarse. */
 msrsb_status msrsb_set_prolongation(msrsb_ctx *ctx, const double *val, int where);
-/* Copy P out (FP64 values; any pointer may be NULL). */
+/* Copy P out (FP64 values; any pointer may be NULL): the prolongation of
+ * Sec. 2.1 as Alg. 1 left it, rowptr (n + 1) and col (nnz_P) its frozen
+ * support pattern.  Errors: E_STATE before set_coarse, or for val before
+ * the basis exists. */
 msrsb_status msrsb_get_prolongation(msrsb_ctx *ctx, int32_t *rowptr, int32_t *col,
                                     double *val, int where);
 
@@ -269,7 +279,10 @@ typedef struct {
  * Errors: E_STATE before setup_basis; E_ARG for an unknown restriction;
  * E_COARSE_SINGULAR on a zero pivot (pivoting form). */
 msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);
-/* Copy A_c out as a dense row-major nc x nc FP64 matrix. */
+/* Copy A_c = R A P (eq. lin_system_coarse, Alg. 2) out as a dense row-major
+ * nc x nc FP64 matrix; the caller owns dense (nc * nc values).
+ * Errors: E_STATE before build_coarse, or when a further level holds A_c
+ * (then msrsb_get_matrix on that level's context). */
 msrsb_status msrsb_get_coarse_matrix(msrsb_ctx *ctx, double *dense, int where);
 
 typedef struct {
@@ -389,7 +402,10 @@ msrsb_status msrsb_q1_adjoint_grad(msrsb_ctx *ctx, const double *u, const double
                                    double *grad, int where);
 
 /* Milliseconds of the last run of each phase (MSRSB_PHASE_*), measured
- * with HIP events on the context's stream.  Synchronises. */
+ * with HIP events on the context's stream: the set-up steps of Alg. 1 and
+ * Alg. 2 and the solves around Alg. 3-4 (instrumentation, not part of the
+ * method).  Writes n_phases values, zero for phases past MSRSB_N_PHASES
+ * or not run yet.  Synchronises. */
 msrsb_status msrsb_get_timings(msrsb_ctx *ctx, double *ms_by_phase, int32_t n_phases);
 
 #ifdef __cplusplus
