@@ -186,10 +186,26 @@ def system_info():
     try:
         import torch
         if torch.cuda.is_available():
-            info["gpu"] = torch.cuda.get_device_name(0)
+            prop = torch.cuda.get_device_properties(0)
+            info["gpu"] = prop.name or ""
+            info["gpu_arch"] = getattr(prop, "gcnArchName", "")
+            info["gpu_cus"] = prop.multi_processor_count
+            info["gpu_mem_gib"] = round(prop.total_memory / 2**30, 1)
             info["torch_hip"] = torch.version.hip
     except Exception:  # pragma: no cover
         pass
+    if not info.get("gpu"):
+        # the marketing name from the runtime's agent list when torch has none
+        try:
+            out = subprocess.run(["/opt/rocm/bin/rocminfo"], capture_output=True, text=True,
+                                 timeout=30).stdout
+            names = [l.split(":", 1)[1].strip() for l in out.splitlines()
+                     if l.strip().startswith("Marketing Name")]
+            gpus = [x for x in names if "Instinct" in x or "MI" in x]
+            if gpus:
+                info["gpu"] = gpus[0]
+        except (OSError, subprocess.SubprocessError):
+            pass
     return info
 
 

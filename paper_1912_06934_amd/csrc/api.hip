@@ -1052,6 +1052,26 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         if (le != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
             return fail(c, MSRSB_E_HIP, "coarse pattern failed on the device");
         c->rap_cols_valid = true;
+    } else if (rap_uses_nbs(c->a_ns, c->pw, c->pcol16) && c->a_ns_val) {
+        // node-block stencil A: the same lists through its node offsets; the
+        // product then reserves LDS for the longest list only
+        if (!dalloc(c->rap_cols, static_cast<size_t>(nc) * kMaxCoarseNeighbours) ||
+            !dalloc(c->rap_ncol, nc))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        launch_rap_cols(c->stream, c->n, nc, c->rrp, c->rci, c->a_off, nullptr, c->pcol16,
+                        c->rap_cols, c->rap_ncol, &c->a_ns, c->a_ns_val);
+        std::vector<int> hn(nc);
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess ||
+            hipMemcpyAsync(hn.data(), c->rap_ncol, nc * sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return fail(c, MSRSB_E_HIP, "coarse pattern failed on the device");
+        const int mx = *std::max_element(hn.begin(), hn.end());
+        if (mx <= kMaxCoarseNeighbours) {
+            c->rmaxnb = std::max(mx, 1);
+            c->rap_cols_valid = true;
+        }
     }
     c->has_coarse = true;
     c->has_basis = c->has_coarse_op = false;
@@ -1312,8 +1332,11 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
                            c->r32);
     bool have_csr = false;  // the CSR copy of P, for the general RAP only
     bool lists_rebuilt = false;
+    // the node-block stencil form runs on its column lists (no CSR copy of P)
+    const bool nbs = rap_uses_nbs(c->a_ns, c->pw, c->pcol16) && c->a_ns_val && !csr_rp;
     for (;;) {
-        if (!have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16)) {
+        if (!have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16) &&
+            !(nbs && c->rap_cols_valid)) {
             launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
                               c->p_csr_tmp);
             have_csr = true;
@@ -1324,7 +1347,8 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
                    c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
-                   c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp);
+                   c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp,
+                   nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess)
             return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +
@@ -1344,8 +1368,12 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
             // from A's current values and repeat the product
             if (lists_rebuilt)
                 return fail(c, MSRSB_E_HIP, "coarse operator pattern is inconsistent");
-            launch_rap_cols(s, c->n, nc, c->rrp, c->rci, c->a_off, c->a_dia, c->pcol16,
-                            c->rap_cols, c->rap_ncol);
+            if (nbs)
+                launch_rap_cols(s, c->n, nc, c->rrp, c->rci, c->a_off, nullptr, c->pcol16,
+                                c->rap_cols, c->rap_ncol, &c->a_ns, c->a_ns_val);
+            else
+                launch_rap_cols(s, c->n, nc, c->rrp, c->rci, c->a_off, c->a_dia, c->pcol16,
+                                c->rap_cols, c->rap_ncol);
             lists_rebuilt = true;
             continue;
         }

@@ -362,12 +362,17 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols = nullptr, const int *ncol = nullptr,
-                const int *csr_rp = nullptr);
-// the column lists of R A P by coarse row (ELL form only; see k_rap_cols):
-// cols [nc][kMaxCoarseNeighbours], ncol [nc]
+                const int *csr_rp = nullptr, const NodeStencil *ns = nullptr,
+                const double *nsv = nullptr);
+// whether the node-block stencil form of A (ns, values in FP64) takes the
+// stencil/ELL product (k_rap_nbs; needs its column lists, no CSR copy of P)
+bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16);
+// the column lists of R A P by coarse row (stencil forms only; see
+// k_rap_cols, k_rap_nbs_cols): cols [nc][kMaxCoarseNeighbours], ncol [nc];
+// with ns (node-block form) nsv holds its values and d, ad are not used
 void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,
                      const DiaOffsets &d, const double *ad, const uint16_t *pcol16, int *cols,
-                     int *ncol);
+                     int *ncol, const NodeStencil *ns = nullptr, const double *nsv = nullptr);
 msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
                                 double *pk, int *flag, int *host_flag);
 // y = S x for the symmetric S in the packed lower-tile form (acinv_pk)

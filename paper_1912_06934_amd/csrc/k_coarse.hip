@@ -5,6 +5,8 @@
 
 #include "internal.h"
 
+#include <type_traits>
+
 namespace msrsb {
 namespace {
 
@@ -166,14 +168,53 @@ __device__ __forceinline__ void load_prow(const PT *__restrict__ p, const uint16
 // order, map[c] = slot or -1 and inv[slot] = c.  Returns their count (in
 // every thread); the numbering is done only when the count fits cap.
 // Called by all NT threads.
+// Numbers the coarse columns marked in map (nc entries, 1 = marked) in
+// ascending order: map[c] = slot or -1 and inv[slot] = c.  Returns their
+// count (in every thread); the numbering is done only when the count fits
+// cap.  Called by all NT threads after the marking.
+template <int NT>
+__device__ inline int number_columns(int nc, int cap, short *map, int *inv)
+{
+    __shared__ int wsum[NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int chunk = (nc + NT - 1) / NT;
+    const int lo = tid * chunk, hi = min(nc, lo + chunk);
+    int cnt = 0;
+    for (int t = lo; t < hi; ++t) cnt += map[t];
+    int pre = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(pre, off, 64);
+        if (lane >= off) pre += o;
+    }
+    if (lane == 63) wsum[wid] = pre;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        total += wsum[w];
+    }
+    if (total > cap) return total;
+    int slot = base + pre - cnt;
+    __syncthreads();
+    for (int t = lo; t < hi; ++t) {
+        if (map[t]) {
+            inv[slot] = t;
+            map[t] = static_cast<short>(slot++);
+        } else {
+            map[t] = -1;
+        }
+    }
+    return total;
+}
+
 template <int NT, int ND>
 __device__ inline int rap_columns(int n, int nc, int j, int cap, const int *__restrict__ rrp,
                                   const int *__restrict__ rci, const DiaOffsets &d,
                                   const double *__restrict__ ad,
                                   const uint16_t *__restrict__ pcol, short *map, int *inv)
 {
-    __shared__ int wsum[NT / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x;
     for (int t = tid; t < nc; t += NT) map[t] = 0;
     __syncthreads();
     const int t0 = rrp[j], t1 = rrp[j + 1];
@@ -212,36 +253,7 @@ __device__ inline int rap_columns(int n, int nc, int j, int cap, const int *__re
             }
     }
     __syncthreads();
-    // number the marked coarse columns in ascending order (block scan)
-    const int chunk = (nc + NT - 1) / NT;
-    const int lo = tid * chunk, hi = min(nc, lo + chunk);
-    int cnt = 0;
-    for (int t = lo; t < hi; ++t) cnt += map[t];
-    int pre = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(pre, off, 64);
-        if (lane >= off) pre += o;
-    }
-    if (lane == 63) wsum[wid] = pre;
-    __syncthreads();
-    int base = 0, total = 0;
-    for (int w = 0; w < NT / 64; ++w) {
-        if (w < wid) base += wsum[w];
-        total += wsum[w];
-    }
-    if (total > cap) return total;
-    int slot = base + pre - cnt;
-    __syncthreads();
-    for (int t = lo; t < hi; ++t) {
-        if (map[t]) {
-            inv[slot] = t;
-            map[t] = static_cast<short>(slot++);
-        } else {
-            map[t] = -1;
-        }
-    }
-    return total;
+    return number_columns<NT>(nc, cap, map, inv);
 }
 
 // The column lists of R A P by coarse row, once per pattern (set-up of the
@@ -374,6 +386,177 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
             ac[csr_rp[j] + s] = sum;
         else
             ac[static_cast<int64_t>(j) * nc + col] = sum;
+        if (sum != 0.0) {
+            bl = max(bl, j - col);
+            bu = max(bu, col - j);
+        }
+    }
+    if (bl > 0) atomicMax(band, bl);
+    if (bu > 0) atomicMax(band + 1, bu);
+}
+
+// ---------------------------------------------------------------------------
+// R A P for a node-block stencil A (NodeStencil: BS components per node,
+// coefficient of row r at node offset o and column component l in
+// v[(o BS + l) n + r], zero where the row has no such entry) and P in its
+// row-major ELL form (8 slots, 16-bit columns).  Fine row i of R's row j
+// reaches, through A, the P rows BS (node(i) + off[o]) + l; their columns
+// are A_c's columns of row j.  Same structure as the DIA form above: the
+// column lists once per pattern, then a numeric pass with per-thread LDS
+// partial sums added in thread order (bitwise reproducible).
+// ---------------------------------------------------------------------------
+template <int BS>
+__global__ __launch_bounds__(128) void k_rap_nbs_cols(int n, int nc, const int *__restrict__ rrp,
+                                                      const int *__restrict__ rci, NodeStencil ns,
+                                                      const double *__restrict__ av,
+                                                      const uint16_t *__restrict__ pcol,
+                                                      int *__restrict__ cols,
+                                                      int *__restrict__ ncol)
+{
+    extern __shared__ double smem[];
+    int *inv = reinterpret_cast<int *>(smem);                            // kMaxCoarseNeighbours
+    short *map = reinterpret_cast<short *>(inv + kMaxCoarseNeighbours);  // nc
+    typedef uint16_t cvec __attribute__((ext_vector_type(8)));
+    const int j = blockIdx.x;
+    for (int t = threadIdx.x; t < nc; t += 128) map[t] = 0;
+    __syncthreads();
+    const int t0 = rrp[j], t1 = rrp[j + 1];
+    for (int t = t0 + threadIdx.x; t < t1; t += 128) {
+        const int i = rci[t];
+        const int node = i / BS;
+        for (int o = 0; o < ns.n; ++o) {
+            const int nb = node + ns.off[o];
+            const bool in = nb >= 0 && nb < ns.nn;
+            double a[BS];
+            cvec cc[BS];
+#pragma unroll
+            for (int l = 0; l < BS; ++l) {
+                a[l] = in ? av[static_cast<int64_t>(o * BS + l) * n + i] : 0.0;
+                cc[l] = *reinterpret_cast<const cvec *>(
+                    pcol + static_cast<int64_t>(in ? nb * BS + l : i) * 8);
+            }
+#pragma unroll
+            for (int l = 0; l < BS; ++l) {
+                if (a[l] == 0.0) continue;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (cc[l][u] != 0xFFFFu) map[cc[l][u]] = 1;
+            }
+        }
+    }
+    __syncthreads();
+    const int total = number_columns<128>(nc, kMaxCoarseNeighbours, map, inv);
+    __syncthreads();
+    if (total <= kMaxCoarseNeighbours)
+        for (int q = threadIdx.x; q < total; q += 128)
+            cols[static_cast<int64_t>(j) * kMaxCoarseNeighbours + q] = inv[q];
+    if (threadIdx.x == 0) ncol[j] = total;
+}
+
+// The numeric product (one wavefront per coarse row): a thread takes R
+// entries t, t + 64, ...; for each node offset it loads the BS coefficients
+// and P rows, the next offset's loads issued before the current one's sums.
+template <typename T, int BS>
+__global__ __launch_bounds__(64) void k_rap_nbs(int n, int nc, int maxnb,
+                                                const int *__restrict__ rrp,
+                                                const int *__restrict__ rci,
+                                                const T *__restrict__ rv, NodeStencil ns,
+                                                const double *__restrict__ av,
+                                                const uint16_t *__restrict__ pcol,
+                                                const T *__restrict__ pv, double *__restrict__ ac,
+                                                int *__restrict__ flag, int *__restrict__ band,
+                                                const int *__restrict__ cols,
+                                                const int *__restrict__ ncol)
+{
+    constexpr int NT = 64;
+    extern __shared__ double smem[];
+    double *acc = smem;                                    // maxnb * NT
+    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);  // maxnb
+    short *map = reinterpret_cast<short *>(inv + maxnb);   // nc
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int total = ncol[j];
+    if (total > maxnb) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    for (int t = tid; t < nc; t += NT) map[t] = -1;
+    __syncthreads();
+    for (int q = tid; q < total; q += NT) {
+        const int c = cols[static_cast<int64_t>(j) * kMaxCoarseNeighbours + q];
+        inv[q] = c;
+        map[c] = static_cast<short>(q);
+    }
+    for (int q = 0; q < total; ++q) acc[q * NT + tid] = 0.0;
+    __syncthreads();
+    const int t0 = rrp[j], t1 = rrp[j + 1];
+    bool miss = false;
+    // UE entries of a thread per step (t, t + NT, ...), each with the BS
+    // coefficients and P rows of one node offset; the next offset's loads
+    // are issued before the current one's sums
+    constexpr int UE = 2;
+    double a[2][UE][BS];
+    T v[2][UE][BS][8];
+    uint16_t cl[2][UE][BS][8];
+    int ie[UE], ne[UE];
+    double pe[UE];
+    auto load = [&](int b, int o) {
+#pragma unroll
+        for (int e = 0; e < UE; ++e) {
+            const int nb = ne[e] + ns.off[o];
+            const bool in = nb >= 0 && nb < ns.nn && pe[e] != 0.0;
+#pragma unroll
+            for (int l = 0; l < BS; ++l) {
+                a[b][e][l] = in ? av[static_cast<int64_t>(o * BS + l) * n + ie[e]] : 0.0;
+                load_prow<T>(pv, pcol, in ? nb * BS + l : ie[e], v[b][e][l], cl[b][e][l]);
+            }
+        }
+    };
+    auto add = [&](int b) {
+#pragma unroll
+        for (int e = 0; e < UE; ++e)
+#pragma unroll
+            for (int l = 0; l < BS; ++l) {
+                if (a[b][e][l] == 0.0) continue;
+                const double pa = pe[e] * a[b][e][l];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (cl[b][e][l][u] == 0xFFFFu) continue;
+                    const int sl = map[cl[b][e][l][u]];
+                    const double prod = pa * static_cast<double>(v[b][e][l][u]);
+                    if (sl >= 0)
+                        atomicAdd(&acc[sl * NT + tid], prod);
+                    else if (prod != 0.0)
+                        miss = true;
+                }
+            }
+    };
+    for (int t = t0 + tid; t < t1; t += UE * NT) {
+        // entries past the row, and R's padding (value 0), add nothing
+#pragma unroll
+        for (int e = 0; e < UE; ++e) {
+            const bool ok = t + e * NT < t1;
+            ie[e] = rci[ok ? t + e * NT : t];
+            pe[e] = ok ? static_cast<double>(rv[t + e * NT]) : 0.0;
+            ne[e] = ie[e] / BS;
+        }
+        load(0, 0);
+        for (int o = 0; o < ns.n; o += 2) {
+            if (o + 1 < ns.n) load(1, o + 1);
+            add(0);
+            if (o + 1 >= ns.n) break;
+            if (o + 2 < ns.n) load(0, o + 2);
+            add(1);
+        }
+    }
+    if (miss) flag[1] = 1;
+    __syncthreads();
+    int bl = 0, bu = 0;
+    for (int q = tid; q < total; q += NT) {
+        double sum = 0.0;
+        for (int l = 0; l < NT; ++l) sum += acc[q * NT + l];
+        const int col = inv[q];
+        ac[static_cast<int64_t>(j) * nc + col] = sum;
         if (sum != 0.0) {
             bl = max(bl, j - col);
             bu = max(bu, col - j);
@@ -1514,11 +1697,26 @@ bool rap_uses_ell(int maxnb, const DiaOffsets &d, int pw, const uint16_t *pcol16
            (d.n == 3 || d.n == 5 || d.n == 7 || d.n == 9);
 }
 
+bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16)
+{
+    return ns.n > 0 && (ns.bs == 2 || ns.bs == 3) && pw == 8 && pcol16;
+}
+
 void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,
                      const DiaOffsets &d, const double *ad, const uint16_t *pcol16, int *cols,
-                     int *ncol)
+                     int *ncol, const NodeStencil *ns, const double *nsv)
 {
     const size_t shmem = sizeof(int) * kMaxCoarseNeighbours + sizeof(short) * nc + 16;
+    if (ns) {
+        if (ns->bs == 3) {
+            allow_lds(k_rap_nbs_cols<3>, shmem);
+            k_rap_nbs_cols<3><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, *ns, nsv, pcol16, cols, ncol);
+        } else if (ns->bs == 2) {
+            allow_lds(k_rap_nbs_cols<2>, shmem);
+            k_rap_nbs_cols<2><<<nc, 128, shmem, s>>>(n, nc, rrp, rci, *ns, nsv, pcol16, cols, ncol);
+        }
+        return;
+    }
     switch (d.n) {
     case 3:
         allow_lds(k_rap_cols<3>, shmem);
@@ -1545,8 +1743,33 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
-                const int *cols, const int *ncol, const int *csr_rp)
+                const int *cols, const int *ncol, const int *csr_rp, const NodeStencil *ns,
+                const double *nsv)
 {
+    // node-block stencil A with its column lists: one wavefront per coarse row
+    if (ns && nsv && cols && !csr_rp && rap_uses_nbs(*ns, pw, pcol16)) {
+        const size_t sh = sizeof(double) * maxnb * 64 + sizeof(int) * maxnb +
+                          sizeof(short) * static_cast<size_t>(nc) + 16;
+        auto go = [&](auto tag, auto bsc) {
+            using T = decltype(tag);
+            constexpr int BS = decltype(bsc)::value;
+            allow_lds(k_rap_nbs<T, BS>, sh);
+            const T *rv = std::is_same<T, float>::value ? reinterpret_cast<const T *>(r32)
+                                                        : reinterpret_cast<const T *>(r64);
+            const T *pv = std::is_same<T, float>::value ? reinterpret_cast<const T *>(pe32)
+                                                        : reinterpret_cast<const T *>(pe64);
+            k_rap_nbs<T, BS><<<nc, 64, sh, s>>>(n, nc, maxnb, rrp, rci, rv, *ns, nsv, pcol16, pv,
+                                                ac, flag, band, cols, ncol);
+        };
+        if (ns->bs == 3) {
+            if (fp32) go(0.0f, std::integral_constant<int, 3>{});
+            else go(0.0, std::integral_constant<int, 3>{});
+        } else {
+            if (fp32) go(0.0f, std::integral_constant<int, 2>{});
+            else go(0.0, std::integral_constant<int, 2>{});
+        }
+        return;
+    }
     // 128 threads while the per-thread partial sums fit in 32 KB of LDS
     const int nt = maxnb <= 32 ? 128 : 64;
     const size_t shmem = sizeof(double) * maxnb * nt + sizeof(int) * maxnb +
