@@ -194,8 +194,9 @@ def system_info():
             info["torch_hip"] = torch.version.hip
     except Exception:  # pragma: no cover
         pass
-    if not info.get("gpu"):
-        # the marketing name from the runtime's agent list when torch has none
+    if "Instinct" not in info.get("gpu", ""):
+        # the marketing name from the runtime's agent list when torch's is
+        # missing or generic
         try:
             out = subprocess.run(["/opt/rocm/bin/rocminfo"], capture_output=True, text=True,
                                  timeout=30).stdout
