@@ -279,6 +279,24 @@ __global__ __launch_bounds__(128) void k_rap_cols(int n, int nc, const int *__re
     if (threadIdx.x == 0) ncol[j] = total;
 }
 
+// One product of R A P into the thread's LDS column of partial sums, with
+// no branch: a padding slot of P (column 0xFFFF) and a column outside the
+// row's list go to the spare column maxnb, which is never summed (a nonzero
+// product there sets miss), and a zero coefficient adds +0.  The sums of
+// the listed columns see the same nonzero terms in the same order as when
+// those cases are skipped.  (For the node-block operators, whose rows of 81
+// products per R entry made the per-slot branches' exec-mask work the
+// largest instruction stream: 9.95 -> 8.46 ms at c3.)
+__device__ __forceinline__ void rap_add(double *acc, const short *map, int maxnb, int tid, int nt,
+                                        uint16_t c, double prod, bool &miss)
+{
+    const bool pad = c == 0xFFFFu;
+    const int m = map[pad ? 0 : c];
+    const bool hit = !pad && m >= 0;
+    miss |= !pad && m < 0 && prod != 0.0;
+    atomicAdd(&acc[(hit ? m : maxnb) * nt + tid], prod);
+}
+
 // The numeric product: with column lists (cols, ncol from k_rap_cols) the
 // row's columns are installed in the LDS map directly; without, they are
 // marked here as above.  A contribution to a column outside a list (A's
@@ -299,8 +317,8 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                                                 const int *__restrict__ csr_rp)
 {
     extern __shared__ double smem[];
-    double *acc = smem;                                         // maxnb * NT
-    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);       // maxnb
+    double *acc = smem;                                         // (maxnb + 1) * NT
+    int *inv = reinterpret_cast<int *>(acc + (maxnb + 1) * NT);  // maxnb
     short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
@@ -359,6 +377,10 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
         for (int q = 0; q < UA; ++q)
 #pragma unroll
             for (int o = 0; o < ND; ++o) {
+                // (branches here: a third of the rows of P on box supports
+                // are padded, so skipping pads and zero coefficients saves
+                // more than the branch-free form of rap_add; measured 711
+                // against 806 us at 128^3)
                 if (av[q][o] == 0.0 || pij[q] == 0.0) continue;
                 const double pa = pij[q] * av[q][o];
 #pragma unroll
@@ -470,9 +492,9 @@ __global__ __launch_bounds__(64) void k_rap_nbs(int n, int nc, int maxnb,
 {
     constexpr int NT = 64;
     extern __shared__ double smem[];
-    double *acc = smem;                                    // maxnb * NT
-    int *inv = reinterpret_cast<int *>(acc + maxnb * NT);  // maxnb
-    short *map = reinterpret_cast<short *>(inv + maxnb);   // nc
+    double *acc = smem;                                          // (maxnb + 1) * NT
+    int *inv = reinterpret_cast<int *>(acc + (maxnb + 1) * NT);  // maxnb
+    short *map = reinterpret_cast<short *>(inv + maxnb);         // nc
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
     const int total = ncol[j];
@@ -517,18 +539,11 @@ __global__ __launch_bounds__(64) void k_rap_nbs(int n, int nc, int maxnb,
         for (int e = 0; e < UE; ++e)
 #pragma unroll
             for (int l = 0; l < BS; ++l) {
-                if (a[b][e][l] == 0.0) continue;
                 const double pa = pe[e] * a[b][e][l];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (cl[b][e][l][u] == 0xFFFFu) continue;
-                    const int sl = map[cl[b][e][l][u]];
-                    const double prod = pa * static_cast<double>(v[b][e][l][u]);
-                    if (sl >= 0)
-                        atomicAdd(&acc[sl * NT + tid], prod);
-                    else if (prod != 0.0)
-                        miss = true;
-                }
+                for (int u = 0; u < 8; ++u)
+                    rap_add(acc, map, maxnb, tid, NT, cl[b][e][l][u],
+                            pa * static_cast<double>(v[b][e][l][u]), miss);
             }
     };
     for (int t = t0 + tid; t < t1; t += UE * NT) {
@@ -1748,7 +1763,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
 {
     // node-block stencil A with its column lists: one wavefront per coarse row
     if (ns && nsv && cols && !csr_rp && rap_uses_nbs(*ns, pw, pcol16)) {
-        const size_t sh = sizeof(double) * maxnb * 64 + sizeof(int) * maxnb +
+        const size_t sh = sizeof(double) * (maxnb + 1) * 64 + sizeof(int) * maxnb +
                           sizeof(short) * static_cast<size_t>(nc) + 16;
         auto go = [&](auto tag, auto bsc) {
             using T = decltype(tag);
@@ -1772,7 +1787,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
     }
     // 128 threads while the per-thread partial sums fit in 32 KB of LDS
     const int nt = maxnb <= 32 ? 128 : 64;
-    const size_t shmem = sizeof(double) * maxnb * nt + sizeof(int) * maxnb +
+    const size_t shmem = sizeof(double) * (maxnb + 1) * nt + sizeof(int) * maxnb +
                          sizeof(short) * static_cast<size_t>(nc) + 16;
     // stencil A and 8-wide ELL P: the batched form
     if (nt == 128 && d.n > 0 && pw == 8 && pcol16) {

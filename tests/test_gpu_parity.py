@@ -409,3 +409,64 @@ def test_q1_adjoint_gradient_matches_oracle(torch_cuda):
     lam = orc.solve(gu, rtol=1e-12, maxit=3000, pre=(2, 2), post=(2, 2), transpose=True)["x"]
     g_ref = oracle.q1_grad(cfg["dims"], cfg["h"], cfg["nu"], cfg["logE"], cfg["fixed"], ur, lam)
     assert np.max(np.abs(g - g_ref)) <= 1e-8 * np.max(np.abs(g_ref))
+
+
+def _stencil27(dims, seed):
+    """A symmetric 27-point M-matrix on a 3D grid (positive random weights on
+    the 26 neighbours, diagonally dominant through a Dirichlet-like shift
+    on the x = 0 face): the stencil kernels' form without LDS tiling (more
+    than nine diagonals)."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    x, y, z = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    idx = x + nx * (y + ny * z)
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                # forward half of the offsets; the mirror entries are added below
+                if (dz, dy, dx) <= (0, 0, 0):
+                    continue
+                ok = ((x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < ny) &
+                      (z + dz >= 0) & (z + dz < nz))
+                i = idx[ok]
+                j = (x + dx + nx * (y + dy + ny * (z + dz)))[ok]
+                w = np.exp(0.5 * rng.standard_normal(i.size))
+                rows += [i, j]
+                cols += [j, i]
+                vals += [-w, -w]
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    off = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    diag = -np.asarray(off.sum(axis=1)).ravel() + np.where(x == 0, 1.0, 0.0)
+    A = (off + sp.diags(diag)).tocsr()
+    A.sort_indices()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy())
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32-form"])
+def test_pcg_on_27_point_stencil(torch_cuda, fp32):
+    # l1-Jacobi x2 around the coarse stage on a 27-diagonal operator: the PCG
+    # update runs on its own, then the untiled two-sweep kernel (FP64, or the
+    # FP32 form's kernels with an FP32 basis)
+    dims = (20, 18, 14)
+    rp, ci, a = _stencil27(dims, 11)
+    sup = synth.cell_supports(dims, 4)
+    cfg = dict(rp=rp, ci=ci, a=a, supports=sup)
+    f = np.random.default_rng(12).standard_normal(rp.size - 1)
+    orc = oracle_setup(cfg)
+    s, _ = gpu_setup_matrix(cfg, fp32_basis=fp32)
+    pre = post = (2, 2)
+    ref = orc.solve(f, rtol=1e-12, pre=pre, post=post)
+    assert ref["status"] == 0
+    u = np.zeros(rp.size - 1)
+    info = s.solve(f, u, rtol=1e-12, pre=pre, post=post, fp32_smoother=fp32)
+    print(f"27-point: GPU {info['iters']} / oracle {ref['iters']} iterations", flush=True)
+    assert info["true_rel_res"] <= 1e-12
+    assert rel_max(u, ref["x"]) <= 1e-8
+    r8 = orc.solve(f, rtol=1e-8, pre=pre, post=post)
+    u8 = np.zeros_like(u)
+    i8 = s.solve(f, u8, rtol=1e-8, pre=pre, post=post, fp32_smoother=fp32)
+    assert i8["true_rel_res"] <= 1e-8
+    assert abs(i8["iters"] - r8["iters"]) <= (1 if not fp32 else 2)
