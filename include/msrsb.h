@@ -261,8 +261,22 @@ msrsb_status msrsb_set_prolongation(msrsb_ctx *ctx, const double *val, int where
 msrsb_status msrsb_get_prolongation(msrsb_ctx *ctx, int32_t *rowptr, int32_t *col,
                                     double *val, int where);
 
+/* How the exact coarse solver A_c^{-1} of Alg. 2 is formed (the paper asks
+ * only for a coarse solver; both forms give the exact inverse up to
+ * rounding). */
+enum {
+    MSRSB_FACTOR_AUTO = 0,     /* Cholesky for a symmetric A with the Galerkin
+                                  restriction, falling back to PIVOTED on a
+                                  non-positive pivot; PIVOTED otherwise */
+    MSRSB_FACTOR_PIVOTED = 1,  /* Gauss-Jordan with partial pivoting (the
+                                  elimination of LU with partial pivoting) */
+    MSRSB_FACTOR_CHOLESKY = 2  /* Cholesky only: A_c must be symmetric positive
+                                  definite */
+};
+
 typedef struct {
     int32_t restriction; /* MSRSB_RESTRICT_GALERKIN or MSRSB_RESTRICT_MSFV */
+    int32_t factor;      /* MSRSB_FACTOR_* */
 } msrsb_coarse_opts;
 
 /* Alg. 2: the restriction R (R = P^T, or the MsFV block indicator; opts may
@@ -275,9 +289,14 @@ typedef struct {
  * substitution, the product on the FP64 matrix cores), kept as its lower
  * 64 x 64 tiles; a non-positive pivot falls back to Gauss-Jordan with
  * partial pivoting, which is also used for non-symmetric A and for the MsFV
- * restriction (whose A_c is not symmetric).  Synchronises.
- * Errors: E_STATE before setup_basis; E_ARG for an unknown restriction;
- * E_COARSE_SINGULAR on a zero pivot (pivoting form). */
+ * restriction (whose A_c is not symmetric); opts->factor can force either
+ * form.  With a further level (msrsb_set_coarse_level) the coarse solver is
+ * that level's preconditioner and the factor choice passes down to the last
+ * level.  Synchronises.
+ * Errors: E_STATE before setup_basis; E_ARG for an unknown restriction or
+ * factor, or MSRSB_FACTOR_CHOLESKY with a non-symmetric A or the MsFV
+ * restriction; E_COARSE_SINGULAR on a zero pivot (pivoting form) or a
+ * non-positive pivot (MSRSB_FACTOR_CHOLESKY). */
 msrsb_status msrsb_build_coarse(msrsb_ctx *ctx, const msrsb_coarse_opts *opts);
 /* Copy A_c = R A P (eq. lin_system_coarse, Alg. 2) out as a dense row-major
  * nc x nc FP64 matrix; the caller owns dense (nc * nc values).

@@ -16,11 +16,13 @@ numerical work runs in the HIP library ``libmsrsb.so`` (C ABI in
 from ._binding import (Msrsb, MsrsbError, load, HOST, DEVICE, SMOOTH_NONE, SMOOTH_JACOBI,
                        SMOOTH_L1JACOBI, SMOOTH_ILU0, SMOOTH_SGS, SMOOTH_IC0, KRYLOV_PCG,
                        KRYLOV_GMRES, KRYLOV_RICHARDSON, KRYLOV_BICGSTAB, ORDER_NATURAL,
-                       ORDER_MULTICOLOR, RESTRICT_GALERKIN, RESTRICT_MSFV, PHASES, LIB_PATH)
+                       ORDER_MULTICOLOR, RESTRICT_GALERKIN, RESTRICT_MSFV, FACTOR_AUTO,
+                       FACTOR_PIVOTED, FACTOR_CHOLESKY, PHASES, LIB_PATH)
 from .autograd import MsrsbTPFASolve, TPFAProblem, MsrsbQ1Solve, Q1Problem
 
 __all__ = ["Msrsb", "MsrsbError", "load", "HOST", "DEVICE", "SMOOTH_NONE", "SMOOTH_JACOBI",
            "SMOOTH_L1JACOBI", "SMOOTH_ILU0", "SMOOTH_SGS", "SMOOTH_IC0", "KRYLOV_PCG",
            "KRYLOV_GMRES", "KRYLOV_RICHARDSON", "KRYLOV_BICGSTAB", "ORDER_NATURAL",
-           "ORDER_MULTICOLOR", "RESTRICT_GALERKIN", "RESTRICT_MSFV", "PHASES", "LIB_PATH",
+           "ORDER_MULTICOLOR", "RESTRICT_GALERKIN", "RESTRICT_MSFV", "FACTOR_AUTO",
+           "FACTOR_PIVOTED", "FACTOR_CHOLESKY", "PHASES", "LIB_PATH",
            "MsrsbTPFASolve", "TPFAProblem", "MsrsbQ1Solve", "Q1Problem"]

@@ -23,6 +23,8 @@ ORDER_NATURAL, ORDER_MULTICOLOR = 0, 1
 ORDERING = {"natural": ORDER_NATURAL, "multicolor": ORDER_MULTICOLOR}
 RESTRICT_GALERKIN, RESTRICT_MSFV = 0, 1
 RESTRICTION = {"galerkin": RESTRICT_GALERKIN, "msfv": RESTRICT_MSFV}
+FACTOR_AUTO, FACTOR_PIVOTED, FACTOR_CHOLESKY = 0, 1, 2
+FACTOR = {"auto": FACTOR_AUTO, "pivoted": FACTOR_PIVOTED, "cholesky": FACTOR_CHOLESKY}
 PHASES = ["filter", "init", "smooth", "rap", "factor", "solve", "solve_t", "grad", "assemble",
           "smoother_setup"]
 
@@ -51,7 +53,7 @@ class BasisInfo(C.Structure):
 
 
 class CoarseOpts(C.Structure):
-    _fields_ = [("restriction", C.c_int32)]
+    _fields_ = [("restriction", C.c_int32), ("factor", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -305,8 +307,8 @@ class Msrsb:
             va.ctypes.data_as(C.c_void_p), HOST), "get_prolongation")
         return rp, ci, va
 
-    def build_coarse(self, restriction="galerkin"):
-        o = CoarseOpts(RESTRICTION.get(restriction, restriction))
+    def build_coarse(self, restriction="galerkin", factor="auto"):
+        o = CoarseOpts(RESTRICTION.get(restriction, restriction), FACTOR.get(factor, factor))
         self._check(self._lib.msrsb_build_coarse(self._h, C.byref(o)), "build_coarse")
 
     def get_coarse_matrix(self):

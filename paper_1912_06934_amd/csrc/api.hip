@@ -1303,8 +1303,16 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     c->err.clear();
     if (!c->has_basis) return fail(c, MSRSB_E_STATE, "setup_basis must come first");
     const int restriction = o ? o->restriction : MSRSB_RESTRICT_GALERKIN;
+    const int factor = o ? o->factor : MSRSB_FACTOR_AUTO;
     if (restriction != MSRSB_RESTRICT_GALERKIN && restriction != MSRSB_RESTRICT_MSFV)
         return fail(c, MSRSB_E_ARG, "unknown restriction");
+    if (factor != MSRSB_FACTOR_AUTO && factor != MSRSB_FACTOR_PIVOTED &&
+        factor != MSRSB_FACTOR_CHOLESKY)
+        return fail(c, MSRSB_E_ARG, "unknown factor");
+    if (factor == MSRSB_FACTOR_CHOLESKY && !c->child &&
+        !(c->a_symmetric && restriction == MSRSB_RESTRICT_GALERKIN))
+        return fail(c, MSRSB_E_ARG, "the Cholesky form needs a symmetric A and the Galerkin "
+                                    "restriction");
     c->has_coarse_op = false;
     c->restriction = restriction;
     hipStream_t s = c->stream;
@@ -1393,7 +1401,7 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         msrsb_ctx *ch = c->child;
         st = refresh_values(ch);
         if (!st) st = msrsb_setup_basis(ch, &c->basis_opts, nullptr);
-        msrsb_coarse_opts co{MSRSB_RESTRICT_GALERKIN};
+        msrsb_coarse_opts co{MSRSB_RESTRICT_GALERKIN, factor};
         if (!st) st = msrsb_build_coarse(ch, &co);
         phase_end(c, MSRSB_PHASE_FACTOR);
         if (st) return fail(c, st, "next level: " + ch->err);
@@ -1404,13 +1412,19 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     st = MSRSB_E_COARSE_SINGULAR;
     c->acinv_sym = false;
     double *work = c->gj_b + 8 * 64 + 64 * static_cast<size_t>(nc);
-    if (c->a_symmetric && restriction == MSRSB_RESTRICT_GALERKIN) {
+    if (c->a_symmetric && restriction == MSRSB_RESTRICT_GALERKIN &&
+        factor != MSRSB_FACTOR_PIVOTED) {
         // symmetric positive definite A_c: band Cholesky, W = L^{-1} and
-        // W^T W; a non-positive pivot falls back to partial pivoting
+        // W^T W; a non-positive pivot falls back to partial pivoting (unless
+        // the Cholesky form was asked for)
         hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
         st = coarse_inverse_spd(s, nc, c->acinv, std::max(c->h_band[0], c->h_band[1]), c->spd_buf,
                                 work, c->acinv_pk, c->dev_flag, &hflag);
         c->acinv_sym = st == MSRSB_OK;
+        if (st == MSRSB_E_COARSE_SINGULAR && factor == MSRSB_FACTOR_CHOLESKY) {
+            phase_end(c, MSRSB_PHASE_FACTOR);
+            return fail(c, st, "non-positive pivot: the coarse operator is not positive definite");
+        }
     }
     if (st == MSRSB_E_COARSE_SINGULAR) {
         hipMemcpyAsync(work, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);

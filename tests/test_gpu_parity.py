@@ -470,3 +470,31 @@ def test_pcg_on_27_point_stencil(torch_cuda, fp32):
     i8 = s.solve(f, u8, rtol=1e-8, pre=pre, post=post, fp32_smoother=fp32)
     assert i8["true_rel_res"] <= 1e-8
     assert abs(i8["iters"] - r8["iters"]) <= (1 if not fp32 else 2)
+
+
+def test_coarse_factor_choices(torch_cuda):
+    # the automatic (Cholesky) and the pivoted Gauss-Jordan inverse of the
+    # same SPD A_c both give the oracle's coarse solve; the Cholesky form is
+    # refused where A_c need not be symmetric
+    from paper_1912_06934_amd import MsrsbError
+    cfg = tpfa_inputs("c5", (24, 20, 18), 8)
+    orc = oracle_setup(cfg)
+    n = cfg["rp"].size - 1
+    v = np.random.default_rng(21).standard_normal(n)
+    ref = orc.apply(v, pre=(2, 2), post=(2, 2))
+    s, _, _ = gpu_setup_tpfa(cfg)
+    out = {}
+    for factor in ("auto", "pivoted", "cholesky"):
+        s.build_coarse(factor=factor)
+        z = np.zeros(n)
+        s.apply(v, z, pre=(2, 2), post=(2, 2))
+        assert rel_max(z, ref) <= 1e-11, factor
+        out[factor] = z
+    assert rel_max(out["pivoted"], out["cholesky"]) <= 1e-12
+    with pytest.raises(MsrsbError) as e:
+        s.build_coarse(restriction="msfv", factor="cholesky")
+    assert e.value.code == -1
+    with pytest.raises(MsrsbError) as e:
+        s.build_coarse(factor=7)
+    assert e.value.code == -1
+    s.build_coarse(restriction="msfv", factor="pivoted")   # usable again
