@@ -204,6 +204,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->band);
     dfree(c->rap_cols);
     dfree(c->rap_ncol);
+    dfree(c->rap_order);
     c->rap_cols_valid = false;
     if (c->jmap_idx) hipFree(c->jmap_idx);
     c->jmap_idx = nullptr;
@@ -954,6 +955,22 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                        c->stream);
     }
     if (!paxes.empty()) {
+        // the product's row order: 4 x 4 x 4 bricks of coarse nodes (ragged
+        // at the far faces), bricks and the nodes in a brick lexicographic
+        const int cx = ncx, cy = ncxy / ncx, cz = nc / ncxy;
+        std::vector<int> order;
+        order.reserve(nc);
+        for (int bz = 0; bz < cz; bz += 4)
+            for (int by = 0; by < cy; by += 4)
+                for (int bx = 0; bx < cx; bx += 4)
+                    for (int z = bz; z < std::min(bz + 4, cz); ++z)
+                        for (int y = by; y < std::min(by + 4, cy); ++y)
+                            for (int x = bx; x < std::min(bx + 4, cx); ++x)
+                                order.push_back(x + cx * (y + cy * z));
+        if (!dalloc(c->rap_order, order.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        hipMemcpyAsync(c->rap_order, order.data(), order.size() * sizeof(int),
+                       hipMemcpyHostToDevice, c->stream);
         if (!dalloc(c->paxes, paxes.size()))
             return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
         hipMemcpyAsync(c->paxes, paxes.data(), paxes.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -1356,7 +1373,7 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
                    c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
                    c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp,
-                   nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr);
+                   nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr, c->rap_order);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess)
             return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +

@@ -198,6 +198,9 @@ struct msrsb_ctx {
     // ELL form of the RAP applies ([nc][kMaxCoarseNeighbours] and counts)
     int *rap_cols = nullptr, *rap_ncol = nullptr;
     bool rap_cols_valid = false;
+    // coarse rows of a Cartesian coarse grid listed brick by brick (4 x 4 x 4
+    // nodes, bricks in lexicographic order): the stencil product's row order
+    int *rap_order = nullptr;
     int *band = nullptr;  // lower and upper bandwidth of A_c (device)
     int h_band[2] = {0, 0};
 
@@ -363,7 +366,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols = nullptr, const int *ncol = nullptr,
                 const int *csr_rp = nullptr, const NodeStencil *ns = nullptr,
-                const double *nsv = nullptr);
+                const double *nsv = nullptr, const int *order = nullptr);
 // whether the node-block stencil form of A (ns, values in FP64) takes the
 // stencil/ELL product (k_rap_nbs; needs its column lists, no CSR copy of P)
 bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16);

@@ -314,13 +314,17 @@ __global__ __launch_bounds__(NT) void k_rap_ell(int n, int nc, int maxnb,
                                                 int *__restrict__ flag, int *__restrict__ band,
                                                 const int *__restrict__ cols,
                                                 const int *__restrict__ ncol,
-                                                const int *__restrict__ csr_rp)
+                                                const int *__restrict__ csr_rp,
+                                                const int *__restrict__ order)
 {
     extern __shared__ double smem[];
     double *acc = smem;                                         // (maxnb + 1) * NT
     int *inv = reinterpret_cast<int *>(acc + (maxnb + 1) * NT);  // maxnb
     short *map = reinterpret_cast<short *>(inv + maxnb);        // nc
-    const int j = blockIdx.x;
+    // with order, each XCD walks a contiguous run of the coarse rows listed
+    // brick by brick, so that the rows it runs at once share their P rows
+    // in its L2
+    const int j = order ? order[xcd_group(blockIdx.x, gridDim.x)] : static_cast<int>(blockIdx.x);
     const int tid = threadIdx.x;
     int total;
     if (cols != nullptr) {
@@ -1668,18 +1672,18 @@ template <typename T, int ND>
 void rap_ell_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
                const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
                const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
-               const int *cols, const int *ncol, const int *csr_rp)
+               const int *cols, const int *ncol, const int *csr_rp, const int *order)
 {
     if (csr_rp) {
         allow_lds(k_rap_ell<T, 128, ND, true>, shmem);
         k_rap_ell<T, 128, ND, true><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad,
                                                            pcol16, pv, ac, flag, band, cols,
-                                                           ncol, csr_rp);
+                                                           ncol, csr_rp, order);
     } else {
         allow_lds(k_rap_ell<T, 128, ND, false>, shmem);
         k_rap_ell<T, 128, ND, false><<<nc, 128, shmem, s>>>(n, nc, maxnb, rrp, rci, rv, d, ad,
                                                             pcol16, pv, ac, flag, band, cols,
-                                                            ncol, nullptr);
+                                                            ncol, nullptr, order);
     }
 }
 
@@ -1687,20 +1691,20 @@ template <typename T>
 bool rap_ell(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp,
              const int *rci, const T *rv, const DiaOffsets &d, const double *ad,
              const uint16_t *pcol16, const T *pv, double *ac, int *flag, int *band,
-             const int *cols, const int *ncol, const int *csr_rp)
+             const int *cols, const int *ncol, const int *csr_rp, const int *order)
 {
     switch (d.n) {
     case 3: rap_ell_t<T, 3>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol, csr_rp);
+                            cols, ncol, csr_rp, order);
         return true;
     case 5: rap_ell_t<T, 5>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol, csr_rp);
+                            cols, ncol, csr_rp, order);
         return true;
     case 7: rap_ell_t<T, 7>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol, csr_rp);
+                            cols, ncol, csr_rp, order);
         return true;
     case 9: rap_ell_t<T, 9>(s, shmem, n, nc, maxnb, rrp, rci, rv, d, ad, pcol16, pv, ac, flag, band,
-                            cols, ncol, csr_rp);
+                            cols, ncol, csr_rp, order);
         return true;
     default: return false;
     }
@@ -1759,7 +1763,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols, const int *ncol, const int *csr_rp, const NodeStencil *ns,
-                const double *nsv)
+                const double *nsv, const int *order)
 {
     // node-block stencil A with its column lists: one wavefront per coarse row
     if (ns && nsv && cols && !csr_rp && rap_uses_nbs(*ns, pw, pcol16)) {
@@ -1793,9 +1797,9 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
     if (nt == 128 && d.n > 0 && pw == 8 && pcol16) {
         const bool done =
             fp32 ? rap_ell<float>(s, shmem, n, nc, maxnb, rrp, rci, r32, d, ad, pcol16, pe32, ac,
-                                  flag, band, cols, ncol, csr_rp)
+                                  flag, band, cols, ncol, csr_rp, order)
                  : rap_ell<double>(s, shmem, n, nc, maxnb, rrp, rci, r64, d, ad, pcol16, pe64, ac,
-                                   flag, band, cols, ncol, csr_rp);
+                                   flag, band, cols, ncol, csr_rp, order);
         if (done) return;
     }
     if (nt == 128) {
