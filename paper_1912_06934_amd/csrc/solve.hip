@@ -18,10 +18,14 @@ namespace {
 // Apply the previous Givens rotations to the new Hessenberg column (h[0..j]
 // from the Gram-Schmidt, ||w||^2 in nrm2), form the new rotation, update g
 // and write |g[j+1]| and the rotated diagonal to res.
+// With host_out (coherent pinned memory) the residual estimate and the
+// denominator also go to the host mailbox: the values, a system-scope fence,
+// then the step's tag the host waits for.
 __global__ void k_gmres_givens(int j, int m, double *__restrict__ H, const double *__restrict__ h,
                                const double *__restrict__ nrm2, double *__restrict__ cs,
                                double *__restrict__ sn, double *__restrict__ g,
-                               double *__restrict__ res)
+                               double *__restrict__ res, double *__restrict__ host_out,
+                               double tag)
 {
     if (threadIdx.x != 0) return;
     double col[65];
@@ -48,6 +52,11 @@ __global__ void k_gmres_givens(int j, int m, double *__restrict__ H, const doubl
     g[j] = c * g[j];
     res[0] = fabs(g[j + 1]);
     res[1] = den;
+    if (host_out == nullptr) return;
+    host_out[0] = res[0];
+    host_out[1] = den;
+    __threadfence_system();
+    host_out[2] = tag;
 }
 
 // y = H(0:k,0:k)^{-1} g(0:k) (upper triangular back substitution)
@@ -630,6 +639,9 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
     double *hc = y + (m + 2), *h2 = hc + (m + 2), *gsc = h2 + (m + 2);  // gsc: 2 scalars
     double *w = c->w[0], *zt = c->w[1], *r = c->w[2];
     double *sc = c->scal;
+    // two mailbox slots in coherent pinned memory (steps alternate)
+    volatile double *mbox[2] = {c->h_pinned + 16, c->h_pinned + 24};
+    mbox[0][2] = mbox[1][2] = -1.0;
     launch_dot(s, n, f, f, c->partials, sc + S_FF);
     if (read_scalars(c, S_FF, 1)) return MSRSB_E_HIP;
     double fn = std::sqrt(c->h_pinned[0]);
@@ -649,25 +661,38 @@ msrsb_status gmres(msrsb_ctx *c, const double *f, double *x, const msrsb_solve_o
         if (it >= o->max_iter) break;
         launch_norm_scale(s, n, r, V, c->partials, sc + S_RR);
         k_gmres_init_g<<<1, 64, 0, s>>>(m, g, sc + S_RR);
-        int j = 0;
-        bool brk = false;
-        for (j = 0; j < m && it < o->max_iter; ++j) {
-            const double *vj = V + static_cast<int64_t>(j) * n;
-            double *vn = V + static_cast<int64_t>(j + 1) * n;
+        // one Arnoldi step: v_{j+1} and column j of H, its Givens rotation,
+        // and the residual estimate posted to mailbox slot j mod 2 with tag
+        auto step = [&](int jj, int tag) {
+            const double *vj = V + static_cast<int64_t>(jj) * n;
+            double *vn = V + static_cast<int64_t>(jj + 1) * n;
             apply_two_stage(c, o, vj, zt, trans, nullptr);
             op_spmv(s, n, op, zt, w);
             // CGS2: h = V^T w; w -= V h; h2 = V^T w; w -= V h2; h += h2
-            launch_multi_dot(s, n, j + 1, V, n, w, c->partials, hc);
-            launch_multi_axpy(s, n, j + 1, V, n, hc, w, -1.0);
-            launch_multi_dot(s, n, j + 1, V, n, w, c->partials, h2);
-            launch_multi_axpy(s, n, j + 1, V, n, h2, w, -1.0);
-            k_vec_add<<<1, 64, 0, s>>>(j + 1, hc, h2);
+            launch_multi_dot(s, n, jj + 1, V, n, w, c->partials, hc);
+            launch_multi_axpy(s, n, jj + 1, V, n, hc, w, -1.0);
+            launch_multi_dot(s, n, jj + 1, V, n, w, c->partials, h2);
+            launch_multi_axpy(s, n, jj + 1, V, n, h2, w, -1.0);
+            k_vec_add<<<1, 64, 0, s>>>(jj + 1, hc, h2);
             launch_norm_scale(s, n, w, vn, c->partials, sc + S_TMP1);
-            k_gmres_givens<<<1, 64, 0, s>>>(j, m, H, hc, sc + S_TMP1, cs, sn, g, gsc);
-            hipMemcpyAsync(c->h_pinned, gsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-            if (hipStreamSynchronize(s) != hipSuccess) return MSRSB_E_HIP;
+            k_gmres_givens<<<1, 64, 0, s>>>(jj, m, H, hc, sc + S_TMP1, cs, sn, g, gsc,
+                                            const_cast<double *>(mbox[jj & 1]), tag);
+        };
+        int j = 0;
+        bool brk = false;
+        if (it < o->max_iter) step(0, it + 1);
+        for (j = 0; j < m && it < o->max_iter; ++j) {
+            // step j + 1 goes into the queue before step j's residual is read,
+            // so the device does not wait for the host; it writes only column
+            // j + 1 of H, g[j + 1 ..] and v_{j + 2}, none of which the solution
+            // after step j uses
+            if (j + 1 < m && it + 1 < o->max_iter) step(j + 1, it + 2);
+            if (!wait_mailbox(s, mbox[j & 1], it + 1)) {
+                c->err = "the device did not report the residual of a Krylov step";
+                return MSRSB_E_HIP;
+            }
             ++it;
-            const double res = c->h_pinned[0], den = c->h_pinned[1];
+            const double res = mbox[j & 1][0], den = mbox[j & 1][1];
             if (hist && it < hcap) hist[it] = res / fn;
             if (!std::isfinite(res) || !(den > 0.0)) { brk = true; break; }
             if (res <= o->rtol * fn) { ++j; break; }
