@@ -80,6 +80,7 @@ struct TriOrder {
     bool built = false;
     bool sym_pattern = false;  // A_ij stored <=> A_ji stored
     int ncolours = 0;          // multicolour order: number of colours
+    int n = 0;                 // rows
     const int *rp = nullptr, *ci = nullptr, *dpos = nullptr;  // A's pattern (not owned)
     int *rank = nullptr;       // position of each row in the order
     int8_t *side = nullptr;    // per entry: -1 earlier column, 0 diagonal, +1 later

@@ -153,6 +153,84 @@ __global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow(TriArgs t, RowOp 
     }
 }
 
+// The triangular solves of a run of narrow levels in the natural order, for
+// systems of at most kNarrowLdsRows rows: x lives in LDS for the whole run,
+// and a row's entries on the solved side (contiguous in the natural order:
+// the columns before or after the diagonal) are loaded into registers while
+// the previous level is still being solved, so a level costs LDS reads and
+// one barrier instead of a chain of memory round trips.  The arithmetic and
+// its order are those of solve_row.  A thread's first row of a level takes
+// this path; further rows (levels wider than the work-group) and rows with
+// more than kRowRegs entries on the side read their data from memory.
+constexpr int kNarrowLdsRows = 16384;  // 128 KB of LDS
+constexpr int kRowRegs = 8;
+
+struct SolveRow {
+    int i, ne;
+    int c[kRowRegs];
+    double v[kRowRegs];
+    double d;
+};
+
+__global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow_lds(TriArgs t, RowOp r,
+                                                                   const int *__restrict__ lev_ptr,
+                                                                   const int *__restrict__ rows,
+                                                                   int lev0, int lev1, int n)
+{
+    extern __shared__ double sx[];
+    const int tid = threadIdx.x;
+    const bool lower = r.op == OP_LOWER;
+    const int side = lower ? -1 : 1;
+    for (int i = tid; i < n; i += kNarrowThreads) sx[i] = r.x[i];
+    auto load = [&](int l, SolveRow &q) {
+        q.i = -1;
+        q.ne = 0;
+        if (l >= lev1) return;
+        const int u = lev_ptr[l] + tid;
+        if (u >= lev_ptr[l + 1]) return;
+        const int i = rows[u];
+        const int dp = t.dpos[i];
+        const int b = lower ? t.rp[i] : dp + 1, e = lower ? dp : t.rp[i + 1];
+        q.i = i;
+        q.ne = e - b;
+#pragma unroll
+        for (int k = 0; k < kRowRegs; ++k) {
+            const int idx = b + k < e ? b + k : dp;
+            q.c[k] = t.ci[idx];
+            q.v[k] = r.f[idx];
+        }
+        q.d = r.unit ? 1.0 : r.f[dp];
+    };
+    auto slow = [&](int i) {
+        double s = sx[i];
+        for (int e = t.rp[i]; e < t.rp[i + 1]; ++e)
+            if (t.side[e] == side) s -= r.f[e] * sx[t.ci[e]];
+        sx[i] = r.unit ? s : s / r.f[t.dpos[i]];
+    };
+    SolveRow cur, nxt;
+    load(lev0, cur);
+    __syncthreads();
+    for (int l = lev0; l < lev1; ++l) {
+        load(l + 1, nxt);  // independent of x: in flight while this level is solved
+        if (cur.i >= 0) {
+            if (cur.ne <= kRowRegs) {
+                double s = sx[cur.i];
+#pragma unroll
+                for (int k = 0; k < kRowRegs; ++k)
+                    if (k < cur.ne) s -= cur.v[k] * sx[cur.c[k]];
+                sx[cur.i] = r.unit ? s : s / cur.d;
+            } else {
+                slow(cur.i);
+            }
+        }
+        for (int u = lev_ptr[l] + tid + kNarrowThreads; u < lev_ptr[l + 1]; u += kNarrowThreads)
+            slow(rows[u]);
+        __syncthreads();
+        cur = nxt;
+    }
+    for (int i = tid; i < n; i += kNarrowThreads) r.x[i] = sx[i];
+}
+
 // upper entries of the IC(0) array take the factor value of their transpose
 __global__ __launch_bounds__(256) void k_ic_mirror(int64_t nnz, const int8_t *__restrict__ side,
                                                    const int *__restrict__ tpos,
@@ -265,6 +343,14 @@ void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
         if (g.wide) {
             const int cnt = ptr[g.lev0 + 1] - ptr[g.lev0];
             k_tri_wide<<<(cnt + 255) / 256, 256, 0, s>>>(a, r, rows + ptr[g.lev0], cnt);
+        } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
+                   t.n <= kNarrowLdsRows) {
+            const size_t sh = static_cast<size_t>(t.n) * sizeof(double);
+            if (sh > 65536)
+                hipFuncSetAttribute(reinterpret_cast<const void *>(k_tri_narrow_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(sh));
+            k_tri_narrow_lds<<<1, kNarrowThreads, sh, s>>>(a, r, dptr, rows, g.lev0, g.lev1, t.n);
         } else {
             k_tri_narrow<<<1, kNarrowThreads, 0, s>>>(a, r, dptr, rows, g.lev0, g.lev1);
         }
@@ -303,6 +389,7 @@ msrsb_status tri_order_setup(msrsb_ctx *c, int ordering)
         std::iota(order.begin(), order.end(), 0);
         t.ncolours = 0;
     }
+    t.n = n;
     for (int k = 0; k < n; ++k) rank[order[k]] = k;
     const int64_t nnz = c->nnz;
     std::vector<int8_t> side(nnz);
