@@ -205,6 +205,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rap_cols);
     dfree(c->rap_ncol);
     dfree(c->rap_order);
+    c->rap_box_threads = 0;
     c->rap_cols_valid = false;
     if (c->jmap_idx) hipFree(c->jmap_idx);
     c->jmap_idx = nullptr;
@@ -806,6 +807,8 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     std::vector<int> rrp(nc + 1, 0);
     for (int jj = 0; jj < nc; ++jj) rrp[jj + 1] = rrp[jj] + (rlen[jj] + 63) / 64 * 64;
     const int64_t rnnz = rrp[nc];
+    int rmaxlen = 0;
+    for (int jj = 0; jj < nc; ++jj) rmaxlen = std::max(rmaxlen, rrp[jj + 1] - rrp[jj]);
     std::vector<int> rci(rnnz), rsrc(rnnz, -1);
     {
         std::vector<int> pos(rrp.begin(), rrp.end() - 1);
@@ -907,6 +910,43 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
             paxes.clear();
         }
     }
+    // the box form of R A P: the cells next to a coarse node's support have
+    // their candidates within one node of it on every axis, and the support
+    // box widened by one cell has at most 512 (x, y) columns
+    int rap_box_threads = 0;
+    if (!paxes.empty() && pw == 8) {
+        const int nx = c->tdims[0], ny = c->tdims[1], nz = c->tdims[2];
+        const int cdim[3] = {ncx, ncxy / ncx, nc / ncxy};
+        const int alen[3] = {nx, ny, nz}, abase[3] = {0, nx, nx + ny};
+        bool ok = true;
+        for (int ax = 0; ax < 3 && ok; ++ax) {
+            std::vector<int> first(cdim[ax], -1), last(cdim[ax], -1);
+            for (int x = 0; x < alen[ax]; ++x) {
+                const int t = paxes[abase[ax] + x], c0 = t & 0xFFFF, cn = t >> 16;
+                for (int q = c0; q < c0 + cn && q < cdim[ax]; ++q) {
+                    if (first[q] < 0) first[q] = x;
+                    last[q] = x;
+                }
+            }
+            for (int q = 0; q < cdim[ax] && ok; ++q) {
+                ok = first[q] >= 0;
+                const int x1 = std::min(last[q] + 1, alen[ax] - 1);
+                for (int x = std::max(first[q] - 1, 0); ok && x <= x1; ++x) {
+                    const int t = paxes[abase[ax] + x], c0 = t & 0xFFFF, cn = t >> 16;
+                    ok = c0 >= q - 1 && c0 + cn - 1 <= q + 1;
+                }
+            }
+        }
+        int maxcols = 0;
+        for (int jj = 0; jj < nc && ok; ++jj) {
+            const int f = rbox[4 * jj], bx = rbox[4 * jj + 1], by = rbox[4 * jj + 2] / bx;
+            const int x0 = f % nx, y0 = (f / nx) % ny;
+            const int ex = std::min(x0 + bx + 1, nx) - std::max(x0 - 1, 0);
+            const int ey = std::min(y0 + by + 1, ny) - std::max(y0 - 1, 0);
+            maxcols = std::max(maxcols, ex * ey);
+        }
+        if (ok && maxcols <= 512) rap_box_threads = (maxcols + 63) / 64 * 64;
+    }
     // 16-bit column offsets when every 64-entry group spans fewer than 2^16 rows
     bool r16 = true;
     std::vector<int> rbase(rnnz / 64);
@@ -920,6 +960,8 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         }
     }
     c->rnnz = rnnz;
+    c->rmaxlen = rmaxlen;
+    c->rap_box_threads = rap_box_threads;
     if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
         !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, rnnz) ||
         !dalloc(c->rsrc, rnnz) ||
@@ -1355,6 +1397,18 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     else  // the block indicator, on the pattern of P^T (which contains it)
         launch_r_indicator(s, nc, c->rnnz, c->rrp, c->rci, c->rsrc, c->part, fp32, c->r64,
                            c->r32);
+    RapBoxGeom boxg;  // the box form's geometry (threads 0: not applicable)
+    if (c->rap_box_threads > 0 && c->rbox && c->paxes) {
+        boxg.box = c->rbox;
+        boxg.tab = c->paxes;
+        boxg.nx = c->tdims[0];
+        boxg.ny = c->tdims[1];
+        boxg.nz = c->tdims[2];
+        boxg.ncx = c->pax_ncx;
+        boxg.ncy = c->pax_ncxy / c->pax_ncx;
+        boxg.ncz = nc / c->pax_ncxy;
+        boxg.threads = c->rap_box_threads;
+    }
     bool have_csr = false;  // the CSR copy of P, for the general RAP only
     bool lists_rebuilt = false;
     // the node-block stencil form runs on its column lists (no CSR copy of P)
@@ -1373,7 +1427,8 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
                    c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
                    c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp,
-                   nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr, c->rap_order);
+                   nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr, c->rap_order,
+                   boxg.threads > 0 && c->a_dia && !nbs ? &boxg : nullptr);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess)
             return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +

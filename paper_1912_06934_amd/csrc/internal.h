@@ -182,6 +182,7 @@ struct msrsb_ctx {
     // entries in all.  With roff16, the columns are also kept as 16-bit
     // offsets from a base per 64-entry group (rbase), for the restriction.
     int *rrp = nullptr, *rci = nullptr, *rsrc = nullptr;
+    int rmaxlen = 0;  // longest row of R, pads included
     uint16_t *roff16 = nullptr;
     int *rbase = nullptr;
     // supports that are boxes of the assembled grid: per coarse row the first
@@ -202,6 +203,9 @@ struct msrsb_ctx {
     // coarse rows of a Cartesian coarse grid listed brick by brick (4 x 4 x 4
     // nodes, bricks in lexicographic order): the stencil product's row order
     int *rap_order = nullptr;
+    // threads of the box form of R A P (0: its conditions on the supports
+    // and P's candidates do not hold)
+    int rap_box_threads = 0;
     int *band = nullptr;  // lower and upper bandwidth of A_c (device)
     int h_band[2] = {0, 0};
 
@@ -360,6 +364,15 @@ void launch_gather_r(hipStream_t s, int64_t m, const int *rsrc, bool fp32, const
                      const float *p32, double *r64, float *r32);
 // whether launch_rap takes the stencil/ELL form (which needs no CSR copy of P)
 bool rap_uses_ell(int maxnb, const DiaOffsets &d, int pw, const uint16_t *pcol16);
+// R A P by coarse-row boxes (see k_rap_box): the supports as boxes, P's
+// per-axis candidate tables (ProlongAxes layout) on an nx x ny x nz grid of
+// fine cells and an ncx x ncy x ncz grid of coarse nodes, and the work-group
+// size (one thread per column of a support box widened by one cell)
+struct RapBoxGeom {
+    const int *box = nullptr, *tab = nullptr;
+    int nx = 0, ny = 0, nz = 0, ncx = 0, ncy = 0, ncz = 0;
+    int threads = 0;
+};
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
@@ -367,7 +380,8 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols = nullptr, const int *ncol = nullptr,
                 const int *csr_rp = nullptr, const NodeStencil *ns = nullptr,
-                const double *nsv = nullptr, const int *order = nullptr);
+                const double *nsv = nullptr, const int *order = nullptr,
+                const RapBoxGeom *boxg = nullptr);
 // whether the node-block stencil form of A (ns, values in FP64) takes the
 // stencil/ELL product (k_rap_nbs; needs its column lists, no CSR copy of P)
 bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16);
@@ -398,9 +412,12 @@ void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const doub
                   const double *v, const double *zin, double *zout, bool zero_start);
 // Coarse rows whose entries (fine rows ascending) are the cells of a box of
 // an nx x ny x nz grid: box[4 j ..] = first row, bx, bx * by, entry count.
+// maxlen: R's longest row with its pads (0 when unknown), which sets the
+// restriction's entries per lane; used with or without boxes.
 struct RestrictBoxes {
     const int *box = nullptr;
     int nx = 0, nxy = 0;
+    int maxlen = 0;
 };
 // P's pattern on an nx x ny x nz grid whose row (x, y, z) reaches the coarse
 // nodes (ax + ix) + ncx (ay + iy) + ncxy (az + iz) for ix < cx, iy < cy,

@@ -1658,6 +1658,185 @@ void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp
                                                   pci, pv, ac, flag, band);
 }
 
+// ---------------------------------------------------------------------------
+// R A P for the 7-point stencil on a Cartesian grid whose supports are boxes
+// and whose P rows reach the products of per-axis candidates (ProlongAxes):
+// A_c[j, :] = sum over cells k of (R A)[j, k] P[k, :], with
+// (R A)[j, k] = sum over the stencil neighbours i of k of R[j, i] A[i, k].
+// R[j, :] lives on j's support box, so (R A)[j, :] lives on that box widened
+// by one cell, D(j).  The candidates of a cell of D(j) lie within one coarse
+// node of j on every axis (checked when the coarse space is set), so a row
+// of A_c has at most the 27 columns of j's coarse neighbourhood.
+//
+// One work-group per coarse row, one thread per (x, y) column of D(j): the
+// thread walks the column upward, forms (R A)[j, k] from the seven R entries
+// and A coefficients around k, loads P's row k once, and adds its slots into
+// 2 x 2 x 3 sums: its columns' x and y candidates are fixed (at most two
+// each) and a plane's z candidates are the same for every thread.  The sums
+// of each of the 27 columns are then added over the wavefront (a fixed
+// butterfly) and over the wavefronts in order, so the result is reproducible.
+// Each product term is formed once per coarse row, where the per-entry form
+// of R A P re-reads a P row for every R entry next to it, and no LDS map or
+// atomic is involved.
+// ---------------------------------------------------------------------------
+constexpr int kRapBoxMaxThreads = 512;
+
+template <typename T, bool SYM>
+__global__ __launch_bounds__(kRapBoxMaxThreads) void k_rap_box(
+    int n, int nc, const int *__restrict__ rrp, RapBoxGeom g, const double *__restrict__ ad,
+    const T *__restrict__ rv, const T *__restrict__ pv, double *__restrict__ ac,
+    int *__restrict__ band, const int *__restrict__ order)
+{
+    constexpr int NW = kRapBoxMaxThreads / 64;
+    __shared__ double part[27][NW];
+    const int j = order ? order[xcd_group(blockIdx.x, gridDim.x)] : static_cast<int>(blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nx = g.nx, nxy = g.nx * g.ny;
+    const int org = g.box[4 * j], bx = g.box[4 * j + 1], bxy = g.box[4 * j + 2];
+    const int by = bxy / bx, bz = g.box[4 * j + 3] / bxy;
+    const int x0 = org % nx, y0 = (org / nx) % g.ny, z0 = org / nxy;
+    // D(j): the support box and the cells next to it, inside the grid
+    const int lx = max(x0 - 1, 0), ly = max(y0 - 1, 0), lz = max(z0 - 1, 0);
+    const int ex = min(x0 + bx + 1, nx) - lx, ey = min(y0 + by + 1, g.ny) - ly;
+    const int hz = min(z0 + bz + 1, g.nz);
+    const int jx = j % g.ncx, jy = (j / g.ncx) % g.ncy, jz = j / (g.ncx * g.ncy);
+    const T *__restrict__ rj = rv + rrp[j];
+    // acc[ix][iy][dz]: column (ax + ix, ay + iy, jz - 1 + dz) of this
+    // thread's cells
+    double acc[2][2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[a][b][c] = 0.0;
+    int tx0 = 0, ty0 = 0;  // first x / y candidate of the column, minus j's, plus 1
+    if (tid < ex * ey) {
+        const int py = tid / ex, x = lx + (tid - py * ex), y = ly + py;
+        const int tx = g.tab[x], ty = g.tab[nx + y];
+        const int cx = tx >> 16, cy = ty >> 16;
+        tx0 = (tx & 0xFFFF) - jx + 1;
+        ty0 = (ty & 0xFFFF) - jy + 1;
+        // membership of the column and its x / y neighbours in the support
+        const bool mxc = x >= x0 && x < x0 + bx, mxl = x - 1 >= x0 && x - 1 < x0 + bx,
+                   mxr = x + 1 >= x0 && x + 1 < x0 + bx;
+        const bool myc = y >= y0 && y < y0 + by, myl = y - 1 >= y0 && y - 1 < y0 + by,
+                   myr = y + 1 >= y0 && y + 1 < y0 + by;
+        // neighbour o of the stencil (-nxy, -nx, -1, 0, 1, nx, nxy): the
+        // in-plane R offsets from the column's own box position
+        const int qc = (x - x0) + bx * (y - y0);
+        const int dq[7] = {-bxy, -bx, -1, 0, 1, bx, bxy};
+        const int off[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+        const bool mxy[7] = {mxc && myc, mxc && myl, mxl && myc, mxc && myc,
+                             mxr && myc, mxc && myr, mxc && myc};
+        for (int z = lz; z < hz; ++z) {
+            const int k = x + nx * y + nxy * z;
+            const int zq = z - z0;  // the plane's position in the box
+            const bool zin = zq >= 0 && zq < bz;
+            const bool mz[7] = {zq - 1 >= 0 && zq - 1 < bz, zin, zin, zin, zin, zin,
+                                zq + 1 >= 0 && zq + 1 < bz};
+            const int q = qc + bxy * zq;
+            // R[j, i] and A[i, k] for the neighbours i = k + off inside the
+            // support (A[i, k] is row i's coefficient at -off; with SYM only
+            // the offsets >= 0 are stored, and A[i, k] = A[k, i] above k)
+            double rr[7], aa[7];
+            bool m[7];
+#pragma unroll
+            for (int o = 0; o < 7; ++o) {
+                m[o] = mxy[o] && mz[o];
+                rr[o] = 0.0;
+                aa[o] = 0.0;
+                if (m[o]) {
+                    rr[o] = static_cast<double>(rj[q + dq[o]]);
+                    aa[o] = (SYM && o > 3) ? ad[static_cast<int64_t>(o) * n + k]
+                                           : ad[static_cast<int64_t>(6 - o) * n + k + off[o]];
+                }
+            }
+            T pr[8];
+            {
+                constexpr int L = 16 / sizeof(T);
+                typedef T tvec __attribute__((ext_vector_type(L)));
+                const tvec *vs = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(k) * 8);
+#pragma unroll
+                for (int u = 0; u < 8 / L; ++u) {
+                    const tvec v = vs[u];
+#pragma unroll
+                    for (int l = 0; l < L; ++l) pr[L * u + l] = v[l];
+                }
+            }
+            double ra = 0.0;
+#pragma unroll
+            for (int o = 0; o < 7; ++o)
+                if (m[o]) ra += rr[o] * aa[o];
+            // P's slots (ix fastest over cx, then iy over cy, then iz) in the
+            // fixed 2 x 2 x 2 order, zero where the column has no such slot
+            const bool x2 = cx == 2, y2 = cy == 2;
+            double cv[2][2][2];
+            const int sz = cx * cy;  // slots per z candidate: 1, 2 or 4
+#pragma unroll
+            for (int iz = 0; iz < 2; ++iz) {
+                // slot iz * sz + ix + cx iy, picked without indexing by a
+                // lane value: sz, cx in {1, 2, 4} and {1, 2}
+                auto pick = [&](int u1, int u2, int u4) -> double {
+                    return static_cast<double>(sz == 4 ? pr[u4] : (sz == 2 ? pr[u2] : pr[u1]));
+                };
+                cv[0][0][iz] = iz == 0 ? static_cast<double>(pr[0]) : pick(1, 2, 4);
+                cv[1][0][iz] = x2 ? (iz == 0 ? static_cast<double>(pr[1]) : pick(2, 3, 5)) : 0.0;
+                cv[0][1][iz] = y2 ? (iz == 0 ? static_cast<double>(x2 ? pr[2] : pr[1])
+                                             : (x2 ? static_cast<double>(pr[6])
+                                                   : static_cast<double>(pr[3])))
+                                  : 0.0;
+                cv[1][1][iz] = (x2 && y2) ? static_cast<double>(iz == 0 ? pr[3] : pr[7]) : 0.0;
+            }
+            const int tz = g.tab[nx + g.ny + z];
+            const int dz0 = (tz & 0xFFFF) - jz + 1, cz = tz >> 16;
+#pragma unroll
+            for (int iz = 0; iz < 2; ++iz) {
+                if (iz >= cz) break;
+                const int dz = dz0 + iz;  // the same for every thread
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d != dz) continue;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) acc[a][b][d] += ra * cv[a][b][iz];
+                }
+            }
+        }
+    }
+    // the 27 columns: each thread's share, then the wavefront, then the
+    // wavefronts in order
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int ix = t % 3 - tx0, iy = (t / 3) % 3 - ty0;
+        double v = 0.0;
+        if (ix == 0 && iy == 0) v = acc[0][0][t / 9];
+        if (ix == 1 && iy == 0) v = acc[1][0][t / 9];
+        if (ix == 0 && iy == 1) v = acc[0][1][t / 9];
+        if (ix == 1 && iy == 1) v = acc[1][1][t / 9];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) part[t][w] = v;
+    }
+    __syncthreads();
+    if (tid < 27) {
+        const int t = tid;
+        const int cx = jx + t % 3 - 1, cy = jy + (t / 3) % 3 - 1, cz = jz + t / 9 - 1;
+        if (cx >= 0 && cx < g.ncx && cy >= 0 && cy < g.ncy && cz >= 0 && cz < g.ncz) {
+            double sum = 0.0;
+            const int nw = (blockDim.x + 63) >> 6;
+            for (int q = 0; q < nw; ++q) sum += part[t][q];
+            const int col = cx + g.ncx * (cy + g.ncy * cz);
+            ac[static_cast<int64_t>(j) * nc + col] = sum;
+            if (sum != 0.0) {
+                if (j > col) atomicMax(band, j - col);
+                if (col > j) atomicMax(band + 1, col - j);
+            }
+        }
+    }
+}
+
 // a kernel's dynamic LDS above the 64 KB default needs the function's limit
 // raised first (the column map of the coarse grid grows with nc)
 template <typename F>
@@ -1763,8 +1942,34 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols, const int *ncol, const int *csr_rp, const NodeStencil *ns,
-                const double *nsv, const int *order)
+                const double *nsv, const int *order, const RapBoxGeom *boxg)
 {
+    // the box form: 7-point stencil (offsets -nxy, -nx, -1, 0, 1, nx, nxy),
+    // dense A_c, P rows of 8 slots, geometry checked with the coarse space
+    if (boxg && boxg->threads > 0 && !csr_rp && d.n == 7 && pw == 8) {
+        const int nx = boxg->nx, nxy = boxg->nx * boxg->ny;
+        const int want[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+        bool match = true;
+        for (int o = 0; o < 7; ++o) match = match && d.off[o] == want[o];
+        if (match) {
+            auto go = [&](auto tag) {
+                using T = decltype(tag);
+                const T *rv = std::is_same<T, float>::value ? reinterpret_cast<const T *>(r32)
+                                                            : reinterpret_cast<const T *>(r64);
+                const T *pv = std::is_same<T, float>::value ? reinterpret_cast<const T *>(pe32)
+                                                            : reinterpret_cast<const T *>(pe64);
+                if (d.sym)
+                    k_rap_box<T, true><<<nc, boxg->threads, 0, s>>>(n, nc, rrp, *boxg, ad, rv, pv,
+                                                                    ac, band, order);
+                else
+                    k_rap_box<T, false><<<nc, boxg->threads, 0, s>>>(n, nc, rrp, *boxg, ad, rv,
+                                                                     pv, ac, band, order);
+            };
+            if (fp32) go(0.0f);
+            else go(0.0);
+            return;
+        }
+    }
     // node-block stencil A with its column lists: one wavefront per coarse row
     if (ns && nsv && cols && !csr_rp && rap_uses_nbs(*ns, pw, pcol16)) {
         const size_t sh = sizeof(double) * (maxnb + 1) * 64 + sizeof(int) * maxnb +

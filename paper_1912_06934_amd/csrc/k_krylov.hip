@@ -112,13 +112,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep32(int n, const int *__restrict
 // pads of value 0): one work-group per coarse row (neighbouring coarse rows,
 // which share fine rows, on one XCD).  With R16 the columns are read as
 // 16-bit offsets from the group's base (a wavefront's 64 entries share one
-// group).  A step takes up to 16 entries per lane, all of them loaded
-// (positions beyond the row end re-read its last entry and are skipped)
-// before their x values are gathered, so a coarse row of up to 4,096
-// entries costs two round trips.  Each lane sums its entries in order, then
-// a fixed butterfly and wavefront order combine the lanes, so the result is
-// reproducible.
-template <typename T, typename XT, bool R16>
+// group).  A step takes U entries per lane, all of them loaded (positions
+// beyond the row end re-read its last entry and are skipped) before their x
+// values are gathered, so a coarse row of up to U kBlock entries costs two
+// round trips; the launch takes the smallest U that covers the longest row.
+// Each lane sums its entries (lane, lane + kBlock, ...) in ascending order
+// whatever U is, then a fixed butterfly and wavefront order combine the
+// lanes, so the result is reproducible and does not depend on U.
+template <typename T, typename XT, bool R16, int U>
 __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__restrict__ rrp,
                                                        const int *__restrict__ rci,
                                                        const uint16_t *__restrict__ roff,
@@ -127,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__rest
                                                        const XT *__restrict__ x,
                                                        double *__restrict__ xc)
 {
-    constexpr int U = 16;
     const int j = xcd_group(blockIdx.x, gridDim.x);
     if (j >= nc) return;
     double s = 0.0;
@@ -158,14 +158,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict_b(int nc, const int *__rest
 // loaded together (one memory round trip instead of two).  The entries per
 // lane and the summation order are those of k_restrict_b; its pads (value 0)
 // are not visited.  q < 2^16, so the float quotients below are exact.
-template <typename T, typename XT>
+template <typename T, typename XT, int U>
 __global__ __launch_bounds__(kBlock) void k_restrict_box(int nc, const int *__restrict__ rrp,
                                                          const int *__restrict__ box, int nx,
                                                          int nxy, const T *__restrict__ rv,
                                                          const XT *__restrict__ x,
                                                          double *__restrict__ xc)
 {
-    constexpr int U = 16;
     const int j = xcd_group(blockIdx.x, gridDim.x);
     if (j >= nc) return;
     const int r0 = rrp[j];
@@ -1293,32 +1292,51 @@ void launch_sweep(hipStream_t s, int n, const int *rp, const int *ci, const doub
                                                  zero_start ? 1 : 0);
 }
 
+// entries per lane and step of the restriction kernels: the smallest power
+// of two (at most 16) whose step covers R's longest row (its pads included);
+// an unknown length (0) takes 16
+template <typename F>
+static void with_restrict_unroll(int maxlen, F &&f)
+{
+    if (maxlen > 0 && maxlen <= kBlock)
+        f(std::integral_constant<int, 1>{});
+    else if (maxlen > 0 && maxlen <= 2 * kBlock)
+        f(std::integral_constant<int, 2>{});
+    else if (maxlen > 0 && maxlen <= 4 * kBlock)
+        f(std::integral_constant<int, 4>{});
+    else if (maxlen > 0 && maxlen <= 8 * kBlock)
+        f(std::integral_constant<int, 8>{});
+    else
+        f(std::integral_constant<int, 16>{});
+}
+
+template <typename T, typename XT>
+static void restrict_kernels(hipStream_t s, int nc, const int *rrp, const int *rci,
+                             const uint16_t *roff16, const int *rbase, const T *rv, const XT *x,
+                             double *xc, const RestrictBoxes &boxes)
+{
+    with_restrict_unroll(boxes.maxlen, [&](auto u) {
+        constexpr int U = decltype(u)::value;
+        if (boxes.box)
+            k_restrict_box<T, XT, U><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx, boxes.nxy,
+                                                           rv, x, xc);
+        else if (roff16)
+            k_restrict_b<T, XT, true, U><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, rv, x,
+                                                               xc);
+        else
+            k_restrict_b<T, XT, false, U><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, rv,
+                                                                x, xc);
+    });
+}
+
 void launch_restrict(hipStream_t s, int nc, const int *rrp, const int *rci,
                      const uint16_t *roff16, const int *rbase, bool fp32, const double *r64,
                      const float *r32, const double *x, double *xc, const RestrictBoxes &boxes)
 {
-    if (boxes.box) {
-        if (fp32)
-            k_restrict_box<float, double><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx,
-                                                                boxes.nxy, r32, x, xc);
-        else
-            k_restrict_box<double, double><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx,
-                                                                 boxes.nxy, r64, x, xc);
-    } else if (fp32) {
-        if (roff16)
-            k_restrict_b<float, double, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
-                                                                    r32, x, xc);
-        else
-            k_restrict_b<float, double, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
-                                                                     r32, x, xc);
-    } else {
-        if (roff16)
-            k_restrict_b<double, double, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase,
-                                                                     r64, x, xc);
-        else
-            k_restrict_b<double, double, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16,
-                                                                      rbase, r64, x, xc);
-    }
+    if (fp32)
+        restrict_kernels<float, double>(s, nc, rrp, rci, roff16, rbase, r32, x, xc, boxes);
+    else
+        restrict_kernels<double, double>(s, nc, rrp, rci, roff16, rbase, r64, x, xc, boxes);
 }
 
 void launch_dot(hipStream_t s, int n, const double *x, const double *y, double *partials,
@@ -1511,15 +1529,7 @@ void launch_prec_f32_pre(hipStream_t s, int n, const DiaOffsets &d, const float 
         k_dia_residual<MSRSB_DIA_ARGS(nd, sym), float, float, float>
             <<<grid_for(n), kBlock, 0, s>>>(n, d, a32, v, z1, tmp);
     });
-    if (boxes.box)
-        k_restrict_box<float, float><<<nc, kBlock, 0, s>>>(nc, rrp, boxes.box, boxes.nx, boxes.nxy,
-                                                           r32, tmp, vc);
-    else if (roff16)
-        k_restrict_b<float, float, true><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, r32,
-                                                               tmp, vc);
-    else
-        k_restrict_b<float, float, false><<<nc, kBlock, 0, s>>>(nc, rrp, rci, roff16, rbase, r32,
-                                                                tmp, vc);
+    restrict_kernels<float, float>(s, nc, rrp, rci, roff16, rbase, r32, tmp, vc, boxes);
 }
 
 // _post: z1 += P wc, z2 = sweep(z1), z = sweep(z2) with r.z, r.(z - zold)

@@ -396,6 +396,7 @@ static ProlongAxes prolong_axes(const msrsb_ctx *c)
 static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
 {
     RestrictBoxes b;
+    b.maxlen = c->rmaxlen;
     if (c->rbox) {
         b.box = c->rbox;
         b.nx = c->tdims[0];
