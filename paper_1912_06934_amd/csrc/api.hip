@@ -206,6 +206,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rap_ncol);
     dfree(c->rap_order);
     c->rap_box_threads = 0;
+    c->ac_outside_zero = false;
     c->rap_cols_valid = false;
     if (c->jmap_idx) hipFree(c->jmap_idx);
     c->jmap_idx = nullptr;
@@ -1413,8 +1414,9 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
     bool lists_rebuilt = false;
     // the node-block stencil form runs on its column lists (no CSR copy of P)
     const bool nbs = rap_uses_nbs(c->a_ns, c->pw, c->pcol16) && c->a_ns_val && !csr_rp;
+    const bool boxr = !c->child && !nbs && c->a_dia && rap_uses_box(c->a_off, c->pw, &boxg);
     for (;;) {
-        if (!have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16) &&
+        if (!boxr && !have_csr && !rap_uses_ell(c->rmaxnb, c->a_off, c->pw, c->pcol16) &&
             !(nbs && c->rap_cols_valid)) {
             launch_ell_to_csr(s, c->n, c->pw, c->prp, fp32, c->p64[c->pcur], c->p32[c->pcur],
                               c->p_csr_tmp);
@@ -1422,17 +1424,27 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         }
         hipMemsetAsync(c->dev_flag, 0, 2 * sizeof(int), s);
         hipMemsetAsync(c->band, 0, 2 * sizeof(int), s);
-        if (!c->child) launch_fill(s, nn, c->ac, 0.0);
+        if (!c->child && !(boxr && c->ac_outside_zero)) launch_fill(s, nn, c->ac, 0.0);
+        c->ac_outside_zero = false;
         launch_rap(s, c->n, nc, c->rmaxnb, c->rrp, c->rci, fp32, c->r64, c->r32, c->rp, c->ci,
                    c->a, c->a_off, c->a_dia, c->prp, c->pci, c->p_csr_tmp, c->pw, c->pcol16,
                    c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
                    c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp,
                    nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr, c->rap_order,
-                   boxg.threads > 0 && c->a_dia && !nbs ? &boxg : nullptr);
+                   boxr ? &boxg : nullptr);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess)
             return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +
                                             hipGetErrorString(le));
+        if (boxr) {
+            // every column of a row lies in its 27-column neighbourhood: no
+            // list can be missed, and the band follows from the coarse grid
+            // (an upper bound of the nonzeros' band), so the factorisation is
+            // queued without waiting for the product
+            c->h_band[0] = c->h_band[1] = rap_box_band(boxg);
+            c->ac_outside_zero = true;
+            break;
+        }
         int hflag[2] = {0, 0};
         hipMemcpyAsync(hflag, c->dev_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(c->h_band, c->band, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1489,9 +1501,8 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         // symmetric positive definite A_c: band Cholesky, W = L^{-1} and
         // W^T W; a non-positive pivot falls back to partial pivoting (unless
         // the Cholesky form was asked for)
-        hipMemcpyAsync(c->acinv, c->ac, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
-        st = coarse_inverse_spd(s, nc, c->acinv, std::max(c->h_band[0], c->h_band[1]), c->spd_buf,
-                                work, c->acinv_pk, c->dev_flag, &hflag);
+        st = coarse_inverse_spd(s, nc, c->ac, c->acinv, std::max(c->h_band[0], c->h_band[1]),
+                                c->spd_buf, work, c->acinv_pk, c->dev_flag, &hflag);
         c->acinv_sym = st == MSRSB_OK;
         if (st == MSRSB_E_COARSE_SINGULAR && factor == MSRSB_FACTOR_CHOLESKY) {
             phase_end(c, MSRSB_PHASE_FACTOR);

@@ -206,6 +206,10 @@ struct msrsb_ctx {
     // threads of the box form of R A P (0: its conditions on the supports
     // and P's candidates do not hold)
     int rap_box_threads = 0;
+    // the dense A_c holds zeros outside every row's 27-column neighbourhood
+    // (a box-form product wrote it since the last fill): the next box-form
+    // product need not clear it again
+    bool ac_outside_zero = false;
     int *band = nullptr;  // lower and upper bandwidth of A_c (device)
     int h_band[2] = {0, 0};
 
@@ -373,6 +377,11 @@ struct RapBoxGeom {
     int nx = 0, ny = 0, nz = 0, ncx = 0, ncy = 0, ncz = 0;
     int threads = 0;
 };
+// whether launch_rap takes the box form (dense A_c, every column of a row in
+// its 27-column coarse neighbourhood), and the half bandwidth that
+// neighbourhood gives A_c in the lexicographic coarse numbering
+bool rap_uses_box(const DiaOffsets &d, int pw, const RapBoxGeom *g);
+int rap_box_band(const RapBoxGeom &g);
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
@@ -391,8 +400,11 @@ bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16);
 void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rci,
                      const DiaOffsets &d, const double *ad, const uint16_t *pcol16, int *cols,
                      int *ncol, const NodeStencil *ns = nullptr, const double *nsv = nullptr);
-msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
-                                double *pk, int *flag, int *host_flag);
+// A^{-1} of a symmetric positive definite band matrix A (dense n x n, half
+// bandwidth bl) into pk (packed lower tiles); X is the factorisation's
+// workspace (n x n, only the tiles within the band are written)
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, const double *A, double *X, int bl,
+                                double *Linv, double *W, double *pk, int *flag, int *host_flag);
 // y = S x for the symmetric S in the packed lower-tile form (acinv_pk)
 void launch_symv_packed(hipStream_t s, int n, const double *pk, const double *x, double *y,
                         double *part);

@@ -1682,7 +1682,7 @@ void rap_t(hipStream_t s, size_t shmem, int n, int nc, int maxnb, const int *rrp
 constexpr int kRapBoxMaxThreads = 512;
 
 template <typename T, bool SYM>
-__global__ __launch_bounds__(kRapBoxMaxThreads) void k_rap_box(
+__global__ __launch_bounds__(kRapBoxMaxThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_rap_box(
     int n, int nc, const int *__restrict__ rrp, RapBoxGeom g, const double *__restrict__ ad,
     const T *__restrict__ rv, const T *__restrict__ pv, double *__restrict__ ac,
     int *__restrict__ band, const int *__restrict__ order)
@@ -1936,6 +1936,23 @@ void launch_rap_cols(hipStream_t s, int n, int nc, const int *rrp, const int *rc
     }
 }
 
+bool rap_uses_box(const DiaOffsets &d, int pw, const RapBoxGeom *g)
+{
+    // 7-point stencil (offsets -nxy, -nx, -1, 0, 1, nx, nxy), P rows of 8
+    // slots, geometry checked with the coarse space (threads > 0)
+    if (!g || g->threads <= 0 || d.n != 7 || pw != 8) return false;
+    const int nx = g->nx, nxy = g->nx * g->ny;
+    const int want[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+    for (int o = 0; o < 7; ++o)
+        if (d.off[o] != want[o]) return false;
+    return true;
+}
+
+int rap_box_band(const RapBoxGeom &g)
+{
+    return (g.ncx > 1 ? 1 : 0) + (g.ncy > 1 ? g.ncx : 0) + (g.ncz > 1 ? g.ncx * g.ncy : 0);
+}
+
 void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const int *rci,
                 bool fp32, const double *r64, const float *r32, const int *rp, const int *ci,
                 const double *a, const DiaOffsets &d, const double *ad, const int *prp,
@@ -1944,14 +1961,8 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *cols, const int *ncol, const int *csr_rp, const NodeStencil *ns,
                 const double *nsv, const int *order, const RapBoxGeom *boxg)
 {
-    // the box form: 7-point stencil (offsets -nxy, -nx, -1, 0, 1, nx, nxy),
-    // dense A_c, P rows of 8 slots, geometry checked with the coarse space
-    if (boxg && boxg->threads > 0 && !csr_rp && d.n == 7 && pw == 8) {
-        const int nx = boxg->nx, nxy = boxg->nx * boxg->ny;
-        const int want[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
-        bool match = true;
-        for (int o = 0; o < 7; ++o) match = match && d.off[o] == want[o];
-        if (match) {
+    if (!csr_rp && rap_uses_box(d, pw, boxg)) {
+        {
             auto go = [&](auto tag) {
                 using T = decltype(tag);
                 const T *rv = std::is_same<T, float>::value ? reinterpret_cast<const T *>(r32)
@@ -2073,14 +2084,31 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
     return *host_flag ? MSRSB_E_COARSE_SINGULAR : MSRSB_OK;
 }
 
-msrsb_status coarse_inverse_spd(hipStream_t s, int n, double *X, int bl, double *Linv, double *W,
-                                double *pk, int *flag, int *host_flag)
+// X's tiles (I, J) with |I - J| <= tb from A: the band Cholesky below reads
+// and writes no other tile of its workspace
+__global__ __launch_bounds__(256) void k_copy_band_tiles(const double *__restrict__ A,
+                                                        double *__restrict__ X, int n, int tb)
+{
+    const int nt = (n + kBP - 1) / kBP, w = 2 * tb + 1;
+    const int I = static_cast<int>(blockIdx.x) / w, J = I - tb + static_cast<int>(blockIdx.x) % w;
+    if (J < 0 || J >= nt) return;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int r = I * kBP + e / kBP, c = J * kBP + e % kBP;
+        if (r < n && c < n) X[static_cast<int64_t>(r) * n + c] = A[static_cast<int64_t>(r) * n + c];
+    }
+}
+
+msrsb_status coarse_inverse_spd(hipStream_t s, int n, const double *A, double *X, int bl,
+                                double *Linv, double *W, double *pk, int *flag, int *host_flag)
 {
     if (n < 1 || n > kMaxCoarse) return MSRSB_E_ARG;
     hipMemsetAsync(flag, 0, sizeof(int), s);
     const int nt = (n + kBP - 1) / kBP;
     // row tiles below a panel that the band reaches
     const int tb = min(nt - 1, (max(bl, 0) + kBP - 1) / kBP);
+    k_copy_band_tiles<<<nt * (2 * tb + 1), 256, 0, s>>>(A, X, n, tb);
     // each panel's update also inverts the next panel's diagonal block, which
     // it finalises; a panel without band rows below it leaves the next block
     // untouched, and that block is inverted on its own.  Row tile K of W =
