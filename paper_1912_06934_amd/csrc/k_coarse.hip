@@ -945,6 +945,48 @@ __device__ inline void tri_pair(int t, int &a, int &b)
     b = t - x * (x + 1) / 2;
 }
 
+// Compile-time loop: f(std::integral_constant<int, K>) for K = B .. E - 1.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Within each row of 16 lanes, lane K's value to every lane of the row
+// (DPP row_newbcast), for a double.
+template <int K>
+__device__ __forceinline__ double lane_to_row_d(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        0, static_cast<int>(static_cast<uint32_t>(u)), 0x150 + K, 0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        0, static_cast<int>(static_cast<uint32_t>(u >> 32)), 0x150 + K, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Row G (lanes 16 G .. 16 G + 15) to every row, lane for lane: the 16-lane
+// swap pairs rows (0, 1) and (2, 3), the 32-lane swap the two halves.
+template <int G>
+__device__ __forceinline__ uint32_t row_to_all(uint32_t v)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const uint32_t y = (G & 1) ? a[1] : a[0];  // rows G & 1 and (G & 1) + 2, each twice
+    const auto b = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+    return (G & 2) ? b[1] : b[0];
+}
+template <int G>
+__device__ __forceinline__ double row_to_all_d(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = row_to_all<G>(static_cast<uint32_t>(u));
+    const uint32_t hi = row_to_all<G>(static_cast<uint32_t>(u >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ inline double readlane_d(double v, int lane)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -983,7 +1025,7 @@ __device__ __forceinline__ double recip_nr(double p)
 // of the left half is dead after step c and column c of the right half is
 // born at step c, so both share one slot.  Lane r + 16 g holds row r, slots
 // 4 g .. 4 g + 3.  Returns true on a non-positive or non-finite pivot.
-__device__ inline bool chol_inv16(const double (*D)[kLds], double (*Li)[kLds], int kb, int lane)
+__device__ __forceinline__ bool chol_inv16(const double (*D)[kLds], double (*Li)[kLds], int kb, int lane)
 {
     const int r = lane & 15, g = lane >> 4, o = 16 * kb;
     double m[4];
@@ -992,20 +1034,19 @@ __device__ inline bool chol_inv16(const double (*D)[kLds], double (*Li)[kLds], i
         const int c = 4 * g + s;
         m[s] = c <= r ? D[o + r][o + c] : D[o + c][o + r];
     }
-    bool bad = false;
-    double ur = 1.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int gk = k >> 2, sk = k & 3;
+    double ur = 1.0;  // this lane's row's pivot
+    static_for<0, 16>([&](auto kc) {
+        constexpr int k = decltype(kc)::value, gk = k >> 2, sk = k & 3;
         const double p = readlane_d(m[sk], k + 16 * gk);
-        bad |= !(p > 0.0) || !isfinite(p);
         if (r == k) ur = p;
         const double rp = recip_nr(p);
-        // x_rk of this lane's row and the pivot row's entries of its slots
-        const double xrk = __shfl(m[sk], r + 16 * gk, 64);
+        // x_rk of this lane's row (the same lane of row gk) and the pivot
+        // row's entries of its slots (lane k of its own row), moved across
+        // lanes by the VALU rather than through the LDS crossbar
+        const double xrk = row_to_all_d<gk>(m[sk]);
         double pk[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) pk[s] = __shfl(m[s], k + 16 * g, 64);
+        for (int s = 0; s < 4; ++s) pk[s] = lane_to_row_d<k>(m[s]);
         const double mult = r > k ? xrk * rp : 0.0;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -1014,14 +1055,15 @@ __device__ inline bool chol_inv16(const double (*D)[kLds], double (*Li)[kLds], i
             else
                 m[s] = fma(-mult, pk[s], m[s]);
         }
-    }
+    });
     const double rs = 1.0 / sqrt(ur);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int c = 4 * g + s;
         Li[o + r][o + c] = c <= r ? m[s] * rs : 0.0;
     }
-    return bad;
+    // every pivot is some lane's ur, so the check per lane covers them all
+    return !(ur > 0.0) || !isfinite(ur);
 }
 
 // acc += (-)A B for 16 x 16 blocks in LDS: A at (ar, ac) by rows; B at
@@ -1184,7 +1226,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ X, 
 // is multiplied), subtracts it from the identity's block, and multiplies by
 // Linv_I.  Entries of W above the diagonal come out as exact zeros (Linv_I is
 // lower triangular).  Rs: 64 x 17 doubles of LDS.
-__device__ inline void w_row_tile(const double *__restrict__ X, int n, int tb,
+__device__ __forceinline__ void w_row_tile(const double *__restrict__ X, int n, int tb,
                                   const double *__restrict__ LinvI, double *__restrict__ W, int c0,
                                   int I, double (*Rs)[17])
 {
