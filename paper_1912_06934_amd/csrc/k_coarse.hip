@@ -607,35 +607,92 @@ constexpr int kLeaf = 8;
 constexpr int kPanel = 64;
 constexpr int kLeafThreads = 1024;
 
-template <int R>
-__global__ __launch_bounds__(kLeafThreads) void k_gj_leaf(double *__restrict__ X, int n, int k0,
+// Wavefront argmax of (v, r) pairs: the larger v wins, the lower r on a tie
+// (a total order, so every lane ends with the same pair whatever the order
+// of combination).  Quads by DPP quad permutes, rows of 16 by DPP rotates,
+// then rows against rows by the 16- and 32-lane swaps: no LDS round trips.
+__device__ __forceinline__ void argmax_take(double &v, int &r, double ov, int orow)
+{
+    if (ov > v || (ov == v && orow < r)) {
+        v = ov;
+        r = orow;
+    }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &r)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u)), CTRL, 0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        0, static_cast<int>(static_cast<uint32_t>(u >> 32)), CTRL, 0xF, 0xF, false));
+    const int orow = __builtin_amdgcn_update_dpp(0, r, CTRL, 0xF, 0xF, false);
+    argmax_take(v, r, __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo), orow);
+}
+template <bool HALVES>
+__device__ __forceinline__ void argmax_swap(double &v, int &r)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(u), hi = static_cast<uint32_t>(u >> 32);
+    const auto sl = HALVES ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                           : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto sh = HALVES ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                           : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const auto sr = HALVES ? __builtin_amdgcn_permlane32_swap(static_cast<uint32_t>(r),
+                                                              static_cast<uint32_t>(r), false, false)
+                           : __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(r),
+                                                              static_cast<uint32_t>(r), false, false);
+    // the two results are this lane's row (or half) and its partner's
+    double a = __builtin_bit_cast(double, (static_cast<uint64_t>(sh[0]) << 32) | sl[0]);
+    int ra = static_cast<int>(sr[0]);
+    argmax_take(a, ra, __builtin_bit_cast(double, (static_cast<uint64_t>(sh[1]) << 32) | sl[1]),
+                static_cast<int>(sr[1]));
+    v = a;
+    r = ra;
+}
+__device__ __forceinline__ void wave_argmax(double &v, int &r)
+{
+    argmax_dpp<0xB1>(v, r);   // quad_perm [1, 0, 3, 2]
+    argmax_dpp<0x4E>(v, r);   // quad_perm [2, 3, 0, 1]
+    argmax_dpp<0x124>(v, r);  // row_ror 4
+    argmax_dpp<0x128>(v, r);  // row_ror 8
+    argmax_swap<false>(v, r);
+    argmax_swap<true>(v, r);
+}
+
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void k_gj_leaf(double *__restrict__ X, int n, int k0,
                                                           int nb, int kl, int lw,
                                                           int *__restrict__ piv,
                                                           double *__restrict__ bbuf,
                                                           int *__restrict__ flag)
 {
-    __shared__ double red_v[kLeafThreads / 64];
-    __shared__ int red_r[kLeafThreads / 64];
+    __shared__ double red_v[NT / 64];
+    __shared__ int red_r[NT / 64];
     __shared__ double rowk[kLeaf], rowp[kLeaf];
-    __shared__ int sh_p;
     __shared__ int sh_piv[kLeaf];
+    __shared__ double sw[2 * kLeaf][kPanel];  // the swap rows of each panel column
     const int tid = threadIdx.x;
     double v[R][kLeaf];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = tid + q * kLeafThreads;
+        const int r = tid + q * NT;
 #pragma unroll
         for (int c = 0; c < kLeaf; ++c)
             v[q][c] = (r < n && c < lw) ? X[static_cast<int64_t>(r) * n + kl + c] : 0.0;
     }
-    for (int c = 0; c < lw; ++c) {
+    // the steps unrolled, so that a step's column of the leaf is a register
+    // known at compile time (lw < kLeaf only for the last leaf)
+#pragma unroll
+    for (int c = 0; c < kLeaf; ++c) {
+        if (c >= lw) break;
         const int k = kl + c;
         // argmax |x_rk| over r >= k; ties go to the lowest row
         double best = -1.0;
         int brow = n;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int r = tid + q * kLeafThreads;
+            const int r = tid + q * NT;
             double val = 0.0;
 #pragma unroll
             for (int cc = 0; cc < kLeaf; ++cc)
@@ -645,39 +702,35 @@ __global__ __launch_bounds__(kLeafThreads) void k_gj_leaf(double *__restrict__ X
                 brow = r;
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int orow = __shfl_xor(brow, off, 64);
-            if (ob > best || (ob == best && orow < brow)) {
-                best = ob;
-                brow = orow;
-            }
-        }
+        wave_argmax(best, brow);
         if ((tid & 63) == 0) {
             red_v[tid >> 6] = best;
             red_r[tid >> 6] = brow;
         }
         __syncthreads();
-        if (tid == 0) {
+        // every thread combines the wavefronts' candidates in the same order
+        // (no second barrier for a broadcast); red_v is written again only
+        // after the next barrier, which every thread reaches after this read
+        int p;
+        {
             double b = red_v[0];
             int br = red_r[0];
-            for (int w = 1; w < kLeafThreads / 64; ++w)
+            for (int w = 1; w < NT / 64; ++w)
                 if (red_v[w] > b || (red_v[w] == b && red_r[w] < br)) {
                     b = red_v[w];
                     br = red_r[w];
                 }
-            if (!(b > 0.0)) flag[0] = 1;  // singular (or NaN) pivot column
             if (br >= n) br = k;
-            sh_p = br;
-            sh_piv[c] = br;
-            piv[k] = br;
+            p = br;
+            if (tid == 0) {
+                if (!(b > 0.0)) flag[0] = 1;  // singular (or NaN) pivot column
+                sh_piv[c] = br;
+                piv[k] = br;
+            }
         }
-        __syncthreads();
-        const int p = sh_p;
         // swap rows k and p of the leaf
-        const int ok = k % kLeafThreads, qk = k / kLeafThreads;
-        const int op = p % kLeafThreads, qp = p / kLeafThreads;
+        const int ok = k % NT, qk = k / NT;
+        const int op = p % NT, qp = p / NT;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (tid == ok && q == qk)
@@ -701,7 +754,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_gj_leaf(double *__restrict__ X
         for (int cc = 0; cc < kLeaf; ++cc) prow[cc] = (cc == c) ? dinv : prow[cc] * dinv;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int r = tid + q * kLeafThreads;
+            const int r = tid + q * NT;
             if (r >= n) continue;
             if (r == k) {
 #pragma unroll
@@ -720,31 +773,61 @@ __global__ __launch_bounds__(kLeafThreads) void k_gj_leaf(double *__restrict__ X
             for (int cc = 0; cc < kLeaf; ++cc)
                 v[q][cc] = (cc == c) ? -f * prow[cc] : v[q][cc] - f * prow[cc];
         }
-        __syncthreads();
+        // rowk / rowp are written again only after the next step's first
+        // barrier, which every thread reaches after these reads
     }
+    __syncthreads();  // sh_piv complete
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = tid + q * kLeafThreads;
+        const int r = tid + q * NT;
         if (r < n)
 #pragma unroll
             for (int c = 0; c < kLeaf; ++c)
                 if (c < lw) X[static_cast<int64_t>(r) * n + kl + c] = v[q][c];
     }
     // the leaf's swaps on the other columns of the panel, then take the leaf
-    // rows of those columns out (B) and zero them
+    // rows of those columns out (B) and zero them.  A column's swaps touch
+    // the leaf rows kl + c and their pivot rows: slot c holds row kl + c and
+    // slot kLeaf + c the pivot row of step c when that lies below the leaf
+    // (a pivot row inside the leaf is that row's own slot).  All of them are
+    // loaded at once, swapped in LDS in step order, and the rows below the
+    // leaf are stored back; the same swaps in the same order as one at a
+    // time in memory.
     if (tid < nb) {
         const int col = k0 + tid;
         if (col < kl || col >= kl + lw) {
+            auto slot = [&](int c) { return sh_piv[c] < kl + lw ? sh_piv[c] - kl : kLeaf + c; };
             for (int c = 0; c < lw; ++c) {
-                const int k = kl + c, p = sh_piv[c];
-                if (p != k) {
-                    const double t = X[static_cast<int64_t>(k) * n + col];
-                    X[static_cast<int64_t>(k) * n + col] = X[static_cast<int64_t>(p) * n + col];
-                    X[static_cast<int64_t>(p) * n + col] = t;
+                sw[c][tid] = X[static_cast<int64_t>(kl + c) * n + col];
+                const int p = sh_piv[c];
+                if (p >= kl + lw) sw[kLeaf + c][tid] = X[static_cast<int64_t>(p) * n + col];
+            }
+            // a pivot row below the leaf chosen at several steps is one row:
+            // its slot at step c starts from its slot at the latest earlier
+            // step that chose it
+            for (int c = 0; c < lw; ++c) {
+                const int p = sh_piv[c];
+                if (p >= kl + lw)
+                    for (int e = c - 1; e >= 0; --e)
+                        if (sh_piv[e] == p) {
+                            sw[kLeaf + c][tid] = sw[kLeaf + e][tid];
+                            break;
+                        }
+                const int sp = slot(c);
+                if (sp != c) {
+                    const double t = sw[c][tid];
+                    sw[c][tid] = sw[sp][tid];
+                    sw[sp][tid] = t;
                 }
             }
             for (int c = 0; c < lw; ++c) {
-                bbuf[c * kPanel + tid] = X[static_cast<int64_t>(kl + c) * n + col];
+                const int p = sh_piv[c];
+                bool last = p >= kl + lw;  // the last step with this pivot row stores it
+                for (int e = c + 1; e < lw && last; ++e) last = sh_piv[e] != p;
+                if (last) X[static_cast<int64_t>(p) * n + col] = sw[kLeaf + c][tid];
+            }
+            for (int c = 0; c < lw; ++c) {
+                bbuf[c * kPanel + tid] = sw[c][tid];
                 X[static_cast<int64_t>(kl + c) * n + col] = 0.0;
             }
         }
@@ -2086,7 +2169,11 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
                             int *piv, int *colsrc, int *flag, int *host_flag)
 {
     if (n < 1 || n > kMaxCoarse) return MSRSB_E_ARG;
-    const int R = (n + kLeafThreads - 1) / kLeafThreads;  // rows per thread
+    // rows per thread and threads of the leaf kernel: one row per thread up
+    // to 1,024 rows (the fewest threads that hold them), then 1,024 threads
+    const int R = (n + kLeafThreads - 1) / kLeafThreads;
+    const int lt = R > 1 ? kLeafThreads : n <= 64 ? 64 : n <= 128 ? 128 : n <= 256 ? 256
+                                                                : n <= 512 ? 512 : 1024;
     hipMemsetAsync(flag, 0, sizeof(int), s);
     double *bleaf = bbuf;                       // kLeaf x kPanel
     double *bpanel = bbuf + kLeaf * kPanel;     // kPanel x n
@@ -2094,19 +2181,18 @@ msrsb_status coarse_inverse(hipStream_t s, int n, double *X, double *inv_out, do
         const int nb = min(kPanel, n - k0);
         for (int kl = k0; kl < k0 + nb; kl += kLeaf) {
             const int lw = min(kLeaf, k0 + nb - kl);
-            switch (R) {
-            case 1:
-                k_gj_leaf<1><<<1, kLeafThreads, 0, s>>>(X, n, k0, nb, kl, lw, piv, bleaf, flag);
-                break;
-            case 2:
-                k_gj_leaf<2><<<1, kLeafThreads, 0, s>>>(X, n, k0, nb, kl, lw, piv, bleaf, flag);
-                break;
-            case 3:
-                k_gj_leaf<3><<<1, kLeafThreads, 0, s>>>(X, n, k0, nb, kl, lw, piv, bleaf, flag);
-                break;
-            default:
-                k_gj_leaf<4><<<1, kLeafThreads, 0, s>>>(X, n, k0, nb, kl, lw, piv, bleaf, flag);
-                break;
+            auto leaf = [&](auto kern, int threads) {
+                kern<<<1, threads, 0, s>>>(X, n, k0, nb, kl, lw, piv, bleaf, flag);
+            };
+            switch (R > 1 ? R + 3 : lt == 64 ? 0 : lt == 128 ? 1 : lt == 256 ? 2 : lt == 512 ? 3 : 4) {
+            case 0: leaf(k_gj_leaf<1, 64>, 64); break;
+            case 1: leaf(k_gj_leaf<1, 128>, 128); break;
+            case 2: leaf(k_gj_leaf<1, 256>, 256); break;
+            case 3: leaf(k_gj_leaf<1, 512>, 512); break;
+            case 4: leaf(k_gj_leaf<1, kLeafThreads>, kLeafThreads); break;
+            case 5: leaf(k_gj_leaf<2, kLeafThreads>, kLeafThreads); break;
+            case 6: leaf(k_gj_leaf<3, kLeafThreads>, kLeafThreads); break;
+            default: leaf(k_gj_leaf<4, kLeafThreads>, kLeafThreads); break;
             }
             if (nb > lw)
                 k_gj_leaf_update<<<grid_for(static_cast<int64_t>(n) * kPanel), kBlock, 0, s>>>(
