@@ -1234,7 +1234,9 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
                          c->j_dia, jsym, fp32 ? nullptr : c->jv, fp32 ? c->jv32 : nullptr,
                          // A's DIA copy when it has J's offsets (scalar A: J's pattern is A's)
                          c->bs == 1 && c->a_off.n == c->jw && c->a_off.n > 0 ? c->a_dia
-                                                                            : nullptr);
+                                                                            : nullptr,
+                         // the node-block copy of A (vector problems)
+                         c->a_ns.n > 0 ? &c->a_ns : nullptr, c->a_ns.n > 0 ? c->a_ns_val : nullptr);
     phase_end(c, MSRSB_PHASE_FILTER);
     phase_begin(c, MSRSB_PHASE_INIT);
     const bool warm = o->warm_start && c->has_basis;

@@ -345,7 +345,8 @@ struct SmoothArgs {
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
                           bool use_dia, bool sym, double *jv64, float *jv32,
-                          const double *ad = nullptr);
+                          const double *ad = nullptr, const NodeStencil *ns = nullptr,
+                          const double *nsv = nullptr);
 void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int *part,
                        double *p64, float *p32);
 void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,

@@ -11,6 +11,8 @@
 // column.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace msrsb {
 namespace {
 
@@ -878,10 +880,67 @@ __global__ __launch_bounds__(kBlock) void k_filter_jacobi_dia(int n, int filter,
     }
 }
 
+// The same for a node-block operator (NodeStencil: a row's coefficients by
+// node offset and component) when J's diagonals are the node offsets'
+// same-component couplings in the same order: row i reads its 27 (say)
+// couplings of component i mod BS from their node-offset planes instead of
+// walking its whole CSR row.  d is summed over the couplings in ascending
+// column order, as in k_filter_jacobi; a coupling of value zero (absent from
+// the row, or filtered) gives a zero entry.
+template <typename T, int BS>
+__global__ __launch_bounds__(kBlock) void k_filter_jacobi_nbs(int n, int filter, double omega,
+                                                              NodeStencil ns,
+                                                              const double *__restrict__ nsv,
+                                                              T *__restrict__ jv)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int ic = i % BS;
+    auto coef = [&](int o) {
+        double g = nsv[static_cast<int64_t>(o * BS + ic) * n + i];
+        if (filter && g > 0.0) g = 0.0;
+        return g;
+    };
+    double d = 0.0;
+    for (int o = 0; o < ns.n; ++o)
+        if (ns.off[o] != 0) d -= coef(o);
+    for (int o = 0; o < ns.n; ++o) {
+        double v;
+        if (d == 0.0) {
+            v = ns.off[o] == 0 ? 1.0 : 0.0;
+        } else if (ns.off[o] == 0) {
+            v = 1.0 - omega;
+        } else {
+            const double g = coef(o);
+            v = g == 0.0 ? 0.0 : -omega * g / d;
+        }
+        jv[static_cast<int64_t>(o) * n + i] = static_cast<T>(v);
+    }
+}
+
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
-                          bool use_dia, bool sym, double *jv64, float *jv32, const double *ad)
+                          bool use_dia, bool sym, double *jv64, float *jv32, const double *ad,
+                          const NodeStencil *ns, const double *nsv)
 {
+    // node-block A whose node offsets are J's diagonals (times bs), in order
+    bool nbs = ns && nsv && use_dia && !sym && ns->bs == bs && (bs == 2 || bs == 3) &&
+               ns->n == jw && joff.n == jw;
+    for (int o = 0; nbs && o < jw; ++o) nbs = joff.off[o] == ns->off[o] * bs;
+    if (nbs) {
+        auto go = [&](auto bsc) {
+            constexpr int BS = decltype(bsc)::value;
+            if (jv32)
+                k_filter_jacobi_nbs<float, BS><<<grid_for(n), kBlock, 0, s>>>(n, filter, omega, *ns,
+                                                                              nsv, jv32);
+            else
+                k_filter_jacobi_nbs<double, BS><<<grid_for(n), kBlock, 0, s>>>(n, filter, omega,
+                                                                               *ns, nsv, jv64);
+        };
+        if (bs == 3) go(std::integral_constant<int, 3>{});
+        else go(std::integral_constant<int, 2>{});
+        return;
+    }
     if (ad && use_dia && bs == 1) {
         if (jv32)
             k_filter_jacobi_dia<float><<<grid_for(n), kBlock, 0, s>>>(n, filter, omega, ad, joff,
