@@ -206,6 +206,9 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rap_ncol);
     dfree(c->rap_order);
     c->rap_box_threads = 0;
+    dfree(c->nrbox);
+    dfree(c->npaxes);
+    c->rap_nbox_threads = 0;
     c->ac_outside_zero = false;
     c->rap_cols_valid = false;
     if (c->jmap_idx) hipFree(c->jmap_idx);
@@ -948,6 +951,134 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
         }
         if (ok && maxcols <= 512) rap_box_threads = (maxcols + 63) / 64 * 64;
     }
+    // the box form of R A P for a node-block operator (3 components per node,
+    // 27 node offsets): the node grid from the stencil's offsets, each coarse
+    // node's support as a box of nodes (the same for its three dofs, checked
+    // on R's rows), P's per-axis candidate coarse nodes (checked on every P
+    // row), then the same window and size conditions as the scalar form
+    std::vector<int> nrbox, npaxes;
+    int ndims[3] = {0, 0, 0}, ncdims[3] = {0, 0, 0}, rap_nbox_threads = 0;
+    if (c->bs == 3 && c->a_ns.n == 27 && pw == 8 && nc % 3 == 0) {
+        const int nn = n / 3, ncn = nc / 3;
+        const int nxn = c->a_ns.off[16], nxyn = c->a_ns.off[22];
+        bool ok = nxn >= 3 && nxyn >= 3 * nxn && nxyn % nxn == 0 && nn % nxyn == 0;
+        for (int o = 0; o < 27 && ok; ++o) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            ok = c->a_ns.off[o] == dx + nxn * dy + nxyn * dz;
+        }
+        const int nyn = ok ? nxyn / nxn : 0, nzn = ok ? nn / nxyn : 0;
+        // support boxes of the coarse nodes, from R's rows of their dofs
+        if (ok) nrbox.resize(static_cast<size_t>(ncn) * 4);
+        for (int J = 0; J < ncn && ok; ++J) {
+            const int len = rlen[3 * J];
+            ok = len > 0 && rlen[3 * J + 1] == len && rlen[3 * J + 2] == len;
+            if (!ok) break;
+            const int r0 = rrp[3 * J];
+            const int f = rci[r0] / 3, l = rci[r0 + len - 1] / 3;
+            const int x0 = f % nxn, y0 = (f / nxn) % nyn, z0 = f / nxyn;
+            const int bx = l % nxn - x0 + 1, by = (l / nxn) % nyn - y0 + 1, bz = l / nxyn - z0 + 1;
+            ok = bx > 0 && by > 0 && bz > 0 && static_cast<int64_t>(bx) * by * bz == len &&
+                 len <= 65536;
+            for (int q = 0; q < len && ok; ++q) {
+                const int node = f + q % bx + ((q / bx) % by) * nxn + (q / (bx * by)) * nxyn;
+                for (int cmp = 0; cmp < 3 && ok; ++cmp)
+                    ok = rci[rrp[3 * J + cmp] + q] == 3 * node + cmp;
+            }
+            nrbox[4 * J] = f;
+            nrbox[4 * J + 1] = bx;
+            nrbox[4 * J + 2] = bx * by;
+            nrbox[4 * J + 3] = len;
+        }
+        // the coarse node grid from the boxes' origins, then per-axis tables
+        int cx = 1, cy = 1;
+        if (ok) {
+            auto oy = [&](int J) { return (nrbox[4 * J] / nxn) % nyn; };
+            auto oz = [&](int J) { return nrbox[4 * J] / nxyn; };
+            while (cx < ncn && oy(cx) == oy(0) && oz(cx) == oz(0)) ++cx;
+            while (cy * cx < ncn && oz(cy * cx) == oz(0)) ++cy;
+            ok = ncn % (cx * cy) == 0;
+        }
+        const int cz = ok ? ncn / (cx * cy) : 0;
+        auto axis = [&](int len, int cnt_axis, auto lo, auto ext) {
+            for (int x = 0; x < len && ok; ++x) {
+                int first = -1, cnt = 0;
+                for (int a = 0; a < cnt_axis; ++a)
+                    if (x >= lo(a) && x < lo(a) + ext(a)) {
+                        if (first < 0) first = a;
+                        ok = ok && a == first + cnt;
+                        ++cnt;
+                    }
+                ok = ok && cnt >= 1 && cnt <= 2 && first <= 0xFFFF;
+                if (ok) npaxes.push_back(first | cnt << 16);
+            }
+        };
+        if (ok) {
+            axis(nxn, cx, [&](int a) { return nrbox[4 * a] % nxn; },
+                 [&](int a) { return nrbox[4 * a + 1]; });
+            axis(nyn, cy, [&](int a) { return (nrbox[4 * a * cx] / nxn) % nyn; },
+                 [&](int a) { return nrbox[4 * a * cx + 2] / nrbox[4 * a * cx + 1]; });
+            axis(nzn, cz, [&](int a) { return nrbox[4 * a * cx * cy] / nxyn; },
+                 [&](int a) { return nrbox[4 * a * cx * cy + 3] / nrbox[4 * a * cx * cy + 2]; });
+        }
+        // every P row: dof 3 i + l reaches the dofs 3 K + l of the product of
+        // node i's candidates, ascending
+        for (int i = 0; i < nn && ok; ++i) {
+            const int x = i % nxn, y = (i / nxn) % nyn, z = i / nxyn;
+            const int tx = npaxes[x], ty = npaxes[nxn + y], tz = npaxes[nxn + nyn + z];
+            const int kx = tx >> 16, ky = ty >> 16, kz = tz >> 16;
+            for (int cmp = 0; cmp < 3 && ok; ++cmp) {
+                const int row = 3 * i + cmp;
+                ok = hprp[row + 1] - hprp[row] == kx * ky * kz;
+                int e = hprp[row];
+                for (int iz = 0; iz < kz && ok; ++iz)
+                    for (int iy = 0; iy < ky && ok; ++iy)
+                        for (int ix = 0; ix < kx && ok; ++ix, ++e)
+                            ok = hpci[e] == 3 * ((tx & 0xFFFF) + ix + cx * ((ty & 0xFFFF) + iy) +
+                                                 cx * cy * ((tz & 0xFFFF) + iz)) + cmp;
+            }
+        }
+        // nodes next to a support have their candidates within one coarse
+        // node of it on every axis; the widened boxes fit a work-group
+        const int cdim[3] = {cx, cy, cz}, alen[3] = {nxn, nyn, nzn}, abase[3] = {0, nxn, nxn + nyn};
+        for (int ax = 0; ax < 3 && ok; ++ax) {
+            std::vector<int> first(cdim[ax], -1), last(cdim[ax], -1);
+            for (int x = 0; x < alen[ax]; ++x) {
+                const int t = npaxes[abase[ax] + x], c0 = t & 0xFFFF, cn = t >> 16;
+                for (int q = c0; q < c0 + cn && q < cdim[ax]; ++q) {
+                    if (first[q] < 0) first[q] = x;
+                    last[q] = x;
+                }
+            }
+            for (int q = 0; q < cdim[ax] && ok; ++q) {
+                ok = first[q] >= 0;
+                const int x1 = std::min(last[q] + 1, alen[ax] - 1);
+                for (int x = std::max(first[q] - 1, 0); ok && x <= x1; ++x) {
+                    const int t = npaxes[abase[ax] + x], c0 = t & 0xFFFF, cn = t >> 16;
+                    ok = c0 >= q - 1 && c0 + cn - 1 <= q + 1;
+                }
+            }
+        }
+        int maxcols = 0;
+        for (int J = 0; J < ncn && ok; ++J) {
+            const int f = nrbox[4 * J], bx = nrbox[4 * J + 1], by = nrbox[4 * J + 2] / bx;
+            const int x0 = f % nxn, y0 = (f / nxn) % nyn;
+            const int ex = std::min(x0 + bx + 1, nxn) - std::max(x0 - 1, 0);
+            const int ey = std::min(y0 + by + 1, nyn) - std::max(y0 - 1, 0);
+            maxcols = std::max(maxcols, ex * ey);
+        }
+        if (ok && maxcols <= 512) {
+            rap_nbox_threads = (maxcols + 63) / 64 * 64;
+            ndims[0] = nxn;
+            ndims[1] = nyn;
+            ndims[2] = nzn;
+            ncdims[0] = cx;
+            ncdims[1] = cy;
+            ncdims[2] = cz;
+        } else {
+            nrbox.clear();
+            npaxes.clear();
+        }
+    }
     // 16-bit column offsets when every 64-entry group spans fewer than 2^16 rows
     bool r16 = true;
     std::vector<int> rbase(rnnz / 64);
@@ -963,6 +1094,11 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
     c->rnnz = rnnz;
     c->rmaxlen = rmaxlen;
     c->rap_box_threads = rap_box_threads;
+    c->rap_nbox_threads = rap_nbox_threads;
+    for (int a = 0; a < 3; ++a) {
+        c->ndims[a] = ndims[a];
+        c->ncdims[a] = ncdims[a];
+    }
     if (!dalloc(c->part, n) || !dalloc(c->prp, n + 1) || !dalloc(c->pci, pnnz) ||
         !dalloc(c->interior, n) || !dalloc(c->rrp, nc + 1) || !dalloc(c->rci, rnnz) ||
         !dalloc(c->rsrc, rnnz) ||
@@ -1020,6 +1156,14 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                        c->stream);
         c->pax_ncx = ncx;
         c->pax_ncxy = ncxy;
+    }
+    if (rap_nbox_threads > 0) {
+        if (!dalloc(c->nrbox, nrbox.size()) || !dalloc(c->npaxes, npaxes.size()))
+            return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+        hipMemcpyAsync(c->nrbox, nrbox.data(), nrbox.size() * sizeof(int), hipMemcpyHostToDevice,
+                       c->stream);
+        hipMemcpyAsync(c->npaxes, npaxes.data(), npaxes.size() * sizeof(int),
+                       hipMemcpyHostToDevice, c->stream);
     }
     if (!rbox.empty()) {
         if (!dalloc(c->rbox, rbox.size()))
@@ -1412,6 +1556,18 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
         boxg.ncz = nc / c->pax_ncxy;
         boxg.threads = c->rap_box_threads;
     }
+    RapBoxGeom nboxg;  // the node-block box form's geometry (threads 0: not applicable)
+    if (c->rap_nbox_threads > 0 && c->nrbox && c->npaxes) {
+        nboxg.box = c->nrbox;
+        nboxg.tab = c->npaxes;
+        nboxg.nx = c->ndims[0];
+        nboxg.ny = c->ndims[1];
+        nboxg.nz = c->ndims[2];
+        nboxg.ncx = c->ncdims[0];
+        nboxg.ncy = c->ncdims[1];
+        nboxg.ncz = c->ncdims[2];
+        nboxg.threads = c->rap_nbox_threads;
+    }
     bool have_csr = false;  // the CSR copy of P, for the general RAP only
     bool lists_rebuilt = false;
     // the node-block stencil form runs on its column lists (no CSR copy of P)
@@ -1433,7 +1589,7 @@ msrsb_status msrsb_build_coarse(msrsb_ctx *c, const msrsb_coarse_opts *o)
                    c->p64[c->pcur], c->p32[c->pcur], acout, c->dev_flag, c->band,
                    c->rap_cols_valid ? c->rap_cols : nullptr, c->rap_ncol, csr_rp,
                    nbs ? &c->a_ns : nullptr, nbs ? c->a_ns_val : nullptr, c->rap_order,
-                   boxr ? &boxg : nullptr);
+                   boxr ? &boxg : nullptr, nbs ? &nboxg : nullptr);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess)
             return fail(c, MSRSB_E_HIP, std::string("coarse product launch failed: ") +

@@ -206,6 +206,14 @@ struct msrsb_ctx {
     // threads of the box form of R A P (0: its conditions on the supports
     // and P's candidates do not hold)
     int rap_box_threads = 0;
+    // the same at node level for a node-block operator (3 components per
+    // node, 27 node offsets): per coarse node the first fine node, bx,
+    // bx * by and the node count of its support box; P's per-axis candidate
+    // coarse nodes (ProlongAxes layout over the node grid); the node grid
+    // and the coarse node grid
+    int *nrbox = nullptr, *npaxes = nullptr;
+    int ndims[3] = {0, 0, 0}, ncdims[3] = {0, 0, 0};
+    int rap_nbox_threads = 0;
     // the dense A_c holds zeros outside every row's 27-column neighbourhood
     // (a box-form product wrote it since the last fill): the next box-form
     // product need not clear it again
@@ -391,7 +399,7 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *cols = nullptr, const int *ncol = nullptr,
                 const int *csr_rp = nullptr, const NodeStencil *ns = nullptr,
                 const double *nsv = nullptr, const int *order = nullptr,
-                const RapBoxGeom *boxg = nullptr);
+                const RapBoxGeom *boxg = nullptr, const RapBoxGeom *nboxg = nullptr);
 // whether the node-block stencil form of A (ns, values in FP64) takes the
 // stencil/ELL product (k_rap_nbs; needs its column lists, no CSR copy of P)
 bool rap_uses_nbs(const NodeStencil &ns, int pw, const uint16_t *pcol16);

@@ -1962,6 +1962,157 @@ __global__ __launch_bounds__(kRapBoxMaxThreads) __attribute__((amdgpu_waves_per_
     }
 }
 
+// R A P for a node-block operator with 3 components per node and the 27
+// node offsets (NodeStencil), on support boxes of nodes (RapBoxGeom over the
+// node grid and the coarse node grid).  Coarse dof j = 3 J + c (coarse node
+// J, component c): R's row j holds component c of the nodes of J's support
+// box; P's row 3 k + c' reaches the dofs 3 K + c' of node k's candidate
+// coarse nodes K.  So
+//   A_c[j, 3 K + c'] = sum over the nodes k of J's box widened by one node
+//                      of (R A)[j, 3 k + c'] P[3 k + c', 3 K + c'],
+//   (R A)[j, 3 k + c'] = sum over the 27 neighbours i of k in the support of
+//                        R[j, 3 i + c] A[3 i + c, 3 k + c'],
+// and a row has at most 27 coarse nodes x 3 components of columns.  As in
+// k_rap_box: one thread per (x, y) column of the widened box walks z, the
+// products go into 3 x 2 x 2 x 3 register sums (component, x and y
+// candidate, z offset), and the 81 sums are added over the wavefront and
+// then over the wavefronts in a fixed order (reproducible).
+template <typename T>
+__global__ __launch_bounds__(kRapBoxMaxThreads) void k_rap_box_nbs(
+    int n, int nc, const int *__restrict__ rrp, RapBoxGeom g, const double *__restrict__ av,
+    const T *__restrict__ rv, const T *__restrict__ pv, double *__restrict__ ac,
+    int *__restrict__ band)
+{
+    constexpr int NW = kRapBoxMaxThreads / 64;
+    __shared__ double part[81][NW];
+    const int j = static_cast<int>(blockIdx.x), J = j / 3, cj = j - 3 * J;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nx = g.nx, nxy = g.nx * g.ny;
+    const int org = g.box[4 * J], bx = g.box[4 * J + 1], bxy = g.box[4 * J + 2];
+    const int by = bxy / bx, bz = g.box[4 * J + 3] / bxy;
+    const int x0 = org % nx, y0 = (org / nx) % g.ny, z0 = org / nxy;
+    const int lx = max(x0 - 1, 0), ly = max(y0 - 1, 0), lz = max(z0 - 1, 0);
+    const int ex = min(x0 + bx + 1, nx) - lx, ey = min(y0 + by + 1, g.ny) - ly;
+    const int hz = min(z0 + bz + 1, g.nz);
+    const int jx = J % g.ncx, jy = (J / g.ncx) % g.ncy, jz = J / (g.ncx * g.ncy);
+    const T *__restrict__ rj = rv + rrp[j];
+    double acc[3][2][2][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[q][a][b][c] = 0.0;
+    int tx0 = 0, ty0 = 0;
+    if (tid < ex * ey) {
+        const int py = tid / ex, x = lx + (tid - py * ex), y = ly + py;
+        const int tx = g.tab[x], ty = g.tab[nx + y];
+        const int cx = tx >> 16, cy = ty >> 16;
+        tx0 = (tx & 0xFFFF) - jx + 1;
+        ty0 = (ty & 0xFFFF) - jy + 1;
+        const bool x2 = cx == 2, y2 = cy == 2;
+        const int sz = cx * cy;
+        for (int z = lz; z < hz; ++z) {
+            const int k = x + nx * y + nxy * z;
+            // (R A)[j, 3 k + c'] over the neighbours i = k - (ox, oy, oz) of
+            // k inside the support (node offset o of row 3 i + cj is k - i)
+            double ra[3] = {0.0, 0.0, 0.0};
+            for (int o = 0; o < 27; ++o) {
+                const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+                const int ix = x - ox, iy = y - oy, iz = z - oz;
+                if (ix < x0 || ix >= x0 + bx || iy < y0 || iy >= y0 + by || iz < z0 ||
+                    iz >= z0 + bz)
+                    continue;
+                const double r =
+                    static_cast<double>(rj[(ix - x0) + bx * ((iy - y0) + by * (iz - z0))]);
+                const int64_t row = 3 * static_cast<int64_t>(k - (ox + nx * oy + nxy * oz)) + cj;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    ra[q] += r * av[static_cast<int64_t>(o * 3 + q) * n + row];
+            }
+            const int tz = g.tab[nx + g.ny + z];
+            const int dz0 = (tz & 0xFFFF) - jz + 1, czz = tz >> 16;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                T pr[8];
+                {
+                    constexpr int L = 16 / sizeof(T);
+                    typedef T tvec __attribute__((ext_vector_type(L)));
+                    const tvec *vs =
+                        reinterpret_cast<const tvec *>(pv + (3 * static_cast<int64_t>(k) + q) * 8);
+#pragma unroll
+                    for (int u = 0; u < 8 / L; ++u) {
+                        const tvec v = vs[u];
+#pragma unroll
+                        for (int l = 0; l < L; ++l) pr[L * u + l] = v[l];
+                    }
+                }
+                // the row's slots (x fastest over cx, then y, then z) in the
+                // fixed 2 x 2 x 2 order, zero where the node has no such slot
+                double cv[2][2][2];
+#pragma unroll
+                for (int iz = 0; iz < 2; ++iz) {
+                    auto pick = [&](int u1, int u2, int u4) -> double {
+                        return static_cast<double>(sz == 4 ? pr[u4] : (sz == 2 ? pr[u2] : pr[u1]));
+                    };
+                    cv[0][0][iz] = iz == 0 ? static_cast<double>(pr[0]) : pick(1, 2, 4);
+                    cv[1][0][iz] = x2 ? (iz == 0 ? static_cast<double>(pr[1]) : pick(2, 3, 5)) : 0.0;
+                    cv[0][1][iz] = y2 ? (iz == 0 ? static_cast<double>(x2 ? pr[2] : pr[1])
+                                                 : (x2 ? static_cast<double>(pr[6])
+                                                       : static_cast<double>(pr[3])))
+                                      : 0.0;
+                    cv[1][1][iz] = (x2 && y2) ? static_cast<double>(iz == 0 ? pr[3] : pr[7]) : 0.0;
+                }
+#pragma unroll
+                for (int iz = 0; iz < 2; ++iz) {
+                    if (iz >= czz) break;
+                    const int dz = dz0 + iz;  // the same for every thread
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if (d != dz) continue;
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+#pragma unroll
+                            for (int b = 0; b < 2; ++b) acc[q][a][b][d] += ra[q] * cv[a][b][iz];
+                    }
+                }
+            }
+        }
+    }
+    // the 81 columns (coarse node offset t / 3, x fastest; component t % 3)
+#pragma unroll
+    for (int t = 0; t < 81; ++t) {
+        const int q = t % 3, tn = t / 3;
+        const int ix = tn % 3 - tx0, iy = (tn / 3) % 3 - ty0;
+        double v = 0.0;
+        if (ix == 0 && iy == 0) v = acc[q][0][0][tn / 9];
+        if (ix == 1 && iy == 0) v = acc[q][1][0][tn / 9];
+        if (ix == 0 && iy == 1) v = acc[q][0][1][tn / 9];
+        if (ix == 1 && iy == 1) v = acc[q][1][1][tn / 9];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) part[t][w] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < 81; t += blockDim.x) {
+        const int q = t % 3, tn = t / 3;
+        const int kx = jx + tn % 3 - 1, ky = jy + (tn / 3) % 3 - 1, kz = jz + tn / 9 - 1;
+        if (kx >= 0 && kx < g.ncx && ky >= 0 && ky < g.ncy && kz >= 0 && kz < g.ncz) {
+            double sum = 0.0;
+            const int nw = (blockDim.x + 63) >> 6;
+            for (int u = 0; u < nw; ++u) sum += part[t][u];
+            const int col = 3 * (kx + g.ncx * (ky + g.ncy * kz)) + q;
+            ac[static_cast<int64_t>(j) * nc + col] = sum;
+            if (sum != 0.0) {
+                if (j > col) atomicMax(band, j - col);
+                if (col > j) atomicMax(band + 1, col - j);
+            }
+        }
+    }
+}
+
 // a kernel's dynamic LDS above the 64 KB default needs the function's limit
 // raised first (the column map of the coarse grid grows with nc)
 template <typename F>
@@ -2084,8 +2235,20 @@ void launch_rap(hipStream_t s, int n, int nc, int maxnb, const int *rrp, const i
                 const int *pci, const double *pcsr, int pw, const uint16_t *pcol16,
                 const double *pe64, const float *pe32, double *ac, int *flag, int *band,
                 const int *cols, const int *ncol, const int *csr_rp, const NodeStencil *ns,
-                const double *nsv, const int *order, const RapBoxGeom *boxg)
+                const double *nsv, const int *order, const RapBoxGeom *boxg,
+                const RapBoxGeom *nboxg)
 {
+    // the node-block box form: 3 components, 27 node offsets, dense A_c
+    if (nboxg && nboxg->threads > 0 && ns && nsv && !csr_rp && ns->bs == 3 && ns->n == 27 &&
+        pw == 8) {
+        if (fp32)
+            k_rap_box_nbs<float><<<nc, nboxg->threads, 0, s>>>(n, nc, rrp, *nboxg, nsv, r32, pe32,
+                                                              ac, band);
+        else
+            k_rap_box_nbs<double><<<nc, nboxg->threads, 0, s>>>(n, nc, rrp, *nboxg, nsv, r64,
+                                                               pe64, ac, band);
+        return;
+    }
     if (!csr_rp && rap_uses_box(d, pw, boxg)) {
         {
             auto go = [&](auto tag) {
