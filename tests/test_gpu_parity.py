@@ -358,6 +358,40 @@ def test_q1_pcg_solution(torch_cuda, case):
     assert rel_max(u32, ref["x"]) <= 1e-8
 
 
+# 2D Q1 elasticity (2 components per node, 9 node offsets): the node-block
+# forms the 3D workload does not take (the two-component filter from the
+# node-offset planes, R A P from the coarse rows' column lists)
+def test_q1_2d_node_block_forms(torch_cuda):
+    from synth.q1 import q1_elasticity
+    elems, h = (24, 20), (1.0 / 24, 1.0 / 20)
+    rng = np.random.default_rng(11)
+    E = np.exp(rng.standard_normal(elems[0] * elems[1]))
+    nnx = elems[0] + 1
+    fixed = np.repeat(np.arange(nnx * (elems[1] + 1)) % nnx == 0, 2)  # the x = 0 edge
+    rp, ci, a = q1_elasticity(elems, h, E, 0.3, fixed)
+    f = rng.standard_normal(rp.size - 1)
+    f[fixed] = 0.0
+    cfg = dict(rp=rp, ci=ci, a=a, f=f, block_size=2,
+               supports=synth.vector_supports(synth.vertex_supports(elems, 4), 2))
+    orc = oracle_setup(cfg)
+    s, info = gpu_setup_matrix(cfg)
+    _, _, pv = s.get_prolongation()
+    assert rel_max(pv, orc.pv) <= 1e-12
+    assert info["max_rowsum_err"] <= 8 * np.finfo(float).eps
+    assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
+    v = rng.standard_normal(rp.size - 1)
+    z_ref = orc.apply(v, pre=(2, 2), post=(2, 2))
+    z = np.zeros_like(v)
+    s.apply(v, z, pre=(2, 2), post=(2, 2))
+    assert rel_max(z, z_ref) <= 1e-11
+    ref = orc.solve(f, rtol=1e-12, maxit=3000, pre=(2, 2), post=(2, 2))
+    assert ref["status"] == 0
+    u = np.zeros_like(f)
+    out = s.solve(f, u, rtol=1e-12, max_iter=3000, pre=(2, 2), post=(2, 2))
+    assert out["true_rel_res"] <= 1e-12
+    assert rel_max(u, ref["x"]) <= 1e-8
+
+
 @pytest.mark.parametrize("elems,h", [((12, 10, 9), (1 / 12, 1 / 10, 1 / 9)),
                                      ((12, 12), (1 / 12, 20 / 12))], ids=["3d", "2d-stretched"])
 def test_q1_assembly_matches_generator(torch_cuda, elems, h):
