@@ -467,7 +467,8 @@ def main():
     sm_bytes = smoothing_bytes(n, nnz_p, 4)
     sm_ach = sm_bytes / sm_s / 1e9
     roofline_smoothing = dict(
-        kernel="k_smooth_map<float, unsigned char, 8, 7, true> (restricted smoothing, FP32)",
+        kernel="k_smooth_map<float, unsigned char, 8, 7, true, true> (restricted smoothing, "
+               "FP32, P split in halves)",
         bound="hbm", achieved=round(sm_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
         frac=round(sm_ach / HBM_PEAK_GBS, 4), traffic=traffic_record("k_smooth_f32_c4_traffic"),
         algorithmic_bytes_per_unit=int(sm_bytes), unit_of_work="smoothing launch",

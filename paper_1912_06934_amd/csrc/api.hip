@@ -184,6 +184,12 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rbase);
     dfree(c->rbox);
     dfree(c->paxes);
+    dfree(c->psplit_tab);
+    c->psplit = SplitRows{};
+    for (int t = 0; t < 2; ++t) {
+        dfree(c->ps64[t]);
+        dfree(c->ps32[t]);
+    }
     dfree(c->r64);
     dfree(c->r32);
     dfree(c->ac);
@@ -1156,6 +1162,41 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                        c->stream);
         c->pax_ncx = ncx;
         c->pax_ncxy = ncxy;
+        // P's split form for the smoothing iteration (8-slot rows on a 3D
+        // grid): per axis, the two-candidate positions before each position
+        // times the counts of the faster axes, bit 31 for two candidates
+        const int gdim[3] = {c->tdims[0], c->tdims[1], c->tdims[2]};
+        if (pw == 8 && gdim[0] > 1 && gdim[1] > 1 && gdim[2] > 1) {
+            std::vector<int> st(static_cast<size_t>(gdim[0]) + gdim[1] + gdim[2]);
+            int64_t scale = 1;
+            bool ok = true;
+            for (int ax = 0, base = 0; ax < 3; base += gdim[ax], ++ax) {
+                int64_t cnt2 = 0;
+                for (int x = 0; x < gdim[ax]; ++x) {
+                    const bool two = (paxes[base + x] >> 16) == 2;
+                    const int64_t v = cnt2 * scale;
+                    ok = ok && v < (int64_t{1} << 29);
+                    st[base + x] = static_cast<int>(v & 0x7FFFFFFF) |
+                                   (two ? static_cast<int>(0x80000000u) : 0);
+                    cnt2 += two ? 1 : 0;
+                }
+                scale *= cnt2;
+            }
+            // the three parts of an index (and of a neighbour's) sum below 2^31
+            if (ok && scale <= (int64_t{1} << 29)) {
+                if (!dalloc(c->psplit_tab, st.size()))
+                    return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
+                hipMemcpyAsync(c->psplit_tab, st.data(), st.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream);
+                c->psplit.tab = c->psplit_tab;
+                c->psplit.nx = gdim[0];
+                c->psplit.ny = gdim[1];
+                c->psplit.nz = gdim[2];
+                c->psplit.rnx = 1.0 / gdim[0];
+                c->psplit.rny = 1.0 / gdim[1];
+                c->psplit.n8 = scale;
+            }
+        }
     }
     if (rap_nbox_threads > 0) {
         if (!dalloc(c->nrbox, nrbox.size()) || !dalloc(c->npaxes, npaxes.size()))
@@ -1415,7 +1456,28 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
     // FP64 rows overflow an XCD's L2 between a row's two z-neighbour reads
     // in the plain order; FP32 rows fit, and measure no faster tiled
     if (c->j_dia && !fp32) sa.go = grid_order_for(c->n, c->j_off);
+    // P split in halves during the iteration (box supports on a 3D grid,
+    // 8-slot rows, the factored 7-point J in the grid's offsets): the zero
+    // slots of rows with fewer than 8 entries are neither read nor written
+    const SplitRows &pg = c->psplit;
+    const int gx = pg.nx, gxy = pg.nx * pg.ny;
     phase_begin(c, MSRSB_PHASE_SMOOTH);
+    const bool split = pg.tab && o->max_iter > 0 && jsym && c->jw == 7 && c->pw == 8 &&
+                       c->jmap_kind == 1 && static_cast<int64_t>(gxy) * pg.nz == c->n &&
+                       c->j_off.off[0] == -gxy && c->j_off.off[1] == -gx &&
+                       c->j_off.off[2] == -1 && c->j_off.off[3] == 0 && c->j_off.off[4] == 1 &&
+                       c->j_off.off[5] == gx && c->j_off.off[6] == gxy;
+    if (split) {
+        const size_t sm = static_cast<size_t>(c->n + pg.n8) * 4;
+        const bool okb = fp32 ? dalloc_keep(c->ps32[0], sm) && dalloc_keep(c->ps32[1], sm)
+                              : dalloc_keep(c->ps64[0], sm) && dalloc_keep(c->ps64[1], sm);
+        if (!okb) return fail(c, MSRSB_E_NOMEM, "allocation of the split basis failed");
+        launch_p_split(s, c->n, pg, fp32, c->p64[c->pcur], c->p32[c->pcur], c->ps64[c->pcur],
+                       c->ps32[c->pcur]);
+        sa.split = pg;
+    }
+    double *const *q64 = split ? c->ps64 : c->p64;
+    float *const *q32 = split ? c->ps32 : c->p32;
     int it = 0;
     double e_last = -1.0;
     for (it = 0; it < o->max_iter; ++it) {
@@ -1423,8 +1485,7 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
         sa.eit_part = check ? c->partials : nullptr;
         sa.eit_out = c->eit_val;
         const int src = c->pcur, dst = 1 - c->pcur;
-        launch_smooth(s, sa, fp32, c->jv, c->jv32, c->p64[src], c->p64[dst], c->p32[src],
-                      c->p32[dst]);
+        launch_smooth(s, sa, fp32, c->jv, c->jv32, q64[src], q64[dst], q32[src], q32[dst]);
         c->pcur = dst;
         if (check && o->tol >= 0.0) {
             hipMemcpyAsync(c->h_pinned, c->eit_val, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1437,6 +1498,9 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
             }
         }
     }
+    if (split)
+        launch_p_merge(s, c->n, pg, fp32, c->ps64[c->pcur], c->ps32[c->pcur], c->p64[c->pcur],
+                       c->p32[c->pcur]);
     phase_end(c, MSRSB_PHASE_SMOOTH);
     // last computed e_it, and P's statistics
     hipMemcpyAsync(c->h_pinned, c->eit_val, sizeof(double), hipMemcpyDeviceToHost, s);

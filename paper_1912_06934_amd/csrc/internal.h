@@ -93,6 +93,23 @@ struct TriOrder {
     std::vector<TriSegment> seg_l, seg_u;
 };
 
+// P's rows in two halves for the smoothing iteration, when the supports are
+// boxes on an nx x ny x nz grid (every row's pattern is a product of one or
+// two candidates per axis, 8 entries only where all three axes have two):
+// slots 0-3 of every row ([n][4]), then slots 4-7 of the 8-entry rows in row
+// order ([n8][4]), so that the zero slots of the narrower rows are neither
+// read nor written.  tab holds, per axis position, the number of two-
+// candidate positions before it on that axis, premultiplied by the counts of
+// the faster axes (x: 1, y: A_x, z: A_x A_y), with bit 31 set where the
+// position has two candidates: the second half of row (x, y, z) sits at
+// tx[x] + ty[y] + tz[z] (low 31 bits) when all three bits are set.
+struct SplitRows {
+    const int *tab = nullptr;  // [nx + ny + nz]; null: rows are not split
+    int nx = 0, ny = 0, nz = 0;
+    double rnx = 0.0, rny = 0.0;  // 1 / nx, 1 / ny
+    int64_t n8 = 0;
+};
+
 }  // namespace msrsb
 
 struct msrsb_ctx {
@@ -192,6 +209,13 @@ struct msrsb_ctx {
     // null unless every row of the pattern was checked to be one)
     int *paxes = nullptr;
     int pax_ncx = 0, pax_ncxy = 0;
+    // P split in halves for the smoothing iteration (see SplitRows; tab null
+    // unless the supports are boxes on a 3D grid with 8-slot rows), and the
+    // two split buffers of the iteration
+    int *psplit_tab = nullptr;
+    msrsb::SplitRows psplit;
+    double *ps64[2] = {nullptr, nullptr};
+    float *ps32[2] = {nullptr, nullptr};
     int64_t rnnz = 0;
     double *r64 = nullptr;
     float *r32 = nullptr;
@@ -349,6 +373,7 @@ struct SmoothArgs {
     bool sym = false;            // J stored factored (k_filter_jacobi's sym form)
     double omega = 0.0;
     GridOrder go;                // work-group order (nx == 0: plain)
+    SplitRows split;             // tab non-null: P in and out in the split form
 };
 void launch_filter_jacobi(hipStream_t s, int n, int bs, int filter, double omega, const int *rp,
                           const int *ci, const double *a, int jw, const DiaOffsets &joff,
@@ -360,6 +385,12 @@ void launch_init_basis(hipStream_t s, int n, int pw, const int *pcol, const int 
 void launch_smooth(hipStream_t s, const SmoothArgs &a, bool fp32, const double *jv64,
                    const float *jv32, const double *pin64, double *pout64, const float *pin32,
                    float *pout32);
+// padded rows [n][8] <-> the split form (q: [n][4] then [n8][4]); merging
+// writes zeros to the slots 4-7 of the narrower rows
+void launch_p_split(hipStream_t s, int n, const SplitRows &g, bool fp32, const double *p64,
+                    const float *p32, double *q64, float *q32);
+void launch_p_merge(hipStream_t s, int n, const SplitRows &g, bool fp32, const double *q64,
+                    const float *q32, double *p64, float *p32);
 void launch_basis_stats(hipStream_t s, int n, int pw, const int *pcol, bool fp32,
                         const double *p64, const float *p32, double *partials, double *out3);
 void launch_p_convert(hipStream_t s, int64_t m, const float *src, double *dst);

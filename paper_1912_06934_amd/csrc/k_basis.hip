@@ -266,6 +266,55 @@ __host__ __device__ inline bool map_is_diag(uint32_t m)
     return true;
 }
 
+// t / d for 0 <= t < 2^31 from the FP64 product with 1 / d, which is off
+// by at most one
+__device__ __forceinline__ int div_by(int t, int d, double rd)
+{
+    int q = static_cast<int>(static_cast<double>(t) * rd);
+    const int r = t - q * d;
+    q += r < 0 ? -1 : (r >= d ? 1 : 0);
+    return q;
+}
+
+// Second-half indices (h) of row row0 + threadIdx.x and of its six 7-point
+// neighbours, in the order of the ascending offsets (-z, -y, -x, 0, +x, +y,
+// +z), and whether each has 8 entries (f; a neighbour position outside the
+// grid has none).  Rows run x fastest; the row must lie in the grid.
+__device__ __forceinline__ void split_rows7(const SplitRows &g, int row0, int (&h)[7],
+                                            bool (&f)[7])
+{
+    const int nx = g.nx, ny = g.ny;
+    const int line0 = div_by(row0, nx, g.rnx);
+    const int z0 = div_by(line0, ny, g.rny);
+    const int t = row0 - line0 * nx + static_cast<int>(threadIdx.x);
+    const int q = div_by(t, nx, g.rnx);
+    const int x = t - q * nx;
+    const int yy = line0 - z0 * ny + q;
+    const int q2 = div_by(yy, ny, g.rny);
+    const int y = yy - q2 * ny, z = z0 + q2;
+    const int *tx = g.tab, *ty = g.tab + nx, *tz = g.tab + nx + ny;
+    const int ax = tx[x], ay = ty[y], az = tz[z];
+    const int axm = x > 0 ? tx[x - 1] : 0, axp = x + 1 < nx ? tx[x + 1] : 0;
+    const int aym = y > 0 ? ty[y - 1] : 0, ayp = y + 1 < ny ? ty[y + 1] : 0;
+    const int azm = z > 0 ? tz[z - 1] : 0, azp = z + 1 < g.nz ? tz[z + 1] : 0;
+    constexpr int M = 0x7FFFFFFF;
+    const int bx = ax & M, by = ay & M, bz = az & M;
+    h[0] = bx + by + (azm & M);
+    f[0] = (ax & ay & azm) < 0;
+    h[1] = bx + (aym & M) + bz;
+    f[1] = (ax & aym & az) < 0;
+    h[2] = (axm & M) + by + bz;
+    f[2] = (axm & ay & az) < 0;
+    h[3] = bx + by + bz;
+    f[3] = (ax & ay & az) < 0;
+    h[4] = (axp & M) + by + bz;
+    f[4] = (axp & ay & az) < 0;
+    h[5] = bx + (ayp & M) + bz;
+    f[5] = (ax & ayp & az) < 0;
+    h[6] = bx + by + (azp & M);
+    f[6] = (ax & ay & azp) < 0;
+}
+
 // JW > 0: J has exactly JW slots per row, known at compile time, and the
 // neighbours are taken in chunks whose map indices, weights and rows are all
 // loaded before any is used (one wavefront keeps a whole chunk in flight).
@@ -273,13 +322,16 @@ __host__ __device__ inline bool map_is_diag(uint32_t m)
 // SYM (JW > 0, stencil J stored factored by k_filter_jacobi's sym form):
 // J_io = s_i Ghat_up[JW-1-o][i+off_o] below the diagonal, s_i Ghat_up[o][i]
 // above it, and 1 - omega (1 for a frozen row) on it.
-template <typename T, typename IDX, int PW, int JW, bool SYM = false>
+// SPLIT (PW 8, the 7-point J): P in and out in the split form (SplitRows):
+// the first halves of all rows, then the second halves of the 8-entry rows.
+template <typename T, typename IDX, int PW, int JW, bool SYM = false, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_smooth_map(
     int n, int jw, DiaOffsets joff, const int *__restrict__ jcol, const T *__restrict__ jv,
     const IDX *__restrict__ jmap, const uint32_t *__restrict__ tab, int ntab,
     const T *__restrict__ pin, T *__restrict__ pout, const uint8_t *__restrict__ interior,
-    double *__restrict__ eit_part, double omega, GridOrder go)
+    double *__restrict__ eit_part, double omega, GridOrder go, SplitRows sg)
 {
+    static_assert(!SPLIT || (PW == 8 && JW == 7), "the split form covers 8-slot rows, 7-point J");
     // a one-byte map index selects from a table of at most 256 maps kept in
     // LDS; the sign bit of sdiag marks diagonal maps
     __shared__ uint32_t stab[256];
@@ -288,7 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
     __shared__ T sperm[JW > 0 ? (PW + 1) * kBlock : 1];
     T *sb = sperm + (JW > 0 ? threadIdx.x : 0);
     if constexpr (JW > 0) sb[PW * kBlock] = T(0);
-    const int i = grid_row0(go) + static_cast<int>(threadIdx.x);
+    const int row0 = grid_row0(go);
+    const int i = row0 + static_cast<int>(threadIdx.x);
     // chunk: up to 9 FP32 rows or 7 FP64 rows in registers at once
     constexpr int CMAX = sizeof(T) == 8 ? 7 : 9;
     constexpr int MID = JW / 2;
@@ -301,6 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
     constexpr int N1 = kOne ? JW : 1;
     int t1[N1];
     T w1[N1], v1[N1][PW];
+    // split form: this row's second-half index and whether it has one
+    int h_own = 0;
+    bool f_own = false;
     if constexpr (kOne) {
         if (i < n) {
             // the neighbour rows first, then the map indices and J values
@@ -313,10 +369,36 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
 #pragma unroll
                 for (int o = 0; o < JW; ++o) k[o] = i + joff.off[o];
             }
+            if constexpr (SPLIT) {
+                // first halves by row; second halves where the row has 8
+                // entries (its other slots are zero and not stored)
+                int hs[7];
+                bool fs[7];
+                split_rows7(sg, row0, hs, fs);
+                const T *phi = pin + static_cast<int64_t>(n) * 4;
 #pragma unroll
-            for (int o = 0; o < JW; ++o) {
-                const int kk = (k[o] >= 0 && k[o] < n) ? k[o] : i;
-                load_row<T, PW>(pin, kk, v1[o]);
+                for (int o = 0; o < JW; ++o) {
+                    const int kk = (k[o] >= 0 && k[o] < n) ? k[o] : i;
+                    T a4[4];
+                    load_row<T, 4>(pin, kk, a4);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) v1[o][s] = a4[s];
+                }
+#pragma unroll
+                for (int o = 0; o < JW; ++o) {
+                    T b4[4] = {T(0), T(0), T(0), T(0)};
+                    if (fs[o]) load_row<T, 4>(phi, hs[o], b4);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) v1[o][4 + s] = b4[s];
+                }
+                h_own = hs[MID];
+                f_own = fs[MID];
+            } else {
+#pragma unroll
+                for (int o = 0; o < JW; ++o) {
+                    const int kk = (k[o] >= 0 && k[o] < n) ? k[o] : i;
+                    load_row<T, PW>(pin, kk, v1[o]);
+                }
             }
             // J values as stored (the weights are formed after the table)
             T jraw[JW];
@@ -469,7 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
 #pragma unroll
         for (int s = 0; s < PW; ++s) rs += static_cast<double>(acc[s]);
         T old[PW];
-        load_row<T, PW>(pin, i, old);
+        if constexpr (SPLIT) {
+            // the row itself is the middle neighbour
+#pragma unroll
+            for (int s = 0; s < PW; ++s) old[s] = v1[MID][s];
+        } else {
+            load_row<T, PW>(pin, i, old);
+        }
         const bool inner = eit_part != nullptr && interior[i] != 0;
         const double rinv = 1.0 / rs;
 #pragma unroll
@@ -480,7 +568,20 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
             }
             out[s] = static_cast<T>(static_cast<double>(acc[s]) * rinv);
         }
-        if constexpr (!kStream) store_row<T, PW>(pout, i, out);
+        if constexpr (!kStream) {
+            if constexpr (SPLIT) {
+                T lo4[4], hi4[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    lo4[s] = out[s];
+                    hi4[s] = out[4 + s];
+                }
+                store_row<T, 4>(pout, i, lo4);
+                if (f_own) store_row<T, 4>(pout + static_cast<int64_t>(n) * 4, h_own, hi4);
+            } else {
+                store_row<T, PW>(pout, i, out);
+            }
+        }
     }
     if constexpr (kStream) {
         // FP64 rows are written as streaming stores: they are not read again
@@ -491,21 +592,66 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
         // first transposed through the threads' LDS columns, which the
         // accumulation no longer needs: each store instruction then covers
         // 1 KB of whole cache lines instead of 16 bytes of each of 64 rows.
-        constexpr int L = 16 / sizeof(T), CH = PW / L;
+        constexpr int L = 16 / sizeof(T);
         typedef T vec __attribute__((ext_vector_type(L)));
-#pragma unroll
-        for (int t = 0; t < PW; ++t) sb[t * kBlock] = out[t];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
-        const int64_t row0 = static_cast<int64_t>(i) - lane;  // the wavefront's first row
+        const int64_t wrow0 = static_cast<int64_t>(i) - lane;  // the wavefront's first row
+        if constexpr (SPLIT) {
+            // first halves: 64 consecutive rows of 4 slots
+            constexpr int CH = 4 / L;
 #pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            const int piece = q * 64 + lane, r = piece / CH, c = piece % CH;
-            vec x;
+            for (int t = 0; t < 4; ++t) sb[t * kBlock] = out[t];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-            for (int l = 0; l < L; ++l) x[l] = sperm[(c * L + l) * kBlock + wbase + r];
-            if (row0 + r < n)
-                __builtin_nontemporal_store(x, reinterpret_cast<vec *>(pout + (row0 + r) * PW) + c);
+            for (int q = 0; q < CH; ++q) {
+                const int piece = q * 64 + lane, r = piece / CH, c = piece % CH;
+                vec x;
+#pragma unroll
+                for (int l = 0; l < L; ++l) x[l] = sperm[(c * L + l) * kBlock + wbase + r];
+                if (wrow0 + r < n)
+                    __builtin_nontemporal_store(x, reinterpret_cast<vec *>(pout + (wrow0 + r) * 4) + c);
+            }
+            // second halves of the wavefront's 8-entry rows: consecutive in
+            // the second part, packed into the first columns before storing
+            const bool mine = i < n && f_own;
+            const uint64_t bal = __ballot(mine);
+            if (bal != 0) {
+                const int p = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                    static_cast<uint32_t>(bal >> 32),
+                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+                const int cnt = __popcll(bal), first = __ffsll(static_cast<long long>(bal)) - 1;
+                const int64_t h0 = __builtin_amdgcn_readlane(h_own - p, first);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (mine)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) sperm[t * kBlock + wbase + p] = out[4 + t];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                T *phi = pout + static_cast<int64_t>(n) * 4;
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int piece = q * 64 + lane, r = piece / CH, c = piece % CH;
+                    if (r < cnt) {
+                        vec x;
+#pragma unroll
+                        for (int l = 0; l < L; ++l) x[l] = sperm[(c * L + l) * kBlock + wbase + r];
+                        __builtin_nontemporal_store(x, reinterpret_cast<vec *>(phi + (h0 + r) * 4) + c);
+                    }
+                }
+            }
+        } else {
+            constexpr int CH = PW / L;
+#pragma unroll
+            for (int t = 0; t < PW; ++t) sb[t * kBlock] = out[t];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int piece = q * 64 + lane, r = piece / CH, c = piece % CH;
+                vec x;
+#pragma unroll
+                for (int l = 0; l < L; ++l) x[l] = sperm[(c * L + l) * kBlock + wbase + r];
+                if (wrow0 + r < n)
+                    __builtin_nontemporal_store(x, reinterpret_cast<vec *>(pout + (wrow0 + r) * PW) + c);
+            }
         }
     }
     if (eit_part != nullptr) eit_block(emax, eit_part);
@@ -755,15 +901,24 @@ void smooth_map_launch(hipStream_t s, const SmoothArgs &a, const T *jv, const T 
 {
     if constexpr (JW > 0) {
         if (a.sym) {
+            if constexpr (PW == 8 && JW == 7 && sizeof(IDX) == 1) {
+                if (a.split.tab) {
+                    k_smooth_map<T, IDX, 8, 7, true, true><<<grid_n(a.n), kBlock, 0, s>>>(
+                        a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx),
+                        a.jmap_tab, a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega, a.go,
+                        a.split);
+                    return;
+                }
+            }
             k_smooth_map<T, IDX, PW, JW, true><<<grid_n(a.n), kBlock, 0, s>>>(
                 a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx), a.jmap_tab,
-                a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega, a.go);
+                a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega, a.go, SplitRows{});
             return;
         }
     }
     k_smooth_map<T, IDX, PW, JW><<<grid_n(a.n), kBlock, 0, s>>>(
         a.n, a.jw, a.joff, a.jcol, jv, static_cast<const IDX *>(a.jmap_idx), a.jmap_tab,
-        a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega, a.go);
+        a.jmap_ntab, pin, pout, a.interior, a.eit_part, a.omega, a.go, SplitRows{});
 }
 
 template <typename T, typename IDX, int PW>
@@ -813,7 +968,65 @@ void smooth_t(hipStream_t s, const SmoothArgs &a, const T *jv, const T *pin, T *
                                                            a.pcol, pin, pout, a.interior, a.eit_part);
 }
 
+// Row i's second-half index and whether it has 8 entries (see SplitRows)
+__device__ inline bool split_row(const SplitRows &g, int i, int &h)
+{
+    const int x = i % g.nx, line = i / g.nx, y = line % g.ny, z = line / g.ny;
+    const int a = g.tab[x], b = g.tab[g.nx + y], c = g.tab[g.nx + g.ny + z];
+    h = (a & 0x7FFFFFFF) + (b & 0x7FFFFFFF) + (c & 0x7FFFFFFF);
+    return (a & b & c) < 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_p_split(int n, SplitRows g, const T *__restrict__ p,
+                                                    T *__restrict__ q)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int h;
+    const bool f = split_row(g, i, h);
+    const int64_t r = static_cast<int64_t>(i) * 8;
+    for (int s = 0; s < 4; ++s) q[static_cast<int64_t>(i) * 4 + s] = p[r + s];
+    if (f)
+        for (int s = 0; s < 4; ++s)
+            q[(static_cast<int64_t>(n) + h) * 4 + s] = p[r + 4 + s];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_p_merge(int n, SplitRows g, const T *__restrict__ q,
+                                                    T *__restrict__ p)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int h;
+    const bool f = split_row(g, i, h);
+    const int64_t r = static_cast<int64_t>(i) * 8;
+    for (int s = 0; s < 4; ++s) p[r + s] = q[static_cast<int64_t>(i) * 4 + s];
+    for (int s = 0; s < 4; ++s)
+        p[r + 4 + s] = f ? q[(static_cast<int64_t>(n) + h) * 4 + s] : T(0);
+}
+
 }  // namespace
+
+void launch_p_split(hipStream_t s, int n, const SplitRows &g, bool fp32, const double *p64,
+                    const float *p32, double *q64, float *q32)
+{
+    if (n <= 0) return;
+    if (fp32)
+        k_p_split<float><<<grid_n(n), kBlock, 0, s>>>(n, g, p32, q32);
+    else
+        k_p_split<double><<<grid_n(n), kBlock, 0, s>>>(n, g, p64, q64);
+}
+
+void launch_p_merge(hipStream_t s, int n, const SplitRows &g, bool fp32, const double *q64,
+                    const float *q32, double *p64, float *p32)
+{
+    if (n <= 0) return;
+    if (fp32)
+        k_p_merge<float><<<grid_n(n), kBlock, 0, s>>>(n, g, q32, p32);
+    else
+        k_p_merge<double><<<grid_n(n), kBlock, 0, s>>>(n, g, q64, p64);
+}
 
 GridOrder grid_order_for(int n, const DiaOffsets &d)
 {

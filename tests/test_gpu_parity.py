@@ -252,9 +252,15 @@ def test_coarse_inverse_many_panels(torch_cuda, case):
     assert rel_max(z, z_ref) <= 1e-10
 
 
-def test_coarse_inverse_pivoting_nonsymmetric(torch_cuda):
-    # a non-symmetric operator takes the partial-pivoting Gauss-Jordan path
-    cfg = _nonsymmetric(tpfa_inputs("c1", (64, 64), 4))
+@pytest.mark.parametrize("dims", [(32, 32), (40, 40), (64, 64), (80, 80), (100, 92),
+                                  (176, 176), (212, 200), (256, 256)],
+                         ids=["64coarse", "100coarse", "256coarse", "400coarse", "575coarse",
+                              "1936coarse", "2650coarse", "4096coarse"])
+def test_coarse_inverse_pivoting_nonsymmetric(torch_cuda, dims):
+    # a non-symmetric operator takes the partial-pivoting Gauss-Jordan path;
+    # the sizes reach every leaf form (64 to 1,024 threads with one row each,
+    # then 2, 3 and 4 rows per thread up to the largest coarse system)
+    cfg = _nonsymmetric(tpfa_inputs("c1", dims, 4))
     orc = oracle_setup(cfg, kmax=20)
     s, _ = gpu_setup_matrix(cfg, kmax=20)
     assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
