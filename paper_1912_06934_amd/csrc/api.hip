@@ -185,7 +185,9 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rbox);
     dfree(c->paxes);
     dfree(c->psplit_tab);
+    dfree(c->psplit_tab2);
     c->psplit = SplitRows{};
+    c->ps_valid = false;
     for (int t = 0; t < 2; ++t) {
         dfree(c->ps64[t]);
         dfree(c->ps32[t]);
@@ -1182,11 +1184,17 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
                 }
                 scale *= cnt2;
             }
-            // the three parts of an index (and of a neighbour's) sum below 2^31
-            if (ok && scale <= (int64_t{1} << 29)) {
-                if (!dalloc(c->psplit_tab, st.size()))
+            // the three parts of an index (and of a neighbour's) sum below
+            // 2^31, and the second halves' bytes (FP64) stay below 2^31 (one
+            // buffer resource covers them)
+            if (ok && scale * 32 <= INT32_MAX) {
+                std::vector<int2> st2(st.size());
+                for (size_t k = 0; k < st.size(); ++k) st2[k] = make_int2(paxes[k], st[k]);
+                if (!dalloc(c->psplit_tab, st.size()) || !dalloc(c->psplit_tab2, st2.size()))
                     return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
                 hipMemcpyAsync(c->psplit_tab, st.data(), st.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream);
+                hipMemcpyAsync(c->psplit_tab2, st2.data(), st2.size() * sizeof(int2),
                                hipMemcpyHostToDevice, c->stream);
                 c->psplit.tab = c->psplit_tab;
                 c->psplit.nx = gdim[0];
@@ -1423,6 +1431,7 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
                          // the node-block copy of A (vector problems)
                          c->a_ns.n > 0 ? &c->a_ns : nullptr, c->a_ns.n > 0 ? c->a_ns_val : nullptr);
     phase_end(c, MSRSB_PHASE_FILTER);
+    c->ps_valid = false;  // P changes from here on
     phase_begin(c, MSRSB_PHASE_INIT);
     const bool warm = o->warm_start && c->has_basis;
     if (!warm) {
@@ -1498,9 +1507,11 @@ msrsb_status msrsb_setup_basis(msrsb_ctx *c, const msrsb_basis_opts *o, msrsb_ba
             }
         }
     }
-    if (split)
+    if (split) {
         launch_p_merge(s, c->n, pg, fp32, c->ps64[c->pcur], c->ps32[c->pcur], c->p64[c->pcur],
                        c->p32[c->pcur]);
+        c->ps_valid = true;
+    }
     phase_end(c, MSRSB_PHASE_SMOOTH);
     // last computed e_it, and P's statistics
     hipMemcpyAsync(c->h_pinned, c->eit_val, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1537,6 +1548,7 @@ msrsb_status msrsb_set_prolongation(msrsb_ctx *c, const double *val, int where)
         return fail(c, MSRSB_E_NOMEM, "allocation failed");
     c->pcur = 0;
     c->p_is32 = false;
+    c->ps_valid = false;
     hipMemcpyAsync(c->p_csr_tmp, val, c->pnnz * sizeof(double), kind_in(where), c->stream);
     launch_csr_to_ell(c->stream, c->n, c->pw, c->prp, c->p_csr_tmp, c->p64[0]);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MSRSB_E_HIP, "copy failed");

@@ -213,9 +213,11 @@ struct msrsb_ctx {
     // unless the supports are boxes on a 3D grid with 8-slot rows), and the
     // two split buffers of the iteration
     int *psplit_tab = nullptr;
+    int2 *psplit_tab2 = nullptr;  // per axis position {paxes entry, psplit_tab entry}
     msrsb::SplitRows psplit;
     double *ps64[2] = {nullptr, nullptr};
     float *ps32[2] = {nullptr, nullptr};
+    bool ps_valid = false;  // ps64/ps32[pcur] hold the current P (the prolongation reads it)
     int64_t rnnz = 0;
     double *r64 = nullptr;
     float *r32 = nullptr;
@@ -478,6 +480,10 @@ struct RestrictBoxes {
 struct ProlongAxes {
     const int *tab = nullptr;
     int nx = 0, ny = 0, ncx = 0, ncxy = 0;
+    // non-null: P is given in the split form (SplitRows, n8 rows of 8
+    // entries), and per axis position {tab entry, SplitRows entry}
+    const int2 *tab2 = nullptr;
+    int64_t n8 = 0;
 };
 // xc = R x; columns from the boxes when given, else from rci, or (roff16
 // non-null) rbase[e / 64] + roff16[e]

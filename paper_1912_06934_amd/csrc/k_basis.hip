@@ -276,12 +276,13 @@ __device__ __forceinline__ int div_by(int t, int d, double rd)
     return q;
 }
 
-// Second-half indices (h) of row row0 + threadIdx.x and of its six 7-point
-// neighbours, in the order of the ascending offsets (-z, -y, -x, 0, +x, +y,
-// +z), and whether each has 8 entries (f; a neighbour position outside the
-// grid has none).  Rows run x fastest; the row must lie in the grid.
-__device__ __forceinline__ void split_rows7(const SplitRows &g, int row0, int (&h)[7],
-                                            bool (&f)[7])
+// The split form's table entries of row row0 + threadIdx.x and of its six
+// 7-point neighbours' axis positions (rows run x fastest; the row must lie in
+// the grid): a[0..2] x, y, z; a[3..5] x-1, y-1, z-1; a[6..8] x+1, y+1, z+1,
+// 0 for a position outside the grid.  All nine are loaded at once (indices
+// clamped, no branches) and used only by split_index7, so that other loads
+// can be issued while they are in flight.
+__device__ __forceinline__ void split_load7(const SplitRows &g, int row0, int (&a)[9])
 {
     const int nx = g.nx, ny = g.ny;
     const int line0 = div_by(row0, nx, g.rnx);
@@ -293,26 +294,45 @@ __device__ __forceinline__ void split_rows7(const SplitRows &g, int row0, int (&
     const int q2 = div_by(yy, ny, g.rny);
     const int y = yy - q2 * ny, z = z0 + q2;
     const int *tx = g.tab, *ty = g.tab + nx, *tz = g.tab + nx + ny;
-    const int ax = tx[x], ay = ty[y], az = tz[z];
-    const int axm = x > 0 ? tx[x - 1] : 0, axp = x + 1 < nx ? tx[x + 1] : 0;
-    const int aym = y > 0 ? ty[y - 1] : 0, ayp = y + 1 < ny ? ty[y + 1] : 0;
-    const int azm = z > 0 ? tz[z - 1] : 0, azp = z + 1 < g.nz ? tz[z + 1] : 0;
+    a[0] = tx[x];
+    a[1] = ty[y];
+    a[2] = tz[z];
+    a[3] = tx[max(x - 1, 0)];
+    a[4] = ty[max(y - 1, 0)];
+    a[5] = tz[max(z - 1, 0)];
+    a[6] = tx[min(x + 1, nx - 1)];
+    a[7] = ty[min(y + 1, ny - 1)];
+    a[8] = tz[min(z + 1, g.nz - 1)];
+    a[3] = x > 0 ? a[3] : 0;
+    a[4] = y > 0 ? a[4] : 0;
+    a[5] = z > 0 ? a[5] : 0;
+    a[6] = x + 1 < nx ? a[6] : 0;
+    a[7] = y + 1 < ny ? a[7] : 0;
+    a[8] = z + 1 < g.nz ? a[8] : 0;
+}
+
+// Second-half indices (h) of the row and its neighbours in the order of the
+// ascending 7-point offsets (-z, -y, -x, 0, +x, +y, +z), and whether each has
+// 8 entries (f)
+__device__ __forceinline__ void split_index7(const int (&a)[9], int (&h)[7], bool (&f)[7])
+{
     constexpr int M = 0x7FFFFFFF;
+    const int ax = a[0], ay = a[1], az = a[2];
     const int bx = ax & M, by = ay & M, bz = az & M;
-    h[0] = bx + by + (azm & M);
-    f[0] = (ax & ay & azm) < 0;
-    h[1] = bx + (aym & M) + bz;
-    f[1] = (ax & aym & az) < 0;
-    h[2] = (axm & M) + by + bz;
-    f[2] = (axm & ay & az) < 0;
+    h[0] = bx + by + (a[5] & M);
+    f[0] = (ax & ay & a[5]) < 0;
+    h[1] = bx + (a[4] & M) + bz;
+    f[1] = (ax & a[4] & az) < 0;
+    h[2] = (a[3] & M) + by + bz;
+    f[2] = (a[3] & ay & az) < 0;
     h[3] = bx + by + bz;
     f[3] = (ax & ay & az) < 0;
-    h[4] = (axp & M) + by + bz;
-    f[4] = (axp & ay & az) < 0;
-    h[5] = bx + (ayp & M) + bz;
-    f[5] = (ax & ayp & az) < 0;
-    h[6] = bx + by + (azp & M);
-    f[6] = (ax & ay & azp) < 0;
+    h[4] = (a[6] & M) + by + bz;
+    f[4] = (a[6] & ay & az) < 0;
+    h[5] = bx + (a[7] & M) + bz;
+    f[5] = (ax & a[7] & az) < 0;
+    h[6] = bx + by + (a[8] & M);
+    f[6] = (ax & ay & a[8]) < 0;
 }
 
 // JW > 0: J has exactly JW slots per row, known at compile time, and the
@@ -369,13 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
 #pragma unroll
                 for (int o = 0; o < JW; ++o) k[o] = i + joff.off[o];
             }
+            // split form: the table entries, then the first halves by row;
+            // the second halves follow the J loads (below)
+            int sa[SPLIT ? 9 : 1];
             if constexpr (SPLIT) {
-                // first halves by row; second halves where the row has 8
-                // entries (its other slots are zero and not stored)
-                int hs[7];
-                bool fs[7];
-                split_rows7(sg, row0, hs, fs);
-                const T *phi = pin + static_cast<int64_t>(n) * 4;
+                split_load7(sg, row0, sa);
 #pragma unroll
                 for (int o = 0; o < JW; ++o) {
                     const int kk = (k[o] >= 0 && k[o] < n) ? k[o] : i;
@@ -384,15 +402,6 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
 #pragma unroll
                     for (int s = 0; s < 4; ++s) v1[o][s] = a4[s];
                 }
-#pragma unroll
-                for (int o = 0; o < JW; ++o) {
-                    T b4[4] = {T(0), T(0), T(0), T(0)};
-                    if (fs[o]) load_row<T, 4>(phi, hs[o], b4);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) v1[o][4 + s] = b4[s];
-                }
-                h_own = hs[MID];
-                f_own = fs[MID];
             } else {
 #pragma unroll
                 for (int o = 0; o < JW; ++o) {
@@ -422,6 +431,38 @@ __global__ __launch_bounds__(kBlock) void k_smooth_map(
             }
 #pragma unroll
             for (int o = 0; o < JW; ++o) w1[o] = jraw[o];
+            if constexpr (SPLIT) {
+                // second halves where the row has 8 entries (the other rows'
+                // slots 4-7 are zero and not stored): a buffer load whose
+                // offset lies past the end returns zeros without a memory
+                // access, so no lane branches.  The indices are formed only
+                // here (the scheduler may not hoist them above the loads
+                // issued so far, which would wait for the table entries
+                // before issuing those).
+                __builtin_amdgcn_sched_barrier(0);
+                int hs[7];
+                bool fs[7];
+                split_index7(sa, hs, fs);
+                const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<T *>(pin + static_cast<int64_t>(n) * 4), 0,
+                    static_cast<int>(sg.n8 * 4 * static_cast<int64_t>(sizeof(T))), 0x00020000);
+                constexpr int L = 16 / sizeof(T);
+                typedef T vec __attribute__((ext_vector_type(L)));
+#pragma unroll
+                for (int o = 0; o < JW; ++o) {
+                    const uint32_t off =
+                        fs[o] ? static_cast<uint32_t>(hs[o]) * (4 * sizeof(T)) : 0x80000000u;
+#pragma unroll
+                    for (int q = 0; q < 4 / L; ++q) {
+                        const vec x = __builtin_bit_cast(
+                            vec, __builtin_amdgcn_raw_buffer_load_b128(rh, off + 16 * q, 0, 0));
+#pragma unroll
+                        for (int l = 0; l < L; ++l) v1[o][4 + q * L + l] = x[l];
+                    }
+                }
+                h_own = hs[MID];
+                f_own = fs[MID];
+            }
         }
     }
     if constexpr (sizeof(IDX) == 1) {

@@ -1168,23 +1168,57 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *_
 // (ProlongAxes) instead of loaded: the row's values are the only P data read.
 // Slot u of the row is (ix, iy, iz) with ix fastest, as the ascending column
 // order puts them; slots past cx cy cz are padding.
-template <typename T, int PW, typename ZT = double>
+// SPLIT (PW 8): pv is P's split form (slots 0-3 of every row, then slots
+// 4-7 of the 8-entry rows), located through ax.tab2's second entries.
+template <typename T, int PW, typename ZT = double, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_prolong_axes(int n, ProlongAxes ax,
                                                          const T *__restrict__ pv,
                                                          const double *__restrict__ wc,
                                                          ZT *__restrict__ z, int zero)
 {
+    static_assert(!SPLIT || PW == 8, "the split form has 8-slot rows");
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const unsigned xy = static_cast<unsigned>(i) / static_cast<unsigned>(ax.nx);
     const int x = i - static_cast<int>(xy) * ax.nx;
     const unsigned zz = xy / static_cast<unsigned>(ax.ny);
     const int y = static_cast<int>(xy - zz * static_cast<unsigned>(ax.ny));
-    const int tx = ax.tab[x], ty = ax.tab[ax.nx + y], tz = ax.tab[ax.nx + ax.ny + zz];
+    int tx, ty, tz;
     T val[PW];
-    {
-        constexpr int L = 16 / sizeof(T);
-        typedef T tvec __attribute__((ext_vector_type(L)));
+    constexpr int L = 16 / sizeof(T);
+    typedef T tvec __attribute__((ext_vector_type(L)));
+    if constexpr (SPLIT) {
+        const int2 ex = ax.tab2[x], ey = ax.tab2[ax.nx + y], ez = ax.tab2[ax.nx + ax.ny + zz];
+        tx = ex.x;
+        ty = ey.x;
+        tz = ez.x;
+        constexpr int M = 0x7FFFFFFF;
+        const int h = (ex.y & M) + (ey.y & M) + (ez.y & M);
+        const bool f = (ex.y & ey.y & ez.y) < 0;
+        const tvec *lo = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * 4);
+#pragma unroll
+        for (int q = 0; q < 4 / L; ++q) {
+            const tvec v = lo[q];
+#pragma unroll
+            for (int u = 0; u < L; ++u) val[L * q + u] = v[u];
+        }
+        // a row with fewer than 8 entries uses slots 0-3 only: its buffer
+        // load lies past the end and returns zeros without a memory access
+        const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T *>(pv + static_cast<int64_t>(n) * 4), 0,
+            static_cast<int>(ax.n8 * 4 * static_cast<int64_t>(sizeof(T))), 0x00020000);
+        const uint32_t off = f ? static_cast<uint32_t>(h) * (4 * sizeof(T)) : 0x80000000u;
+#pragma unroll
+        for (int q = 0; q < 4 / L; ++q) {
+            const tvec v = __builtin_bit_cast(
+                tvec, __builtin_amdgcn_raw_buffer_load_b128(rh, off + 16 * q, 0, 0));
+#pragma unroll
+            for (int u = 0; u < L; ++u) val[4 + L * q + u] = v[u];
+        }
+    } else {
+        tx = ax.tab[x];
+        ty = ax.tab[ax.nx + y];
+        tz = ax.tab[ax.nx + ax.ny + zz];
         const tvec *vs = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * PW);
 #pragma unroll
         for (int q = 0; q < PW / L; ++q) {
@@ -1541,7 +1575,10 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
                           const double *part_rr, double *host_out, int tag,
                           const ProlongAxes &axes)
 {
-    if (axes.tab && pw == 8)
+    if (axes.tab2 && pw == 8)
+        k_prolong_axes<float, 8, float, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1,
+                                                                            0);
+    else if (axes.tab && pw == 8)
         k_prolong_axes<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
     else if (axes.tab)
         k_prolong_axes<float, 4, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
@@ -1595,7 +1632,10 @@ template <typename T>
 void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16, const T *pv,
                const double *wc, double *z, bool zero, const ProlongAxes &axes)
 {
-    if (axes.tab && pw == 4)
+    if (axes.tab2 && pw == 8)
+        k_prolong_axes<T, 8, double, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z,
+                                                                          zero ? 1 : 0);
+    else if (axes.tab && pw == 4)
         k_prolong_axes<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);
     else if (axes.tab && pw == 8)
         k_prolong_axes<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);

@@ -380,6 +380,15 @@ ApplyBufs ctx_apply_bufs(msrsb_ctx *c)
     return b;
 }
 
+// The FP64 prolongation reads P's split form while it holds the current P
+// (fewer bytes: the zero slots of rows with fewer than 8 entries are not
+// stored).  The FP32 one keeps the padded rows: its second-half address
+// waits on a table load, and in FP32 that costs more time than the bytes
+// save.  prolong_p64 / prolong_p32 return the matching values.
+static bool prolong_split(const msrsb_ctx *c)
+{
+    return c->paxes && c->ps_valid && c->pw == 8 && !c->p_is32;
+}
 static ProlongAxes prolong_axes(const msrsb_ctx *c)
 {
     ProlongAxes a;
@@ -389,8 +398,20 @@ static ProlongAxes prolong_axes(const msrsb_ctx *c)
         a.ny = c->tdims[1];
         a.ncx = c->pax_ncx;
         a.ncxy = c->pax_ncxy;
+        if (prolong_split(c)) {
+            a.tab2 = c->psplit_tab2;
+            a.n8 = c->psplit.n8;
+        }
     }
     return a;
+}
+static const double *prolong_p64(const msrsb_ctx *c)
+{
+    return prolong_split(c) ? c->ps64[c->pcur] : c->p64[c->pcur];
+}
+static const float *prolong_p32(const msrsb_ctx *c)
+{
+    return c->p32[c->pcur];
 }
 
 static RestrictBoxes restrict_boxes(const msrsb_ctx *c)
@@ -438,7 +459,7 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
                             c->roff16, c->rbase, c->r32, b.vc, restrict_boxes(c), upd);
         coarse_apply(c, trans, b);
         launch_prec_f32_post(s, n, op.d, op.ad32, dinv, v, z1, z2, c->pw, c->pcol16,
-                             c->p32[c->pcur], b.wc, zout, dots->zold, dots->part, dots->scal,
+                             prolong_p32(c), b.wc, zout, dots->zold, dots->part, dots->scal,
                              dots->part_rr, dots->host_out, dots->tag, prolong_axes(c));
         return;
     }
@@ -464,7 +485,8 @@ void apply_two_stage(msrsb_ctx *c, const msrsb_solve_opts *o, const double *v, d
         launch_restrict(s, c->nc, c->rrp, c->rci, c->roff16, c->rbase, c->p_is32, c->r64, c->r32,
                         res, b.vc, restrict_boxes(c));
         coarse_apply(c, trans, b);
-        launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, c->p64[c->pcur], c->p32[c->pcur],
+        launch_prolong_ell(s, n, c->pw, c->pcol_ell, c->pcol16, c->p_is32, prolong_p64(c),
+                           prolong_p32(c),
                            b.wc, z, zero, prolong_axes(c));
         zero = false;
     }
