@@ -252,6 +252,45 @@ def test_coarse_inverse_many_panels(torch_cuda, case):
     assert rel_max(z, z_ref) <= 1e-10
 
 
+def test_split_basis_warm_start_and_set_prolongation(torch_cuda):
+    # box supports on a 3D grid: the smoothing iteration runs on P split in
+    # halves and the FP64 prolongation reads that form while it holds the
+    # current P.  A warm start continues from the current P; a P set from
+    # outside must replace the split copy in the prolongation; a warm start
+    # in FP32 converts the set P.  The grid's row count is not a multiple
+    # of the work-group size.
+    cfg = tpfa_inputs("c5", (44, 40, 36), 4)
+    orc = oracle_setup(cfg, kmax=6)
+    s, _, _ = gpu_setup_tpfa(cfg, kmax=6)
+    n = cfg["rp"].size - 1
+    v = np.random.default_rng(5).standard_normal(n)
+
+    def check_apply(tol):
+        z_ref = orc.apply(v)
+        z = np.zeros_like(v)
+        s.apply(v, z)
+        assert rel_max(z, z_ref) <= tol
+
+    orc.setup_basis(kmax=5, warm_start=True)
+    orc.build_coarse()
+    s.setup_basis(max_iter=5, warm_start=True)
+    s.build_coarse()
+    assert rel_max(s.get_prolongation()[2], orc.pv) <= 1e-12
+    check_apply(1e-10)
+
+    pset = orc.pv * (1.0 + 0.01 * np.random.default_rng(6).standard_normal(orc.pv.size))
+    orc.pv = pset.copy()
+    orc.build_coarse()
+    s.set_prolongation(pset)
+    s.build_coarse()
+    assert rel_max(s.get_coarse_matrix(), orc.ac) <= 1e-12
+    check_apply(1e-10)
+
+    orc.setup_basis(kmax=3, warm_start=True)
+    s.setup_basis(max_iter=3, warm_start=True, fp32_basis=True)
+    assert rel_max(s.get_prolongation()[2], orc.pv) <= 1e-5
+
+
 @pytest.mark.parametrize("dims", [(32, 32), (40, 40), (64, 64), (80, 80), (100, 92),
                                   (176, 176), (212, 200), (256, 256)],
                          ids=["64coarse", "100coarse", "256coarse", "400coarse", "575coarse",
