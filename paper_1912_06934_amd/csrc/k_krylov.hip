@@ -1575,10 +1575,8 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
                           const double *part_rr, double *host_out, int tag,
                           const ProlongAxes &axes)
 {
-    if (axes.tab2 && pw == 8)
-        k_prolong_axes<float, 8, float, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1,
-                                                                            0);
-    else if (axes.tab && pw == 8)
+    // (FP32 P is read in its padded rows: axes.tab2 is not set for it)
+    if (axes.tab && pw == 8)
         k_prolong_axes<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
     else if (axes.tab)
         k_prolong_axes<float, 4, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
@@ -1632,10 +1630,15 @@ template <typename T>
 void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pcol16, const T *pv,
                const double *wc, double *z, bool zero, const ProlongAxes &axes)
 {
-    if (axes.tab2 && pw == 8)
-        k_prolong_axes<T, 8, double, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z,
-                                                                          zero ? 1 : 0);
-    else if (axes.tab && pw == 4)
+    if constexpr (std::is_same_v<T, double>) {
+        // FP64 P in the split form
+        if (axes.tab2 && pw == 8) {
+            k_prolong_axes<T, 8, double, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z,
+                                                                              zero ? 1 : 0);
+            return;
+        }
+    }
+    if (axes.tab && pw == 4)
         k_prolong_axes<T, 4><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);
     else if (axes.tab && pw == 8)
         k_prolong_axes<T, 8><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z, zero ? 1 : 0);
