@@ -184,7 +184,10 @@ msrsb_status msrsb_assemble_tpfa(msrsb_ctx *ctx, int32_t dim, const int32_t dims
  * When the matrix came from msrsb_assemble_tpfa and every support is a box
  * of grid cells whose pattern rows are products of per-axis coarse nodes,
  * the restriction and prolongation form their column indices from the grid
- * instead of loading them (checked for every row here; results unchanged).
+ * instead of loading them (checked for every row here; results unchanged),
+ * and on a 3D grid the basis iteration (and the FP64 prolongation) hold P
+ * without the unused slots of rows with fewer than 8 entries (results
+ * unchanged; msrsb_setup_basis then also allocates two such copies).
  * Errors: E_ARG for nc < 1 or nc > 32768 (more than 4096 needs a further
  * level, see msrsb_set_coarse_level), empty rows, unsorted or out-of-range
  * columns, part[i] not in row i's pattern, a coarse block without rows. */
