@@ -252,6 +252,25 @@ def test_coarse_inverse_many_panels(torch_cuda, case):
     assert rel_max(z, z_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("case", [("c5", (13, 9, 7), 4), ("c5", (7, 5, 4), 2)],
+                         ids=["13x9x7", "7x5x4"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_split_basis_small_grids(torch_cuda, case, fp32):
+    # the split form on grids whose x lines are much shorter than a
+    # wavefront (a wavefront's rows span several lines and planes): P in
+    # both precisions and the apply (FP64 P: the split prolongation)
+    cfg = tpfa_inputs(*case)
+    orc = oracle_setup(cfg, kmax=30)
+    s, _, _ = gpu_setup_tpfa(cfg, kmax=30, fp32_basis=fp32)
+    assert rel_max(s.get_prolongation()[2], orc.pv) <= (1e-5 if fp32 else 1e-12)
+    if not fp32:
+        v = np.random.default_rng(7).standard_normal(cfg["rp"].size - 1)
+        z_ref = orc.apply(v)
+        z = np.zeros_like(v)
+        s.apply(v, z)
+        assert rel_max(z, z_ref) <= 1e-10
+
+
 def test_split_basis_warm_start_and_set_prolongation(torch_cuda):
     # box supports on a 3D grid: the smoothing iteration runs on P split in
     # halves and the FP64 prolongation reads that form while it holds the
