@@ -185,7 +185,7 @@ void free_coarse(msrsb_ctx *c)
     dfree(c->rbox);
     dfree(c->paxes);
     dfree(c->psplit_tab);
-    dfree(c->psplit_tab2);
+    dfree(c->psplit_wtab);
     c->psplit = SplitRows{};
     c->ps_valid = false;
     for (int t = 0; t < 2; ++t) {
@@ -1188,13 +1188,29 @@ msrsb_status msrsb_set_coarse(msrsb_ctx *c, int32_t nc, const int32_t *part,
             // 2^31, and the second halves' bytes (FP64) stay below 2^31 (one
             // buffer resource covers them)
             if (ok && scale * 32 <= INT32_MAX) {
-                std::vector<int2> st2(st.size());
-                for (size_t k = 0; k < st.size(); ++k) st2[k] = make_int2(paxes[k], st[k]);
-                if (!dalloc(c->psplit_tab, st.size()) || !dalloc(c->psplit_tab2, st2.size()))
+                // per 64 rows: first second-half index and the 8-entry mask
+                std::vector<int4> wt((n + 63) / 64, make_int4(0, 0, 0, 0));
+                int h8 = 0;
+                for (int i = 0; i < n; ++i) {
+                    const int x = i % gdim[0], y = (i / gdim[0]) % gdim[1],
+                              z = i / (gdim[0] * gdim[1]);
+                    const bool f8 = (st[x] & st[gdim[0] + y] & st[gdim[0] + gdim[1] + z]) < 0;
+                    int4 &e = wt[i / 64];
+                    if (i % 64 == 0) e.x = h8;
+                    if (f8) {
+                        const int b = i % 64;
+                        if (b < 32)
+                            e.y = static_cast<int>(static_cast<uint32_t>(e.y) | (1u << b));
+                        else
+                            e.z = static_cast<int>(static_cast<uint32_t>(e.z) | (1u << (b - 32)));
+                        ++h8;
+                    }
+                }
+                if (!dalloc(c->psplit_tab, st.size()) || !dalloc(c->psplit_wtab, wt.size()))
                     return fail(c, MSRSB_E_NOMEM, "device allocation of the coarse data failed");
-                hipMemcpyAsync(c->psplit_tab, st.data(), st.size() * sizeof(int),
+                hipMemcpyAsync(c->psplit_wtab, wt.data(), wt.size() * sizeof(int4),
                                hipMemcpyHostToDevice, c->stream);
-                hipMemcpyAsync(c->psplit_tab2, st2.data(), st2.size() * sizeof(int2),
+                hipMemcpyAsync(c->psplit_tab, st.data(), st.size() * sizeof(int),
                                hipMemcpyHostToDevice, c->stream);
                 c->psplit.tab = c->psplit_tab;
                 c->psplit.nx = gdim[0];

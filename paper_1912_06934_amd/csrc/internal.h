@@ -213,7 +213,7 @@ struct msrsb_ctx {
     // unless the supports are boxes on a 3D grid with 8-slot rows), and the
     // two split buffers of the iteration
     int *psplit_tab = nullptr;
-    int2 *psplit_tab2 = nullptr;  // per axis position {paxes entry, psplit_tab entry}
+    int4 *psplit_wtab = nullptr;  // per 64 rows (ProlongAxes::wtab)
     msrsb::SplitRows psplit;
     double *ps64[2] = {nullptr, nullptr};
     float *ps32[2] = {nullptr, nullptr};
@@ -481,8 +481,10 @@ struct ProlongAxes {
     const int *tab = nullptr;
     int nx = 0, ny = 0, ncx = 0, ncxy = 0;
     // non-null: P is given in the split form (SplitRows, n8 rows of 8
-    // entries), and per axis position {tab entry, SplitRows entry}
-    const int2 *tab2 = nullptr;
+    // entries), located through a table with one entry per 64 rows: the
+    // second-half index of their first 8-entry row and a 64-bit mask of
+    // their 8-entry rows (low, high words)
+    const int4 *wtab = nullptr;
     int64_t n8 = 0;
 };
 // xc = R x; columns from the boxes when given, else from rci, or (roff16

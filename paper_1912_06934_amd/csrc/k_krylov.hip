@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_ell(int n, const uint16_t *_
 // Slot u of the row is (ix, iy, iz) with ix fastest, as the ascending column
 // order puts them; slots past cx cy cz are padding.
 // SPLIT (PW 8): pv is P's split form (slots 0-3 of every row, then slots
-// 4-7 of the 8-entry rows), located through ax.tab2's second entries.
+// 4-7 of the 8-entry rows), located through ax.wtab.
 template <typename T, int PW, typename ZT = double, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_prolong_axes(int n, ProlongAxes ax,
                                                          const T *__restrict__ pv,
@@ -1188,13 +1188,19 @@ __global__ __launch_bounds__(kBlock) void k_prolong_axes(int n, ProlongAxes ax,
     constexpr int L = 16 / sizeof(T);
     typedef T tvec __attribute__((ext_vector_type(L)));
     if constexpr (SPLIT) {
-        const int2 ex = ax.tab2[x], ey = ax.tab2[ax.nx + y], ez = ax.tab2[ax.nx + ax.ny + zz];
-        tx = ex.x;
-        ty = ey.x;
-        tz = ez.x;
-        constexpr int M = 0x7FFFFFFF;
-        const int h = (ex.y & M) + (ey.y & M) + (ez.y & M);
-        const bool f = (ex.y & ey.y & ez.y) < 0;
+        // the wavefront's entry of the per-64-row table (a scalar load): the
+        // second-half index needs no per-row table load
+        const int4 wt = ax.wtab[__builtin_amdgcn_readfirstlane(i >> 6)];
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint64_t mask = static_cast<uint64_t>(static_cast<uint32_t>(wt.y)) |
+                              (static_cast<uint64_t>(static_cast<uint32_t>(wt.z)) << 32);
+        const bool f = (mask >> lane) & 1u;
+        const int h = wt.x + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                 static_cast<uint32_t>(mask >> 32),
+                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
+        tx = ax.tab[x];
+        ty = ax.tab[ax.nx + y];
+        tz = ax.tab[ax.nx + ax.ny + zz];
         const tvec *lo = reinterpret_cast<const tvec *>(pv + static_cast<int64_t>(i) * 4);
 #pragma unroll
         for (int q = 0; q < 4 / L; ++q) {
@@ -1575,7 +1581,7 @@ void launch_prec_f32_post(hipStream_t s, int n, const DiaOffsets &d, const float
                           const double *part_rr, double *host_out, int tag,
                           const ProlongAxes &axes)
 {
-    // (FP32 P is read in its padded rows: axes.tab2 is not set for it)
+    // (FP32 P is read in its padded rows: axes.wtab is not set for it)
     if (axes.tab && pw == 8)
         k_prolong_axes<float, 8, float><<<grid_for(n), kBlock, 0, s>>>(n, axes, p32, wc, z1, 0);
     else if (axes.tab)
@@ -1632,7 +1638,7 @@ void prolong_t(hipStream_t s, int n, int pw, const int *pcol, const uint16_t *pc
 {
     if constexpr (std::is_same_v<T, double>) {
         // FP64 P in the split form
-        if (axes.tab2 && pw == 8) {
+        if (axes.wtab && pw == 8) {
             k_prolong_axes<T, 8, double, true><<<grid_for(n), kBlock, 0, s>>>(n, axes, pv, wc, z,
                                                                               zero ? 1 : 0);
             return;

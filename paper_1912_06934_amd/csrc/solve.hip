@@ -382,9 +382,8 @@ ApplyBufs ctx_apply_bufs(msrsb_ctx *c)
 
 // The FP64 prolongation reads P's split form while it holds the current P
 // (fewer bytes: the zero slots of rows with fewer than 8 entries are not
-// stored).  The FP32 one keeps the padded rows: its second-half address
-// waits on a table load, and in FP32 that costs more time than the bytes
-// save.  prolong_p64 / prolong_p32 return the matching values.
+// stored).  The FP32 one keeps the padded rows, which it reads as fast.
+// prolong_p64 / prolong_p32 return the matching values.
 static bool prolong_split(const msrsb_ctx *c)
 {
     return c->paxes && c->ps_valid && c->pw == 8 && !c->p_is32;
@@ -399,7 +398,7 @@ static ProlongAxes prolong_axes(const msrsb_ctx *c)
         a.ncx = c->pax_ncx;
         a.ncxy = c->pax_ncxy;
         if (prolong_split(c)) {
-            a.tab2 = c->psplit_tab2;
+            a.wtab = c->psplit_wtab;
             a.n8 = c->psplit.n8;
         }
     }
