@@ -91,6 +91,10 @@ struct TriOrder {
     int *ptr_l = nullptr, *ptr_u = nullptr;    // level pointers (device copies)
     std::vector<int> h_lev_l, h_lev_u;
     std::vector<TriSegment> seg_l, seg_u;
+    void *packed = nullptr;    // natural order: per level position, the row's
+                               // entries on the solved side (k_tri.hip)
+    int max_lo = 0, max_up = 0;            // most entries of a row on each side
+    int max_w_l = 0, max_w_u = 0;          // widest level of each triangle
 };
 
 // P's rows in two halves for the smoothing iteration, when the supports are

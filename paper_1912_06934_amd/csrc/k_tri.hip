@@ -231,6 +231,112 @@ __global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow_lds(TriArgs t, Ro
     for (int i = tid; i < n; i += kNarrowThreads) r.x[i] = sx[i];
 }
 
+// A run of narrow levels in the natural order solved by one wavefront, with
+// no barrier between levels: a wavefront's LDS operations complete in
+// order, so a level reads the x values the previous levels wrote.  Each
+// lane takes up to two rows of a level (levels of at most kTriWaveRows rows,
+// rows of at most kRowRegs entries on the solved side), whose entries are
+// packed beforehand (k_tri_pack) and loaded kTriDepth levels ahead, so a
+// level costs LDS reads, its products and one division.  The arithmetic and
+// its order are those of solve_row.
+constexpr int kTriDepth = 3;
+constexpr int kTriWaveRows = 128;       // rows per level (two per lane)
+constexpr size_t kTriWaveLds = 160 * 1024;  // x, the spare slot and the level pointers
+
+struct alignas(16) PackedRow {
+    int i, ne, b, pad;     // row; its entries on the solved side: count, first
+    int c[kRowRegs];       // their columns (at most kRowRegs kept)
+    double v[kRowRegs];    // their values
+    double d, pad2;        // the diagonal (1 for a unit diagonal)
+};
+
+__global__ __launch_bounds__(256) void k_tri_pack(TriArgs t, RowOp r,
+                                                  const int *__restrict__ rows, int u0, int u1,
+                                                  PackedRow *__restrict__ rec)
+{
+    const int u = u0 + static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+    if (u >= u1) return;
+    const int i = rows[u];
+    const int dp = t.dpos[i];
+    const bool lower = r.op == OP_LOWER;
+    const int b = lower ? t.rp[i] : dp + 1, e = lower ? dp : t.rp[i + 1];
+    PackedRow q;
+    q.i = i;
+    q.ne = e - b;
+    q.b = b;
+    q.pad = 0;
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k) {
+        const int idx = b + k < e ? b + k : dp;
+        q.c[k] = t.ci[idx];
+        q.v[k] = r.f[idx];
+    }
+    q.d = r.unit ? 1.0 : r.f[dp];
+    q.pad2 = 0.0;
+    rec[u] = q;
+}
+
+// One packed row (at most kRowRegs entries): s = x_i - (its entries times
+// x), x_i = s or s / d, in solve_row's order.  The slots past the row's
+// count hold its own column (a valid index) and add zero, and a lane
+// without a row (ok false) writes its duplicate's value to the spare slot
+// sx[n]: no branch, so the loads kTriDepth levels ahead stay in flight.
+__device__ __forceinline__ void tri_wave_solve(const RowOp &r, double *sx, int n,
+                                               const PackedRow &q, bool ok)
+{
+    double s = sx[q.i];
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k) {
+        const double xv = sx[q.c[k]];
+        s -= (k < q.ne ? q.v[k] : 0.0) * xv;
+    }
+    sx[ok ? q.i : n] = r.unit ? s : s / q.d;
+}
+
+__global__ __launch_bounds__(64) void k_tri_wave(RowOp r, const int *__restrict__ lev_ptr,
+                                                 const PackedRow *__restrict__ rec, int lev0,
+                                                 int lev1, int n)
+{
+    // n + 1 values: x and a spare slot; then the run's level pointers, kept
+    // in LDS so that no other memory load sits between the rows' loads (a
+    // wait for one would wait for all rows loaded before it)
+    extern __shared__ double sx[];
+    int *slev = reinterpret_cast<int *>(sx + n + 1);
+    const int lane = threadIdx.x;
+    for (int i = lane; i < n; i += 64) sx[i] = r.x[i];
+    for (int l = lev0 + lane; l <= lev1; l += 64) slev[l - lev0] = lev_ptr[l];
+    // the first kTriWaveRows rows of level l (positions clamped to the level,
+    // and a level past the run to the last one: every load is in bounds)
+    auto load = [&](int l, PackedRow (&q)[2], bool (&ok)[2]) {
+        const int lc = min(l, lev1 - 1) - lev0;
+        const int u0 = slev[lc], u1 = slev[lc + 1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int u = u0 + lane + 64 * h;
+            ok[h] = l < lev1 && u < u1;
+            q[h] = rec[min(u, u1 - 1)];
+        }
+    };
+    PackedRow ring[kTriDepth][2];
+    bool rok[kTriDepth][2];
+#pragma unroll
+    for (int k = 0; k < kTriDepth; ++k) load(lev0 + k, ring[k], rok[k]);
+    for (int l = lev0; l < lev1; l += kTriDepth) {
+#pragma unroll
+        for (int k = 0; k < kTriDepth; ++k) {
+            // (levels past the run: their rows are marked, nothing is written;
+            // the scheduling barriers keep a later level's arithmetic, and
+            // with it the wait for its rows, below this level's)
+            __builtin_amdgcn_sched_barrier(0);
+            tri_wave_solve(r, sx, n, ring[k][0], rok[k][0]);
+            tri_wave_solve(r, sx, n, ring[k][1], rok[k][1]);
+            load(l + k + kTriDepth, ring[k], rok[k]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (int i = lane; i < n; i += 64) r.x[i] = sx[i];
+}
+
 // upper entries of the IC(0) array take the factor value of their transpose
 __global__ __launch_bounds__(256) void k_ic_mirror(int64_t nnz, const int8_t *__restrict__ side,
                                                    const int *__restrict__ tpos,
@@ -344,6 +450,23 @@ void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
             const int cnt = ptr[g.lev0 + 1] - ptr[g.lev0];
             k_tri_wide<<<(cnt + 255) / 256, 256, 0, s>>>(a, r, rows + ptr[g.lev0], cnt);
         } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
+                   t.n <= kNarrowLdsRows && t.packed &&
+                   (lower ? t.max_lo : t.max_up) <= kRowRegs &&
+                   (lower ? t.max_w_l : t.max_w_u) <= kTriWaveRows &&
+                   static_cast<size_t>(t.n + 1) * sizeof(double) +
+                           static_cast<size_t>(g.lev1 - g.lev0 + 1) * sizeof(int) <=
+                       kTriWaveLds) {
+            const size_t sh = static_cast<size_t>(t.n + 1) * sizeof(double) +
+                              static_cast<size_t>(g.lev1 - g.lev0 + 1) * sizeof(int);
+            if (sh > 65536)
+                hipFuncSetAttribute(reinterpret_cast<const void *>(k_tri_wave),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(sh));
+            auto *rec = static_cast<PackedRow *>(t.packed);
+            const int u0 = ptr[g.lev0], u1 = ptr[g.lev1];
+            k_tri_pack<<<(u1 - u0 + 255) / 256, 256, 0, s>>>(a, r, rows, u0, u1, rec);
+            k_tri_wave<<<1, 64, sh, s>>>(r, dptr, rec, g.lev0, g.lev1, t.n);
+        } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
                    t.n <= kNarrowLdsRows) {
             const size_t sh = static_cast<size_t>(t.n) * sizeof(double);
             if (sh > 65536)
@@ -365,7 +488,7 @@ void free_tri_order(TriOrder &t)
                     static_cast<void *>(t.lord), static_cast<void *>(t.nlow),
                     static_cast<void *>(t.tpos), static_cast<void *>(t.rows_l),
                     static_cast<void *>(t.rows_u), static_cast<void *>(t.ptr_l),
-                    static_cast<void *>(t.ptr_u)})
+                    static_cast<void *>(t.ptr_u), t.packed})
         if (p) hipFree(p);
     t = TriOrder();
 }
@@ -415,11 +538,29 @@ msrsb_status tri_order_setup(msrsb_ctx *c, int ordering)
     level_sets(n, rp, ci, order, rank, false, pu, ru);
     segments(pl, t.seg_l);
     segments(pu, t.seg_u);
+    for (int i = 0; i < n; ++i) {
+        int lo = 0, up = 0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            lo += side[e] < 0 ? 1 : 0;
+            up += side[e] > 0 ? 1 : 0;
+        }
+        t.max_lo = std::max(t.max_lo, lo);
+        t.max_up = std::max(t.max_up, up);
+    }
+    for (size_t l = 0; l + 1 < pl.size(); ++l) t.max_w_l = std::max(t.max_w_l, pl[l + 1] - pl[l]);
+    for (size_t l = 0; l + 1 < pu.size(); ++l) t.max_w_u = std::max(t.max_w_u, pu[l + 1] - pu[l]);
     t.h_lev_l = pl;
     t.h_lev_u = pu;
     if (!upload(t.rank, rank) || !upload(t.side, side) || !upload(t.lord, lord) ||
         !upload(t.nlow, nlow) || !upload(t.tpos, tpos) || !upload(t.rows_l, rl) ||
         !upload(t.rows_u, ru) || !upload(t.ptr_l, pl) || !upload(t.ptr_u, pu)) {
+        free_tri_order(t);
+        return MSRSB_E_NOMEM;
+    }
+    // natural order on a system small enough for x in LDS: the solves' rows
+    // packed by level position (one row per position of either triangle)
+    if (t.ncolours == 0 && n <= kNarrowLdsRows &&
+        hipMalloc(&t.packed, static_cast<size_t>(n) * sizeof(PackedRow)) != hipSuccess) {
         free_tri_order(t);
         return MSRSB_E_NOMEM;
     }
