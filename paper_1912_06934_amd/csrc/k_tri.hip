@@ -240,6 +240,7 @@ __global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow_lds(TriArgs t, Ro
 // level costs LDS reads, its products and one division.  The arithmetic and
 // its order are those of solve_row.
 constexpr int kTriDepth = 3;
+constexpr int kTriUnroll = 8;
 constexpr int kTriWaveRows = 128;       // rows per level (two per lane)
 constexpr size_t kTriWaveLds = 160 * 1024;  // x, the spare slot and the level pointers
 
@@ -281,18 +282,22 @@ __global__ __launch_bounds__(256) void k_tri_pack(TriArgs t, RowOp r,
 // count hold its own column (a valid index) and add zero, and a lane
 // without a row (ok false) writes its duplicate's value to the spare slot
 // sx[n]: no branch, so the loads kTriDepth levels ahead stay in flight.
+template <int W>
 __device__ __forceinline__ void tri_wave_solve(const RowOp &r, double *sx, int n,
                                                const PackedRow &q, bool ok)
 {
     double s = sx[q.i];
 #pragma unroll
-    for (int k = 0; k < kRowRegs; ++k) {
+    for (int k = 0; k < W; ++k) {
         const double xv = sx[q.c[k]];
         s -= (k < q.ne ? q.v[k] : 0.0) * xv;
     }
     sx[ok ? q.i : n] = r.unit ? s : s / q.d;
 }
 
+// W: the most entries of a row on the solved side (4 or kRowRegs); only
+// those slots of the packed rows are loaded and used
+template <int W>
 __global__ __launch_bounds__(64) void k_tri_wave(RowOp r, const int *__restrict__ lev_ptr,
                                                  const PackedRow *__restrict__ rec, int lev0,
                                                  int lev1, int n)
@@ -314,23 +319,34 @@ __global__ __launch_bounds__(64) void k_tri_wave(RowOp r, const int *__restrict_
         for (int h = 0; h < 2; ++h) {
             const int u = u0 + lane + 64 * h;
             ok[h] = l < lev1 && u < u1;
-            q[h] = rec[min(u, u1 - 1)];
+            const PackedRow &g = rec[min(u, u1 - 1)];
+            q[h].i = g.i;
+            q[h].ne = g.ne;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                q[h].c[k] = g.c[k];
+                q[h].v[k] = g.v[k];
+            }
+            q[h].d = g.d;
         }
     };
     PackedRow ring[kTriDepth][2];
     bool rok[kTriDepth][2];
 #pragma unroll
     for (int k = 0; k < kTriDepth; ++k) load(lev0 + k, ring[k], rok[k]);
-    for (int l = lev0; l < lev1; l += kTriDepth) {
+    // kTriUnroll steps of kTriDepth levels per loop trip: the compiler waits
+    // for every row in flight where the loop closes, so it closes rarely
+    for (int l = lev0; l < lev1; l += kTriDepth * kTriUnroll) {
 #pragma unroll
-        for (int k = 0; k < kTriDepth; ++k) {
+        for (int kk = 0; kk < kTriDepth * kTriUnroll; ++kk) {
+            const int k = kk % kTriDepth;
             // (levels past the run: their rows are marked, nothing is written;
             // the scheduling barriers keep a later level's arithmetic, and
             // with it the wait for its rows, below this level's)
             __builtin_amdgcn_sched_barrier(0);
-            tri_wave_solve(r, sx, n, ring[k][0], rok[k][0]);
-            tri_wave_solve(r, sx, n, ring[k][1], rok[k][1]);
-            load(l + k + kTriDepth, ring[k], rok[k]);
+            tri_wave_solve<W>(r, sx, n, ring[k][0], rok[k][0]);
+            tri_wave_solve<W>(r, sx, n, ring[k][1], rok[k][1]);
+            load(l + kk + kTriDepth, ring[k], rok[k]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -458,14 +474,20 @@ void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
                        kTriWaveLds) {
             const size_t sh = static_cast<size_t>(t.n + 1) * sizeof(double) +
                               static_cast<size_t>(g.lev1 - g.lev0 + 1) * sizeof(int);
-            if (sh > 65536)
-                hipFuncSetAttribute(reinterpret_cast<const void *>(k_tri_wave),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    static_cast<int>(sh));
             auto *rec = static_cast<PackedRow *>(t.packed);
             const int u0 = ptr[g.lev0], u1 = ptr[g.lev1];
             k_tri_pack<<<(u1 - u0 + 255) / 256, 256, 0, s>>>(a, r, rows, u0, u1, rec);
-            k_tri_wave<<<1, 64, sh, s>>>(r, dptr, rec, g.lev0, g.lev1, t.n);
+            auto wave = [&](auto kern) {
+                if (sh > 65536)
+                    hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        static_cast<int>(sh));
+                kern<<<1, 64, sh, s>>>(r, dptr, rec, g.lev0, g.lev1, t.n);
+            };
+            if ((lower ? t.max_lo : t.max_up) <= 4)
+                wave(k_tri_wave<4>);
+            else
+                wave(k_tri_wave<kRowRegs>);
         } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
                    t.n <= kNarrowLdsRows) {
             const size_t sh = static_cast<size_t>(t.n) * sizeof(double);
