@@ -235,12 +235,16 @@ __global__ __launch_bounds__(kNarrowThreads) void k_tri_narrow_lds(TriArgs t, Ro
 // no barrier between levels: a wavefront's LDS operations complete in
 // order, so a level reads the x values the previous levels wrote.  Each
 // lane takes up to two rows of a level (levels of at most kTriWaveRows rows,
-// rows of at most kRowRegs entries on the solved side), whose entries are
+// rows of at most kTriWaveW entries on the solved side), whose entries are
 // packed beforehand (k_tri_pack) and loaded kTriDepth levels ahead, so a
 // level costs LDS reads, its products and one division.  The arithmetic and
 // its order are those of solve_row.
-constexpr int kTriDepth = 3;
-constexpr int kTriUnroll = 8;
+// levels loaded ahead and steps per loop trip, by row width (the ring of
+// loaded rows has to fit the registers); the solve takes rows of at most
+// kTriWaveW entries on the solved side (2D 9-point stencils and narrower)
+template <int W> constexpr int kTriDepth = W <= 4 ? 6 : 3;
+template <int W> constexpr int kTriUnroll = W <= 4 ? 4 : 8;
+constexpr int kTriWaveW = 4;
 constexpr int kTriWaveRows = 128;       // rows per level (two per lane)
 constexpr size_t kTriWaveLds = 160 * 1024;  // x, the spare slot and the level pointers
 
@@ -330,23 +334,23 @@ __global__ __launch_bounds__(64) void k_tri_wave(RowOp r, const int *__restrict_
             q[h].d = g.d;
         }
     };
-    PackedRow ring[kTriDepth][2];
-    bool rok[kTriDepth][2];
+    PackedRow ring[kTriDepth<W>][2];
+    bool rok[kTriDepth<W>][2];
 #pragma unroll
-    for (int k = 0; k < kTriDepth; ++k) load(lev0 + k, ring[k], rok[k]);
+    for (int k = 0; k < kTriDepth<W>; ++k) load(lev0 + k, ring[k], rok[k]);
     // kTriUnroll steps of kTriDepth levels per loop trip: the compiler waits
     // for every row in flight where the loop closes, so it closes rarely
-    for (int l = lev0; l < lev1; l += kTriDepth * kTriUnroll) {
+    for (int l = lev0; l < lev1; l += kTriDepth<W> * kTriUnroll<W>) {
 #pragma unroll
-        for (int kk = 0; kk < kTriDepth * kTriUnroll; ++kk) {
-            const int k = kk % kTriDepth;
+        for (int kk = 0; kk < kTriDepth<W> * kTriUnroll<W>; ++kk) {
+            const int k = kk % kTriDepth<W>;
             // (levels past the run: their rows are marked, nothing is written;
             // the scheduling barriers keep a later level's arithmetic, and
             // with it the wait for its rows, below this level's)
             __builtin_amdgcn_sched_barrier(0);
             tri_wave_solve<W>(r, sx, n, ring[k][0], rok[k][0]);
             tri_wave_solve<W>(r, sx, n, ring[k][1], rok[k][1]);
-            load(l + kk + kTriDepth, ring[k], rok[k]);
+            load(l + kk + kTriDepth<W>, ring[k], rok[k]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -467,7 +471,7 @@ void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
             k_tri_wide<<<(cnt + 255) / 256, 256, 0, s>>>(a, r, rows + ptr[g.lev0], cnt);
         } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
                    t.n <= kNarrowLdsRows && t.packed &&
-                   (lower ? t.max_lo : t.max_up) <= kRowRegs &&
+                   (lower ? t.max_lo : t.max_up) <= kTriWaveW &&
                    (lower ? t.max_w_l : t.max_w_u) <= kTriWaveRows &&
                    static_cast<size_t>(t.n + 1) * sizeof(double) +
                            static_cast<size_t>(g.lev1 - g.lev0 + 1) * sizeof(int) <=
@@ -484,10 +488,7 @@ void run_levels(hipStream_t s, const TriOrder &t, bool lower, const RowOp &r)
                                         static_cast<int>(sh));
                 kern<<<1, 64, sh, s>>>(r, dptr, rec, g.lev0, g.lev1, t.n);
             };
-            if ((lower ? t.max_lo : t.max_up) <= 4)
-                wave(k_tri_wave<4>);
-            else
-                wave(k_tri_wave<kRowRegs>);
+            wave(k_tri_wave<kTriWaveW>);
         } else if (t.ncolours == 0 && (r.op == OP_LOWER || r.op == OP_UPPER) &&
                    t.n <= kNarrowLdsRows) {
             const size_t sh = static_cast<size_t>(t.n) * sizeof(double);
